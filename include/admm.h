@@ -1,0 +1,187 @@
+/*
+ * admm.h -- C ABI of the MI355X split-lasso ADMM library (libadmm.so).
+ *
+ * Solves  min_u  1/2 |g - H u|^2 + lambda |u|_1  over complex u with the
+ * consensus-and-sectioning ADMM of Heredia-Juesas et al. (arXiv 1811.05571,
+ * Sec. III-C): H (m x n) is cut into Q row blocks and P column blocks; block
+ * (i,j) keeps a replica u_j^i of image section j, a scaled dual s_j^i and its
+ * estimated data ghat_ij = H_ij u_j^i.  Q = 1 is the sectioning scheme
+ * (Sec. III-B), P = 1 the consensus scheme (Sec. III-A).  One iteration is
+ *   g'_ij = g_i - sum_{q!=j} ghat_iq                     (eq. g_rows_columns)
+ *   u_j^i = (H_ij^H H_ij + rho I)^{-1}(H_ij^H g'_ij + rho(v_j - s_j^i))
+ *                                   (eq. x_solution_rows_columns, evaluated
+ *                                    with the inversion lemma, eq. inversion_lemma3)
+ *   v_j   = S_{lambda/(Q rho)}(mean_i u_j^i + mean_i s_j^i) (eq. v_variable_rows_columns,
+ *                                    soft threshold eq. softhresholding, sign(a)=a/|a|)
+ *   s_j^i += u_j^i - v_j                                  (eq. s_variable_rows_columns)
+ * All blocks live on one GPU.  The solver output is v = [v_1; ...; v_P].
+ *
+ * Conventions for every entry point:
+ *   - Complex data are interleaved single precision (re, im) pairs, i.e. the
+ *     layout of C99 `float _Complex` / numpy complex64, unless stated.
+ *   - "device" pointers are HIP device (or managed) memory; "host" pointers
+ *     are ordinary host memory.  The library never allocates device memory:
+ *     the caller passes one workspace buffer sized by admm_workspace_bytes.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; calls that return host values synchronise it.
+ *   - Every call returns 0 (ADMM_OK) or a negative status; admm_strerror
+ *     names the code and admm_last_error() (per thread) gives the detail.
+ *   - A plan must not be used from two host threads at once.
+ */
+#ifndef ADMM_H
+#define ADMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define ADMM_OK            0
+#define ADMM_EINVAL       (-1) /* bad argument: NULL, size, split, rho, lambda, iters   */
+#define ADMM_EWORKSPACE   (-2) /* workspace NULL, too small or not 256-byte aligned     */
+#define ADMM_EHIP         (-3) /* a HIP runtime call failed (detail in last_error)      */
+#define ADMM_ENOTPD       (-4) /* Gram matrix not positive definite (non-finite H)     */
+#define ADMM_ENONFINITE   (-5) /* NaN/Inf found in H, g or the iterates                 */
+#define ADMM_ESTATE       (-6) /* call out of order (e.g. backward without a record)   */
+#define ADMM_EUNSUPPORTED (-7) /* valid but not implemented combination                */
+
+/* ---- storage of H inside the plan ------------------------------------ */
+#define ADMM_STORAGE_C64   0   /* complex64, as given                                  */
+#define ADMM_STORAGE_BF16  1   /* bfloat16 real and imaginary planes (RNE rounding)    */
+#define ADMM_STORAGE_FP8   2   /* OCP fp8 e4m3 planes, one fp32 scale per row          */
+
+typedef struct admm_plan admm_plan;
+
+/* Library version as an integer (major*10000 + minor*100 + patch). */
+int admm_version(void);
+
+/* Static name of a status code (never NULL). */
+const char* admm_strerror(int status);
+
+/* Detail of the last failing call on this thread ("" when none). */
+const char* admm_last_error(void);
+
+/*
+ * admm_workspace_bytes -- device workspace needed by admm_setup.
+ *   m, n      rows (measurements) and columns (pixels) of H, both >= 1.
+ *   Q, P      number of row and column blocks, 1 <= Q <= m, 1 <= P <= n.
+ *   row_off   host int64[Q+1] block boundaries, strictly increasing from 0
+ *             to m, or NULL for the equal split (the first m mod Q blocks
+ *             get one extra row).  col_off likewise with P and n.
+ *   storage   ADMM_STORAGE_*.
+ *   out_bytes host, receives the size.
+ * Errors: EINVAL for any bad size or split; EUNSUPPORTED when some block is
+ * not wide (m_i >= n_j), since only the inversion-lemma x-update is built.
+ */
+int admm_workspace_bytes(int64_t m, int64_t n, int Q, const int64_t* row_off,
+                         int P, const int64_t* col_off, int storage,
+                         size_t* out_bytes);
+
+/*
+ * admm_setup -- build a plan: copy/quantise H into the workspace and factor
+ * every block's Gram matrix G_ij = rho I + H_ij H_ij^H once (FP64 Gram,
+ * Cholesky and inverse on the GPU, stored as an FP32 Hermitian inverse).
+ * This is the paper's one-off "inversion" step (Sec. III, inversion lemma;
+ * Table tab:timing, "Inversion time").
+ *   out       host, receives the plan (host memory, free with admm_destroy).
+ *   H         device, m x n complex64, row-major with leading dimension n.
+ *             Read only during this call; the caller may free it afterwards.
+ *   m..storage  as for admm_workspace_bytes.
+ *   rho       augmented-Lagrangian parameter, finite and > 0.
+ *   lambda    l1 weight, finite and >= 0 (changeable by admm_set_lambda).
+ *   workspace device, >= admm_workspace_bytes, 256-byte aligned; owned by the
+ *             caller and must outlive the plan.
+ *   stream    hipStream_t (void*).
+ * Synchronises `stream`.  Errors: EINVAL, EUNSUPPORTED, EWORKSPACE,
+ * ENONFINITE (NaN/Inf in H), ENOTPD, EHIP.  On error *out is set to NULL.
+ */
+int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n,
+               int Q, const int64_t* row_off, int P, const int64_t* col_off,
+               double rho, double lambda, int storage,
+               void* workspace, size_t workspace_bytes, void* stream);
+
+/* Change lambda (finite, >= 0) of a plan; the Gram factors do not depend on
+ * it.  Errors: EINVAL. */
+int admm_set_lambda(admm_plan* plan, double lambda);
+
+/*
+ * admm_solve -- run ADMM iterations on measurements g.
+ *   g          device complex64[m]; must stay valid until the stream reaches
+ *              the end of this call's work.
+ *   iters      >= 0 iterations to run (0 only copies the current image).
+ *   tol        <= 0: run exactly `iters`.  > 0: after every `check_every`-th
+ *              iteration stop when |r_p| <= tol max(|(u^i)|, sqrt(Q)|v|) and
+ *              |r_d| <= tol rho |(s^i)| (residuals of Sec. III-C).
+ *   check_every >= 1 (ignored when tol <= 0).
+ *   v_out      device complex64[n], receives the image v after the last
+ *              iteration.
+ *   iters_done host int or NULL: iterations actually run.
+ *   resid_hist device double[2*iters] or NULL: per iteration |r_p|^2 and
+ *              |r_d|^2 (r_d uses rho^2 Q |v^k - v^{k-1}|^2).
+ *   warm       0: start from u = v = s = ghat = 0.  1: continue from the
+ *              plan's current state (previous solve or admm_set_state).
+ *   stream     hipStream_t.
+ * Synchronises `stream` at the end (and at every check when tol > 0).
+ * Errors: EINVAL, ENONFINITE (a NaN/Inf reached the image), EHIP.
+ */
+int admm_solve(admm_plan* plan, const void* g, int iters, double tol,
+               int check_every, void* v_out, int* iters_done,
+               double* resid_hist, int warm, void* stream);
+
+/*
+ * admm_get_state / admm_set_state -- the iteration state (k, v, s, ghat),
+ * which fixes every later iterate (c = v - s and g'_ij follows from ghat).
+ *   v     device complex64[n];  s device complex64[Q*n] (replica i at i*n);
+ *   ghat  device complex64[P*m] (for column block j, entry j*m + row holds
+ *         ghat_ij for the row's block i);  k host int.
+ * get may pass NULL for any output it does not want.  Errors: EINVAL, EHIP.
+ */
+int admm_get_state(admm_plan* plan, void* v, void* s, void* ghat, int* k,
+                   void* stream);
+int admm_set_state(admm_plan* plan, const void* v, const void* s,
+                   const void* ghat, int k, void* stream);
+
+/*
+ * admm_kkt -- lasso optimality check of an image in FP64 (one pass over the
+ * stored H, accumulated in double):  z = H^H (g - H v);  the result is
+ * max_n dist(z_n, lambda * subdifferential of |v_n|) / lambda, i.e.
+ * |z_n - lambda v_n/|v_n|| on the support and max(0, |z_n| - lambda) off it.
+ * Zero at the lasso minimiser; every splitting's fixed point satisfies it.
+ *   g, v    device complex64[m], complex64[n].
+ *   out     host double.
+ *   lambda must be > 0.  Synchronises `stream`.  Errors: EINVAL, EHIP.
+ */
+int admm_kkt(admm_plan* plan, const void* g, const void* v, double* out,
+             void* stream);
+
+/*
+ * Profiling.  admm_profile(plan, 1) makes later solves bracket every kernel
+ * launch with HIP events on the solve's stream; admm_profile_read returns
+ * the summed duration in ms and the launch count of one kernel class since
+ * profiling was enabled (ADMM_K_* below).  admm_profile(plan, 0) stops and
+ * clears.  Reading synchronises the recorded events.  Errors: EINVAL, EHIP.
+ */
+#define ADMM_K_GEMV_N   0   /* r_ij = g'_ij - H_ij c_j^i            */
+#define ADMM_K_GRAM     1   /* y_ij = G_ij^{-1} r_ij, ghat update   */
+#define ADMM_K_GEMV_H   2   /* partial H_ij^H y_ij                  */
+#define ADMM_K_ZUPDATE  3   /* mean, soft threshold, duals, norms   */
+#define ADMM_K_COUNT    4
+int admm_profile(admm_plan* plan, int enable);
+int admm_profile_read(admm_plan* plan, int kernel, double* total_ms,
+                      int64_t* launches);
+
+/* Static description of the plan: fills host int64 info[16] with
+ * m, n, Q, P, storage, chunks of the adjoint product, workspace bytes,
+ * bytes of stored H, bytes of stored inverses, iterations done, 0... */
+int admm_plan_info(const admm_plan* plan, int64_t* info16);
+
+/* Release the plan (host memory only; the workspace stays the caller's). */
+void admm_destroy(admm_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADMM_H */

@@ -1,0 +1,219 @@
+"""MI355X split-lasso ADMM (consensus / sectioning / both) -- Python binding.
+
+Thin ctypes layer over libadmm.so (C ABI in include/admm.h).  PyTorch is used
+only to allocate device memory (H, g, outputs and the workspace) and to hand
+the current HIP stream to the library; every step of the solver runs in the
+library's HIP kernels.  There is no fallback: if libadmm.so is missing or no
+GPU is present the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadmm.so")
+
+ADMM_OK = 0
+STATUS = {
+    -1: "ADMM_EINVAL", -2: "ADMM_EWORKSPACE", -3: "ADMM_EHIP", -4: "ADMM_ENOTPD",
+    -5: "ADMM_ENONFINITE", -6: "ADMM_ESTATE", -7: "ADMM_EUNSUPPORTED",
+}
+STORAGE = {"c64": 0, "bf16": 1, "fp8": 2}
+K_GEMV_N, K_GRAM, K_GEMV_H, K_ZUPDATE = 0, 1, 2, 3
+KERNEL_NAMES = {K_GEMV_N: "k_gemv_n", K_GRAM: "k_gram", K_GEMV_H: "k_gemv_h", K_ZUPDATE: "k_zupdate"}
+
+# (name, restype, argtypes) for every symbol of include/admm.h
+_c = ctypes
+_vp, _i64, _int, _dbl, _sz = _c.c_void_p, _c.c_int64, _c.c_int, _c.c_double, _c.c_size_t
+SIGNATURES = [
+    ("admm_version", _int, []),
+    ("admm_strerror", _c.c_char_p, [_int]),
+    ("admm_last_error", _c.c_char_p, []),
+    ("admm_workspace_bytes", _int, [_i64, _i64, _int, _vp, _int, _vp, _int, _c.POINTER(_sz)]),
+    ("admm_setup", _int, [_c.POINTER(_vp), _vp, _i64, _i64, _int, _vp, _int, _vp, _dbl, _dbl, _int,
+                          _vp, _sz, _vp]),
+    ("admm_set_lambda", _int, [_vp, _dbl]),
+    ("admm_solve", _int, [_vp, _vp, _int, _dbl, _int, _vp, _c.POINTER(_int), _vp, _int, _vp]),
+    ("admm_get_state", _int, [_vp, _vp, _vp, _vp, _c.POINTER(_int), _vp]),
+    ("admm_set_state", _int, [_vp, _vp, _vp, _vp, _int, _vp]),
+    ("admm_kkt", _int, [_vp, _vp, _vp, _c.POINTER(_dbl), _vp]),
+    ("admm_profile", _int, [_vp, _int]),
+    ("admm_profile_read", _int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
+    ("admm_plan_info", _int, [_vp, _c.POINTER(_i64)]),
+    ("admm_destroy", None, [_vp]),
+]
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libadmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python paper_1811_05571_amd/build.py`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class ADMMError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        L = lib()
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+        detail = L.admm_last_error().decode()
+        super().__init__(f"{where}: {self.status}: {detail}")
+
+
+def _check(code: int, where: str):
+    if code != ADMM_OK:
+        raise ADMMError(code, where)
+
+
+def _offsets(o):
+    if o is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(o, dtype=np.int64))
+    return arr, arr.ctypes.data_as(ctypes.c_void_p)
+
+
+def workspace_bytes(m: int, n: int, Q: int, P: int, row_off=None, col_off=None,
+                    storage: str = "c64") -> int:
+    ro, rp = _offsets(row_off)
+    co, cp = _offsets(col_off)
+    out = ctypes.c_size_t(0)
+    _check(lib().admm_workspace_bytes(m, n, Q, rp, P, cp, STORAGE[storage], ctypes.byref(out)),
+           "admm_workspace_bytes")
+    return int(out.value)
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _stream(torch, device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Plan:
+    """A factored split of H living on one GPU.
+
+    H: torch complex64 CUDA tensor (m, n), row-major contiguous.  The plan
+    copies it into its workspace, so H may be freed afterwards.
+    """
+
+    def __init__(self, H, Q: int, P: int, rho: float, lam: float, row_off=None, col_off=None,
+                 storage: str = "c64"):
+        import torch
+        if not (H.is_cuda and H.dtype == torch.complex64 and H.dim() == 2 and H.is_contiguous()):
+            raise ValueError("H must be a contiguous complex64 CUDA tensor (m, n)")
+        self.torch = torch
+        self.device = H.device
+        self.m, self.n = H.shape
+        self.Q, self.P = Q, P
+        self.rho, self.lam = float(rho), float(lam)
+        self.storage = storage
+        self.row_off, self.col_off = row_off, col_off
+        nbytes = workspace_bytes(self.m, self.n, Q, P, row_off, col_off, storage)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        _, rp = _offsets(row_off)
+        _, cp = _offsets(col_off)
+        ro_keep, _ = _offsets(row_off)
+        co_keep, _ = _offsets(col_off)
+        self._keep = (ro_keep, co_keep)
+        rp = None if ro_keep is None else ro_keep.ctypes.data_as(ctypes.c_void_p)
+        cp = None if co_keep is None else co_keep.ctypes.data_as(ctypes.c_void_p)
+        h = ctypes.c_void_p(0)
+        _check(lib().admm_setup(ctypes.byref(h), _ptr(H), self.m, self.n, Q, rp, P, cp, self.rho,
+                                self.lam, STORAGE[storage], _ptr(self.workspace), nbytes,
+                                _stream(torch, self.device)), "admm_setup")
+        self._h = h
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().admm_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- solver -------------------------------------------------------------
+    def set_lambda(self, lam: float):
+        _check(lib().admm_set_lambda(self._h, float(lam)), "admm_set_lambda")
+        self.lam = float(lam)
+
+    def solve(self, g, iters: int, tol: float = 0.0, check_every: int = 10, warm: bool = False,
+              history: bool = False, out=None):
+        """Run `iters` iterations on g (complex64 CUDA, length m); returns v
+        (complex64, length n) and, with history=True, a (k, 2) float64 tensor
+        of |r_p|^2, |r_d|^2 per iteration."""
+        torch = self.torch
+        if not (g.is_cuda and g.dtype == torch.complex64 and g.numel() == self.m and g.is_contiguous()):
+            raise ValueError("g must be a contiguous complex64 CUDA tensor of length m")
+        v = out if out is not None else torch.empty(self.n, dtype=torch.complex64, device=self.device)
+        hist = torch.zeros((max(iters, 1), 2), dtype=torch.float64, device=self.device) if history else None
+        done = ctypes.c_int(0)
+        _check(lib().admm_solve(self._h, _ptr(g), int(iters), float(tol), int(check_every), _ptr(v),
+                                ctypes.byref(done), None if hist is None else _ptr(hist), int(bool(warm)),
+                                _stream(torch, self.device)), "admm_solve")
+        self.iters_done = int(done.value)
+        if history:
+            return v, hist[: self.iters_done]
+        return v
+
+    def kkt(self, g, v) -> float:
+        out = ctypes.c_double(0.0)
+        _check(lib().admm_kkt(self._h, _ptr(g), _ptr(v), ctypes.byref(out),
+                              _stream(self.torch, self.device)), "admm_kkt")
+        return float(out.value)
+
+    def get_state(self):
+        torch = self.torch
+        v = torch.empty(self.n, dtype=torch.complex64, device=self.device)
+        s = torch.empty((self.Q, self.n), dtype=torch.complex64, device=self.device)
+        ghat = torch.empty((self.P, self.m), dtype=torch.complex64, device=self.device)
+        k = ctypes.c_int(0)
+        _check(lib().admm_get_state(self._h, _ptr(v), _ptr(s), _ptr(ghat), ctypes.byref(k),
+                                    _stream(torch, self.device)), "admm_get_state")
+        return int(k.value), v, s, ghat
+
+    def set_state(self, k: int, v, s, ghat):
+        _check(lib().admm_set_state(self._h, _ptr(v.contiguous()), _ptr(s.contiguous()),
+                                    _ptr(ghat.contiguous()), int(k), _stream(self.torch, self.device)),
+               "admm_set_state")
+
+    # -- profiling ----------------------------------------------------------
+    def profile(self, enable: bool):
+        _check(lib().admm_profile(self._h, int(bool(enable))), "admm_profile")
+
+    def profile_read(self, kernel: int):
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        _check(lib().admm_profile_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n)),
+               "admm_profile_read")
+        return float(ms.value), int(n.value)
+
+    def info(self) -> dict:
+        arr = (ctypes.c_int64 * 16)()
+        _check(lib().admm_plan_info(self._h, arr), "admm_plan_info")
+        keys = ["m", "n", "Q", "P", "storage", "chunks", "workspace_bytes", "h_bytes", "ginv_bytes",
+                "iters_done", "m_pad", "n_pad"]
+        return {k: int(arr[i]) for i, k in enumerate(keys)}

@@ -1,0 +1,615 @@
+// C ABI of the split-lasso ADMM library: argument checks, workspace layout,
+// plan lifetime and the host side of setup / solve / KKT check.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/admm.h"
+#include "plan.h"
+
+using namespace admm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(ADMM_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                                   \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+namespace admm {
+
+int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* row_off, int P,
+                   const int64_t* col_off, int storage, std::string& err) {
+  char buf[256];
+  if (m < 1 || n < 1) {
+    err = "m and n must be >= 1";
+    return ADMM_EINVAL;
+  }
+  if (m > (int64_t)1 << 30 || n > (int64_t)1 << 30) {
+    err = "m and n must be < 2^30";
+    return ADMM_EINVAL;
+  }
+  if (Q < 1 || Q > m || P < 1 || P > n) {
+    snprintf(buf, sizeof buf, "need 1 <= Q <= m and 1 <= P <= n (Q=%d P=%d m=%lld n=%lld)", Q, P,
+             (long long)m, (long long)n);
+    err = buf;
+    return ADMM_EINVAL;
+  }
+  if (storage != ADMM_STORAGE_C64 && storage != ADMM_STORAGE_BF16 && storage != ADMM_STORAGE_FP8) {
+    err = "unknown storage";
+    return ADMM_EINVAL;
+  }
+  auto offsets = [&](int64_t total, int parts, const int64_t* given, std::vector<int64_t>& o) -> bool {
+    o.assign(parts + 1, 0);
+    if (given) {
+      for (int k = 0; k <= parts; ++k) o[k] = given[k];
+      if (o[0] != 0 || o[parts] != total) return false;
+      for (int k = 0; k < parts; ++k)
+        if (o[k + 1] <= o[k]) return false;
+      return true;
+    }
+    const int64_t base = total / parts, extra = total % parts;
+    for (int k = 0; k < parts; ++k) o[k + 1] = o[k] + base + (k < extra ? 1 : 0);
+    return true;
+  };
+  if (!offsets(m, Q, row_off, geo.ro)) {
+    err = "row offsets must increase strictly from 0 to m";
+    return ADMM_EINVAL;
+  }
+  if (!offsets(n, P, col_off, geo.co)) {
+    err = "column offsets must increase strictly from 0 to n";
+    return ADMM_EINVAL;
+  }
+  geo.m = m;
+  geo.n = n;
+  geo.Q = Q;
+  geo.P = P;
+  geo.storage = storage;
+  if (storage != ADMM_STORAGE_C64) {
+    err = "only complex64 storage is built";
+    return ADMM_EUNSUPPORTED;
+  }
+  // padded spaces
+  std::vector<int64_t> ldc(P), cpad0(P), ldr(Q), rpad0(Q);
+  int64_t acc = 0;
+  for (int j = 0; j < P; ++j) {
+    ldc[j] = round_up(geo.co[j + 1] - geo.co[j], kColPad);
+    cpad0[j] = acc;
+    acc += ldc[j];
+  }
+  geo.n_pad = acc;
+  acc = 0;
+  for (int i = 0; i < Q; ++i) {
+    ldr[i] = round_up(geo.ro[i + 1] - geo.ro[i], kRowPad);
+    rpad0[i] = acc;
+    acc += ldr[i];
+  }
+  geo.m_pad = acc;
+  if (geo.n_pad > INT32_MAX || geo.m_pad > INT32_MAX) {
+    err = "problem too large";
+    return ADMM_EINVAL;
+  }
+  geo.blocks.clear();
+  int64_t hoff = 0, gioff = 0, foff = 0;
+  int max_mi = 0;
+  geo.max_mt = 0;
+  for (int i = 0; i < Q; ++i)
+    for (int j = 0; j < P; ++j) {
+      BlockDesc d{};
+      d.i = i;
+      d.j = j;
+      d.mi = (int32_t)(geo.ro[i + 1] - geo.ro[i]);
+      d.nj = (int32_t)(geo.co[j + 1] - geo.co[j]);
+      if (d.mi >= d.nj) {
+        snprintf(buf, sizeof buf,
+                 "block (%d,%d) is %d x %d: only wide blocks (rows < columns) use the inversion-lemma "
+                 "x-update that is built",
+                 i, j, d.mi, d.nj);
+        err = buf;
+        return ADMM_EUNSUPPORTED;
+      }
+      d.ld = (int32_t)ldc[j];
+      d.ldr = (int32_t)ldr[i];
+      d.mt = (int32_t)round_up(d.mi, kTile);
+      d.row0 = (int32_t)geo.ro[i];
+      d.col0 = (int32_t)geo.co[j];
+      d.rpad0 = (int32_t)rpad0[i];
+      d.cpad0 = (int32_t)cpad0[j];
+      d.h_off = hoff;
+      d.gi_off = gioff;
+      d.f_off = foff;
+      hoff += (int64_t)d.mi * d.ld;
+      gioff += (int64_t)d.mi * d.ldr;
+      foff += (int64_t)d.mt * d.mt;
+      max_mi = std::max(max_mi, d.mi);
+      geo.max_mt = std::max(geo.max_mt, d.mt);
+      geo.blocks.push_back(d);
+    }
+  geo.cols.resize(P);
+  for (int j = 0; j < P; ++j)
+    geo.cols[j] = ColDesc{(int32_t)(geo.co[j + 1] - geo.co[j]), (int32_t)cpad0[j], (int32_t)geo.co[j],
+                          (int32_t)ldc[j]};
+  // workgroup tables
+  geo.t_rows.clear();
+  geo.t_cols.clear();
+  geo.t_z.clear();
+  geo.t_gram.clear();
+  int wg_per_chunk = 0;
+  for (size_t b = 0; b < geo.blocks.size(); ++b) {
+    const BlockDesc& d = geo.blocks[b];
+    for (int r = 0; r < d.mi; r += kRowsPerWG) geo.t_rows.push_back(make_int4((int)b, r, 0, 0));
+    wg_per_chunk += (int)((((d.nj + 1) / 2) + kColsPerWG4 - 1) / kColsPerWG4);
+    const int nt = d.mt / kTile;
+    for (int a = 0; a < nt; ++a)
+      for (int c = 0; c <= a; ++c) geo.t_gram.push_back(make_int4((int)b, a, c, 0));
+  }
+  // Row chunks of the adjoint product: enough workgroups to fill the chip,
+  // at least 16 rows per chunk.
+  {
+    const int want = std::max(1, (2048 + wg_per_chunk - 1) / wg_per_chunk);
+    const int cap = std::max(1, (max_mi + 15) / 16);
+    geo.KH = std::min(std::min(want, cap), 32);
+  }
+  for (int k = 0; k < geo.KH; ++k)
+    for (size_t b = 0; b < geo.blocks.size(); ++b) {
+      const BlockDesc& d = geo.blocks[b];
+      const int n4 = (d.nj + 1) / 2;
+      for (int c4 = 0; c4 < n4; c4 += kColsPerWG4) geo.t_cols.push_back(make_int4((int)b, c4, k, 0));
+    }
+  for (int j = 0; j < P; ++j)
+    for (int c = 0; c < geo.cols[j].nj; c += kZCols) geo.t_z.push_back(make_int4(j, c, 0, 0));
+
+  // workspace layout
+  Layout& L = geo.lay;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.h_bytes = (size_t)hoff * 8;
+  L.H = take(L.h_bytes);
+  L.ginv_bytes = (size_t)gioff * 8;
+  L.Ginv = take(L.ginv_bytes);
+  L.F64a = take((size_t)foff * 16);
+  L.F64b = take((size_t)foff * 16);
+  const size_t colv = (size_t)geo.n_pad * 8, rowv = (size_t)geo.m_pad * 8;
+  L.c = take(colv * Q);
+  L.s = take(colv * Q);
+  L.v = take(colv);
+  L.part = take(colv * Q * geo.KH);
+  L.gp = take(rowv * P);
+  L.ghat = take(rowv * P);
+  L.r = take(rowv * P);
+  L.y = take(rowv * P);
+  L.blocks = take(sizeof(BlockDesc) * geo.blocks.size());
+  L.cols = take(sizeof(ColDesc) * P);
+  L.t_rows = take(16 * geo.t_rows.size());
+  L.t_cols = take(16 * geo.t_cols.size());
+  L.t_z = take(16 * geo.t_z.size());
+  L.t_gram = take(16 * geo.t_gram.size());
+  L.ctl = take(sizeof(Control));
+  L.redpart = take(8 * kRedCount * geo.t_z.size());
+  L.row_block = take(8 * (size_t)m);
+  L.kkt_e = take(16 * (size_t)m);
+  L.kkt_v = take(colv);
+  L.kkt_part = take(2 * colv * Q * geo.KH);
+  L.kkt_max = take(8 * geo.t_z.size());
+  L.total = off;
+  return ADMM_OK;
+}
+
+}  // namespace admm
+
+struct admm_plan {
+  Geometry geo;
+  double rho = 1.0, lam = 0.0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  float2 *H = nullptr, *Ginv = nullptr, *c = nullptr, *s = nullptr, *v = nullptr, *part = nullptr;
+  float2 *gp = nullptr, *ghat = nullptr, *r = nullptr, *y = nullptr, *kkt_v = nullptr;
+  double2 *F64a = nullptr, *F64b = nullptr, *kkt_e = nullptr, *kkt_part = nullptr;
+  BlockDesc* d_blocks = nullptr;
+  ColDesc* d_cols = nullptr;
+  int4 *t_rows = nullptr, *t_cols = nullptr, *t_z = nullptr, *t_gram = nullptr;
+  Control* ctl = nullptr;
+  double *redpart = nullptr, *kkt_max = nullptr;
+  int64_t* row_block = nullptr;
+  std::vector<int64_t> h_row_block;
+  int k_done = 0;
+  // profiling
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[ADMM_K_COUNT];
+  std::vector<hipEvent_t> pool;
+  double prof_ms[ADMM_K_COUNT] = {0, 0, 0, 0};
+  int64_t prof_n[ADMM_K_COUNT] = {0, 0, 0, 0};
+};
+
+namespace {
+
+template <class T>
+T* at(admm_plan* p, size_t off) {
+  return reinterpret_cast<T*>(p->ws + off);
+}
+
+hipError_t ev_get(admm_plan* p, hipEvent_t* e) {
+  if (!p->pool.empty()) {
+    *e = p->pool.back();
+    p->pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+// Launch through the profiler when it is on.
+template <class F>
+int timed(admm_plan* p, int kind, hipStream_t st, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (p->prof) {
+    HIP_TRY(ev_get(p, &a));
+    HIP_TRY(ev_get(p, &b));
+    HIP_TRY(hipEventRecord(a, st));
+  }
+  hipError_t e = launch();
+  if (e != hipSuccess) return fail(ADMM_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+  if (p->prof) {
+    HIP_TRY(hipEventRecord(b, st));
+    p->ev[kind].emplace_back(a, b);
+  }
+  return ADMM_OK;
+}
+
+int drain_profile(admm_plan* p) {
+  for (int k = 0; k < ADMM_K_COUNT; ++k) {
+    for (auto& pr : p->ev[k]) {
+      HIP_TRY(hipEventSynchronize(pr.second));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+      p->prof_ms[k] += ms;
+      p->prof_n[k] += 1;
+      p->pool.push_back(pr.first);
+      p->pool.push_back(pr.second);
+    }
+    p->ev[k].clear();
+  }
+  return ADMM_OK;
+}
+
+IterArgs iter_args(admm_plan* p, const float2* g, double* hist) {
+  IterArgs a{};
+  a.blocks = p->d_blocks;
+  a.cols = p->d_cols;
+  a.H = p->H;
+  a.Ginv = p->Ginv;
+  a.g = g;
+  a.c = p->c;
+  a.s = p->s;
+  a.v = p->v;
+  a.part = p->part;
+  a.gp = p->gp;
+  a.ghat = p->ghat;
+  a.r = p->r;
+  a.y = p->y;
+  a.ctl = p->ctl;
+  a.redpart = p->redpart;
+  a.hist = hist;
+  a.m_pad = p->geo.m_pad;
+  a.n_pad = p->geo.n_pad;
+  a.Q = p->geo.Q;
+  a.P = p->geo.P;
+  a.KH = p->geo.KH;
+  a.rho = (float)p->rho;
+  a.kappa = (float)(p->lam / (p->geo.Q * p->rho));
+  a.rho2Q = p->rho * p->rho * p->geo.Q;
+  return a;
+}
+
+int reset_state(admm_plan* p, hipStream_t st) {
+  const Layout& L = p->geo.lay;
+  // c, s, v, part, gp, ghat, r, y are contiguous in the layout
+  const size_t bytes = L.blocks - L.c;
+  HIP_TRY(launch_fill(p->ws + L.c, bytes, st));
+  p->k_done = 0;
+  return ADMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int admm_version(void) { return 100; }
+
+const char* admm_strerror(int status) {
+  switch (status) {
+    case ADMM_OK: return "ADMM_OK";
+    case ADMM_EINVAL: return "ADMM_EINVAL: invalid argument";
+    case ADMM_EWORKSPACE: return "ADMM_EWORKSPACE: workspace missing, too small or misaligned";
+    case ADMM_EHIP: return "ADMM_EHIP: HIP runtime error";
+    case ADMM_ENOTPD: return "ADMM_ENOTPD: Gram matrix not positive definite";
+    case ADMM_ENONFINITE: return "ADMM_ENONFINITE: non-finite value in H, g or the iterates";
+    case ADMM_ESTATE: return "ADMM_ESTATE: call out of order";
+    case ADMM_EUNSUPPORTED: return "ADMM_EUNSUPPORTED: combination not built";
+    default: return "ADMM: unknown status";
+  }
+}
+
+const char* admm_last_error(void) { return g_last_error.c_str(); }
+
+int admm_workspace_bytes(int64_t m, int64_t n, int Q, const int64_t* row_off, int P, const int64_t* col_off,
+                         int storage, size_t* out_bytes) {
+  g_last_error.clear();
+  if (!out_bytes) return fail(ADMM_EINVAL, "out_bytes is NULL");
+  Geometry geo;
+  std::string err;
+  int rc = build_geometry(geo, m, n, Q, row_off, P, col_off, storage, err);
+  if (rc) return fail(rc, "%s", err.c_str());
+  *out_bytes = geo.lay.total;
+  return ADMM_OK;
+}
+
+int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, const int64_t* row_off, int P,
+               const int64_t* col_off, double rho, double lambda, int storage, void* workspace,
+               size_t workspace_bytes, void* stream) {
+  g_last_error.clear();
+  if (!out) return fail(ADMM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!H) return fail(ADMM_EINVAL, "H is NULL");
+  if (!(rho > 0.0) || !std::isfinite(rho)) return fail(ADMM_EINVAL, "rho must be finite and > 0");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(ADMM_EINVAL, "lambda must be finite and >= 0");
+  admm_plan* p = new admm_plan;
+  std::string err;
+  int rc = build_geometry(p->geo, m, n, Q, row_off, P, col_off, storage, err);
+  if (rc) {
+    delete p;
+    return fail(rc, "%s", err.c_str());
+  }
+  const Layout& L = p->geo.lay;
+  if (!workspace || workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255)) {
+    delete p;
+    return fail(ADMM_EWORKSPACE, "workspace needs %zu bytes at 256-byte alignment (got %zu at %p)", L.total,
+                workspace_bytes, workspace);
+  }
+  p->rho = rho;
+  p->lam = lambda;
+  p->ws = static_cast<char*>(workspace);
+  p->ws_bytes = workspace_bytes;
+  p->H = at<float2>(p, L.H);
+  p->Ginv = at<float2>(p, L.Ginv);
+  p->F64a = at<double2>(p, L.F64a);
+  p->F64b = at<double2>(p, L.F64b);
+  p->c = at<float2>(p, L.c);
+  p->s = at<float2>(p, L.s);
+  p->v = at<float2>(p, L.v);
+  p->part = at<float2>(p, L.part);
+  p->gp = at<float2>(p, L.gp);
+  p->ghat = at<float2>(p, L.ghat);
+  p->r = at<float2>(p, L.r);
+  p->y = at<float2>(p, L.y);
+  p->d_blocks = at<BlockDesc>(p, L.blocks);
+  p->d_cols = at<ColDesc>(p, L.cols);
+  p->t_rows = at<int4>(p, L.t_rows);
+  p->t_cols = at<int4>(p, L.t_cols);
+  p->t_z = at<int4>(p, L.t_z);
+  p->t_gram = at<int4>(p, L.t_gram);
+  p->ctl = at<Control>(p, L.ctl);
+  p->redpart = at<double>(p, L.redpart);
+  p->row_block = at<int64_t>(p, L.row_block);
+  p->kkt_e = at<double2>(p, L.kkt_e);
+  p->kkt_v = at<float2>(p, L.kkt_v);
+  p->kkt_part = at<double2>(p, L.kkt_part);
+  p->kkt_max = at<double>(p, L.kkt_max);
+  p->h_row_block.resize(m);
+  for (int i = 0; i < Q; ++i)
+    for (int64_t r = p->geo.ro[i]; r < p->geo.ro[i + 1]; ++r) p->h_row_block[r] = i;
+
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto cleanup_fail = [&](int code) {
+    delete p;
+    return code;
+  };
+#define SETUP_TRY(expr)                                                                        \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return cleanup_fail(fail(ADMM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)));     \
+  } while (0)
+  // zero everything the kernels rely on being zero (stores with pads, state, control)
+  SETUP_TRY(launch_fill(p->ws + L.H, L.h_bytes, st));
+  SETUP_TRY(launch_fill(p->ws + L.Ginv, L.ginv_bytes, st));
+  SETUP_TRY(launch_fill(p->ws + L.c, L.total - L.c, st));
+  const Geometry& G = p->geo;
+  SETUP_TRY(hipMemcpyAsync(p->d_blocks, G.blocks.data(), sizeof(BlockDesc) * G.blocks.size(),
+                           hipMemcpyHostToDevice, st));
+  SETUP_TRY(hipMemcpyAsync(p->d_cols, G.cols.data(), sizeof(ColDesc) * G.cols.size(), hipMemcpyHostToDevice, st));
+  SETUP_TRY(hipMemcpyAsync(p->t_rows, G.t_rows.data(), 16 * G.t_rows.size(), hipMemcpyHostToDevice, st));
+  SETUP_TRY(hipMemcpyAsync(p->t_cols, G.t_cols.data(), 16 * G.t_cols.size(), hipMemcpyHostToDevice, st));
+  SETUP_TRY(hipMemcpyAsync(p->t_z, G.t_z.data(), 16 * G.t_z.size(), hipMemcpyHostToDevice, st));
+  SETUP_TRY(hipMemcpyAsync(p->t_gram, G.t_gram.data(), 16 * G.t_gram.size(), hipMemcpyHostToDevice, st));
+  SETUP_TRY(hipMemcpyAsync(p->row_block, p->h_row_block.data(), 8 * (size_t)m, hipMemcpyHostToDevice, st));
+  int max_mi = 0;
+  for (auto& d : G.blocks) max_mi = std::max(max_mi, d.mi);
+  SETUP_TRY(launch_pack_c64(static_cast<const float2*>(H), n, p->d_blocks, (int)G.blocks.size(), max_mi, p->H,
+                            p->ctl, st));
+  SETUP_TRY(launch_gram_build(G, p->d_blocks, p->t_gram, p->H, rho, p->F64a, st));
+  SETUP_TRY(launch_cholesky_inverse(G, p->d_blocks, p->t_gram, p->F64a, p->F64b, p->Ginv, p->ctl, st));
+  Control hc;
+  SETUP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
+  SETUP_TRY(hipStreamSynchronize(st));
+#undef SETUP_TRY
+  if (hc.nonfinite) return cleanup_fail(fail(ADMM_ENONFINITE, "H holds NaN or Inf"));
+  if (hc.notpd) return cleanup_fail(fail(ADMM_ENOTPD, "a Gram matrix pivot was not positive"));
+  *out = p;
+  return ADMM_OK;
+}
+
+int admm_set_lambda(admm_plan* p, double lambda) {
+  g_last_error.clear();
+  if (!p) return fail(ADMM_EINVAL, "plan is NULL");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(ADMM_EINVAL, "lambda must be finite and >= 0");
+  p->lam = lambda;
+  return ADMM_OK;
+}
+
+int admm_solve(admm_plan* p, const void* g, int iters, double tol, int check_every, void* v_out, int* iters_done,
+               double* resid_hist, int warm, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(ADMM_EINVAL, "plan is NULL");
+  if (!g || !v_out) return fail(ADMM_EINVAL, "g and v_out must not be NULL");
+  if (iters < 0) return fail(ADMM_EINVAL, "iters must be >= 0");
+  if (std::isnan(tol)) return fail(ADMM_EINVAL, "tol is NaN");
+  if (tol > 0 && check_every < 1) return fail(ADMM_EINVAL, "check_every must be >= 1");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Geometry& G = p->geo;
+  int rc;
+  if (!warm && (rc = reset_state(p, st))) return rc;
+  HIP_TRY(launch_fill(p->ctl, 16, st));  // iteration counter, ticket, flags
+  const IterArgs a = iter_args(p, static_cast<const float2*>(g), resid_hist);
+  const int nr = (int)G.t_rows.size(), nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
+  int done = 0;
+  for (int k = 0; k < iters; ++k) {
+    if ((rc = timed(p, ADMM_K_GEMV_N, st, [&] { return launch_gemv_n(a, p->t_rows, nr, st); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GRAM, st, [&] { return launch_gram(a, p->t_rows, nr, st); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GEMV_H, st, [&] { return launch_gemv_h(a, p->t_cols, nc, st); }))) return rc;
+    if ((rc = timed(p, ADMM_K_ZUPDATE, st, [&] { return launch_zupdate(a, p->t_z, nz, st); }))) return rc;
+    ++done;
+    if (tol > 0 && (k + 1) % check_every == 0) {
+      Control hc;
+      HIP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (hc.nonfinite) break;
+      const double Q = G.Q;
+      const double rp = std::sqrt(hc.red[kRedRp2]), rd = p->rho * std::sqrt(Q * hc.red[kRedDv2]);
+      const double pri = tol * std::max(std::sqrt(hc.red[kRedU2]), std::sqrt(Q * hc.red[kRedV2]));
+      const double dua = tol * p->rho * std::sqrt(hc.red[kRedS2]);
+      if (rp <= pri && rd <= dua) break;
+    }
+  }
+  p->k_done += done;
+  HIP_TRY(launch_unpad_cols(p->d_cols, G.P, G.n, p->v, static_cast<float2*>(v_out), 0, 0, 1, 0, st));
+  Control hc;
+  HIP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (iters_done) *iters_done = done;
+  if (hc.nonfinite) return fail(ADMM_ENONFINITE, "a NaN or Inf reached the iterates (check g and rho)");
+  return ADMM_OK;
+}
+
+int admm_get_state(admm_plan* p, void* v, void* s, void* ghat, int* k, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(ADMM_EINVAL, "plan is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Geometry& G = p->geo;
+  if (v) HIP_TRY(launch_unpad_cols(p->d_cols, G.P, G.n, p->v, static_cast<float2*>(v), 0, 0, 1, 0, st));
+  if (s)
+    HIP_TRY(launch_unpad_cols(p->d_cols, G.P, G.n, p->s, static_cast<float2*>(s), G.n_pad, G.n, G.Q, 0, st));
+  if (ghat)
+    HIP_TRY(launch_unpad_rows(p->d_blocks, (int)G.blocks.size(), G.m, G.m_pad, p->ghat, static_cast<float2*>(ghat),
+                              0, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (k) *k = p->k_done;
+  return ADMM_OK;
+}
+
+int admm_set_state(admm_plan* p, const void* v, const void* s, const void* ghat, int k, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(ADMM_EINVAL, "plan is NULL");
+  if (!v || !s || !ghat) return fail(ADMM_EINVAL, "v, s and ghat must not be NULL");
+  if (k < 0) return fail(ADMM_EINVAL, "k must be >= 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Geometry& G = p->geo;
+  int rc;
+  if ((rc = reset_state(p, st))) return rc;
+  HIP_TRY(launch_unpad_cols(p->d_cols, G.P, G.n, static_cast<const float2*>(v), p->v, 0, 0, 1, 1, st));
+  HIP_TRY(launch_unpad_cols(p->d_cols, G.P, G.n, static_cast<const float2*>(s), p->s, G.n, G.n_pad, G.Q, 1, st));
+  HIP_TRY(launch_unpad_rows(p->d_blocks, (int)G.blocks.size(), G.m, G.m_pad, static_cast<const float2*>(ghat),
+                            p->ghat, 1, st));
+  HIP_TRY(launch_make_c(p->d_cols, G.P, G.Q, G.n_pad, p->v, p->s, p->c, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  p->k_done = k;
+  return ADMM_OK;
+}
+
+int admm_kkt(admm_plan* p, const void* g, const void* v, double* out, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(ADMM_EINVAL, "plan is NULL");
+  if (!g || !v || !out) return fail(ADMM_EINVAL, "g, v and out must not be NULL");
+  if (!(p->lam > 0.0)) return fail(ADMM_EINVAL, "the KKT check needs lambda > 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Geometry& G = p->geo;
+  HIP_TRY(launch_unpad_cols(p->d_cols, G.P, G.n, static_cast<const float2*>(v), p->kkt_v, 0, 0, 1, 1, st));
+  HIP_TRY(launch_kkt_all(p->d_blocks, p->d_cols, p->row_block, p->t_cols, (int)G.t_cols.size(), p->t_z,
+                         (int)G.t_z.size(), G.m, G.n_pad, G.Q, G.P, G.KH, p->H, static_cast<const float2*>(g),
+                         p->kkt_v, p->lam, p->kkt_e, p->kkt_part, p->kkt_max, p->ctl, st));
+  Control hc;
+  HIP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *out = hc.kkt / p->lam;
+  return ADMM_OK;
+}
+
+int admm_profile(admm_plan* p, int enable) {
+  g_last_error.clear();
+  if (!p) return fail(ADMM_EINVAL, "plan is NULL");
+  int rc = drain_profile(p);
+  if (rc) return rc;
+  for (int k = 0; k < ADMM_K_COUNT; ++k) {
+    p->prof_ms[k] = 0;
+    p->prof_n[k] = 0;
+  }
+  p->prof = enable != 0;
+  return ADMM_OK;
+}
+
+int admm_profile_read(admm_plan* p, int kernel, double* total_ms, int64_t* launches) {
+  g_last_error.clear();
+  if (!p) return fail(ADMM_EINVAL, "plan is NULL");
+  if (kernel < 0 || kernel >= ADMM_K_COUNT) return fail(ADMM_EINVAL, "unknown kernel id %d", kernel);
+  int rc = drain_profile(p);
+  if (rc) return rc;
+  if (total_ms) *total_ms = p->prof_ms[kernel];
+  if (launches) *launches = p->prof_n[kernel];
+  return ADMM_OK;
+}
+
+int admm_plan_info(const admm_plan* p, int64_t* info) {
+  g_last_error.clear();
+  if (!p || !info) return fail(ADMM_EINVAL, "plan and info must not be NULL");
+  const Geometry& G = p->geo;
+  int64_t v[16] = {G.m, G.n, G.Q, G.P, G.storage, G.KH, (int64_t)G.lay.total, (int64_t)G.lay.h_bytes,
+                   (int64_t)G.lay.ginv_bytes, p->k_done, G.m_pad, G.n_pad, 0, 0, 0, 0};
+  std::memcpy(info, v, sizeof v);
+  return ADMM_OK;
+}
+
+void admm_destroy(admm_plan* p) {
+  if (!p) return;
+  drain_profile(p);
+  for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
+  delete p;
+}
+
+}  // extern "C"

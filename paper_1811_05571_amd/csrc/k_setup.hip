@@ -1,0 +1,422 @@
+// One-off setup of the split-lasso ADMM: copy H into the block store and
+// build, per block (i,j), the Hermitian inverse of G_ij = rho I + H_ij H_ij^H
+// in FP64 (Gram, Cholesky, triangular inverse, W^H W), stored as complex64.
+// This is the paper's inversion step: the small m_i x m_i matrix of the
+// inversion lemma (eq. inversion_lemma3), since (I + H H^H/rho)^{-1} = rho G^{-1}.
+//
+// Every FP64 matrix is padded to a multiple of kTile with identity rows, so
+// the tiled algorithms never see a ragged tile.  Tiles are 64 x 64 double2;
+// each workgroup (256 threads) owns one output tile and every thread a 4 x 4
+// sub-block of it.  All blocks of the split are processed by the same launch.
+#include <algorithm>
+#include <cmath>
+
+#include "plan.h"
+
+namespace admm {
+
+namespace {
+
+constexpr int T = kTile;  // 64
+constexpr int KC = 32;    // K chunk staged in LDS
+
+struct __align__(16) Smem {
+  double2 A[T][KC + 1];
+  double2 B[KC][T + 1];
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
+
+// acc[a][b] += sum_kk A[tr+16a][kk] * B[kk][tc+16b]
+__device__ __forceinline__ void mma_chunk(const Smem& sm, double2 (&acc)[4][4], int tr, int tc) {
+#pragma unroll 4
+  for (int kk = 0; kk < KC; ++kk) {
+    double2 av[4], bv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      av[q] = sm.A[tr + 16 * q][kk];
+      bv[q] = sm.B[kk][tc + 16 * q];
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc[p][q].x = fma(av[p].x, bv[q].x, acc[p][q].x);
+        acc[p][q].x = fma(-av[p].y, bv[q].y, acc[p][q].x);
+        acc[p][q].y = fma(av[p].x, bv[q].y, acc[p][q].y);
+        acc[p][q].y = fma(av[p].y, bv[q].x, acc[p][q].y);
+      }
+  }
+}
+
+__device__ __forceinline__ void zero_acc(double2 (&acc)[4][4]) {
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[p][q] = make_double2(0.0, 0.0);
+}
+
+// acc += opA(X) opB(Y) over one 64-wide K range of FP64 tiles.
+// X, Y point at tile origins in an ld-strided double2 matrix.
+// conjTA: use X^H instead of X.  conjTB: use Y^H instead of Y.
+template <bool conjTA, bool conjTB>
+__device__ void tile_product(Smem& sm, const double2* __restrict__ X, const double2* __restrict__ Y,
+                            int64_t ld, double2 (&acc)[4][4]) {
+  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+  for (int k0 = 0; k0 < T; k0 += KC) {
+    __syncthreads();
+    for (int e = tid; e < T * KC; e += kBlockThreads) {
+      int r = e / KC, kk = e % KC;           // A[r][kk]
+      sm.A[r][kk] = conjTA ? conjd(X[(int64_t)(k0 + kk) * ld + r]) : X[(int64_t)r * ld + k0 + kk];
+      int kb = e / T, c = e % T;             // B[kb][c]
+      sm.B[kb][c] = conjTB ? conjd(Y[(int64_t)c * ld + k0 + kb]) : Y[(int64_t)(k0 + kb) * ld + c];
+    }
+    __syncthreads();
+    mma_chunk(sm, acc, tr, tc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Copy H (row-major m x n, complex64) into the block store with zero pads.
+// grid = (rows, blocks); one workgroup per block row.
+__global__ __launch_bounds__(kBlockThreads) void k_pack_c64(const float2* __restrict__ Hin, int64_t n,
+                                                            const BlockDesc* __restrict__ blocks,
+                                                            float2* __restrict__ Hout,
+                                                            Control* ctl) {
+  const BlockDesc d = blocks[blockIdx.y];
+  const int r = blockIdx.x;
+  if (r >= d.mi) return;
+  const float2* src = Hin + (int64_t)(d.row0 + r) * n + d.col0;
+  float2* dst = Hout + d.h_off + (int64_t)r * d.ld;
+  bool bad = false;
+  for (int c = threadIdx.x; c < d.ld; c += kBlockThreads) {
+    float2 h = make_float2(0.f, 0.f);
+    if (c < d.nj) {
+      h = src[c];
+      bad |= !(isfinite(h.x) && isfinite(h.y));
+    }
+    dst[c] = h;
+  }
+  if (bad) ctl->nonfinite = 1;
+}
+
+// Lower tiles of G = rho I + H H^H (FP64 accumulation of the stored values).
+// tiles[x] = {block, tile row, tile col, -} with tile row >= tile col.
+__global__ __launch_bounds__(kBlockThreads) void k_gram_build(const int4* __restrict__ tiles,
+                                                              const BlockDesc* __restrict__ blocks,
+                                                              const float2* __restrict__ H, double rho,
+                                                              double2* __restrict__ A) {
+  __shared__ Smem sm;
+  const int4 t = tiles[blockIdx.x];
+  const BlockDesc d = blocks[t.x];
+  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+  const int r0 = t.y * T, c0 = t.z * T;
+  const float2* Hb = H + d.h_off;
+  double2 acc[4][4];
+  zero_acc(acc);
+  for (int k0 = 0; k0 < d.nj; k0 += KC) {
+    __syncthreads();
+    for (int e = tid; e < T * KC; e += kBlockThreads) {
+      int r = e / KC, kk = e % KC;
+      float2 a = (r0 + r < d.mi) ? Hb[(int64_t)(r0 + r) * d.ld + k0 + kk] : make_float2(0.f, 0.f);
+      sm.A[r][kk] = make_double2(a.x, a.y);
+      int kb = e / T, c = e % T;
+      float2 b = (c0 + c < d.mi) ? Hb[(int64_t)(c0 + c) * d.ld + k0 + kb] : make_float2(0.f, 0.f);
+      sm.B[kb][c] = make_double2(b.x, -(double)b.y);
+    }
+    __syncthreads();
+    mma_chunk(sm, acc, tr, tc);
+  }
+  double2* Ab = A + d.f_off;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + tr + 16 * p, c = c0 + tc + 16 * q;
+      double2 val = acc[p][q];
+      if (r >= d.mi || c >= d.mi) val = make_double2(r == c ? 1.0 : 0.0, 0.0);
+      else if (r == c) val.x += rho;
+      Ab[(int64_t)r * d.mt + c] = val;
+    }
+}
+
+// Cholesky of diagonal tile k (lower, in place).  One workgroup per block.
+__global__ __launch_bounds__(kBlockThreads) void k_potrf_diag(int k, const BlockDesc* __restrict__ blocks,
+                                                              double2* __restrict__ A, Control* ctl) {
+  __shared__ double2 S[T][T + 1];
+  const BlockDesc d = blocks[blockIdx.x];
+  if (k * T >= d.mt) return;
+  double2* Ak = A + d.f_off + (int64_t)(k * T) * d.mt + k * T;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < T * T; e += kBlockThreads) S[e / T][e % T] = Ak[(int64_t)(e / T) * d.mt + e % T];
+  __syncthreads();
+  bool bad = false;
+  for (int p = 0; p < T; ++p) {
+    double dpp = S[p][p].x;
+    if (!(dpp > 0.0) || !isfinite(dpp)) {
+      bad = true;
+      dpp = 1.0;
+    }
+    const double l = sqrt(dpp);
+    __syncthreads();
+    if (tid < T) {
+      if (tid > p) S[tid][p] = make_double2(S[tid][p].x / l, S[tid][p].y / l);
+      else if (tid == p) S[p][p] = make_double2(l, 0.0);
+    }
+    __syncthreads();
+    for (int e = tid; e < T * T; e += kBlockThreads) {
+      const int r = e / T, c = e % T;
+      if (c > p && r >= c) {
+        double2 x = cmul(S[r][p], conjd(S[c][p]));
+        S[r][c].x -= x.x;
+        S[r][c].y -= x.y;
+      }
+    }
+    __syncthreads();
+  }
+  if (bad && tid == 0) ctl->notpd = 1;
+  for (int e = tid; e < T * T; e += kBlockThreads) {
+    const int r = e / T, c = e % T;
+    Ak[(int64_t)r * d.mt + c] = (c <= r) ? S[r][c] : make_double2(0.0, 0.0);
+  }
+}
+
+// Panel: A[i,k] <- A[i,k] L[k,k]^{-H} for every tile i > k.
+// grid = (tile rows below k of the largest block, blocks).
+__global__ __launch_bounds__(kBlockThreads) void k_trsm_panel(int k, const BlockDesc* __restrict__ blocks,
+                                                              double2* __restrict__ A) {
+  __shared__ double2 L[T][T + 1];
+  __shared__ double2 X[T][T + 1];
+  const BlockDesc d = blocks[blockIdx.y];
+  const int i = k + 1 + blockIdx.x;
+  if (i * T >= d.mt) return;
+  const int tid = threadIdx.x;
+  const double2* Lk = A + d.f_off + (int64_t)(k * T) * d.mt + k * T;
+  double2* Ai = A + d.f_off + (int64_t)(i * T) * d.mt + k * T;
+  for (int e = tid; e < T * T; e += kBlockThreads) {
+    L[e / T][e % T] = Lk[(int64_t)(e / T) * d.mt + e % T];
+    X[e / T][e % T] = Ai[(int64_t)(e / T) * d.mt + e % T];
+  }
+  __syncthreads();
+  // Solve X L^H = A column by column: X[:,p] = (A[:,p] - sum_{q<p} X[:,q] conj(L[p][q])) / L[p][p]
+  for (int p = 0; p < T; ++p) {
+    if (tid < T) {
+      const double l = L[p][p].x;
+      X[tid][p] = make_double2(X[tid][p].x / l, X[tid][p].y / l);
+    }
+    __syncthreads();
+    for (int e = tid; e < T * T; e += kBlockThreads) {
+      const int r = e / T, q = e % T;
+      if (q > p) {
+        double2 x = cmul(X[r][p], conjd(L[q][p]));
+        X[r][q].x -= x.x;
+        X[r][q].y -= x.y;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < T * T; e += kBlockThreads) Ai[(int64_t)(e / T) * d.mt + e % T] = X[e / T][e % T];
+}
+
+__device__ __forceinline__ void tri_index(int p, int& a, int& b) {
+  // p -> (a, b) with 0 <= b <= a, p = a(a+1)/2 + b
+  int aa = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+  while ((aa + 1) * (aa + 2) / 2 <= p) ++aa;
+  while (aa * (aa + 1) / 2 > p) --aa;
+  a = aa;
+  b = p - aa * (aa + 1) / 2;
+}
+
+// Trailing update A[i,l] -= A[i,k] A[l,k]^H for k < l <= i.
+// grid = (pairs of the largest block, blocks).
+__global__ __launch_bounds__(kBlockThreads) void k_herk_trail(int k, const BlockDesc* __restrict__ blocks,
+                                                              double2* __restrict__ A) {
+  __shared__ Smem sm;
+  const BlockDesc d = blocks[blockIdx.y];
+  const int nt = d.mt / T - k - 1;
+  int ia, la;
+  tri_index(blockIdx.x, ia, la);
+  if (ia >= nt) return;
+  const int i = k + 1 + ia, l = k + 1 + la;
+  double2* Ab = A + d.f_off;
+  double2 acc[4][4];
+  zero_acc(acc);
+  tile_product<false, true>(sm, Ab + (int64_t)(i * T) * d.mt + k * T, Ab + (int64_t)(l * T) * d.mt + k * T,
+                            d.mt, acc);
+  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+  double2* C = Ab + (int64_t)(i * T) * d.mt + l * T;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double2& o = C[(int64_t)(tr + 16 * p) * d.mt + tc + 16 * q];
+      o.x -= acc[p][q].x;
+      o.y -= acc[p][q].y;
+    }
+}
+
+// W[k,k] = L[k,k]^{-1} (lower).  grid = (tiles of the largest block, blocks).
+__global__ __launch_bounds__(kBlockThreads) void k_trtri_diag(const BlockDesc* __restrict__ blocks,
+                                                              const double2* __restrict__ A,
+                                                              double2* __restrict__ W) {
+  __shared__ double2 L[T][T + 1];
+  __shared__ double2 X[T][T + 1];
+  const BlockDesc d = blocks[blockIdx.y];
+  const int k = blockIdx.x;
+  if (k * T >= d.mt) return;
+  const int tid = threadIdx.x;
+  const double2* Lk = A + d.f_off + (int64_t)(k * T) * d.mt + k * T;
+  for (int e = tid; e < T * T; e += kBlockThreads) {
+    const int r = e / T, c = e % T;
+    L[r][c] = Lk[(int64_t)r * d.mt + c];
+    X[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  // Forward substitution L X = I, row by row: X[p,:] /= L[p][p]; X[r,:] -= L[r][p] X[p,:] for r > p.
+  for (int p = 0; p < T; ++p) {
+    if (tid < T) {
+      const double l = L[p][p].x;
+      X[p][tid] = make_double2(X[p][tid].x / l, X[p][tid].y / l);
+    }
+    __syncthreads();
+    for (int e = tid; e < T * T; e += kBlockThreads) {
+      const int r = e / T, c = e % T;
+      if (r > p) {
+        double2 x = cmul(L[r][p], X[p][c]);
+        X[r][c].x -= x.x;
+        X[r][c].y -= x.y;
+      }
+    }
+    __syncthreads();
+  }
+  double2* Wk = W + d.f_off + (int64_t)(k * T) * d.mt + k * T;
+  for (int e = tid; e < T * T; e += kBlockThreads) {
+    const int r = e / T, c = e % T;
+    Wk[(int64_t)r * d.mt + c] = (c <= r) ? X[r][c] : make_double2(0.0, 0.0);
+  }
+}
+
+// Off-diagonal tiles of W = L^{-1} at distance dist below the diagonal:
+// W[k+dist,k] = -W[k+dist,k+dist] sum_{l=k}^{k+dist-1} L[k+dist,l] W[l,k].
+// grid = (tiles of the largest block, blocks).
+__global__ __launch_bounds__(kBlockThreads) void k_trtri_off(int dist, const BlockDesc* __restrict__ blocks,
+                                                             const double2* __restrict__ A,
+                                                             double2* __restrict__ W) {
+  __shared__ Smem sm;
+  __shared__ double2 Sx[T][T + 1];
+  const BlockDesc d = blocks[blockIdx.y];
+  const int k = blockIdx.x, i = k + dist;
+  if (i * T >= d.mt) return;
+  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+  const double2* Ab = A + d.f_off;
+  double2* Wb = W + d.f_off;
+  double2 acc[4][4];
+  zero_acc(acc);
+  for (int l = k; l < i; ++l)
+    tile_product<false, false>(sm, Ab + (int64_t)(i * T) * d.mt + l * T, Wb + (int64_t)(l * T) * d.mt + k * T,
+                               d.mt, acc);
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Sx[tr + 16 * p][tc + 16 * q] = acc[p][q];
+  zero_acc(acc);
+  const double2* Wii = Wb + (int64_t)(i * T) * d.mt + i * T;
+  for (int k0 = 0; k0 < T; k0 += KC) {
+    __syncthreads();
+    for (int e = tid; e < T * KC; e += kBlockThreads) {
+      const int r = e / KC, kk = e % KC;
+      sm.A[r][kk] = Wii[(int64_t)r * d.mt + k0 + kk];
+      const int kb = e / T, c = e % T;
+      sm.B[kb][c] = Sx[k0 + kb][c];
+    }
+    __syncthreads();
+    mma_chunk(sm, acc, tr, tc);
+  }
+  double2* C = Wb + (int64_t)(i * T) * d.mt + k * T;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      C[(int64_t)(tr + 16 * p) * d.mt + tc + 16 * q] = make_double2(-acc[p][q].x, -acc[p][q].y);
+}
+
+// G^{-1} = W^H W: tile (i,l), l <= i, = sum_{k>=i} W[k,i]^H W[k,l]; written as
+// complex64 to (i,l) and, conjugate-transposed, to (l,i).  Only the block's
+// mi x mi part is stored.  tiles[x] = {block, i, l, -}.
+__global__ __launch_bounds__(kBlockThreads) void k_lauum(const int4* __restrict__ tiles,
+                                                         const BlockDesc* __restrict__ blocks,
+                                                         const double2* __restrict__ W,
+                                                         float2* __restrict__ Ginv) {
+  __shared__ Smem sm;
+  const int4 t = tiles[blockIdx.x];
+  const BlockDesc d = blocks[t.x];
+  const int i = t.y, l = t.z, nt = d.mt / T;
+  const double2* Wb = W + d.f_off;
+  double2 acc[4][4];
+  zero_acc(acc);
+  for (int k = i; k < nt; ++k)
+    tile_product<true, false>(sm, Wb + (int64_t)(k * T) * d.mt + i * T, Wb + (int64_t)(k * T) * d.mt + l * T,
+                              d.mt, acc);
+  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+  float2* G = Ginv + d.gi_off;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = i * T + tr + 16 * p, c = l * T + tc + 16 * q;
+      if (r < d.mi && c < d.mi) {
+        G[(int64_t)r * d.ldr + c] = make_float2((float)acc[p][q].x, (float)acc[p][q].y);
+        if (i != l) G[(int64_t)c * d.ldr + r] = make_float2((float)acc[p][q].x, -(float)acc[p][q].y);
+      }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_pack_c64(const float2* Hin, int64_t n, const BlockDesc* blocks, int nblocks, int max_rows,
+                           float2* Hout, Control* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_c64, dim3(max_rows, nblocks), dim3(kBlockThreads), 0, st, Hin, n, blocks, Hout,
+                     ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_build(const Geometry& geo, const BlockDesc* dblocks, const int4* t_gram,
+                             const float2* H, double rho, double2* A, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram_build, dim3((unsigned)geo.t_gram.size()), dim3(kBlockThreads), 0, st, t_gram,
+                     dblocks, H, rho, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholesky_inverse(const Geometry& geo, const BlockDesc* dblocks, const int4* t_gram,
+                                   double2* A, double2* W, float2* Ginv, Control* ctl, hipStream_t st) {
+  const int nb = (int)geo.blocks.size();
+  const int NT = geo.max_mt / T;
+  hipError_t e;
+  for (int k = 0; k < NT; ++k) {
+    hipLaunchKernelGGL(k_potrf_diag, dim3(nb), dim3(kBlockThreads), 0, st, k, dblocks, A, ctl);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int below = NT - k - 1;
+    if (below > 0) {
+      hipLaunchKernelGGL(k_trsm_panel, dim3(below, nb), dim3(kBlockThreads), 0, st, k, dblocks, A);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_herk_trail, dim3(below * (below + 1) / 2, nb), dim3(kBlockThreads), 0, st, k,
+                         dblocks, A);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL(k_trtri_diag, dim3(NT, nb), dim3(kBlockThreads), 0, st, dblocks, A, W);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int dist = 1; dist < NT; ++dist) {
+    hipLaunchKernelGGL(k_trtri_off, dim3(NT - dist, nb), dim3(kBlockThreads), 0, st, dist, dblocks, A, W);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // the lower tile pairs are the same as those of the Gram build
+  hipLaunchKernelGGL(k_lauum, dim3((unsigned)geo.t_gram.size()), dim3(kBlockThreads), 0, st, t_gram,
+                     dblocks, W, Ginv);
+  return hipGetLastError();
+}
+
+}  // namespace admm

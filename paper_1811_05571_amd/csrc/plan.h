@@ -1,0 +1,93 @@
+// Host-side plan of the ADMM library and the launchers each kernel file
+// exports to the C ABI layer.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace admm {
+
+struct ColDesc {       // one column block j
+  int32_t nj, cpad0, col0, ld;
+};
+
+// Workspace carve-up (byte offsets from the workspace base, 256-aligned).
+struct Layout {
+  size_t H = 0, H_im = 0, H_scale = 0, Ginv = 0, F64a = 0, F64b = 0;
+  size_t c = 0, s = 0, v = 0, part = 0, gp = 0, ghat = 0, r = 0, y = 0;
+  size_t blocks = 0, cols = 0, t_rows = 0, t_cols = 0, t_z = 0, t_gram = 0;
+  size_t ctl = 0, redpart = 0, row_block = 0, kkt_e = 0, kkt_v = 0, kkt_part = 0, kkt_max = 0;
+  size_t total = 0;
+  size_t h_bytes = 0, ginv_bytes = 0;
+};
+
+struct Geometry {
+  int64_t m = 0, n = 0;
+  int Q = 0, P = 0, storage = 0;
+  std::vector<int64_t> ro, co;
+  std::vector<BlockDesc> blocks;   // Q*P, index b = i*P + j
+  std::vector<ColDesc> cols;       // P
+  int64_t m_pad = 0, n_pad = 0;    // padded row / column space lengths
+  int KH = 1;                      // row chunks of the adjoint product
+  int max_mt = 0;                  // largest tile-padded block edge
+  std::vector<int4> t_rows, t_cols, t_z, t_gram;
+  Layout lay;
+};
+
+// Rows handled by one workgroup of the row-parallel products.
+constexpr int kRowsPerWave = 4;
+constexpr int kRowsPerWG = kRowsPerWave * (kBlockThreads / kWave);
+// Float4 (two complex) columns handled by one workgroup of the adjoint product.
+constexpr int kColsPerWG4 = kBlockThreads;
+constexpr int kZCols = kBlockThreads;
+
+int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* row_off, int P,
+                   const int64_t* col_off, int storage, std::string& err);
+
+// ---- kernel launchers (return hipError_t) --------------------------------
+struct IterArgs {
+  const BlockDesc* blocks;
+  const ColDesc* cols;
+  const float2* H;
+  const float2* Ginv;
+  const float2* g;      // caller's measurements
+  float2 *c, *s, *v, *part, *gp, *ghat, *r, *y;
+  Control* ctl;
+  double* redpart;
+  double* hist;         // device, 2 per iteration, or null
+  int64_t m_pad, n_pad;
+  int Q, P, KH;
+  float rho, kappa;
+  double rho2Q;         // rho^2 Q for the dual residual
+};
+
+hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st);
+hipError_t launch_gram(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st);
+hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st);
+hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st);
+hipError_t launch_unpad_cols(const ColDesc* cols, int P, int64_t n, const float2* src, float2* dst,
+                             int64_t src_stride, int64_t dst_stride, int reps, int to_padded,
+                             hipStream_t st);
+hipError_t launch_unpad_rows(const BlockDesc* blocks, int nblocks, int64_t m, int64_t m_pad,
+                             const float2* src, float2* dst, int to_padded, hipStream_t st);
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
+
+// setup
+hipError_t launch_pack_c64(const float2* Hin, int64_t n, const BlockDesc* blocks, int nblocks,
+                           int max_rows, float2* Hout, Control* ctl, hipStream_t st);
+hipError_t launch_gram_build(const Geometry& geo, const BlockDesc* dblocks, const int4* t_gram,
+                             const float2* H, double rho, double2* A, hipStream_t st);
+hipError_t launch_cholesky_inverse(const Geometry& geo, const BlockDesc* dblocks, const int4* t_gram,
+                                   double2* A, double2* W, float2* Ginv, Control* ctl, hipStream_t st);
+
+// KKT check (FP64)
+hipError_t launch_kkt_all(const BlockDesc* dblocks, const ColDesc* dcols, const int64_t* drow_block,
+                          const int4* t_cols, int n_tcols, const int4* t_z, int n_tz, int64_t m, int64_t n_pad,
+                          int Q, int P, int KH, const float2* H, const float2* g, const float2* vpad,
+                          double lam, double2* e, double2* part, double* wgmax, Control* ctl, hipStream_t st);
+hipError_t launch_make_c(const ColDesc* cols, int P, int Q, int64_t n_pad, const float2* v, const float2* s,
+                         float2* c, hipStream_t st);
+
+}  // namespace admm
