@@ -1,0 +1,231 @@
+"""Throughput of the split-lasso ADMM hot path on one MI355X.
+
+A step is one ADMM iteration of the full CRA-like imaging workload
+(6144 x 32000 complex64 H, Q=4 row blocks x P=8 column blocks): local data
+and forward block products, Gram apply with the estimated-data update,
+adjoint block products, thresholded consensus mean, dual update and the
+residual norms.  Inputs are resident in HBM before the timed region; the
+one-off setup (FP64 Gram, Cholesky, inverse) is timed and reported apart.
+
+Prints one JSON line:  metric/value (iterations/s), the per-kernel event
+timings, a roofline object for the dominant kernel and the FP64 oracle timed
+on the host cores on a bounded sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash() -> str:
+    src = os.path.join(ROOT, "paper_1811_05571_amd", "csrc", "k_iter.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+ELEM_BYTES = {"c64": 8, "bf16": 4, "fp8": 2}   # stored bytes per complex element of H
+
+
+def algorithmic_bytes(geo: dict, P: int, Q: int, KH: int, storage: str = "c64") -> dict:
+    """Bytes each kernel must move per launch, from the kernel's definition
+    (not from counters).  Vectors are complex64 (8 B); H elements take
+    ELEM_BYTES[storage] (+ 4 B per row of fp8 scales)."""
+    m, n = geo["m"], geo["n"]
+    mi2 = geo["sum_mi2"]          # sum over blocks of m_i^2
+    c = 8
+    h = m * n * ELEM_BYTES[storage] + (4 * m * P if storage == "fp8" else 0)
+    vec_rows = P * m * c          # one row-space vector (all column blocks)
+    vec_cols = Q * n * c          # one column-space vector (all replicas)
+    gemv_n = h + vec_cols + m * c + (P - 1) * vec_rows * (P > 1) + vec_rows * (2 if P > 1 else 1)
+    gram = mi2 * c + vec_rows * (4 if P > 1 else 3)
+    gemv_h = h + vec_rows + KH * vec_cols
+    zupd = KH * vec_cols + 2 * vec_cols * 2 + 2 * n * c
+    return {"k_gemv_n": gemv_n, "k_gram": gram, "k_gemv_h": gemv_h, "k_zupdate": zupd}
+
+
+def load_traffic(kernel: str, workload: str):
+    """Counter-derived HBM bytes per launch, if a summary taken on the current
+    kernel source is committed under profiles/."""
+    path = os.path.join(PROFILES, f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(prob, n_iter: int):
+    """The FP64 oracle on the host cores: setup once, then n_iter iterations."""
+    from oracle import admm as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
+        blas = ",".join(sorted({d.get("internal_api", "?") for d in threadpool_info()}))
+    except Exception:
+        threads, blas = os.cpu_count(), "?"
+    H = prob.H.astype(np.complex128)
+    ro = O.split_offsets(prob.m, prob.Q)
+    co = O.split_offsets(prob.n, prob.P)
+    t0 = time.perf_counter()
+    blocks = O.setup(H, ro, co, prob.rho)
+    t1 = time.perf_counter()
+    st = O.State.zeros(prob.m, prob.n, prob.Q, prob.P)
+    g = prob.g.astype(np.complex128)
+    for _ in range(n_iter):
+        st, _, _ = O.step(H, g, ro, co, prob.rho, prob.lam, blocks, st)
+    t2 = time.perf_counter()
+    return {
+        "setup_s": t1 - t0, "iter_s": (t2 - t1) / n_iter, "iters": n_iter, "threads": threads,
+        "blas": blas, "v": st.v, "cpu": platform.processor() or platform.machine(),
+        "affinity": len(os.sched_getaffinity(0)),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-forms", action="store_true", help="skip the bf16 / fp8 storage forms")
+    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the solver keeps every block of the split on a single "
+              "MI355X; runs on more than one GPU are not part of this build.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1811_05571_amd as A
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    prob = W.full_imaging(seed=args.seed)
+    gen_s = time.perf_counter() - t
+    print(f"[bench] generated {prob.name} m={prob.m} n={prob.n} Q={prob.Q} P={prob.P} rho={prob.rho} "
+          f"lam={prob.lam:.4g} in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    H = torch.from_numpy(prob.H).to(dev)
+    g = torch.from_numpy(prob.g).to(dev)
+    torch.cuda.synchronize()
+
+    sizes = [prob.m // prob.Q + (1 if i < prob.m % prob.Q else 0) for i in range(prob.Q)]
+    geo = {"m": prob.m, "n": prob.n, "sum_mi2": int(sum(s * s for s in sizes) * prob.P)}
+    workload = prob.name
+
+    def measure(storage: str, steps: int, warmup: int):
+        t = time.perf_counter()
+        plan = A.Plan(H, prob.Q, prob.P, prob.rho, prob.lam, storage=storage)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t
+        info = plan.info()
+        if warmup > 0:
+            plan.solve(g, warmup)
+        plan.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v, hist = plan.solve(g, steps, history=True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        prof = {A.KERNEL_NAMES[k]: plan.profile_read(k) for k in A.KERNEL_NAMES}
+        plan.profile(False)
+        algo = algorithmic_bytes(geo, prob.P, prob.Q, info["chunks"], storage)
+        kern = {}
+        for name, (ms, cnt) in prof.items():
+            avg_ms = ms / max(cnt, 1)
+            kern[name] = {"avg_us": round(avg_ms * 1e3, 3), "launches": cnt, "algo_bytes": algo[name],
+                          "gbs": round(algo[name] / (avg_ms * 1e-3) / 1e9, 1)}
+        dominant = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
+        dk = kern[dominant]
+        v_np = v.cpu().numpy()
+        res = {
+            "plan": plan, "v": v, "elapsed": elapsed, "setup_s": setup_s, "info": info, "kern": kern,
+            "dominant": dominant,
+            "roofline": {"bound": "hbm", "kernel": dominant, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(dk["gbs"] / HBM_PEAK_GBS, 4),
+                         "traffic": load_traffic(dominant, f"{workload}_{storage}"),
+                         "algo_bytes_per_launch": dk["algo_bytes"], "avg_launch_us": dk["avg_us"]},
+            "iteration_gbs": round(sum(algo.values()) * steps / elapsed / 1e9, 1),
+            "nmse": float(np.linalg.norm(v_np - prob.u_true) ** 2 / np.linalg.norm(prob.u_true) ** 2),
+            "kkt": plan.kkt(g, v), "final_residuals": [float(x) for x in hist[-1].cpu().numpy()],
+        }
+        print(f"[bench] {storage}: setup {setup_s * 1e3:.1f} ms, {steps} iterations in {elapsed * 1e3:.1f} ms",
+              file=sys.stderr, flush=True)
+        return res
+
+    main = measure("c64", args.steps, args.warmup)
+    plan = main["plan"]
+    out = {
+        "metric": "ADMM iters/s", "value": round(args.steps / main["elapsed"], 2), "unit": "iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(main["elapsed"] / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": workload, "m": prob.m, "n": prob.n, "Q": prob.Q, "P": prob.P,
+                   "rho": prob.rho, "lam_ratio": 0.02, "storage": "c64", "parallelism": "single-gpu"},
+        "roofline": main["roofline"],
+        "iteration_gbs": main["iteration_gbs"],
+        "kernels": main["kern"],
+        "setup_ms": round(main["setup_s"] * 1e3, 1),
+        "nmse_vs_truth": main["nmse"], "kkt_violation": main["kkt"],
+        "final_residuals": main["final_residuals"],
+    }
+    if not args.no_forms:
+        forms = {}
+        v_ref = main["v"].cpu().numpy()
+        for storage in ("bf16", "fp8"):
+            r = measure(storage, args.steps, args.warmup)
+            vq = r["v"].cpu().numpy()
+            forms[storage] = {
+                "value": round(args.steps / r["elapsed"], 2), "unit": "iters/s",
+                "ms_per_step": round(r["elapsed"] / args.steps * 1e3, 4), "roofline": r["roofline"],
+                "iteration_gbs": r["iteration_gbs"], "kernels": r["kern"], "setup_ms": round(r["setup_s"] * 1e3, 1),
+                "nmse_vs_truth": r["nmse"], "kkt_violation": r["kkt"],
+                "rel_diff_vs_c64_image": float(np.linalg.norm(vq - v_ref) / max(np.linalg.norm(v_ref), 1e-300)),
+            }
+            r["plan"].close()
+            del r
+        out["forms"] = forms
+    del H
+
+    if not args.no_cpu:
+        print(f"[bench] oracle CPU baseline: setup + {args.cpu_iters} iterations", file=sys.stderr, flush=True)
+        cb = cpu_baseline(prob, args.cpu_iters)
+        # parity at full size on the same sample: GPU from zero, same iteration count
+        vg = plan.solve(g, args.cpu_iters).cpu().numpy()
+        err = float(np.linalg.norm(vg - cb["v"]) / max(np.linalg.norm(cb["v"]), 1e-300))
+        out["cpu_baseline"] = {
+            "value": round(1.0 / cb["iter_s"], 4), "unit": "iters/s", "cores": cb["threads"], "kind": "oracle",
+            "sample": f"{prob.name}: oracle setup ({cb['setup_s']:.1f} s, not in value) then "
+                      f"{cb['iters']} iterations from zero, FP64 complex128, {cb['blas']} BLAS with "
+                      f"{cb['threads']} threads on {cb['affinity']} available cores",
+            "setup_s": round(cb["setup_s"], 2),
+        }
+        out["parity_at_full_size"] = {"iters": args.cpu_iters, "rel_err_vs_oracle": err}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

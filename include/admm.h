@@ -50,8 +50,14 @@ extern "C" {
 
 /* ---- storage of H inside the plan ------------------------------------ */
 #define ADMM_STORAGE_C64   0   /* complex64, as given                                  */
-#define ADMM_STORAGE_BF16  1   /* bfloat16 real and imaginary planes (RNE rounding)    */
-#define ADMM_STORAGE_FP8   2   /* OCP fp8 e4m3 planes, one fp32 scale per row          */
+#define ADMM_STORAGE_BF16  1   /* bfloat16 real and imaginary planes, each value the   */
+                               /* round-to-nearest-even bfloat16 of the fp32 value     */
+#define ADMM_STORAGE_FP8   2   /* OCP fp8 e4m3 (bias 7, max 448) real and imaginary    */
+                               /* planes of x / s_r, round to nearest even, saturating;*/
+                               /* s_r = max over row r of |Re|,|Im|, divided by 448    */
+                               /* (1 for an all-zero row).  The Gram factors are built */
+                               /* in FP64 from the dequantised values; products       */
+                               /* accumulate in FP32.                                  */
 
 typedef struct admm_plan admm_plan;
 
@@ -156,6 +162,18 @@ int admm_set_state(admm_plan* plan, const void* v, const void* s,
  */
 int admm_kkt(admm_plan* plan, const void* g, const void* v, double* out,
              void* stream);
+
+/*
+ * admm_get_stored_h -- copy the plan's stored H back out as dense m x n
+ * row-major planes (for checking the quantiser):
+ *   C64:  re_out receives complex64[m*n]; im_out and scale_out are ignored.
+ *   BF16: re_out, im_out receive uint16 bfloat16 codes [m*n].
+ *   FP8:  re_out, im_out receive uint8 e4m3 codes [m*n]; scale_out receives
+ *         float[m], the row scales s_r (value = s_r * e4m3(code)).
+ * All outputs are device memory.  Synchronises `stream`.  Errors: EINVAL, EHIP.
+ */
+int admm_get_stored_h(admm_plan* plan, void* re_out, void* im_out,
+                      float* scale_out, void* stream);
 
 /*
  * Profiling.  admm_profile(plan, 1) makes later solves bracket every kernel

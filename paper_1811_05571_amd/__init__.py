@@ -41,6 +41,7 @@ SIGNATURES = [
     ("admm_get_state", _int, [_vp, _vp, _vp, _vp, _c.POINTER(_int), _vp]),
     ("admm_set_state", _int, [_vp, _vp, _vp, _vp, _int, _vp]),
     ("admm_kkt", _int, [_vp, _vp, _vp, _c.POINTER(_dbl), _vp]),
+    ("admm_get_stored_h", _int, [_vp, _vp, _vp, _vp, _vp]),
     ("admm_profile", _int, [_vp, _int]),
     ("admm_profile_read", _int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
     ("admm_plan_info", _int, [_vp, _c.POINTER(_i64)]),
@@ -199,6 +200,25 @@ class Plan:
         _check(lib().admm_set_state(self._h, _ptr(v.contiguous()), _ptr(s.contiguous()),
                                     _ptr(ghat.contiguous()), int(k), _stream(self.torch, self.device)),
                "admm_set_state")
+
+    def stored_h(self):
+        """The stored H as dense device tensors: complex64 (C64); uint16 bf16
+        codes (re, im) (BF16); uint8 e4m3 codes (re, im) and float32 row scales
+        (FP8)."""
+        torch = self.torch
+        m, n = self.m, self.n
+        if self.storage == "c64":
+            h = torch.empty((m, n), dtype=torch.complex64, device=self.device)
+            _check(lib().admm_get_stored_h(self._h, _ptr(h), None, None, _stream(torch, self.device)),
+                   "admm_get_stored_h")
+            return h
+        dt = torch.int16 if self.storage == "bf16" else torch.uint8
+        re = torch.empty((m, n), dtype=dt, device=self.device)
+        im = torch.empty((m, n), dtype=dt, device=self.device)
+        sc = torch.empty(m, dtype=torch.float32, device=self.device) if self.storage == "fp8" else None
+        _check(lib().admm_get_stored_h(self._h, _ptr(re), _ptr(im), None if sc is None else _ptr(sc),
+                                       _stream(torch, self.device)), "admm_get_stored_h")
+        return re, im, sc
 
     # -- profiling ----------------------------------------------------------
     def profile(self, enable: bool):

@@ -89,10 +89,6 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   geo.Q = Q;
   geo.P = P;
   geo.storage = storage;
-  if (storage != ADMM_STORAGE_C64) {
-    err = "only complex64 storage is built";
-    return ADMM_EUNSUPPORTED;
-  }
   // padded spaces
   std::vector<int64_t> ldc(P), cpad0(P), ldr(Q), rpad0(Q);
   int64_t acc = 0;
@@ -158,27 +154,31 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   geo.t_cols.clear();
   geo.t_z.clear();
   geo.t_gram.clear();
+  geo.t_kadj.clear();
+  const int cpl = cols_per_load(storage);
   int wg_per_chunk = 0;
   for (size_t b = 0; b < geo.blocks.size(); ++b) {
     const BlockDesc& d = geo.blocks[b];
     for (int r = 0; r < d.mi; r += kRowsPerWG) geo.t_rows.push_back(make_int4((int)b, r, 0, 0));
-    wg_per_chunk += (int)((((d.nj + 1) / 2) + kColsPerWG4 - 1) / kColsPerWG4);
+    const int nl = (d.nj + cpl - 1) / cpl;
+    wg_per_chunk += (nl + kColsPerWGLoads - 1) / kColsPerWGLoads;
     const int nt = d.mt / kTile;
     for (int a = 0; a < nt; ++a)
       for (int c = 0; c <= a; ++c) geo.t_gram.push_back(make_int4((int)b, a, c, 0));
   }
-  // Row chunks of the adjoint product: enough workgroups to fill the chip,
-  // at least 16 rows per chunk.
+  // Row chunks of the adjoint product: about 2048 workgroups in total, at
+  // least 32 rows (8 per wave) per chunk.
   {
     const int want = std::max(1, (2048 + wg_per_chunk - 1) / wg_per_chunk);
-    const int cap = std::max(1, (max_mi + 15) / 16);
+    const int cap = std::max(1, max_mi / 32);
     geo.KH = std::min(std::min(want, cap), 32);
   }
   for (int k = 0; k < geo.KH; ++k)
     for (size_t b = 0; b < geo.blocks.size(); ++b) {
       const BlockDesc& d = geo.blocks[b];
-      const int n4 = (d.nj + 1) / 2;
-      for (int c4 = 0; c4 < n4; c4 += kColsPerWG4) geo.t_cols.push_back(make_int4((int)b, c4, k, 0));
+      const int nl = (d.nj + cpl - 1) / cpl;
+      for (int c = 0; c < nl; c += kColsPerWGLoads) geo.t_cols.push_back(make_int4((int)b, c, k, 0));
+      for (int c = 0; c < d.nj; c += kBlockThreads) geo.t_kadj.push_back(make_int4((int)b, c, k, 0));
     }
   for (int j = 0; j < P; ++j)
     for (int c = 0; c < geo.cols[j].nj; c += kZCols) geo.t_z.push_back(make_int4(j, c, 0, 0));
@@ -191,8 +191,17 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
     off = align256(off + bytes);
     return o;
   };
-  L.h_bytes = (size_t)hoff * 8;
-  L.H = take(L.h_bytes);
+  const size_t plane = (size_t)hoff * (storage == ADMM_STORAGE_C64 ? 8 : (storage == ADMM_STORAGE_BF16 ? 2 : 1));
+  L.H = take(plane);
+  L.h_bytes = plane;
+  if (storage != ADMM_STORAGE_C64) {
+    L.H_im = take(plane);
+    L.h_bytes += plane;
+  }
+  if (storage == ADMM_STORAGE_FP8) {
+    L.H_scale = take(4 * (size_t)m);
+    L.h_bytes += 4 * (size_t)m;
+  }
   L.ginv_bytes = (size_t)gioff * 8;
   L.Ginv = take(L.ginv_bytes);
   L.F64a = take((size_t)foff * 16);
@@ -212,6 +221,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   L.t_cols = take(16 * geo.t_cols.size());
   L.t_z = take(16 * geo.t_z.size());
   L.t_gram = take(16 * geo.t_gram.size());
+  L.t_kadj = take(16 * geo.t_kadj.size());
   L.ctl = take(sizeof(Control));
   L.redpart = take(8 * kRedCount * geo.t_z.size());
   L.row_block = take(8 * (size_t)m);
@@ -235,7 +245,8 @@ struct admm_plan {
   double2 *F64a = nullptr, *F64b = nullptr, *kkt_e = nullptr, *kkt_part = nullptr;
   BlockDesc* d_blocks = nullptr;
   ColDesc* d_cols = nullptr;
-  int4 *t_rows = nullptr, *t_cols = nullptr, *t_z = nullptr, *t_gram = nullptr;
+  int4 *t_rows = nullptr, *t_cols = nullptr, *t_z = nullptr, *t_gram = nullptr, *t_kadj = nullptr;
+  HStore hs{};
   Control* ctl = nullptr;
   double *redpart = nullptr, *kkt_max = nullptr;
   int64_t* row_block = nullptr;
@@ -303,7 +314,7 @@ IterArgs iter_args(admm_plan* p, const float2* g, double* hist) {
   IterArgs a{};
   a.blocks = p->d_blocks;
   a.cols = p->d_cols;
-  a.H = p->H;
+  a.hs = p->hs;
   a.Ginv = p->Ginv;
   a.g = g;
   a.c = p->c;
@@ -415,6 +426,11 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   p->t_cols = at<int4>(p, L.t_cols);
   p->t_z = at<int4>(p, L.t_z);
   p->t_gram = at<int4>(p, L.t_gram);
+  p->t_kadj = at<int4>(p, L.t_kadj);
+  p->hs.storage = storage;
+  p->hs.base = p->ws + L.H;
+  p->hs.base_im = storage == ADMM_STORAGE_C64 ? nullptr : p->ws + L.H_im;
+  p->hs.row_scale = storage == ADMM_STORAGE_FP8 ? at<float>(p, L.H_scale) : nullptr;
   p->ctl = at<Control>(p, L.ctl);
   p->redpart = at<double>(p, L.redpart);
   p->row_block = at<int64_t>(p, L.row_block);
@@ -438,7 +454,7 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
       return cleanup_fail(fail(ADMM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)));     \
   } while (0)
   // zero everything the kernels rely on being zero (stores with pads, state, control)
-  SETUP_TRY(launch_fill(p->ws + L.H, L.h_bytes, st));
+  SETUP_TRY(launch_fill(p->ws + L.H, L.Ginv - L.H, st));
   SETUP_TRY(launch_fill(p->ws + L.Ginv, L.ginv_bytes, st));
   SETUP_TRY(launch_fill(p->ws + L.c, L.total - L.c, st));
   const Geometry& G = p->geo;
@@ -449,12 +465,17 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   SETUP_TRY(hipMemcpyAsync(p->t_cols, G.t_cols.data(), 16 * G.t_cols.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->t_z, G.t_z.data(), 16 * G.t_z.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->t_gram, G.t_gram.data(), 16 * G.t_gram.size(), hipMemcpyHostToDevice, st));
+  SETUP_TRY(hipMemcpyAsync(p->t_kadj, G.t_kadj.data(), 16 * G.t_kadj.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->row_block, p->h_row_block.data(), 8 * (size_t)m, hipMemcpyHostToDevice, st));
   int max_mi = 0;
   for (auto& d : G.blocks) max_mi = std::max(max_mi, d.mi);
-  SETUP_TRY(launch_pack_c64(static_cast<const float2*>(H), n, p->d_blocks, (int)G.blocks.size(), max_mi, p->H,
-                            p->ctl, st));
-  SETUP_TRY(launch_gram_build(G, p->d_blocks, p->t_gram, p->H, rho, p->F64a, st));
+  if (storage == ADMM_STORAGE_C64)
+    SETUP_TRY(launch_pack_c64(static_cast<const float2*>(H), n, p->d_blocks, (int)G.blocks.size(), max_mi, p->H,
+                              p->ctl, st));
+  else
+    SETUP_TRY(launch_pack_quant(static_cast<const float2*>(H), m, n, p->d_blocks, (int)G.blocks.size(), max_mi,
+                                p->hs, p->ctl, st));
+  SETUP_TRY(launch_gram_build(G, p->d_blocks, p->t_gram, p->hs, rho, p->F64a, st));
   SETUP_TRY(launch_cholesky_inverse(G, p->d_blocks, p->t_gram, p->F64a, p->F64b, p->Ginv, p->ctl, st));
   Control hc;
   SETUP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
@@ -561,13 +582,29 @@ int admm_kkt(admm_plan* p, const void* g, const void* v, double* out, void* stre
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Geometry& G = p->geo;
   HIP_TRY(launch_unpad_cols(p->d_cols, G.P, G.n, static_cast<const float2*>(v), p->kkt_v, 0, 0, 1, 1, st));
-  HIP_TRY(launch_kkt_all(p->d_blocks, p->d_cols, p->row_block, p->t_cols, (int)G.t_cols.size(), p->t_z,
-                         (int)G.t_z.size(), G.m, G.n_pad, G.Q, G.P, G.KH, p->H, static_cast<const float2*>(g),
+  HIP_TRY(launch_kkt_all(p->d_blocks, p->d_cols, p->row_block, p->t_kadj, (int)G.t_kadj.size(), p->t_z,
+                         (int)G.t_z.size(), G.m, G.n_pad, G.Q, G.P, G.KH, p->hs, static_cast<const float2*>(g),
                          p->kkt_v, p->lam, p->kkt_e, p->kkt_part, p->kkt_max, p->ctl, st));
   Control hc;
   HIP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   *out = hc.kkt / p->lam;
+  return ADMM_OK;
+}
+
+int admm_get_stored_h(admm_plan* p, void* re_out, void* im_out, float* scale_out, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(ADMM_EINVAL, "plan is NULL");
+  const Geometry& G = p->geo;
+  if (!re_out || (G.storage != ADMM_STORAGE_C64 && !im_out) || (G.storage == ADMM_STORAGE_FP8 && !scale_out))
+    return fail(ADMM_EINVAL, "output planes for this storage must not be NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int max_mi = 0;
+  for (auto& d : G.blocks) max_mi = std::max(max_mi, d.mi);
+  HIP_TRY(launch_export_h(p->hs, G.n, p->d_blocks, (int)G.blocks.size(), max_mi, re_out, im_out, st));
+  if (G.storage == ADMM_STORAGE_FP8)
+    HIP_TRY(hipMemcpyAsync(scale_out, p->hs.row_scale, 4 * (size_t)G.m, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
   return ADMM_OK;
 }
 

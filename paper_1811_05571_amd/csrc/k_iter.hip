@@ -21,116 +21,32 @@
 // keeps two columns per lane and splits the rows into chunks whose partials
 // the z-update adds in a fixed order (no float atomics: runs are bitwise
 // reproducible).
-#include "plan.h"
+#include "gemv.h"
 
 namespace admm {
 
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-// Streaming 16-byte load (H and the inverse are read once per iteration).
-__device__ __forceinline__ float4 ldnt(const float4* p) {
-  const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
-  return make_float4(v.x, v.y, v.z, v.w);
-}
-
-// acc += a * b  (complex)
-__device__ __forceinline__ void cmac(float& ar, float& ai, float a_r, float a_i, float b_r,
-                                     float b_i) {
-  ar = fmaf(a_r, b_r, ar);
-  ar = fmaf(-a_i, b_i, ar);
-  ai = fmaf(a_r, b_i, ai);
-  ai = fmaf(a_i, b_r, ai);
-}
-// acc += conj(a) * b
-__device__ __forceinline__ void cmacc(float& ar, float& ai, float a_r, float a_i, float b_r,
-                                      float b_i) {
-  ar = fmaf(a_r, b_r, ar);
-  ar = fmaf(a_i, b_i, ar);
-  ai = fmaf(a_r, b_i, ai);
-  ai = fmaf(-a_i, b_r, ai);
-}
-
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
-  return x;
-}
-__device__ __forceinline__ double wave_sum_d(double x) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
-  return x;
-}
-
-// Dot products of R consecutive rows of a complex64 matrix with x.
-// A points at the first row, lda4 is the row stride in float4 (2 complex)
-// units, n4 the number of float4 per row to use, rows >= nvalid are clamped.
-// Every lane walks columns lane, lane+64, ... with U independent loads per row
-// in flight.  Result: full sums in every lane (xor reduction).
-template <int R, int U>
-__device__ __forceinline__ void rows_dot(const float4* __restrict__ A, int64_t lda4, int nvalid,
-                                         const float4* __restrict__ x, int n4, float (&acc)[R][2]) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const float4* rowp[R];
-#pragma unroll
-  for (int rr = 0; rr < R; ++rr) {
-    int r = rr < nvalid ? rr : (nvalid - 1);
-    rowp[rr] = A + (int64_t)r * lda4;
-    acc[rr][0] = 0.f;
-    acc[rr][1] = 0.f;
-  }
-  int c = lane;
-  for (; c + (U - 1) * kWave < n4; c += U * kWave) {
-    float4 xv[U];
-    float4 hv[U][R];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      xv[u] = x[c + u * kWave];
-#pragma unroll
-      for (int rr = 0; rr < R; ++rr) hv[u][rr] = ldnt(rowp[rr] + c + u * kWave);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int rr = 0; rr < R; ++rr) {
-        cmac(acc[rr][0], acc[rr][1], hv[u][rr].x, hv[u][rr].y, xv[u].x, xv[u].y);
-        cmac(acc[rr][0], acc[rr][1], hv[u][rr].z, hv[u][rr].w, xv[u].z, xv[u].w);
-      }
-  }
-  for (; c < n4; c += kWave) {
-    float4 xv = x[c];
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) {
-      float4 hv = ldnt(rowp[rr] + c);
-      cmac(acc[rr][0], acc[rr][1], hv.x, hv.y, xv.x, xv.y);
-      cmac(acc[rr][0], acc[rr][1], hv.z, hv.w, xv.z, xv.w);
-    }
-  }
-#pragma unroll
-  for (int rr = 0; rr < R; ++rr) {
-    acc[rr][0] = wave_sum(acc[rr][0]);
-    acc[rr][1] = wave_sum(acc[rr][1]);
-  }
-}
-
 // r_ij = g'_ij - H_ij c_j^i for kRowsPerWG rows of one block per workgroup.
 // tiles[x] = {block, first row, -, -}.
+template <class F>
 __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4* __restrict__ tiles) {
+  const F f = MakeFmt<F>::make(a.hs);
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = a.blocks[t.x];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int row = t.y + wave * kRowsPerWave;
   if (row >= d.mi) return;
   const int nvalid = min(kRowsPerWave, d.mi - row);
-  const float4* A = reinterpret_cast<const float4*>(a.H + d.h_off + (int64_t)row * d.ld);
   const float4* x = reinterpret_cast<const float4*>(a.c + (int64_t)d.i * a.n_pad + d.cpad0);
   float acc[kRowsPerWave][2];
-  rows_dot<kRowsPerWave, 4>(A, d.ld / 2, nvalid, x, (d.nj + 1) / 2, acc);
+  rows_dot<F, kRowsPerWave, RowUnroll<F>::U>(f, d.h_off + (int64_t)row * d.ld, d.ld, nvalid, x,
+                                             (d.nj + F::CPL - 1) / F::CPL, acc);
   if (lane < nvalid) {
     float ar = 0.f, ai = 0.f;
 #pragma unroll
     for (int rr = 0; rr < kRowsPerWave; ++rr)
       if (rr == lane) { ar = acc[rr][0]; ai = acc[rr][1]; }
     const int lr = row + lane;                       // row inside the block
+    const float sc = f.row_scale(d.row0 + lr);
     const int64_t vi = (int64_t)d.j * a.m_pad + d.rpad0 + lr;
     float2 gpv = a.g[d.row0 + lr];
     if (a.P > 1) {
@@ -143,24 +59,24 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4
       }
       a.gp[vi] = gpv;
     }
-    a.r[vi] = make_float2(gpv.x - ar, gpv.y - ai);
+    a.r[vi] = make_float2(fmaf(-sc, ar, gpv.x), fmaf(-sc, ai, gpv.y));
   }
 }
 
 // y_ij = G_ij^{-1} r_ij (row-parallel over the stored Hermitian inverse) and
 // ghat_ij = g'_ij - rho y_ij.
 __global__ __launch_bounds__(kBlockThreads) void k_gram(IterArgs a, const int4* __restrict__ tiles) {
+  const FmtC64 f{a.Ginv};
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = a.blocks[t.x];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int row = t.y + wave * kRowsPerWave;
   if (row >= d.mi) return;
   const int nvalid = min(kRowsPerWave, d.mi - row);
-  const float4* A = reinterpret_cast<const float4*>(a.Ginv + d.gi_off + (int64_t)row * d.ldr);
   const int64_t seg = (int64_t)d.j * a.m_pad + d.rpad0;
   const float4* x = reinterpret_cast<const float4*>(a.r + seg);
   float acc[kRowsPerWave][2];
-  rows_dot<kRowsPerWave, 4>(A, d.ldr / 2, nvalid, x, (d.mi + 1) / 2, acc);
+  rows_dot<FmtC64, kRowsPerWave, 4>(f, d.gi_off + (int64_t)row * d.ldr, d.ldr, nvalid, x, (d.mi + 1) / 2, acc);
   if (lane < nvalid) {
     float ar = 0.f, ai = 0.f;
 #pragma unroll
@@ -175,52 +91,27 @@ __global__ __launch_bounds__(kBlockThreads) void k_gram(IterArgs a, const int4* 
 }
 
 // Partial adjoint products: part[chunk][i][col] = sum over the chunk's rows
-// of conj(H_ij[row, col]) y_ij[row].  Two columns per lane, kColsPerWG4 lanes
-// per workgroup.  tiles[x] = {block, first float4 column, chunk, -}.
-template <int U>
+// of conj(H_ij[row, col]) y_ij[row] (cols_partial).
+// tiles[x] = {block, first lane load, chunk, -}.
+template <class F>
 __global__ __launch_bounds__(kBlockThreads) void k_gemv_h(IterArgs a, const int4* __restrict__ tiles) {
+  __shared__ float red[kBlockThreads / kWave - 1][2 * F::CPL][kWave];
+  const F f = MakeFmt<F>::make(a.hs);
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = a.blocks[t.x];
-  const int c4 = t.y + threadIdx.x;
-  const int n4 = (d.nj + 1) / 2;
-  if (c4 >= n4) return;
-  const int rc = (d.mi + a.KH - 1) / a.KH;
-  const int rb = min(d.mi, t.z * rc), re = min(d.mi, rb + rc);
-  const int64_t lda4 = d.ld / 2;
-  const float4* A = reinterpret_cast<const float4*>(a.H + d.h_off) + c4;
-  const float2* y = a.y + (int64_t)d.j * a.m_pad + d.rpad0;
-  float a0r = 0.f, a0i = 0.f, a1r = 0.f, a1i = 0.f;
-  int r = rb;
-  for (; r + U <= re; r += U) {
-    float4 hv[U];
-    float2 yv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      hv[u] = ldnt(A + (int64_t)(r + u) * lda4);
-      yv[u] = y[r + u];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      cmacc(a0r, a0i, hv[u].x, hv[u].y, yv[u].x, yv[u].y);
-      cmacc(a1r, a1i, hv[u].z, hv[u].w, yv[u].x, yv[u].y);
-    }
-  }
-  for (; r < re; ++r) {
-    float4 hv = ldnt(A + (int64_t)r * lda4);
-    float2 yv = y[r];
-    cmacc(a0r, a0i, hv.x, hv.y, yv.x, yv.y);
-    cmacc(a1r, a1i, hv.z, hv.w, yv.x, yv.y);
-  }
-  float4* out = reinterpret_cast<float4*>(a.part + ((int64_t)t.z * a.Q + d.i) * a.n_pad + d.cpad0);
-  out[c4] = make_float4(a0r, a0i, a1r, a1i);
+  cols_partial<F>(f, d, t, a.KH, a.y + (int64_t)d.j * a.m_pad + d.rpad0,
+                  a.part + ((int64_t)t.z * a.Q + d.i) * a.n_pad + d.cpad0, red);
 }
 
 // z-update, dual update and residual norms for kZCols columns of one column
-// block.  tiles[x] = {column block, first column, -, -}.  Each workgroup
+// block (one wavefront per workgroup, one column per lane).
+// tiles[x] = {column block, first column, -, -}.  Replicas stay in registers
+// when Q <= MAXQ (MAXQ = 0: any Q, partials are read twice).  Each workgroup
 // writes its five FP64 partial sums; the last workgroup to arrive (ticket)
-// adds them in workgroup order, so the result does not depend on timing.
-__global__ __launch_bounds__(kBlockThreads) void k_zupdate(IterArgs a, const int4* __restrict__ tiles) {
-  __shared__ double red[kBlockThreads / kWave][kRedCount];
+// adds them with a fixed assignment of partials to lanes and a fixed
+// shuffle tree, so the result does not depend on timing.
+template <int MAXQ>
+__global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __restrict__ tiles) {
   __shared__ int last;
   const int4 t = tiles[blockIdx.x];
   const ColDesc cd = a.cols[t.x];
@@ -229,18 +120,36 @@ __global__ __launch_bounds__(kBlockThreads) void k_zupdate(IterArgs a, const int
   double acc[kRedCount] = {0, 0, 0, 0, 0};
   if (valid) {
     const int64_t p = cd.cpad0 + col;
-    float ar = 0.f, ai = 0.f;
-    for (int i = 0; i < a.Q; ++i) {
-      float2 ci = a.c[(int64_t)i * a.n_pad + p];
-      float ur = ci.x, ui = ci.y;
+    const int Q = MAXQ > 0 ? MAXQ : a.Q;
+    float ur[MAXQ > 0 ? MAXQ : 1], ui[MAXQ > 0 ? MAXQ : 1];
+    auto replica = [&](int i, float& xr, float& xi) {
+      const float2 ci = a.c[(int64_t)i * a.n_pad + p];
+      float sr = ci.x, si = ci.y;
+      const float2* pp = a.part + (int64_t)i * a.n_pad + p;
+      const int64_t stride = (int64_t)a.Q * a.n_pad;
+#pragma unroll 8
       for (int k = 0; k < a.KH; ++k) {
-        float2 pk = a.part[((int64_t)k * a.Q + i) * a.n_pad + p];
-        ur += pk.x;
-        ui += pk.y;
+        const float2 pk = pp[k * stride];
+        sr += pk.x;
+        si += pk.y;
       }
-      float2 si = a.s[(int64_t)i * a.n_pad + p];
-      ar += ur + si.x;
-      ai += ui + si.y;
+      xr = sr;
+      xi = si;
+    };
+    constexpr int kUnrollQ = MAXQ > 0 ? MAXQ : 1;
+    float ar = 0.f, ai = 0.f;
+#pragma unroll kUnrollQ
+    for (int i = 0; i < Q; ++i) {
+      if (MAXQ > 0 && i >= a.Q) break;
+      float xr, xi;
+      replica(i, xr, xi);
+      if (MAXQ > 0) {
+        ur[i] = xr;
+        ui[i] = xi;
+      }
+      const float2 si = a.s[(int64_t)i * a.n_pad + p];
+      ar += xr + si.x;
+      ai += xi + si.y;
     }
     const float invQ = 1.0f / (float)a.Q;
     ar *= invQ;
@@ -256,63 +165,60 @@ __global__ __launch_bounds__(kBlockThreads) void k_zupdate(IterArgs a, const int
     }
     const float2 vold = a.v[p];
     a.v[p] = make_float2(vr, vi);
-    for (int i = 0; i < a.Q; ++i) {
+#pragma unroll kUnrollQ
+    for (int i = 0; i < Q; ++i) {
+      if (MAXQ > 0 && i >= a.Q) break;
       const int64_t ip = (int64_t)i * a.n_pad + p;
-      float2 ci = a.c[ip];
-      float ur = ci.x, ui = ci.y;
-      for (int k = 0; k < a.KH; ++k) {
-        float2 pk = a.part[((int64_t)k * a.Q + i) * a.n_pad + p];
-        ur += pk.x;
-        ui += pk.y;
+      float xr, xi;
+      if (MAXQ > 0) {
+        xr = ur[i];
+        xi = ui[i];
+      } else {
+        replica(i, xr, xi);
       }
-      float2 si = a.s[ip];
-      const float dr = ur - vr, di = ui - vi;
+      const float2 si = a.s[ip];
+      const float dr = xr - vr, di = xi - vi;
       const float sr = si.x + dr, sim = si.y + di;
       a.s[ip] = make_float2(sr, sim);
       a.c[ip] = make_float2(vr - sr, vi - sim);
       acc[kRedRp2] += (double)dr * dr + (double)di * di;
-      acc[kRedU2] += (double)ur * ur + (double)ui * ui;
+      acc[kRedU2] += (double)xr * xr + (double)xi * xi;
       acc[kRedS2] += (double)sr * sr + (double)sim * sim;
     }
     const double dvr = (double)vr - vold.x, dvi = (double)vi - vold.y;
     acc[kRedDv2] = dvr * dvr + dvi * dvi;
     acc[kRedV2] = (double)vr * vr + (double)vi * vi;
   }
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int lane = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < kRedCount; ++q) {
-    double w = wave_sum_d(acc[q]);
-    if (lane == 0) red[wave][q] = w;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 0; q < kRedCount; ++q) {
-      double s = 0.0;
-      for (int w = 0; w < kBlockThreads / kWave; ++w) s += red[w][q];
-      a.redpart[(int64_t)blockIdx.x * kRedCount + q] = s;
-    }
+  for (int q = 0; q < kRedCount; ++q) acc[q] = wave_sum_d(acc[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < kRedCount; ++q) a.redpart[(int64_t)blockIdx.x * kRedCount + q] = acc[q];
     __threadfence();
-    const int tk = atomicAdd(&a.ctl->ticket, 1);
-    last = (tk == (int)gridDim.x - 1);
+    last = (atomicAdd(&a.ctl->ticket, 1) == (int)gridDim.x - 1);
   }
   __syncthreads();
   if (!last) return;
   __threadfence();
-  if (threadIdx.x < kRedCount) {
-    const int q = threadIdx.x;
-    double s = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b)
-      s += __hip_atomic_load(a.redpart + (int64_t)b * kRedCount + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a.ctl->red[q] = s;
+  double tot[kRedCount] = {0, 0, 0, 0, 0};
+  for (unsigned b = lane; b < gridDim.x; b += kZCols) {
+#pragma unroll
+    for (int q = 0; q < kRedCount; ++q)
+      tot[q] += __hip_atomic_load(a.redpart + (int64_t)b * kRedCount + q, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  }
+#pragma unroll
+  for (int q = 0; q < kRedCount; ++q) tot[q] = wave_sum_d(tot[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < kRedCount; ++q) a.ctl->red[q] = tot[q];
     const int it = a.ctl->iter;
     if (a.hist) {
-      if (q == kRedRp2) a.hist[2 * (int64_t)it] = s;
-      if (q == kRedDv2) a.hist[2 * (int64_t)it + 1] = s * a.rho2Q;
+      a.hist[2 * (int64_t)it] = tot[kRedRp2];
+      a.hist[2 * (int64_t)it + 1] = tot[kRedDv2] * a.rho2Q;
     }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    a.ctl->iter += 1;
+    a.ctl->iter = it + 1;
     a.ctl->ticket = 0;
   }
 }
@@ -364,7 +270,11 @@ __global__ void k_fill_zero(uint4* p, size_t n16) {
 
 // ---- launchers ------------------------------------------------------------
 hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st) {
-  hipLaunchKernelGGL(k_gemv_n, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles);
+  switch (a.hs.storage) {
+    case 0: hipLaunchKernelGGL(k_gemv_n<FmtC64>, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles); break;
+    case 1: hipLaunchKernelGGL(k_gemv_n<FmtBF16>, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles); break;
+    default: hipLaunchKernelGGL(k_gemv_n<FmtFP8>, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles); break;
+  }
   return hipGetLastError();
 }
 hipError_t launch_gram(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st) {
@@ -372,11 +282,20 @@ hipError_t launch_gram(const IterArgs& a, const int4* tiles, int ntiles, hipStre
   return hipGetLastError();
 }
 hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st) {
-  hipLaunchKernelGGL(k_gemv_h<8>, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles);
+  switch (a.hs.storage) {
+    case 0: hipLaunchKernelGGL(k_gemv_h<FmtC64>, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles); break;
+    case 1: hipLaunchKernelGGL(k_gemv_h<FmtBF16>, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles); break;
+    default: hipLaunchKernelGGL(k_gemv_h<FmtFP8>, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles); break;
+  }
   return hipGetLastError();
 }
 hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st) {
-  hipLaunchKernelGGL(k_zupdate, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles);
+  if (a.Q <= 4)
+    hipLaunchKernelGGL(k_zupdate<4>, dim3(ntiles), dim3(kZCols), 0, st, a, tiles);
+  else if (a.Q <= 8)
+    hipLaunchKernelGGL(k_zupdate<8>, dim3(ntiles), dim3(kZCols), 0, st, a, tiles);
+  else
+    hipLaunchKernelGGL(k_zupdate<0>, dim3(ntiles), dim3(kZCols), 0, st, a, tiles);
   return hipGetLastError();
 }
 hipError_t launch_unpad_cols(const ColDesc* cols, int P, int64_t n, const float2* src, float2* dst,

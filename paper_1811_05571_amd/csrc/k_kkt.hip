@@ -6,6 +6,7 @@
 // This check computes z = H^H (g - H v) accumulated in double and the largest
 // distance of z_n to lambda * d|v_n|: |z_n - lambda v_n/|v_n|| on the support,
 // max(0, |z_n| - lambda) off it.
+#include "hstore.h"
 #include "plan.h"
 
 namespace admm {
@@ -25,12 +26,14 @@ __device__ __forceinline__ double wmax(double x) {
 
 // e[row] = g[row] - sum_j H_ij[row,:] v_j for every global row; one wave per
 // row, looping over the P blocks of the row.  grid = ceil(m / 4) workgroups.
+template <class F>
 __global__ __launch_bounds__(kBlockThreads) void k_kkt_resid(const BlockDesc* __restrict__ blocks, int Q, int P,
                                                              const int64_t* __restrict__ row_block,
-                                                             int64_t m, const float2* __restrict__ H,
+                                                             int64_t m, HStore hs,
                                                              const float2* __restrict__ g,
                                                              const float2* __restrict__ vpad,
                                                              double2* __restrict__ e) {
+  const F f = MakeFmt<F>::make(hs);
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int64_t row = (int64_t)blockIdx.x * (kBlockThreads / kWave) + wave;
   if (row >= m) return;
@@ -38,12 +41,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_kkt_resid(const BlockDesc* __
   double ar = 0.0, ai = 0.0;
   for (int j = 0; j < P; ++j) {
     const BlockDesc d = blocks[i * P + j];
-    const float2* Hr = H + d.h_off + (row - d.row0) * d.ld;
+    const int64_t ro = d.h_off + (row - d.row0) * d.ld;
     const float2* vj = vpad + d.cpad0;
     for (int c = lane; c < d.nj; c += kWave) {
-      const float2 h = Hr[c], v = vj[c];
-      ar += (double)h.x * v.x - (double)h.y * v.y;
-      ai += (double)h.x * v.y + (double)h.y * v.x;
+      const double2 h = f.getd(ro + c, (int)row);
+      const float2 v = vj[c];
+      ar += h.x * v.x - h.y * v.y;
+      ai += h.x * v.y + h.y * v.x;
     }
   }
   ar = wsum(ar);
@@ -52,33 +56,29 @@ __global__ __launch_bounds__(kBlockThreads) void k_kkt_resid(const BlockDesc* __
 }
 
 // part[(chunk*Q + i)*n_pad + col] = sum over the chunk's rows of block (i,j)
-// of conj(H[row,col]) e[row], in double.  tiles = the adjoint-product tiles
-// {block, first float4 column, chunk}: two columns per thread.
+// of conj(H[row,col]) e[row], in double; one column per thread.
+// tiles[x] = {block, first column, chunk, -}.
+template <class F>
 __global__ __launch_bounds__(kBlockThreads) void k_kkt_adj(const int4* __restrict__ tiles,
                                                            const BlockDesc* __restrict__ blocks, int Q, int KH,
-                                                           int64_t n_pad, const float2* __restrict__ H,
+                                                           int64_t n_pad, HStore hs,
                                                            const double2* __restrict__ e,
                                                            double2* __restrict__ part) {
+  const F f = MakeFmt<F>::make(hs);
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = blocks[t.x];
-  const int c4 = t.y + threadIdx.x;
-  if (c4 >= (d.nj + 1) / 2) return;
+  const int col = t.y + threadIdx.x;
+  if (col >= d.nj) return;
   const int rc = (d.mi + KH - 1) / KH;
   const int rb = min(d.mi, t.z * rc), re = min(d.mi, rb + rc);
-  const float4* A = reinterpret_cast<const float4*>(H + d.h_off) + c4;
-  const int64_t lda4 = d.ld / 2;
-  double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
+  double ar = 0, ai = 0;
   for (int r = rb; r < re; ++r) {
-    const float4 h = A[(int64_t)r * lda4];
+    const double2 h = f.getd(d.h_off + (int64_t)r * d.ld + col, d.row0 + r);
     const double2 y = e[d.row0 + r];
-    a0r += (double)h.x * y.x + (double)h.y * y.y;
-    a0i += (double)h.x * y.y - (double)h.y * y.x;
-    a1r += (double)h.z * y.x + (double)h.w * y.y;
-    a1i += (double)h.z * y.y - (double)h.w * y.x;
+    ar += h.x * y.x + h.y * y.y;
+    ai += h.x * y.y - h.y * y.x;
   }
-  double2* out = part + ((int64_t)t.z * Q + d.i) * n_pad + d.cpad0 + 2 * (int64_t)c4;
-  out[0] = make_double2(a0r, a0i);
-  out[1] = make_double2(a1r, a1i);
+  part[((int64_t)t.z * Q + d.i) * n_pad + d.cpad0 + col] = make_double2(ar, ai);
 }
 
 // z = sum of the partials over chunks and row blocks; violation per column;
@@ -94,6 +94,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_kkt_final(const int4* __restr
   const int4 t = tiles[blockIdx.x];
   const ColDesc cd = cols[t.x];
   const int col = t.y + threadIdx.x;
+  const int nw = blockDim.x / kWave;
   double viol = 0.0;
   if (col < cd.nj) {
     const int64_t p = cd.cpad0 + col;
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_kkt_final(const int4* __restr
   __syncthreads();
   if (threadIdx.x == 0) {
     double mx = 0.0;
-    for (int q = 0; q < kBlockThreads / kWave; ++q) mx = fmax(mx, red[q]);
+    for (int q = 0; q < nw; ++q) mx = fmax(mx, red[q]);
     wgmax[blockIdx.x] = mx;
     __threadfence();
     last = (atomicAdd(&ctl->kkt_ticket, 1) == (int)gridDim.x - 1);
@@ -140,18 +141,29 @@ __global__ __launch_bounds__(kBlockThreads) void k_kkt_final(const int4* __restr
 }  // namespace
 
 hipError_t launch_kkt_all(const BlockDesc* dblocks, const ColDesc* dcols, const int64_t* drow_block,
-                          const int4* t_cols, int n_tcols, const int4* t_z, int n_tz, int64_t m, int64_t n_pad,
-                          int Q, int P, int KH, const float2* H, const float2* g, const float2* vpad,
+                          const int4* t_kadj, int n_tkadj, const int4* t_z, int n_tz, int64_t m, int64_t n_pad,
+                          int Q, int P, int KH, const HStore& hs, const float2* g, const float2* vpad,
                           double lam, double2* e, double2* part, double* wgmax, Control* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_kkt_resid, dim3((unsigned)((m + 3) / 4)), dim3(kBlockThreads), 0, st, dblocks, Q, P,
-                     drow_block, m, H, g, vpad, e);
+  const dim3 gr((unsigned)((m + 3) / 4)), ga(n_tkadj), blk(kBlockThreads);
+  switch (hs.storage) {
+    case 0:
+      hipLaunchKernelGGL(k_kkt_resid<FmtC64>, gr, blk, 0, st, dblocks, Q, P, drow_block, m, hs, g, vpad, e);
+      hipLaunchKernelGGL(k_kkt_adj<FmtC64>, ga, blk, 0, st, t_kadj, dblocks, Q, KH, n_pad, hs, e, part);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_kkt_resid<FmtBF16>, gr, blk, 0, st, dblocks, Q, P, drow_block, m, hs, g, vpad, e);
+      hipLaunchKernelGGL(k_kkt_adj<FmtBF16>, ga, blk, 0, st, t_kadj, dblocks, Q, KH, n_pad, hs, e, part);
+      break;
+    default:
+      hipLaunchKernelGGL(k_kkt_resid<FmtFP8>, gr, blk, 0, st, dblocks, Q, P, drow_block, m, hs, g, vpad, e);
+      hipLaunchKernelGGL(k_kkt_adj<FmtFP8>, ga, blk, 0, st, t_kadj, dblocks, Q, KH, n_pad, hs, e, part);
+      break;
+  }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_kkt_adj, dim3(n_tcols), dim3(kBlockThreads), 0, st, t_cols, dblocks, Q, KH, n_pad, H, e,
-                     part);
-  if ((err = hipGetLastError()) != hipSuccess) return err;
-  hipLaunchKernelGGL(k_kkt_final, dim3(n_tz), dim3(kBlockThreads), 0, st, t_z, dcols, Q, KH, n_pad, part, vpad,
-                     lam, wgmax, ctl);
+  // one z-update tile (kZCols columns) per workgroup
+  hipLaunchKernelGGL(k_kkt_final, dim3(n_tz), dim3(kZCols), 0, st, t_z, dcols, Q, KH, n_pad, part, vpad, lam, wgmax,
+                     ctl);
   return hipGetLastError();
 }
 

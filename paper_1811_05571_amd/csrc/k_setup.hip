@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "hstore.h"
 #include "plan.h"
 
 namespace admm {
@@ -103,29 +104,30 @@ __global__ __launch_bounds__(kBlockThreads) void k_pack_c64(const float2* __rest
   if (bad) ctl->nonfinite = 1;
 }
 
-// Lower tiles of G = rho I + H H^H (FP64 accumulation of the stored values).
-// tiles[x] = {block, tile row, tile col, -} with tile row >= tile col.
+// Lower tiles of G = rho I + H H^H in FP64 from the stored (dequantised)
+// values.  tiles[x] = {block, tile row, tile col, -} with tile row >= tile col.
+template <class F>
 __global__ __launch_bounds__(kBlockThreads) void k_gram_build(const int4* __restrict__ tiles,
-                                                              const BlockDesc* __restrict__ blocks,
-                                                              const float2* __restrict__ H, double rho,
-                                                              double2* __restrict__ A) {
+                                                              const BlockDesc* __restrict__ blocks, HStore hs,
+                                                              double rho, double2* __restrict__ A) {
   __shared__ Smem sm;
+  const F f = MakeFmt<F>::make(hs);
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = blocks[t.x];
   const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
   const int r0 = t.y * T, c0 = t.z * T;
-  const float2* Hb = H + d.h_off;
   double2 acc[4][4];
   zero_acc(acc);
   for (int k0 = 0; k0 < d.nj; k0 += KC) {
     __syncthreads();
     for (int e = tid; e < T * KC; e += kBlockThreads) {
       int r = e / KC, kk = e % KC;
-      float2 a = (r0 + r < d.mi) ? Hb[(int64_t)(r0 + r) * d.ld + k0 + kk] : make_float2(0.f, 0.f);
-      sm.A[r][kk] = make_double2(a.x, a.y);
+      sm.A[r][kk] = (r0 + r < d.mi) ? f.getd(d.h_off + (int64_t)(r0 + r) * d.ld + k0 + kk, d.row0 + r0 + r)
+                                    : make_double2(0.0, 0.0);
       int kb = e / T, c = e % T;
-      float2 b = (c0 + c < d.mi) ? Hb[(int64_t)(c0 + c) * d.ld + k0 + kb] : make_float2(0.f, 0.f);
-      sm.B[kb][c] = make_double2(b.x, -(double)b.y);
+      const double2 b = (c0 + c < d.mi) ? f.getd(d.h_off + (int64_t)(c0 + c) * d.ld + k0 + kb, d.row0 + c0 + c)
+                                        : make_double2(0.0, 0.0);
+      sm.B[kb][c] = make_double2(b.x, -b.y);
     }
     __syncthreads();
     mma_chunk(sm, acc, tr, tc);
@@ -141,6 +143,111 @@ __global__ __launch_bounds__(kBlockThreads) void k_gram_build(const int4* __rest
       else if (r == c) val.x += rho;
       Ab[(int64_t)r * d.mt + c] = val;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Quantisers.  bfloat16: round to nearest even of the fp32 value.  fp8: OCP
+// e4m3 (bias 7, max 448), round to nearest even, saturating, of x / s where
+// s = (row max of |Re|, |Im|) / 448 in fp32 (1 for an all-zero row).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ uint8_t f32_to_e4m3_rne(float x) {
+  const unsigned sign = (__float_as_uint(x) >> 24) & 0x80u;
+  const float a = fabsf(x);
+  if (!(a < 448.0f)) return (uint8_t)(sign | 0x7eu);
+  if (a < 0.015625f) {                       // below 2^-6: multiples of 2^-9
+    const float q = rintf(a * 512.0f);       // 0..8, 8 is the code of 2^-6
+    return (uint8_t)(sign | (unsigned)q);
+  }
+  int e;
+  const float fr = frexpf(a, &e);            // a = fr 2^e, fr in [0.5, 1)
+  float mq = rintf((fr * 2.0f - 1.0f) * 8.0f);
+  int E = e - 1;
+  if (mq == 8.0f) {
+    mq = 0.0f;
+    E += 1;
+  }
+  unsigned code = ((unsigned)(E + 7) << 3) | (unsigned)mq;
+  if (code > 0x7eu) code = 0x7eu;
+  return (uint8_t)(sign | code);
+}
+
+// Row scales of the fp8 store: one workgroup per global row of the caller's H.
+__global__ __launch_bounds__(kBlockThreads) void k_row_scale(const float2* __restrict__ Hin, int64_t n,
+                                                             float* __restrict__ scale) {
+  __shared__ float red[kBlockThreads / kWave];
+  const int64_t row = blockIdx.x;
+  float mx = 0.f;
+  for (int64_t c = threadIdx.x; c < n; c += kBlockThreads) {
+    const float2 h = Hin[row * n + c];
+    mx = fmaxf(mx, fmaxf(fabsf(h.x), fabsf(h.y)));
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = 0.f;
+    for (int w = 0; w < kBlockThreads / kWave; ++w) m = fmaxf(m, red[w]);
+    scale[row] = (m > 0.f) ? m / 448.0f : 1.0f;
+  }
+}
+
+// Block store of the quantised planes with zero pads.  grid = (rows, blocks).
+template <int STORAGE>
+__global__ __launch_bounds__(kBlockThreads) void k_pack_q(const float2* __restrict__ Hin, int64_t n,
+                                                          const BlockDesc* __restrict__ blocks, void* re_out,
+                                                          void* im_out, const float* __restrict__ scale,
+                                                          Control* ctl) {
+  const BlockDesc d = blocks[blockIdx.y];
+  const int r = blockIdx.x;
+  if (r >= d.mi) return;
+  const float2* src = Hin + (int64_t)(d.row0 + r) * n + d.col0;
+  const int64_t o = d.h_off + (int64_t)r * d.ld;
+  const float s = STORAGE == 2 ? scale[d.row0 + r] : 1.0f;
+  bool bad = false;
+  for (int c = threadIdx.x; c < d.ld; c += kBlockThreads) {
+    float2 h = make_float2(0.f, 0.f);
+    if (c < d.nj) {
+      h = src[c];
+      bad |= !(isfinite(h.x) && isfinite(h.y));
+    }
+    if (STORAGE == 1) {
+      static_cast<uint16_t*>(re_out)[o + c] = f32_to_bf16_rne(h.x);
+      static_cast<uint16_t*>(im_out)[o + c] = f32_to_bf16_rne(h.y);
+    } else {
+      static_cast<uint8_t*>(re_out)[o + c] = f32_to_e4m3_rne(h.x / s);
+      static_cast<uint8_t*>(im_out)[o + c] = f32_to_e4m3_rne(h.y / s);
+    }
+  }
+  if (bad) ctl->nonfinite = 1;
+}
+
+// Copy the block store back to dense m x n planes (complex64, or the raw
+// bf16 / fp8 codes).  grid = (rows, blocks).
+template <int STORAGE>
+__global__ __launch_bounds__(kBlockThreads) void k_export_h(HStore hs, int64_t n,
+                                                            const BlockDesc* __restrict__ blocks, void* re_out,
+                                                            void* im_out) {
+  const BlockDesc d = blocks[blockIdx.y];
+  const int r = blockIdx.x;
+  if (r >= d.mi) return;
+  const int64_t o = d.h_off + (int64_t)r * d.ld, dst = (int64_t)(d.row0 + r) * n + d.col0;
+  for (int c = threadIdx.x; c < d.nj; c += kBlockThreads) {
+    if (STORAGE == 0) {
+      static_cast<float2*>(re_out)[dst + c] = static_cast<const float2*>(hs.base)[o + c];
+    } else if (STORAGE == 1) {
+      static_cast<uint16_t*>(re_out)[dst + c] = static_cast<const uint16_t*>(hs.base)[o + c];
+      static_cast<uint16_t*>(im_out)[dst + c] = static_cast<const uint16_t*>(hs.base_im)[o + c];
+    } else {
+      static_cast<uint8_t*>(re_out)[dst + c] = static_cast<const uint8_t*>(hs.base)[o + c];
+      static_cast<uint8_t*>(im_out)[dst + c] = static_cast<const uint8_t*>(hs.base_im)[o + c];
+    }
+  }
 }
 
 // Cholesky of diagonal tile k (lower, in place).  One workgroup per block.
@@ -384,9 +491,42 @@ hipError_t launch_pack_c64(const float2* Hin, int64_t n, const BlockDesc* blocks
 }
 
 hipError_t launch_gram_build(const Geometry& geo, const BlockDesc* dblocks, const int4* t_gram,
-                             const float2* H, double rho, double2* A, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_build, dim3((unsigned)geo.t_gram.size()), dim3(kBlockThreads), 0, st, t_gram,
-                     dblocks, H, rho, A);
+                             const HStore& hs, double rho, double2* A, hipStream_t st) {
+  const dim3 grid((unsigned)geo.t_gram.size());
+  switch (hs.storage) {
+    case 0: hipLaunchKernelGGL(k_gram_build<FmtC64>, grid, dim3(kBlockThreads), 0, st, t_gram, dblocks, hs, rho, A); break;
+    case 1: hipLaunchKernelGGL(k_gram_build<FmtBF16>, grid, dim3(kBlockThreads), 0, st, t_gram, dblocks, hs, rho, A); break;
+    default: hipLaunchKernelGGL(k_gram_build<FmtFP8>, grid, dim3(kBlockThreads), 0, st, t_gram, dblocks, hs, rho, A); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_quant(const float2* Hin, int64_t m, int64_t n, const BlockDesc* blocks, int nblocks,
+                             int max_rows, const HStore& hs, Control* ctl, hipStream_t st) {
+  void* re = const_cast<void*>(hs.base);
+  void* im = const_cast<void*>(hs.base_im);
+  float* sc = const_cast<float*>(hs.row_scale);
+  if (hs.storage == 2) {
+    hipLaunchKernelGGL(k_row_scale, dim3((unsigned)m), dim3(kBlockThreads), 0, st, Hin, n, sc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pack_q<2>, dim3(max_rows, nblocks), dim3(kBlockThreads), 0, st, Hin, n, blocks, re, im,
+                       sc, ctl);
+  } else {
+    hipLaunchKernelGGL(k_pack_q<1>, dim3(max_rows, nblocks), dim3(kBlockThreads), 0, st, Hin, n, blocks, re, im,
+                       sc, ctl);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_export_h(const HStore& hs, int64_t n, const BlockDesc* blocks, int nblocks, int max_rows,
+                           void* re_out, void* im_out, hipStream_t st) {
+  const dim3 grid(max_rows, nblocks);
+  switch (hs.storage) {
+    case 0: hipLaunchKernelGGL(k_export_h<0>, grid, dim3(kBlockThreads), 0, st, hs, n, blocks, re_out, im_out); break;
+    case 1: hipLaunchKernelGGL(k_export_h<1>, grid, dim3(kBlockThreads), 0, st, hs, n, blocks, re_out, im_out); break;
+    default: hipLaunchKernelGGL(k_export_h<2>, grid, dim3(kBlockThreads), 0, st, hs, n, blocks, re_out, im_out); break;
+  }
   return hipGetLastError();
 }
 

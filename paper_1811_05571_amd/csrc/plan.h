@@ -17,7 +17,7 @@ struct ColDesc {       // one column block j
 struct Layout {
   size_t H = 0, H_im = 0, H_scale = 0, Ginv = 0, F64a = 0, F64b = 0;
   size_t c = 0, s = 0, v = 0, part = 0, gp = 0, ghat = 0, r = 0, y = 0;
-  size_t blocks = 0, cols = 0, t_rows = 0, t_cols = 0, t_z = 0, t_gram = 0;
+  size_t blocks = 0, cols = 0, t_rows = 0, t_cols = 0, t_z = 0, t_gram = 0, t_kadj = 0;
   size_t ctl = 0, redpart = 0, row_block = 0, kkt_e = 0, kkt_v = 0, kkt_part = 0, kkt_max = 0;
   size_t total = 0;
   size_t h_bytes = 0, ginv_bytes = 0;
@@ -32,16 +32,21 @@ struct Geometry {
   int64_t m_pad = 0, n_pad = 0;    // padded row / column space lengths
   int KH = 1;                      // row chunks of the adjoint product
   int max_mt = 0;                  // largest tile-padded block edge
-  std::vector<int4> t_rows, t_cols, t_z, t_gram;
+  std::vector<int4> t_rows, t_cols, t_z, t_gram, t_kadj;
   Layout lay;
 };
 
 // Rows handled by one workgroup of the row-parallel products.
 constexpr int kRowsPerWave = 4;
 constexpr int kRowsPerWG = kRowsPerWave * (kBlockThreads / kWave);
-// Float4 (two complex) columns handled by one workgroup of the adjoint product.
-constexpr int kColsPerWG4 = kBlockThreads;
-constexpr int kZCols = kBlockThreads;
+// Lane loads (CPL complex columns each) handled by one workgroup of the
+// adjoint product: its four waves share the columns and split the rows.
+constexpr int kColsPerWGLoads = kWave;
+// Complex columns per lane load for a storage format.
+inline int cols_per_load(int storage) { return storage == 0 ? 2 : (storage == 1 ? 8 : 16); }
+// Bytes per stored complex element.
+inline int elem_bytes(int storage) { return storage == 0 ? 8 : (storage == 1 ? 4 : 2); }
+constexpr int kZCols = kWave;   // columns (lanes) per z-update workgroup
 
 int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* row_off, int P,
                    const int64_t* col_off, int storage, std::string& err);
@@ -50,7 +55,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
 struct IterArgs {
   const BlockDesc* blocks;
   const ColDesc* cols;
-  const float2* H;
+  HStore hs;
   const float2* Ginv;
   const float2* g;      // caller's measurements
   float2 *c, *s, *v, *part, *gp, *ghat, *r, *y;
@@ -78,14 +83,18 @@ hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_pack_c64(const float2* Hin, int64_t n, const BlockDesc* blocks, int nblocks,
                            int max_rows, float2* Hout, Control* ctl, hipStream_t st);
 hipError_t launch_gram_build(const Geometry& geo, const BlockDesc* dblocks, const int4* t_gram,
-                             const float2* H, double rho, double2* A, hipStream_t st);
+                             const HStore& hs, double rho, double2* A, hipStream_t st);
+hipError_t launch_pack_quant(const float2* Hin, int64_t m, int64_t n, const BlockDesc* blocks, int nblocks,
+                             int max_rows, const HStore& hs, Control* ctl, hipStream_t st);
+hipError_t launch_export_h(const HStore& hs, int64_t n, const BlockDesc* blocks, int nblocks, int max_rows,
+                           void* re_out, void* im_out, hipStream_t st);
 hipError_t launch_cholesky_inverse(const Geometry& geo, const BlockDesc* dblocks, const int4* t_gram,
                                    double2* A, double2* W, float2* Ginv, Control* ctl, hipStream_t st);
 
 // KKT check (FP64)
 hipError_t launch_kkt_all(const BlockDesc* dblocks, const ColDesc* dcols, const int64_t* drow_block,
-                          const int4* t_cols, int n_tcols, const int4* t_z, int n_tz, int64_t m, int64_t n_pad,
-                          int Q, int P, int KH, const float2* H, const float2* g, const float2* vpad,
+                          const int4* t_kadj, int n_tkadj, const int4* t_z, int n_tz, int64_t m, int64_t n_pad,
+                          int Q, int P, int KH, const HStore& hs, const float2* g, const float2* vpad,
                           double lam, double2* e, double2* part, double* wgmax, Control* ctl, hipStream_t st);
 hipError_t launch_make_c(const ColDesc* cols, int P, int Q, int64_t n_pad, const float2* v, const float2* s,
                          float2* c, hipStream_t st);
