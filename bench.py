@@ -100,6 +100,89 @@ def cpu_baseline(prob, n_iter: int):
     }
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16
+
+
+def bench_batch(args, torch, A, W, dev):
+    """Batched multi-scene form: S scenes (seeds 1000..) sharing the 6144 x
+    32000 instrument, frequency subsets of 12..24 tiles, Q in {2,4,8}, P=8,
+    300 iterations each, solved together with hipGraph replay; compared with
+    the plain complex64 solver run one scene at a time on a subset."""
+    t = time.perf_counter()
+    b = W.batch_scenes(S=args.batch_scenes)
+    gen_s = time.perf_counter() - t
+    H0 = torch.from_numpy(b.H0).to(dev)
+    g = torch.from_numpy(np.concatenate(b.g)).to(dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bb = A.Batch(H0, b.tile_rows, b.tiles, b.cuts, b.phases, b.P, b.rho, b.lam)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    info = bb.info()
+    print(f"[bench] batch: {b.S} scenes generated in {gen_s:.1f}s, setup {setup_s:.2f}s, "
+          f"{info['scene_tiles']} scene-tiles", file=sys.stderr, flush=True)
+    K = b.iters
+    bb.solve(g, 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v = bb.solve(g, K, graph=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # per-kernel event timing on a short run without the graph
+    bb.profile(True)
+    bb.solve(g, 10, graph=False)
+    prof = {bb.KERNELS[k]: bb.profile_read(k) for k in bb.KERNELS}
+    bb.profile(False)
+    n, NST = b.H0.shape[1], info["scene_tiles"]
+    cmacs = NST * b.tile_rows * n                      # complex MACs of one GEMM pass
+    mfma_flop = 2 * 12 * cmacs                         # 3-term split: 12 real MFMA MACs per complex MAC
+    kern = {}
+    for name, (ms, cnt) in prof.items():
+        kern[name] = {"avg_us": round(ms / max(cnt, 1) * 1e3, 2), "launches": cnt}
+    for name in ("k_bgemm_n", "k_bgemm_h"):
+        sec = kern[name]["avg_us"] * 1e-6
+        kern[name]["mfma_tflops"] = round(mfma_flop / sec / 1e12, 1)
+        kern[name]["mfma_frac"] = round(mfma_flop / sec / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)
+        kern[name]["h0_gbs"] = round(b.H0.size * 4 / sec / 1e9, 1)
+    gsec = kern["k_gram"]["avg_us"] * 1e-6
+    kern["k_gram"]["gbs"] = round(info["ginv_bytes"] / gsec / 1e9, 1)
+    vn = v.cpu().numpy()
+    nmse_b = [float(np.linalg.norm(vn[s] - b.u_true[s]) ** 2 / np.linalg.norm(b.u_true[s]) ** 2) for s in range(b.S)]
+    # plain complex64 solver, one scene at a time, on the first scenes
+    seq = []
+    for s in range(min(args.batch_seq, b.S)):
+        rows = torch.from_numpy(b.rows(s)).to(dev)
+        ph = torch.from_numpy(b.phases[s]).to(dev)
+        Hs = (H0.index_select(0, rows) * ph[:, None]).contiguous()
+        gs = torch.from_numpy(b.g[s]).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = A.Plan(Hs, len(b.cuts[s]) - 1, b.P, b.rho, b.lam[s], b.row_off(s))
+        vs = plan.solve(gs, K)
+        torch.cuda.synchronize()
+        seq.append((time.perf_counter() - t0, float(np.linalg.norm(vs.cpu().numpy() - b.u_true[s]) ** 2 /
+                                                   np.linalg.norm(b.u_true[s]) ** 2)))
+        plan.close()
+        del Hs, plan
+    seq_t = float(np.mean([x[0] for x in seq]))
+    res = {
+        "workload": b.name, "scenes": b.S, "iters": K, "value": round(b.S / el, 2), "unit": "scenes/s",
+        "ms_per_batched_iteration": round(el / K * 1e3, 3), "setup_s": round(setup_s, 2),
+        "scene_tiles": NST, "tile_widths": [info["tile_n"], info["tile_h"]], "autotune": bb.tuning(),
+        "kernels": kern, "ginv_gb": round(info["ginv_bytes"] / 1e9, 2),
+        "nmse_mean": float(np.mean(nmse_b)),
+        "plain_one_at_a_time": {
+            "scenes": len(seq), "value": round(1.0 / seq_t, 2), "unit": "scenes/s (setup + 300 iterations each)",
+            "nmse_mean": float(np.mean([x[1] for x in seq])),
+            "batched_nmse_mean_same_scenes": float(np.mean(nmse_b[:len(seq)])),
+        },
+    }
+    bb.close()
+    del H0, g
+    torch.cuda.empty_cache()
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +190,10 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 / fp8 storage forms")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched multi-scene form")
+    ap.add_argument("--batch-scenes", type=int, default=64)
+    ap.add_argument("--batch-seq", type=int, default=8, help="scenes solved one at a time for comparison")
     ap.add_argument("--cpu-iters", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args(argv)
@@ -207,7 +294,36 @@ def main(argv=None):
             r["plan"].close()
             del r
         out["forms"] = forms
+    if not args.no_adjoint:
+        # reverse mode of K = 100 unrolled iterations, checkpoint every 10
+        K, C = 100, 10
+        plan.set_lambda(prob.lam)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vK = plan.solve(g, K)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        vR, tape = plan.solve_record(g, K, C)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ut = torch.from_numpy(prob.u_true.astype(np.complex64)).to(dev)
+        gv = 2 * (vR - ut)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        gg, dl, dr = plan.backward(g, gv, tape)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        out["adjoint"] = {
+            "iters": K, "checkpoint_interval": C, "forward_ms": round((t1 - t0) * 1e3, 2),
+            "record_ms": round((t2 - t1) * 1e3, 2), "backward_ms": round((t4 - t3) * 1e3, 2),
+            "backward_over_forward": round((t4 - t3) / (t1 - t0), 3), "tape_mb": round(tape.numel() / 1e6, 1),
+            "dL_dlambda": dl, "dL_drho": dr, "grad_g_norm": float(torch.linalg.vector_norm(gg).item()),
+        }
+        print(f"[bench] adjoint: forward {out['adjoint']['forward_ms']} ms, backward "
+              f"{out['adjoint']['backward_ms']} ms", file=sys.stderr, flush=True)
     del H
+    if not args.no_batch:
+        out["batch"] = bench_batch(args, torch, A, W, dev)
 
     if not args.no_cpu:
         print(f"[bench] oracle CPU baseline: setup + {args.cpu_iters} iterations", file=sys.stderr, flush=True)

@@ -138,6 +138,41 @@ int admm_solve(admm_plan* plan, const void* g, int iters, double tol,
                double* resid_hist, int warm, void* stream);
 
 /*
+ * Reverse mode of K unrolled iterations (the differentiable map
+ * (g, lambda, rho) -> v^K from the zero state).
+ *
+ * admm_tape_bytes   -- size of the tape for `iters` iterations with a
+ *                      checkpoint of (v, s, ghat) every `interval` iterations.
+ * admm_solve_record -- admm_solve from the zero state for exactly `iters`
+ *                      iterations, writing the checkpoints to `tape` (device,
+ *                      >= admm_tape_bytes, 256-byte aligned, caller-owned) and
+ *                      v^K to v_out (device complex64[n]).
+ * admm_backward     -- given grad_v = dL/dv^K (device complex64[n]), writes
+ *                      grad_g = dL/dg (device complex64[m]) and the host
+ *                      doubles dL/dlambda, dL/drho.  Complex gradients use the
+ *                      convention dL/dRe z + j dL/dIm z.  `g` must be the
+ *                      measurements the tape was recorded with.  Each
+ *                      checkpoint interval is recomputed forward (storing the
+ *                      Gram-apply output y and the pre-threshold mean a of
+ *                      each iteration in the tape) and then swept in reverse:
+ *                      soft-threshold Jacobian, H u, G^{-1} (its rho
+ *                      derivative -G^{-2}), H^H r, estimated-data and
+ *                      local-data adjoints.  FP32 vectors, FP64 scalar sums.
+ *                      Overwrites the plan's iteration state.
+ * Errors: EINVAL; EWORKSPACE (tape too small); ESTATE (tape not recorded by
+ * this plan, or lambda changed since); ENONFINITE; EHIP.  All synchronise
+ * `stream`.
+ */
+int admm_tape_bytes(const admm_plan* plan, int iters, int interval,
+                    size_t* out_bytes);
+int admm_solve_record(admm_plan* plan, const void* g, int iters, int interval,
+                      void* tape, size_t tape_bytes, void* v_out,
+                      void* stream);
+int admm_backward(admm_plan* plan, const void* g, const void* grad_v,
+                  const void* tape, void* grad_g, double* grad_lambda,
+                  double* grad_rho, void* stream);
+
+/*
  * admm_get_state / admm_set_state -- the iteration state (k, v, s, ghat),
  * which fixes every later iterate (c = v - s and g'_ij follows from ghat).
  *   v     device complex64[n];  s device complex64[Q*n] (replica i at i*n);
@@ -198,6 +233,64 @@ int admm_plan_info(const admm_plan* plan, int64_t* info16);
 
 /* Release the plan (host memory only; the workspace stays the caller's). */
 void admm_destroy(admm_plan* plan);
+
+/* ======================================================================
+ * Batched multi-scene form.
+ *
+ * S scenes measured by one instrument matrix H0 (m0 x n).  The rows of H0
+ * come in tiles of `tile_rows` consecutive rows (one frequency each; a
+ * multiple of 32 dividing m0).  Scene s measures the tiles
+ * tiles[tiles_off[s] .. tiles_off[s+1]) (strictly increasing tile indices),
+ * each of its rows multiplied by a unit phase, so its sensing matrix is
+ *     H_s = diag(phase_s) H0[rows of its tiles, :]
+ * (a subsampling of frequencies with a per-row code).  Its Q_s row blocks
+ * are cut at tile boundaries: cuts[cuts_off[s] .. cuts_off[s+1]) = Q_s + 1
+ * increasing tile counts from 0 to its number of tiles.  All scenes share
+ * the column split (P, col_off, NULL = equal) and rho; each has its own
+ * lambda.  Every scene runs the same consensus-and-sectioning iteration as
+ * admm_solve (Sec. III-C).  The products of all scenes with the shared H0
+ * are dense GEMMs per (tile, column block) run on MFMA: H0 is stored in
+ * bfloat16 (round to nearest even) and the FP32 vector operands are split
+ * into three bfloat16 terms, with FP32 accumulation.  Each scene block's Gram
+ * inverse is built in FP64 from the shared Gram of H0's tiles.
+ *   H0       device complex64 m0 x n, row-major (read during setup only).
+ *   phases   device complex64, the scenes' rows packed scene after scene.
+ *   lambdas  host double[S].
+ *   g        device complex64, packed like phases.
+ *   v_out    device complex64 S x n (scene s at s*n).
+ *   use_graph  1: replay one captured hipGraph of the iteration per step.
+ * Errors: EINVAL, EUNSUPPORTED (a block not wide), EWORKSPACE, ENONFINITE,
+ * ENOTPD, EHIP.  setup and solve synchronise `stream`.
+ * ====================================================================== */
+typedef struct admm_batch admm_batch;
+
+int admm_batch_workspace_bytes(int64_t m0, int64_t n, int tile_rows, int S,
+                               const int32_t* tiles, const int64_t* tiles_off,
+                               const int32_t* cuts, const int64_t* cuts_off,
+                               int P, const int64_t* col_off,
+                               size_t* out_bytes);
+int admm_batch_setup(admm_batch** out, const void* H0, int64_t m0, int64_t n,
+                     int tile_rows, int S, const int32_t* tiles,
+                     const int64_t* tiles_off, const int32_t* cuts,
+                     const int64_t* cuts_off, const void* phases, int P,
+                     const int64_t* col_off, double rho,
+                     const double* lambdas, void* workspace,
+                     size_t workspace_bytes, void* stream);
+int admm_batch_solve(admm_batch* batch, const void* g, int iters,
+                     void* v_out, int use_graph, void* stream);
+/* Kernel event timing as admm_profile (solves run without the graph while
+ * on): 0 forward GEMM, 1 Gram apply, 2 adjoint GEMM, 3 z-update. */
+int admm_batch_profile(admm_batch* batch, int enable);
+int admm_batch_profile_read(admm_batch* batch, int kernel, double* total_ms,
+                            int64_t* launches);
+/* info16: m0, n, S, P, row blocks, scene tiles, workspace bytes, inverse
+ * bytes, chosen forward / adjoint tile widths (scene columns per wave),
+ * their work items, packed rows, 0... */
+int admm_batch_info(const admm_batch* batch, int64_t* info16);
+/* Autotuner timings (ms) of the tile widths 16, 32, 64: forward [0..2],
+ * adjoint [3..5]. */
+int admm_batch_tuning(const admm_batch* batch, double* ms6);
+void admm_batch_destroy(admm_batch* batch);
 
 #ifdef __cplusplus
 }

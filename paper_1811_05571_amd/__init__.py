@@ -38,6 +38,9 @@ SIGNATURES = [
                           _vp, _sz, _vp]),
     ("admm_set_lambda", _int, [_vp, _dbl]),
     ("admm_solve", _int, [_vp, _vp, _int, _dbl, _int, _vp, _c.POINTER(_int), _vp, _int, _vp]),
+    ("admm_tape_bytes", _int, [_vp, _int, _int, _c.POINTER(_sz)]),
+    ("admm_solve_record", _int, [_vp, _vp, _int, _int, _vp, _sz, _vp, _vp]),
+    ("admm_backward", _int, [_vp, _vp, _vp, _vp, _vp, _c.POINTER(_dbl), _c.POINTER(_dbl), _vp]),
     ("admm_get_state", _int, [_vp, _vp, _vp, _vp, _c.POINTER(_int), _vp]),
     ("admm_set_state", _int, [_vp, _vp, _vp, _vp, _int, _vp]),
     ("admm_kkt", _int, [_vp, _vp, _vp, _c.POINTER(_dbl), _vp]),
@@ -46,6 +49,15 @@ SIGNATURES = [
     ("admm_profile_read", _int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
     ("admm_plan_info", _int, [_vp, _c.POINTER(_i64)]),
     ("admm_destroy", None, [_vp]),
+    ("admm_batch_workspace_bytes", _int, [_i64, _i64, _int, _int, _vp, _vp, _vp, _vp, _int, _vp, _c.POINTER(_sz)]),
+    ("admm_batch_setup", _int, [_c.POINTER(_vp), _vp, _i64, _i64, _int, _int, _vp, _vp, _vp, _vp, _vp, _int, _vp,
+                                _dbl, _vp, _vp, _sz, _vp]),
+    ("admm_batch_solve", _int, [_vp, _vp, _int, _vp, _int, _vp]),
+    ("admm_batch_profile", _int, [_vp, _int]),
+    ("admm_batch_profile_read", _int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
+    ("admm_batch_info", _int, [_vp, _c.POINTER(_i64)]),
+    ("admm_batch_tuning", _int, [_vp, _c.POINTER(_dbl)]),
+    ("admm_batch_destroy", None, [_vp]),
 ]
 
 _lib = None
@@ -180,6 +192,38 @@ class Plan:
             return v, hist[: self.iters_done]
         return v
 
+    # -- reverse mode -------------------------------------------------------
+    def tape_bytes(self, iters: int, interval: int = 10) -> int:
+        out = ctypes.c_size_t(0)
+        _check(lib().admm_tape_bytes(self._h, int(iters), int(interval), ctypes.byref(out)), "admm_tape_bytes")
+        return int(out.value)
+
+    def solve_record(self, g, iters: int, interval: int = 10, tape=None):
+        """iters iterations from zero, checkpointing every `interval`; returns
+        (v, tape).  The tape is a uint8 device tensor owned by the caller."""
+        torch = self.torch
+        if not (g.is_cuda and g.dtype == torch.complex64 and g.numel() == self.m and g.is_contiguous()):
+            raise ValueError("g must be a contiguous complex64 CUDA tensor of length m")
+        nbytes = self.tape_bytes(iters, interval)
+        if tape is None or tape.numel() < nbytes:
+            tape = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        v = torch.empty(self.n, dtype=torch.complex64, device=self.device)
+        _check(lib().admm_solve_record(self._h, _ptr(g), int(iters), int(interval), _ptr(tape), tape.numel(),
+                                       _ptr(v), _stream(torch, self.device)), "admm_solve_record")
+        return v, tape
+
+    def backward(self, g, grad_v, tape):
+        """(dL/dg, dL/dlambda, dL/drho) for the recorded unrolled solve, given
+        grad_v = dL/dv^K (convention dL/dRe + j dL/dIm)."""
+        torch = self.torch
+        grad_v = grad_v.to(torch.complex64).contiguous()
+        gg = torch.empty(self.m, dtype=torch.complex64, device=self.device)
+        dl = ctypes.c_double(0.0)
+        dr = ctypes.c_double(0.0)
+        _check(lib().admm_backward(self._h, _ptr(g), _ptr(grad_v), _ptr(tape), _ptr(gg), ctypes.byref(dl),
+                                   ctypes.byref(dr), _stream(torch, self.device)), "admm_backward")
+        return gg, float(dl.value), float(dr.value)
+
     def kkt(self, g, v) -> float:
         out = ctypes.c_double(0.0)
         _check(lib().admm_kkt(self._h, _ptr(g), _ptr(v), ctypes.byref(out),
@@ -237,3 +281,125 @@ class Plan:
         keys = ["m", "n", "Q", "P", "storage", "chunks", "workspace_bytes", "h_bytes", "ginv_bytes",
                 "iters_done", "m_pad", "n_pad"]
         return {k: int(arr[i]) for i, k in enumerate(keys)}
+
+
+class Batch:
+    """Many scenes sharing one instrument matrix H0 (see include/admm.h).
+
+    H0: complex64 CUDA tensor (m0, n).  tiles, cuts: per-scene integer
+    sequences (tile indices; row-block cuts in tile units).  phases: per-scene
+    complex64 numpy arrays (one per scene row).  lambdas: per-scene floats."""
+
+    KERNELS = {0: "k_bgemm_n", 1: "k_gram", 2: "k_bgemm_h", 3: "k_bzupdate"}
+
+    def __init__(self, H0, tile_rows: int, tiles, cuts, phases, P: int, rho: float, lambdas, col_off=None):
+        import torch
+        self.torch = torch
+        self.device = H0.device
+        self.m0, self.n = H0.shape
+        self.S = len(tiles)
+        self.P, self.rho = P, float(rho)
+        self._tiles = np.ascontiguousarray(np.concatenate([np.asarray(t, np.int32) for t in tiles]))
+        self._toff = np.ascontiguousarray(np.cumsum([0] + [len(t) for t in tiles]).astype(np.int64))
+        self._cuts = np.ascontiguousarray(np.concatenate([np.asarray(c, np.int32) for c in cuts]))
+        self._coff = np.ascontiguousarray(np.cumsum([0] + [len(c) for c in cuts]).astype(np.int64))
+        self._lams = np.ascontiguousarray(np.asarray(lambdas, np.float64))
+        self._co, cp = _offsets(col_off)
+        cp = None if self._co is None else self._co.ctypes.data_as(ctypes.c_void_p)
+        self.rows = [len(t) * tile_rows for t in tiles]
+        ph = np.concatenate([np.asarray(p_, np.complex64) for p_ in phases])
+        self.phases = torch.from_numpy(ph).to(self.device)
+        v = ctypes.c_void_p
+        args = (self.m0, self.n, int(tile_rows), self.S, self._tiles.ctypes.data_as(v),
+                self._toff.ctypes.data_as(v), self._cuts.ctypes.data_as(v), self._coff.ctypes.data_as(v))
+        out = ctypes.c_size_t(0)
+        _check(lib().admm_batch_workspace_bytes(*args, P, cp, ctypes.byref(out)), "admm_batch_workspace_bytes")
+        self.workspace = torch.empty(int(out.value), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p(0)
+        _check(lib().admm_batch_setup(ctypes.byref(h), _ptr(H0), *args[:], _ptr(self.phases), P, cp, self.rho,
+                                      self._lams.ctypes.data_as(v), _ptr(self.workspace), self.workspace.numel(),
+                                      _stream(torch, self.device)), "admm_batch_setup")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().admm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, g, iters: int, graph: bool = True):
+        """g: packed complex64 CUDA tensor of all scenes' rows; returns (S, n)."""
+        torch = self.torch
+        if not (g.is_cuda and g.dtype == torch.complex64 and g.numel() == sum(self.rows) and g.is_contiguous()):
+            raise ValueError("g must be the packed complex64 CUDA measurements of all scenes")
+        v = torch.empty((self.S, self.n), dtype=torch.complex64, device=self.device)
+        _check(lib().admm_batch_solve(self._h, _ptr(g), int(iters), _ptr(v), int(bool(graph)),
+                                      _stream(torch, self.device)), "admm_batch_solve")
+        return v
+
+    def profile(self, enable: bool):
+        _check(lib().admm_batch_profile(self._h, int(bool(enable))), "admm_batch_profile")
+
+    def profile_read(self, kernel: int):
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        _check(lib().admm_batch_profile_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n)),
+               "admm_batch_profile_read")
+        return float(ms.value), int(n.value)
+
+    def info(self) -> dict:
+        arr = (ctypes.c_int64 * 16)()
+        _check(lib().admm_batch_info(self._h, arr), "admm_batch_info")
+        keys = ["m0", "n", "S", "P", "row_blocks", "scene_tiles", "workspace_bytes", "ginv_bytes", "tile_n",
+                "tile_h", "items_n", "items_h", "rows"]
+        return {k: int(arr[i]) for i, k in enumerate(keys)}
+
+    def tuning(self):
+        arr = (ctypes.c_double * 6)()
+        _check(lib().admm_batch_tuning(self._h, arr), "admm_batch_tuning")
+        return {"forward_ms": list(arr[:3]), "adjoint_ms": list(arr[3:]), "widths": [16, 32, 64]}
+
+
+def _unrolled_function():
+    import torch
+
+    class UnrolledADMM(torch.autograd.Function):
+        """v^K = ADMM(g, lambda, rho) for K iterations from zero, differentiable
+        in g, lambda and rho through the library's hand-written adjoint.
+
+        The plan's Gram factors depend on rho, so `rho` must equal plan.rho
+        (build a new Plan to change it); lambda is applied with set_lambda."""
+
+        @staticmethod
+        def forward(ctx, g, lam, rho, plan, iters, interval):
+            if abs(float(rho) - plan.rho) > 1e-12 * max(1.0, plan.rho):
+                raise ValueError("rho differs from the plan's rho: build a new Plan")
+            plan.set_lambda(float(lam))
+            v, tape = plan.solve_record(g.detach().contiguous(), iters, interval)
+            ctx.plan, ctx.tape = plan, tape
+            ctx.save_for_backward(g)
+            return v
+
+        @staticmethod
+        def backward(ctx, grad_v):
+            (g,) = ctx.saved_tensors
+            gg, dl, dr = ctx.plan.backward(g.detach().contiguous(), grad_v, ctx.tape)
+            dt = torch.float64
+            return gg, torch.tensor(dl, dtype=dt), torch.tensor(dr, dtype=dt), None, None, None
+
+    return UnrolledADMM
+
+
+def unrolled(g, lam, rho, plan, iters: int, interval: int = 10):
+    """Differentiable K-iteration solve (torch.autograd.Function)."""
+    global _UNROLLED
+    try:
+        F = _UNROLLED
+    except NameError:
+        F = _UNROLLED = _unrolled_function()
+    return F.apply(g, lam, rho, plan, iters, interval)

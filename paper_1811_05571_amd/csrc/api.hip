@@ -1,6 +1,7 @@
 // C ABI of the split-lasso ADMM library: argument checks, workspace layout,
 // plan lifetime and the host side of setup / solve / KKT check.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -39,6 +40,19 @@ int fail(int code, const char* fmt, ...) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
+
+namespace admm {
+// Error helper shared with the batched form (sets admm_last_error).
+int admm_fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+}  // namespace admm
 
 namespace admm {
 
@@ -92,8 +106,9 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   // padded spaces
   std::vector<int64_t> ldc(P), cpad0(P), ldr(Q), rpad0(Q);
   int64_t acc = 0;
+  const int colpad = std::max(kColPad, 64 * cols_per_load(storage));
   for (int j = 0; j < P; ++j) {
-    ldc[j] = round_up(geo.co[j + 1] - geo.co[j], kColPad);
+    ldc[j] = round_up(geo.co[j + 1] - geo.co[j], colpad);
     cpad0[j] = acc;
     acc += ldc[j];
   }
@@ -128,7 +143,12 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
         err = buf;
         return ADMM_EUNSUPPORTED;
       }
-      d.ld = (int32_t)ldc[j];
+      // H store row stride: whole 64-element groups (every lane load stays in
+      // the row), moved off multiples of 4 KB so consecutive rows do not all
+      // start on the same HBM channel.
+      int64_t ldh = round_up(d.nj, kColPad);
+      if ((ldh * elem_bytes(storage)) % 4096 == 0) ldh += kColPad;
+      d.ld = (int32_t)ldh;
       d.ldr = (int32_t)ldr[i];
       d.mt = (int32_t)round_up(d.mi, kTile);
       d.row0 = (int32_t)geo.ro[i];
@@ -155,11 +175,14 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   geo.t_z.clear();
   geo.t_gram.clear();
   geo.t_kadj.clear();
+  geo.t_hrows.clear();
   const int cpl = cols_per_load(storage);
   int wg_per_chunk = 0;
   for (size_t b = 0; b < geo.blocks.size(); ++b) {
     const BlockDesc& d = geo.blocks[b];
     for (int r = 0; r < d.mi; r += kRowsPerWG) geo.t_rows.push_back(make_int4((int)b, r, 0, 0));
+    const int hrows = rows_per_wave(storage) * (kBlockThreads / kWave);
+    for (int r = 0; r < d.mi; r += hrows) geo.t_hrows.push_back(make_int4((int)b, r, 0, 0));
     const int nl = (d.nj + cpl - 1) / cpl;
     wg_per_chunk += (nl + kColsPerWGLoads - 1) / kColsPerWGLoads;
     const int nt = d.mt / kTile;
@@ -222,6 +245,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   L.t_z = take(16 * geo.t_z.size());
   L.t_gram = take(16 * geo.t_gram.size());
   L.t_kadj = take(16 * geo.t_kadj.size());
+  L.t_hrows = take(16 * geo.t_hrows.size());
   L.ctl = take(sizeof(Control));
   L.redpart = take(8 * kRedCount * geo.t_z.size());
   L.row_block = take(8 * (size_t)m);
@@ -229,6 +253,17 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   L.kkt_v = take(colv);
   L.kkt_part = take(2 * colv * Q * geo.KH);
   L.kkt_max = take(8 * geo.t_z.size());
+  // adjoint sweep
+  L.vb = take(colv);
+  L.sb = take(colv * Q);
+  L.ub = take(colv * Q);
+  L.ghb = take(rowv * P);
+  L.gpb = take(rowv * P);
+  L.yb = take(rowv * P);
+  L.rb = take(rowv * P);
+  L.gbar = take(16 * (size_t)m);
+  L.kpart = take(8 * geo.t_z.size());
+  L.rpart = take(8 * geo.t_rows.size());
   L.total = off;
   return ADMM_OK;
 }
@@ -245,13 +280,17 @@ struct admm_plan {
   double2 *F64a = nullptr, *F64b = nullptr, *kkt_e = nullptr, *kkt_part = nullptr;
   BlockDesc* d_blocks = nullptr;
   ColDesc* d_cols = nullptr;
-  int4 *t_rows = nullptr, *t_cols = nullptr, *t_z = nullptr, *t_gram = nullptr, *t_kadj = nullptr;
+  int4 *t_rows = nullptr, *t_cols = nullptr, *t_z = nullptr, *t_gram = nullptr, *t_kadj = nullptr, *t_hrows = nullptr;
   HStore hs{};
   Control* ctl = nullptr;
   double *redpart = nullptr, *kkt_max = nullptr;
   int64_t* row_block = nullptr;
   std::vector<int64_t> h_row_block;
   int k_done = 0;
+  uint64_t serial = 0;
+  float2 *vb = nullptr, *sb = nullptr, *ub = nullptr, *ghb = nullptr, *gpb = nullptr, *yb = nullptr, *rb = nullptr;
+  double2* gbar = nullptr;
+  double *kpart = nullptr, *rpart = nullptr;
   // profiling
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[ADMM_K_COUNT];
@@ -328,6 +367,7 @@ IterArgs iter_args(admm_plan* p, const float2* g, double* hist) {
   a.ctl = p->ctl;
   a.redpart = p->redpart;
   a.hist = hist;
+  a.arec = nullptr;
   a.m_pad = p->geo.m_pad;
   a.n_pad = p->geo.n_pad;
   a.Q = p->geo.Q;
@@ -336,6 +376,7 @@ IterArgs iter_args(admm_plan* p, const float2* g, double* hist) {
   a.rho = (float)p->rho;
   a.kappa = (float)(p->lam / (p->geo.Q * p->rho));
   a.rho2Q = p->rho * p->rho * p->geo.Q;
+  a.cpl = cols_per_load(p->geo.storage);
   return a;
 }
 
@@ -346,6 +387,42 @@ int reset_state(admm_plan* p, hipStream_t st) {
   HIP_TRY(launch_fill(p->ws + L.c, bytes, st));
   p->k_done = 0;
   return ADMM_OK;
+}
+
+}  // namespace
+
+
+namespace {
+
+constexpr uint32_t kTapeMagic = 0x45504154u;  // "TAPE"
+
+struct TapeHeader {
+  uint32_t magic, version;
+  int32_t iters, interval, nseg, Q, P, pad;
+  int64_t m_pad, n_pad;
+  double lam, rho;
+  uint64_t serial;
+  uint64_t pad2[23];
+};
+static_assert(sizeof(TapeHeader) == 256, "tape header");
+
+struct TapeLayout {
+  size_t ckpt = 0, ckpt_stride = 0, v = 0, s = 0, ghat = 0, yrec = 0, arec = 0, total = 0;
+};
+
+TapeLayout tape_layout(const Geometry& G, int iters, int interval) {
+  TapeLayout t;
+  const size_t colv = (size_t)G.n_pad * 8, rowv = (size_t)G.m_pad * 8;
+  t.v = 0;
+  t.s = align256(colv);
+  t.ghat = t.s + align256(colv * G.Q);
+  t.ckpt_stride = t.ghat + align256(rowv * G.P);
+  const int nseg = (iters + interval - 1) / interval;
+  t.ckpt = 256;
+  t.yrec = t.ckpt + t.ckpt_stride * nseg;
+  t.arec = t.yrec + align256(rowv * G.P) * interval;
+  t.total = t.arec + align256(colv) * interval;
+  return t;
 }
 
 }  // namespace
@@ -427,6 +504,7 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   p->t_z = at<int4>(p, L.t_z);
   p->t_gram = at<int4>(p, L.t_gram);
   p->t_kadj = at<int4>(p, L.t_kadj);
+  p->t_hrows = at<int4>(p, L.t_hrows);
   p->hs.storage = storage;
   p->hs.base = p->ws + L.H;
   p->hs.base_im = storage == ADMM_STORAGE_C64 ? nullptr : p->ws + L.H_im;
@@ -438,6 +516,20 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   p->kkt_v = at<float2>(p, L.kkt_v);
   p->kkt_part = at<double2>(p, L.kkt_part);
   p->kkt_max = at<double>(p, L.kkt_max);
+  p->vb = at<float2>(p, L.vb);
+  p->sb = at<float2>(p, L.sb);
+  p->ub = at<float2>(p, L.ub);
+  p->ghb = at<float2>(p, L.ghb);
+  p->gpb = at<float2>(p, L.gpb);
+  p->yb = at<float2>(p, L.yb);
+  p->rb = at<float2>(p, L.rb);
+  p->gbar = at<double2>(p, L.gbar);
+  p->kpart = at<double>(p, L.kpart);
+  p->rpart = at<double>(p, L.rpart);
+  {
+    static std::atomic<uint64_t> next_serial{1};
+    p->serial = next_serial++;
+  }
   p->h_row_block.resize(m);
   for (int i = 0; i < Q; ++i)
     for (int64_t r = p->geo.ro[i]; r < p->geo.ro[i + 1]; ++r) p->h_row_block[r] = i;
@@ -466,6 +558,7 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   SETUP_TRY(hipMemcpyAsync(p->t_z, G.t_z.data(), 16 * G.t_z.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->t_gram, G.t_gram.data(), 16 * G.t_gram.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->t_kadj, G.t_kadj.data(), 16 * G.t_kadj.size(), hipMemcpyHostToDevice, st));
+  SETUP_TRY(hipMemcpyAsync(p->t_hrows, G.t_hrows.data(), 16 * G.t_hrows.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->row_block, p->h_row_block.data(), 8 * (size_t)m, hipMemcpyHostToDevice, st));
   int max_mi = 0;
   for (auto& d : G.blocks) max_mi = std::max(max_mi, d.mi);
@@ -510,9 +603,10 @@ int admm_solve(admm_plan* p, const void* g, int iters, double tol, int check_eve
   HIP_TRY(launch_fill(p->ctl, 16, st));  // iteration counter, ticket, flags
   const IterArgs a = iter_args(p, static_cast<const float2*>(g), resid_hist);
   const int nr = (int)G.t_rows.size(), nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
+  const int nh = (int)G.t_hrows.size();
   int done = 0;
   for (int k = 0; k < iters; ++k) {
-    if ((rc = timed(p, ADMM_K_GEMV_N, st, [&] { return launch_gemv_n(a, p->t_rows, nr, st); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GEMV_N, st, [&] { return launch_gemv_n(a, p->t_hrows, nh, st); }))) return rc;
     if ((rc = timed(p, ADMM_K_GRAM, st, [&] { return launch_gram(a, p->t_rows, nr, st); }))) return rc;
     if ((rc = timed(p, ADMM_K_GEMV_H, st, [&] { return launch_gemv_h(a, p->t_cols, nc, st); }))) return rc;
     if ((rc = timed(p, ADMM_K_ZUPDATE, st, [&] { return launch_zupdate(a, p->t_z, nz, st); }))) return rc;
@@ -536,6 +630,153 @@ int admm_solve(admm_plan* p, const void* g, int iters, double tol, int check_eve
   HIP_TRY(hipStreamSynchronize(st));
   if (iters_done) *iters_done = done;
   if (hc.nonfinite) return fail(ADMM_ENONFINITE, "a NaN or Inf reached the iterates (check g and rho)");
+  return ADMM_OK;
+}
+
+int admm_tape_bytes(const admm_plan* p, int iters, int interval, size_t* out_bytes) {
+  g_last_error.clear();
+  if (!p || !out_bytes) return fail(ADMM_EINVAL, "plan and out_bytes must not be NULL");
+  if (iters < 1 || interval < 1) return fail(ADMM_EINVAL, "iters and interval must be >= 1");
+  *out_bytes = tape_layout(p->geo, iters, interval).total;
+  return ADMM_OK;
+}
+
+int admm_solve_record(admm_plan* p, const void* g, int iters, int interval, void* tape, size_t tape_bytes,
+                      void* v_out, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(ADMM_EINVAL, "plan is NULL");
+  if (!g || !v_out || !tape) return fail(ADMM_EINVAL, "g, v_out and tape must not be NULL");
+  if (iters < 1 || interval < 1) return fail(ADMM_EINVAL, "iters and interval must be >= 1");
+  const Geometry& G = p->geo;
+  const TapeLayout T = tape_layout(G, iters, interval);
+  if (tape_bytes < T.total || (reinterpret_cast<uintptr_t>(tape) & 255))
+    return fail(ADMM_EWORKSPACE, "tape needs %zu bytes at 256-byte alignment", T.total);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* tp = static_cast<char*>(tape);
+  int rc;
+  if ((rc = reset_state(p, st))) return rc;
+  HIP_TRY(launch_fill(p->ctl, 16, st));
+  const IterArgs a = iter_args(p, static_cast<const float2*>(g), nullptr);
+  const int nr = (int)G.t_rows.size(), nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
+  const int nh = (int)G.t_hrows.size();
+  const size_t colv = (size_t)G.n_pad * 8, rowv = (size_t)G.m_pad * 8;
+  for (int k = 0; k < iters; ++k) {
+    if (k % interval == 0) {
+      char* ck = tp + T.ckpt + T.ckpt_stride * (k / interval);
+      HIP_TRY(hipMemcpyAsync(ck + T.v, p->v, colv, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(ck + T.s, p->s, colv * G.Q, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(ck + T.ghat, p->ghat, rowv * G.P, hipMemcpyDeviceToDevice, st));
+    }
+    if ((rc = timed(p, ADMM_K_GEMV_N, st, [&] { return launch_gemv_n(a, p->t_hrows, nh, st); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GRAM, st, [&] { return launch_gram(a, p->t_rows, nr, st); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GEMV_H, st, [&] { return launch_gemv_h(a, p->t_cols, nc, st); }))) return rc;
+    if ((rc = timed(p, ADMM_K_ZUPDATE, st, [&] { return launch_zupdate(a, p->t_z, nz, st); }))) return rc;
+  }
+  p->k_done = iters;
+  TapeHeader h{};
+  h.magic = kTapeMagic;
+  h.version = 1;
+  h.iters = iters;
+  h.interval = interval;
+  h.nseg = (iters + interval - 1) / interval;
+  h.Q = G.Q;
+  h.P = G.P;
+  h.m_pad = G.m_pad;
+  h.n_pad = G.n_pad;
+  h.lam = p->lam;
+  h.rho = p->rho;
+  h.serial = p->serial;
+  HIP_TRY(hipMemcpyAsync(tp, &h, sizeof h, hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_unpad_cols(p->d_cols, G.P, G.n, p->v, static_cast<float2*>(v_out), 0, 0, 1, 0, st));
+  Control hc;
+  HIP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (hc.nonfinite) return fail(ADMM_ENONFINITE, "a NaN or Inf reached the iterates");
+  return ADMM_OK;
+}
+
+int admm_backward(admm_plan* p, const void* g, const void* grad_v, const void* tape, void* grad_g,
+                  double* grad_lambda, double* grad_rho, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(ADMM_EINVAL, "plan is NULL");
+  if (!g || !grad_v || !tape || !grad_g || !grad_lambda || !grad_rho)
+    return fail(ADMM_EINVAL, "g, grad_v, tape, grad_g, grad_lambda and grad_rho must not be NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Geometry& G = p->geo;
+  const char* tp = static_cast<const char*>(tape);
+  TapeHeader h{};
+  HIP_TRY(hipMemcpyAsync(&h, tp, sizeof h, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h.magic != kTapeMagic || h.serial != p->serial)
+    return fail(ADMM_ESTATE, "the tape was not recorded by this plan (admm_solve_record first)");
+  if (h.lam != p->lam || h.rho != p->rho) return fail(ADMM_ESTATE, "lambda changed since the tape was recorded");
+  const int K = h.iters, C = h.interval;
+  const TapeLayout T = tape_layout(G, K, C);
+  const size_t colv = (size_t)G.n_pad * 8, rowv = (size_t)G.m_pad * 8;
+  // adjoint state: vb = grad_v, everything else zero
+  HIP_TRY(launch_fill(p->ws + G.lay.vb, G.lay.total - G.lay.vb, st));
+  HIP_TRY(launch_fill(&p->ctl->kbar, 16, st));
+  HIP_TRY(launch_unpad_cols(p->d_cols, G.P, G.n, static_cast<const float2*>(grad_v), p->vb, 0, 0, 1, 1, st));
+  HIP_TRY(launch_fill(p->ctl, 16, st));
+  IterArgs a = iter_args(p, static_cast<const float2*>(g), nullptr);
+  AdjArgs b{};
+  b.blocks = p->d_blocks;
+  b.cols = p->d_cols;
+  b.hs = p->hs;
+  b.Ginv = p->Ginv;
+  b.vb = p->vb;
+  b.sb = p->sb;
+  b.ub = p->ub;
+  b.ghb = p->ghb;
+  b.gpb = p->gpb;
+  b.yb = p->yb;
+  b.rb = p->rb;
+  b.part = p->part;
+  b.gbar = p->gbar;
+  b.kpart = p->kpart;
+  b.rpart = p->rpart;
+  b.ctl = p->ctl;
+  b.m_pad = G.m_pad;
+  b.n_pad = G.n_pad;
+  b.Q = G.Q;
+  b.P = G.P;
+  b.KH = G.KH;
+  b.rho = (float)p->rho;
+  b.kappa = a.kappa;
+  b.cpl = a.cpl;
+  const int nr = (int)G.t_rows.size(), nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
+  const int nh = (int)G.t_hrows.size();
+  float2* yrec = reinterpret_cast<float2*>(const_cast<char*>(tp) + T.yrec);
+  float2* arec = reinterpret_cast<float2*>(const_cast<char*>(tp) + T.arec);
+  const size_t ystride = align256(rowv * G.P) / 8, astride = align256(colv) / 8;
+  for (int seg = h.nseg - 1; seg >= 0; --seg) {
+    const int k0 = seg * C, k1 = std::min(K, k0 + C);
+    const char* ck = tp + T.ckpt + T.ckpt_stride * seg;
+    HIP_TRY(hipMemcpyAsync(p->v, ck + T.v, colv, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->s, ck + T.s, colv * G.Q, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->ghat, ck + T.ghat, rowv * G.P, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(launch_make_c(p->d_cols, G.P, G.Q, G.n_pad, cols_per_load(G.storage), p->v, p->s, p->c, st));
+    for (int k = k0; k < k1; ++k) {
+      a.y = yrec + ystride * (k - k0);
+      a.arec = arec + astride * (k - k0);
+      HIP_TRY(launch_gemv_n(a, p->t_hrows, nh, st));
+      HIP_TRY(launch_gram(a, p->t_rows, nr, st));
+      HIP_TRY(launch_gemv_h(a, p->t_cols, nc, st));
+      HIP_TRY(launch_zupdate(a, p->t_z, nz, st));
+    }
+    for (int k = k1 - 1; k >= k0; --k)
+      HIP_TRY(launch_adj_iteration(b, G, p->t_hrows, p->t_rows, p->t_cols, p->t_z, arec + astride * (k - k0),
+                                   yrec + ystride * (k - k0), st));
+  }
+  HIP_TRY(launch_adj_gflush(b, p->d_blocks, (int)G.blocks.size(), static_cast<float2*>(grad_g), st));
+  Control hc;
+  HIP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double Q = G.Q;
+  *grad_lambda = hc.kbar / (Q * p->rho);
+  *grad_rho = hc.rbar - hc.kbar * p->lam / (Q * p->rho * p->rho);
+  p->k_done = 0;
+  if (hc.nonfinite) return fail(ADMM_ENONFINITE, "a NaN or Inf reached the recomputed iterates");
   return ADMM_OK;
 }
 
@@ -568,7 +809,7 @@ int admm_set_state(admm_plan* p, const void* v, const void* s, const void* ghat,
   HIP_TRY(launch_unpad_cols(p->d_cols, G.P, G.n, static_cast<const float2*>(s), p->s, G.n, G.n_pad, G.Q, 1, st));
   HIP_TRY(launch_unpad_rows(p->d_blocks, (int)G.blocks.size(), G.m, G.m_pad, static_cast<const float2*>(ghat),
                             p->ghat, 1, st));
-  HIP_TRY(launch_make_c(p->d_cols, G.P, G.Q, G.n_pad, p->v, p->s, p->c, st));
+  HIP_TRY(launch_make_c(p->d_cols, G.P, G.Q, G.n_pad, cols_per_load(G.storage), p->v, p->s, p->c, st));
   HIP_TRY(hipStreamSynchronize(st));
   p->k_done = k;
   return ADMM_OK;

@@ -10,8 +10,9 @@ namespace admm {
 // Column (pixel) and row (measurement) vectors are stored padded per block so
 // that every block segment starts on a 512-byte boundary and every row of the
 // stored H starts 16-byte aligned.  Pads hold zeros and are never written by
-// the iteration.
-constexpr int kColPad = 64;    // complex elements
+// the iteration.  Column blocks are padded to whole groups of 64 lane loads
+// (64 * CPL columns, see cperm).
+constexpr int kColPad = 64;    // complex elements (minimum)
 constexpr int kRowPad = 64;    // complex elements
 constexpr int kTile = 64;      // FP64 setup tile edge (Cholesky / inverse)
 
@@ -19,6 +20,18 @@ constexpr int kWave = 64;      // CDNA wavefront
 constexpr int kBlockThreads = 256;
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Position of column `col` (inside its block) in the lane-permuted layout of
+// the row products' input vector.  Lane l of a wave reads columns
+// l*CPL .. l*CPL+CPL-1 of each group of 64*CPL columns; storing pair q of
+// lane l at pair index q*64 + l makes the q-th load of all 64 lanes one
+// contiguous 1 KB access.  The identity for CPL = 2.
+__host__ __device__ __forceinline__ int cperm(int col, int cpl) {
+  const int grp = 64 * cpl;
+  const int g = col / grp, rem = col - g * grp;
+  const int l = rem / cpl, k = rem - l * cpl;
+  return g * grp + (((k >> 1) * 64 + l) << 1) + (k & 1);
+}
 
 // One (i, j) block of the split.  All offsets are in elements of the
 // region they index.
@@ -55,11 +68,15 @@ struct Control {
   int32_t nonfinite;     // sticky NaN/Inf flag
   int32_t notpd;         // Cholesky pivot failure flag
   int32_t kkt_ticket;    // arrival counter of the KKT reduction
-  int32_t pad[3];
+  int32_t adj_ticket_k;  // arrival counters of the adjoint's scalar sums
+  int32_t adj_ticket_r;
+  int32_t pad;
   double red[kRedCount]; // last iteration's reduction scalars
   double kkt;            // last KKT violation (unscaled)
-  double pad2[2];
+  double kbar;           // adjoint: d L / d kappa accumulated over iterations
+  double rbar;           // adjoint: d L / d rho through G^{-1} and ghat
 };
+static_assert(sizeof(Control) % 16 == 0, "Control size");
 
 // Storage-independent view of an H block row for the device kernels.
 struct HStore {

@@ -37,9 +37,15 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 
 // Loads in flight per row: the same bytes per lane for every format.
 template <class F> struct RowUnroll { static constexpr int U = F::CPL == 2 ? 4 : 2; };
+// H row products: rows per wave and lane loads in flight per row (narrow
+// formats reuse each lane's vector loads across 8 rows).
+template <class F> struct HRows {
+  static constexpr int R = F::CPL == 2 ? 4 : 8;
+  static constexpr int U = F::CPL == 2 ? 4 : 1;
+};
 
 // Dot products of R consecutive rows of a stored matrix with the complex
-// vector x (FP32, padded).  e0: element offset of the first row, ld: row
+// vector x (FP32, padded, in the lane-permuted layout of cperm).  e0: element offset of the first row, ld: row
 // stride in elements, nl: lane loads per row (ceil(ncols / CPL)), rows >=
 // nvalid are clamped.  Lane l walks lane loads l, l+64, ... with U of them
 // per row in flight.  The result (row scale not applied) is in every lane.
@@ -75,7 +81,7 @@ __device__ __forceinline__ void rows_dot(const F& f, int64_t e0, int64_t ld, int
     for (int u = 0; u < U; ++u) {
       float4 xv[X4];
 #pragma unroll
-      for (int q = 0; q < X4; ++q) xv[q] = x[(int64_t)(c + u * kWave) * X4 + q];
+      for (int q = 0; q < X4; ++q) xv[q] = x[(((int64_t)((c + u * kWave) >> 6) * X4 + q) << 6) + ((c + u * kWave) & 63)];
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) consume(raw[u][rr], xv, rr);
     }
@@ -86,7 +92,7 @@ __device__ __forceinline__ void rows_dot(const F& f, int64_t e0, int64_t ld, int
     for (int rr = 0; rr < R; ++rr) raw[rr] = f.load(rowoff[rr] + (int64_t)c * CPL);
     float4 xv[X4];
 #pragma unroll
-    for (int q = 0; q < X4; ++q) xv[q] = x[(int64_t)c * X4 + q];
+    for (int q = 0; q < X4; ++q) xv[q] = x[(((int64_t)(c >> 6) * X4 + q) << 6) + (c & 63)];
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) consume(raw[rr], xv, rr);
   }

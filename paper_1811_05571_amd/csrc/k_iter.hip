@@ -25,7 +25,7 @@
 
 namespace admm {
 
-// r_ij = g'_ij - H_ij c_j^i for kRowsPerWG rows of one block per workgroup.
+// r_ij = g'_ij - H_ij c_j^i for 4 * HRows<F>::R rows of one block per workgroup.
 // tiles[x] = {block, first row, -, -}.
 template <class F>
 __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4* __restrict__ tiles) {
@@ -33,17 +33,18 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = a.blocks[t.x];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int row = t.y + wave * kRowsPerWave;
+  constexpr int R = HRows<F>::R;
+  const int row = t.y + wave * R;
   if (row >= d.mi) return;
-  const int nvalid = min(kRowsPerWave, d.mi - row);
+  const int nvalid = min(R, d.mi - row);
   const float4* x = reinterpret_cast<const float4*>(a.c + (int64_t)d.i * a.n_pad + d.cpad0);
-  float acc[kRowsPerWave][2];
-  rows_dot<F, kRowsPerWave, RowUnroll<F>::U>(f, d.h_off + (int64_t)row * d.ld, d.ld, nvalid, x,
-                                             (d.nj + F::CPL - 1) / F::CPL, acc);
+  float acc[R][2];
+  rows_dot<F, R, HRows<F>::U>(f, d.h_off + (int64_t)row * d.ld, d.ld, nvalid, x, (d.nj + F::CPL - 1) / F::CPL,
+                              acc);
   if (lane < nvalid) {
     float ar = 0.f, ai = 0.f;
 #pragma unroll
-    for (int rr = 0; rr < kRowsPerWave; ++rr)
+    for (int rr = 0; rr < R; ++rr)
       if (rr == lane) { ar = acc[rr][0]; ai = acc[rr][1]; }
     const int lr = row + lane;                       // row inside the block
     const float sc = f.row_scale(d.row0 + lr);
@@ -120,10 +121,11 @@ __global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __re
   double acc[kRedCount] = {0, 0, 0, 0, 0};
   if (valid) {
     const int64_t p = cd.cpad0 + col;
+    const int64_t pc = cd.cpad0 + cperm(col, a.cpl);   // position of c (row-product input layout)
     const int Q = MAXQ > 0 ? MAXQ : a.Q;
     float ur[MAXQ > 0 ? MAXQ : 1], ui[MAXQ > 0 ? MAXQ : 1];
     auto replica = [&](int i, float& xr, float& xi) {
-      const float2 ci = a.c[(int64_t)i * a.n_pad + p];
+      const float2 ci = a.c[(int64_t)i * a.n_pad + pc];
       float sr = ci.x, si = ci.y;
       const float2* pp = a.part + (int64_t)i * a.n_pad + p;
       const int64_t stride = (int64_t)a.Q * a.n_pad;
@@ -155,6 +157,7 @@ __global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __re
     ar *= invQ;
     ai *= invQ;
     if (!(isfinite(ar) && isfinite(ai))) a.ctl->nonfinite = 1;
+    if (a.arec) a.arec[p] = make_float2(ar, ai);
     // eq. softhresholding with sign(a) = a/|a|
     const float mag = sqrtf(ar * ar + ai * ai);
     float vr = 0.f, vi = 0.f;
@@ -180,7 +183,7 @@ __global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __re
       const float dr = xr - vr, di = xi - vi;
       const float sr = si.x + dr, sim = si.y + di;
       a.s[ip] = make_float2(sr, sim);
-      a.c[ip] = make_float2(vr - sr, vi - sim);
+      a.c[(int64_t)i * a.n_pad + pc] = make_float2(vr - sr, vi - sim);
       acc[kRedRp2] += (double)dr * dr + (double)di * di;
       acc[kRedU2] += (double)xr * xr + (double)xi * xi;
       acc[kRedS2] += (double)sr * sr + (double)sim * sim;
@@ -252,14 +255,15 @@ __global__ void k_rows_copy(const BlockDesc* __restrict__ blocks, int64_t m, int
   }
 }
 
-// c_j^i = v_j - s_j^i on the valid columns (after a state import).
-__global__ void k_make_c(const ColDesc* __restrict__ cols, int64_t n_pad, const float2* __restrict__ v,
+// c_j^i = v_j - s_j^i on the valid columns (after a state import), stored in
+// the lane-permuted layout of the row products.
+__global__ void k_make_c(const ColDesc* __restrict__ cols, int64_t n_pad, int cpl, const float2* __restrict__ v,
                          const float2* __restrict__ s, float2* __restrict__ c) {
   const int j = blockIdx.y, i = blockIdx.z;
   const ColDesc cd = cols[j];
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < cd.nj; k += gridDim.x * blockDim.x) {
     const int64_t p = cd.cpad0 + k, ip = (int64_t)i * n_pad + p;
-    c[ip] = make_float2(v[p].x - s[ip].x, v[p].y - s[ip].y);
+    c[(int64_t)i * n_pad + cd.cpad0 + cperm(k, cpl)] = make_float2(v[p].x - s[ip].x, v[p].y - s[ip].y);
   }
 }
 
@@ -312,9 +316,9 @@ hipError_t launch_unpad_rows(const BlockDesc* blocks, int nblocks, int64_t m, in
                      to_padded);
   return hipGetLastError();
 }
-hipError_t launch_make_c(const ColDesc* cols, int P, int Q, int64_t n_pad, const float2* v, const float2* s,
-                         float2* c, hipStream_t st) {
-  hipLaunchKernelGGL(k_make_c, dim3(16, P, Q), dim3(256), 0, st, cols, n_pad, v, s, c);
+hipError_t launch_make_c(const ColDesc* cols, int P, int Q, int64_t n_pad, int cpl, const float2* v,
+                         const float2* s, float2* c, hipStream_t st) {
+  hipLaunchKernelGGL(k_make_c, dim3(16, P, Q), dim3(256), 0, st, cols, n_pad, cpl, v, s, c);
   return hipGetLastError();
 }
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t st) {

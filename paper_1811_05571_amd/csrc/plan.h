@@ -17,8 +17,9 @@ struct ColDesc {       // one column block j
 struct Layout {
   size_t H = 0, H_im = 0, H_scale = 0, Ginv = 0, F64a = 0, F64b = 0;
   size_t c = 0, s = 0, v = 0, part = 0, gp = 0, ghat = 0, r = 0, y = 0;
-  size_t blocks = 0, cols = 0, t_rows = 0, t_cols = 0, t_z = 0, t_gram = 0, t_kadj = 0;
+  size_t blocks = 0, cols = 0, t_rows = 0, t_cols = 0, t_z = 0, t_gram = 0, t_kadj = 0, t_hrows = 0;
   size_t ctl = 0, redpart = 0, row_block = 0, kkt_e = 0, kkt_v = 0, kkt_part = 0, kkt_max = 0;
+  size_t vb = 0, sb = 0, ub = 0, ghb = 0, gpb = 0, yb = 0, rb = 0, gbar = 0, kpart = 0, rpart = 0;
   size_t total = 0;
   size_t h_bytes = 0, ginv_bytes = 0;
 };
@@ -32,7 +33,7 @@ struct Geometry {
   int64_t m_pad = 0, n_pad = 0;    // padded row / column space lengths
   int KH = 1;                      // row chunks of the adjoint product
   int max_mt = 0;                  // largest tile-padded block edge
-  std::vector<int4> t_rows, t_cols, t_z, t_gram, t_kadj;
+  std::vector<int4> t_rows, t_cols, t_z, t_gram, t_kadj, t_hrows;
   Layout lay;
 };
 
@@ -44,6 +45,9 @@ constexpr int kRowsPerWG = kRowsPerWave * (kBlockThreads / kWave);
 constexpr int kColsPerWGLoads = kWave;
 // Complex columns per lane load for a storage format.
 inline int cols_per_load(int storage) { return storage == 0 ? 2 : (storage == 1 ? 8 : 16); }
+// Rows per wave of the H row products: narrow formats share each lane's
+// vector loads across more rows.
+inline int rows_per_wave(int storage) { return storage == 0 ? 4 : 8; }
 // Bytes per stored complex element.
 inline int elem_bytes(int storage) { return storage == 0 ? 8 : (storage == 1 ? 4 : 2); }
 constexpr int kZCols = kWave;   // columns (lanes) per z-update workgroup
@@ -62,11 +66,34 @@ struct IterArgs {
   Control* ctl;
   double* redpart;
   double* hist;         // device, 2 per iteration, or null
+  float2* arec;         // device, pre-threshold mean of this iteration (column space), or null
   int64_t m_pad, n_pad;
   int Q, P, KH;
   float rho, kappa;
   double rho2Q;         // rho^2 Q for the dual residual
+  int cpl;              // columns per lane load of the storage (layout of c, see cperm)
 };
+
+// Adjoint (reverse-mode) sweep of one iteration.
+struct AdjArgs {
+  const BlockDesc* blocks;
+  const ColDesc* cols;
+  HStore hs;
+  const float2* Ginv;
+  float2 *vb, *sb, *ub, *ghb, *gpb, *yb, *rb, *part;
+  double2* gbar;
+  double *kpart, *rpart;
+  Control* ctl;
+  int64_t m_pad, n_pad;
+  int Q, P, KH;
+  float rho, kappa;
+  int cpl;              // layout of ub (see cperm)
+};
+hipError_t launch_adj_iteration(const AdjArgs& a, const Geometry& G, const int4* t_hrows, const int4* t_rows,
+                                const int4* t_cols, const int4* t_z, const float2* arec, const float2* yrec,
+                                hipStream_t st);
+hipError_t launch_adj_gflush(const AdjArgs& a, const BlockDesc* blocks, int nblocks, float2* grad_g,
+                             hipStream_t st);
 
 hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st);
 hipError_t launch_gram(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st);
@@ -96,7 +123,7 @@ hipError_t launch_kkt_all(const BlockDesc* dblocks, const ColDesc* dcols, const 
                           const int4* t_kadj, int n_tkadj, const int4* t_z, int n_tz, int64_t m, int64_t n_pad,
                           int Q, int P, int KH, const HStore& hs, const float2* g, const float2* vpad,
                           double lam, double2* e, double2* part, double* wgmax, Control* ctl, hipStream_t st);
-hipError_t launch_make_c(const ColDesc* cols, int P, int Q, int64_t n_pad, const float2* v, const float2* s,
-                         float2* c, hipStream_t st);
+hipError_t launch_make_c(const ColDesc* cols, int P, int Q, int64_t n_pad, int cpl, const float2* v,
+                         const float2* s, float2* c, hipStream_t st);
 
 }  // namespace admm

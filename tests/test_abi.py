@@ -65,3 +65,28 @@ def test_null_plan_is_rejected():
     assert L.admm_solve(None, None, 1, 0.0, 1, None, None, None, 0, None) == -1
     assert L.admm_profile(None, 1) == -1
     L.admm_destroy(None)
+
+
+def test_batch_workspace_sizing_and_errors():
+    import ctypes
+
+    import numpy as np
+
+    import paper_1811_05571_amd as A
+    L = A.lib()
+    tiles = np.array([0, 2, 3, 1, 2], np.int32)
+    toff = np.array([0, 3, 5], np.int64)
+    cuts = np.array([0, 1, 3, 0, 2], np.int32)
+    coff = np.array([0, 3, 5], np.int64)
+    v = ctypes.c_void_p
+    out = ctypes.c_size_t(0)
+    rc = L.admm_batch_workspace_bytes(256, 4096, 64, 2, tiles.ctypes.data_as(v), toff.ctypes.data_as(v),
+                                      cuts.ctypes.data_as(v), coff.ctypes.data_as(v), 2, None, ctypes.byref(out))
+    assert rc == 0 and out.value > 256 * 4096 * 4
+    bad = np.array([0, 3, 2, 1, 2], np.int32)        # not increasing
+    assert L.admm_batch_workspace_bytes(256, 4096, 64, 2, bad.ctypes.data_as(v), toff.ctypes.data_as(v),
+                                        cuts.ctypes.data_as(v), coff.ctypes.data_as(v), 2, None,
+                                        ctypes.byref(out)) == -1
+    assert L.admm_batch_workspace_bytes(256, 4096, 48, 2, tiles.ctypes.data_as(v), toff.ctypes.data_as(v),
+                                        cuts.ctypes.data_as(v), coff.ctypes.data_as(v), 2, None,
+                                        ctypes.byref(out)) == -1

@@ -1,0 +1,171 @@
+"""Adjoint form: hand-written reverse mode of K unrolled iterations, checked
+against (i) the FP64 oracle's autograd gradient (torch-CPU twin of the
+oracle) and (ii) central finite differences of the GPU forward with a
+relative step of 1e-3, for dL/dg (directional), dL/dlambda and dL/drho with
+L = |v^K - u_true|^2.  Complex64 forward, FP32 adjoint."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import admm as O
+from oracle import admm_torch as OT
+from tests._gpu import rel, to_device
+
+pytestmark = pytest.mark.gpu
+
+# FP32 adjoint vs FP64 autograd (normalised error on dL/dg, relative on scalars)
+TOL_AUTOGRAD = 2e-4
+# central differences (step 1e-3 relative) of the FP32 forward vs the adjoint
+TOL_FD = 2e-2
+
+
+def _cases():
+    return {
+        "consensus": (W.iid_problem(m=128, n=1000, nnz=8, Q=4, P=1, rho=1.0, seed=21), 60),
+        "combined_uneven": (W.iid_problem(m=300, n=2000, nnz=15, Q=3, P=5, rho=10.0, seed=3,
+                                          row_off=[0, 90, 200, 300],
+                                          col_off=[0, 333, 800, 1201, 1600, 2000]), 40),
+        "cra_small": (W.cra_problem(n_tx=6, n_rx=6, n_f=8, nx=12, ny=12, nz=6, Q=2, P=2, rho=10.0,
+                                    patch=(5, 2), iters=50, seed=22), 50),
+    }
+
+
+def _plan(torch, p, rho=None, storage="c64"):
+    import paper_1811_05571_amd as A
+    return A.Plan(to_device(torch, p.H), p.Q, p.P, p.rho if rho is None else rho, p.lam, p.row_off, p.col_off,
+                  storage=storage)
+
+
+def _loss_and_grad_v(v, u_true):
+    return float(np.sum(np.abs(v - u_true) ** 2)), 2 * (v - u_true)
+
+
+@pytest.mark.parametrize("name", ["consensus", "combined_uneven", "cra_small"])
+def test_adjoint_matches_oracle_autograd(torch_gpu, name):
+    torch = torch_gpu
+    p, K = _cases()[name]
+    plan = _plan(torch, p)
+    g = to_device(torch, p.g)
+    v, tape = plan.solve_record(g, K, interval=7)
+    v = v.cpu().numpy()
+    _, gv = _loss_and_grad_v(v.astype(np.complex128), p.u_true)
+    gg, dl, dr = plan.backward(g, to_device(torch, gv.astype(np.complex64)), tape)
+    tg, tl, tr, tv = OT.gradients(p.H.astype(np.complex128), p.g.astype(np.complex128), p.Q, p.P, p.rho, p.lam, K,
+                                  gv, p.row_off, p.col_off)
+    assert rel(v, tv) <= 1e-5
+    eg, el, er = rel(gg.cpu().numpy(), tg), abs(dl - tl) / abs(tl), abs(dr - tr) / abs(tr)
+    print(f"{name}: dL/dg {eg:.2e}  dL/dlam {el:.2e} ({dl:.6g} vs {tl:.6g})  dL/drho {er:.2e} ({dr:.6g} vs {tr:.6g})")
+    assert eg <= TOL_AUTOGRAD and el <= TOL_AUTOGRAD and er <= TOL_AUTOGRAD
+
+
+def _fd_check(f, x0, h, ad, scale):
+    """Central difference of f at x0 with step h against the adjoint value ad.
+    Soft-threshold kinks inside [x0 - h, x0 + h] make the map's left and right
+    slopes differ and the central difference meaningless; then the two
+    one-sided differences must disagree (the kinks' signature) and the
+    adjoint, the derivative at x0, must lie between them.  Returns True when
+    kinks were crossed."""
+    fp, f0, fm = f(x0 + h), f(x0), f(x0 - h)
+    c = (fp - fm) / (2 * h)
+    tol = TOL_FD * (abs(c) + scale)
+    if abs(c - ad) <= tol:
+        return False
+    fwd, bwd = (fp - f0) / h, (f0 - fm) / h
+    assert abs(fwd - bwd) > 2 * tol, ("no kink between the one-sided differences", fwd, bwd, ad)
+    assert min(fwd, bwd) - tol <= ad <= max(fwd, bwd) + tol, ("adjoint outside the one-sided slopes", fwd, bwd, ad)
+    return True
+
+
+@pytest.mark.parametrize("name", ["consensus", "cra_small"])
+def test_adjoint_matches_central_differences(torch_gpu, name):
+    torch = torch_gpu
+    p, K = _cases()[name]
+    g = to_device(torch, p.g)
+
+    def L(gg=None, lam=None, rho=None):
+        plan = _plan(torch, p, rho=rho)
+        if lam is not None:
+            plan.set_lambda(lam)
+        v = plan.solve(to_device(torch, gg) if gg is not None else g, K).cpu().numpy()
+        return float(np.sum(np.abs(v.astype(np.complex128) - p.u_true) ** 2))
+
+    plan = _plan(torch, p)
+    v, tape = plan.solve_record(g, K, interval=10)
+    _, gv = _loss_and_grad_v(v.cpu().numpy().astype(np.complex128), p.u_true)
+    gg, dl, dr = plan.backward(g, to_device(torch, gv.astype(np.complex64)), tape)
+    gg = gg.cpu().numpy().astype(np.complex128)
+    rng = np.random.default_rng(5)
+    kinks = 0
+    for _ in range(4):
+        d = rng.standard_normal(p.m) + 1j * rng.standard_normal(p.m)
+        d /= np.linalg.norm(d)
+        h = 1e-3 * np.linalg.norm(p.g)
+        f = lambda t: L(gg=(p.g + t * d).astype(np.complex64))
+        kinks += _fd_check(f, 0.0, h, float(np.real(np.vdot(gg, d))), 1e-2 * np.linalg.norm(gg))
+    kinks += _fd_check(lambda x: L(lam=x), p.lam, 1e-3 * p.lam, dl, 0.0)
+    kinks += _fd_check(lambda x: L(rho=x), p.rho, 1e-3 * p.rho, dr, 1e-6)
+    print(f"{name}: {kinks} of 6 differences crossed a soft-threshold kink")
+    assert kinks <= 2
+
+
+def test_autograd_function(torch_gpu):
+    import paper_1811_05571_amd as A
+    torch = torch_gpu
+    p, K = _cases()["combined_uneven"]
+    plan = _plan(torch, p)
+    g = to_device(torch, p.g).requires_grad_(True)
+    lam = torch.tensor(p.lam, dtype=torch.float64, requires_grad=True)
+    rho = torch.tensor(p.rho, dtype=torch.float64, requires_grad=True)
+    v = A.unrolled(g, lam, rho, plan, K, 10)
+    ut = to_device(torch, p.u_true.astype(np.complex64))
+    loss = ((v - ut).abs() ** 2).sum()
+    loss.backward()
+    plan2 = _plan(torch, p)
+    v2, tape = plan2.solve_record(to_device(torch, p.g), K, 10)
+    gg, dl, dr = plan2.backward(to_device(torch, p.g), 2 * (v2 - ut), tape)
+    assert rel(g.grad.cpu().numpy(), gg.cpu().numpy()) <= 1e-6
+    assert abs(lam.grad.item() - dl) <= 1e-6 * abs(dl) and abs(rho.grad.item() - dr) <= 1e-6 * abs(dr)
+
+
+def test_tape_errors(torch_gpu):
+    import paper_1811_05571_amd as A
+    torch = torch_gpu
+    p, K = _cases()["consensus"]
+    g = to_device(torch, p.g)
+    plan, other = _plan(torch, p), _plan(torch, p)
+    v, tape = plan.solve_record(g, 10, 5)
+    gv = torch.zeros(p.n, dtype=torch.complex64, device="cuda")
+    with pytest.raises(A.ADMMError) as ei:
+        other.backward(g, gv, tape)
+    assert ei.value.status == "ADMM_ESTATE"
+    plan.set_lambda(2 * p.lam)
+    with pytest.raises(A.ADMMError) as ei:
+        plan.backward(g, gv, tape)
+    assert ei.value.status == "ADMM_ESTATE"
+    with pytest.raises(A.ADMMError) as ei:
+        A.lib().admm_solve_record(plan.handle, g.data_ptr(), 10, 5, tape.data_ptr(), 16, v.data_ptr(), None) and None
+        raise A.ADMMError(A.lib().admm_solve_record(plan.handle, g.data_ptr(), 10, 5, tape.data_ptr(), 16,
+                                                    v.data_ptr(), None), "record")
+    assert ei.value.status == "ADMM_EWORKSPACE"
+
+
+def test_eight_scene_batch_gradients(torch_gpu):
+    """Eight scenes of a small CRA geometry (seeds 2000..2007), K = 100 with a
+    checkpoint every 10 iterations: every scene's adjoint matches the oracle
+    autograd gradient."""
+    torch = torch_gpu
+    worst = 0.0
+    for seed in range(2000, 2008):
+        p = W.cra_problem(n_tx=4, n_rx=4, n_f=8, nx=10, ny=10, nz=5, Q=2, P=2, rho=10.0, patch=(4, 2),
+                          iters=100, seed=seed)
+        plan = _plan(torch, p)
+        g = to_device(torch, p.g)
+        v, tape = plan.solve_record(g, 100, 10)
+        _, gv = _loss_and_grad_v(v.cpu().numpy().astype(np.complex128), p.u_true)
+        gg, dl, dr = plan.backward(g, to_device(torch, gv.astype(np.complex64)), tape)
+        tg, tl, tr, _ = OT.gradients(p.H.astype(np.complex128), p.g.astype(np.complex128), p.Q, p.P, p.rho, p.lam,
+                                     100, gv)
+        e = max(rel(gg.cpu().numpy(), tg), abs(dl - tl) / abs(tl), abs(dr - tr) / abs(tr))
+        print(f"scene {seed}: max rel err {e:.2e}")
+        worst = max(worst, e)
+    assert worst <= TOL_AUTOGRAD

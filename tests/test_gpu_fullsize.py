@@ -1,0 +1,101 @@
+"""Full-size checks on the 6144 x 32000 imaging workload (Q=4, P=8, rho=6):
+parity with the oracle after a few iterations (the oracle runs at full size
+on the host), properties that hold at any size after 300 iterations, the
+precision forms, and the adjoint against central differences."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import admm as O
+from tests._gpu import rel, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def full(torch_gpu):
+    p = W.full_imaging()
+    return p, to_device(torch_gpu, p.H), to_device(torch_gpu, p.g)
+
+
+def test_full_size_parity_first_iterations(torch_gpu, full):
+    import paper_1811_05571_amd as A
+    p, H, g = full
+    plan = A.Plan(H, p.Q, p.P, p.rho, p.lam)
+    K = 3
+    v = plan.solve(g, K).cpu().numpy()
+    k, _, s, ghat = plan.get_state()
+    v_ref, hist, st = O.solve(p.H, p.g, p.Q, p.P, p.rho, p.lam, K)
+    assert rel(v, v_ref) <= 1e-5
+    assert rel(s.cpu().numpy(), st.s) <= 1e-4
+    assert rel(ghat.cpu().numpy(), st.ghat) <= 1e-4
+
+
+def test_full_size_300_iterations_properties(torch_gpu, full):
+    """After the workload's 300 iterations: residuals decrease, the FP64 KKT
+    violation decreases, both runs of the same input agree bit for bit."""
+    import paper_1811_05571_amd as A
+    p, H, g = full
+    plan = A.Plan(H, p.Q, p.P, p.rho, p.lam)
+    v100 = plan.solve(g, 100)
+    k100 = plan.kkt(g, v100)
+    v300, hist = plan.solve(g, 300, history=True)
+    k300 = plan.kkt(g, v300)
+    h = hist.cpu().numpy()
+    assert np.all(np.isfinite(h))
+    assert h[-1, 0] < 1e-3 * h[10, 0] and h[-1, 1] < h[10, 1]
+    assert k300 < k100
+    assert torch_gpu.equal(v300, plan.solve(g, 300))
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp8"])
+def test_full_size_precision_forms(torch_gpu, full, storage):
+    import paper_1811_05571_amd as A
+    from oracle import quant as QZ
+    p, H, g = full
+    plan = A.Plan(H, p.Q, p.P, p.rho, p.lam, storage=storage)
+    re, im, sc = plan.stored_h()
+    rows = np.random.default_rng(0).choice(p.m, 64, replace=False)      # sampled rows of the codes
+    ref = QZ.quantise(p.H[rows], storage)
+    if storage == "bf16":
+        np.testing.assert_array_equal(re.cpu().numpy()[rows].view(np.uint16), ref[0])
+        np.testing.assert_array_equal(im.cpu().numpy()[rows].view(np.uint16), ref[1])
+    else:
+        np.testing.assert_array_equal(sc.cpu().numpy()[rows], ref[2])
+        np.testing.assert_array_equal(re.cpu().numpy()[rows], ref[0])
+        np.testing.assert_array_equal(im.cpu().numpy()[rows], ref[1])
+    v = plan.solve(g, 300).cpu().numpy()
+    v64 = A.Plan(H, p.Q, p.P, p.rho, p.lam).solve(g, 300).cpu().numpy()
+    assert rel(v, v64) <= {"bf16": 5e-3, "fp8": 5e-2}[storage]
+
+
+def test_full_size_adjoint_central_differences(torch_gpu, full):
+    import paper_1811_05571_amd as A
+    from tests.test_gpu_adjoint import _fd_check
+    p, H, g = full
+    K = 100
+    plan = A.Plan(H, p.Q, p.P, p.rho, p.lam)
+    ut = to_device(torch_gpu, p.u_true.astype(np.complex64))
+    v, tape = plan.solve_record(g, K, 10)
+    gg, dl, dr = plan.backward(g, 2 * (v - ut), tape)
+    gg = gg.cpu().numpy().astype(np.complex128)
+
+    def L(gvec=None, lam=None, pl=None):
+        pl = pl or plan
+        pl.set_lambda(p.lam if lam is None else lam)
+        vv = pl.solve(g if gvec is None else to_device(torch_gpu, gvec), K).cpu().numpy()
+        return float(np.sum(np.abs(vv.astype(np.complex128) - p.u_true) ** 2))
+
+    kinks = _fd_check(lambda x: L(lam=x), p.lam, 1e-3 * p.lam, dl, 0.0)
+    d = np.random.default_rng(1).standard_normal(p.m) + 1j * np.random.default_rng(2).standard_normal(p.m)
+    d /= np.linalg.norm(d)
+    kinks += _fd_check(lambda t: L(gvec=(p.g + t * d).astype(np.complex64)), 0.0, 1e-3 * np.linalg.norm(p.g),
+                       float(np.real(np.vdot(gg, d))), 1e-2 * np.linalg.norm(gg))
+    plans = {}
+
+    def Lr(r):
+        if r not in plans:
+            plans[r] = A.Plan(H, p.Q, p.P, r, p.lam)
+        return L(pl=plans[r])
+    kinks += _fd_check(Lr, p.rho, 1e-3 * p.rho, dr, 1e-6)
+    assert kinks <= 1

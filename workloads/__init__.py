@@ -224,3 +224,96 @@ FULL_IMAGING_RHO = 6.0
 def full_imaging(seed: int = 0, rho: float = FULL_IMAGING_RHO) -> Problem:
     """6144 x 32000 CRA-like consensus-and-sectioning workload (Q=4, P=8, 300 it)."""
     return cra_problem(seed=seed, rho=rho, name="cra6144x32000_Q4P8")
+
+
+# --------------------------------------------------------------------------
+# Batched scenes sharing one instrument matrix
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Batch:
+    """S scenes measured by one instrument.  H0 (m0 x n, complex64) is the
+    phase-free, row-normalised CRA-like matrix; its rows come in tiles of
+    `tile_rows` consecutive rows (one frequency each).  Scene s uses the
+    tiles `tiles[s]` (increasing) with one unit phase per row, so
+    H_s = diag(phases[s]) H0[rows of tiles[s], :]; its Q_s row blocks are cut
+    at the tile boundaries `cuts[s]` (tile units, 0 .. len(tiles[s]))."""
+    name: str
+    H0: np.ndarray
+    tile_rows: int
+    tiles: list
+    cuts: list
+    phases: list          # complex64 per scene row
+    g: list               # complex64 per scene
+    u_true: list          # complex128 per scene
+    lam: list
+    P: int
+    rho: float
+    iters: int
+
+    @property
+    def S(self) -> int:
+        return len(self.tiles)
+
+    def rows(self, s: int) -> np.ndarray:
+        t = np.asarray(self.tiles[s])
+        return (t[:, None] * self.tile_rows + np.arange(self.tile_rows)[None, :]).ravel()
+
+    def scene_H(self, s: int, H0=None) -> np.ndarray:
+        """H_s in complex128 from H0 (or from a given dequantised H0)."""
+        base = self.H0 if H0 is None else H0
+        return self.phases[s].astype(np.complex128)[:, None] * base[self.rows(s)].astype(np.complex128)
+
+    def row_off(self, s: int) -> np.ndarray:
+        return np.asarray(self.cuts[s], np.int64) * self.tile_rows
+
+
+def batch_scenes(S: int = 64, seed0: int = 1000, n_tx: int = 16, n_rx: int = 16, n_f: int = 24,
+                 nx: int = 40, ny: int = 40, nz: int = 20, f_min: int = 12, P: int = 8, rho: float = 6.0,
+                 lam_ratio: float = 0.02, snr_db: float = 25.0, iters: int = 300, q_choices=(2, 4, 8),
+                 patch=(15, 5), name: str | None = None) -> Batch:
+    """Scenes from the CRA-like generator that share the instrument.
+
+    H0: the phase-free (phi = 0), row-normalised matrix of the geometry.  Scene
+    s draws from seed seed0 + s, in order: the number of frequencies N_f in
+    U{f_min .. n_f}; a sorted random subset of that many frequency tiles;
+    Q_s in q_choices; Q_s - 1 distinct cuts among the N_f - 1 interior tile
+    boundaries; one phase per scene row; the target patches; the noise.
+    lambda_s = lam_ratio * max|H_s^H g_s| in FP64.
+    """
+    tx, rx, freqs, vox = cra_geometry(n_tx, n_rx, n_f, nx, ny, nz)
+    tile_rows = n_tx * n_rx
+    H0 = cra_matrix(tx, rx, freqs, vox, np.zeros(tile_rows * n_f))
+    m0, n = H0.shape
+    tiles, cuts, phases, gs, us = [], [], [], [], []
+    W = np.zeros((m0, S), dtype=np.complex128)     # conj(phase) * g at each scene's rows
+    for s in range(S):
+        rng = np.random.default_rng(seed0 + s)
+        nf = int(rng.integers(f_min, n_f + 1))
+        t = np.sort(rng.choice(n_f, size=nf, replace=False)).astype(np.int32)
+        Q = int(q_choices[rng.integers(0, len(q_choices))])
+        Q = min(Q, nf)
+        inner = np.sort(rng.choice(np.arange(1, nf), size=Q - 1, replace=False)) if Q > 1 else np.array([], int)
+        c = np.concatenate([[0], inner, [nf]]).astype(np.int32)
+        ph = np.exp(1j * rng.uniform(0.0, 2.0 * np.pi, size=nf * tile_rows)).astype(np.complex64)
+        u = _patch_target(rng, nx, ny, nz, patch[0], patch[1])
+        rows = (t[:, None] * tile_rows + np.arange(tile_rows)[None, :]).ravel()
+        nzc = np.nonzero(u)[0]
+        clean = ph.astype(np.complex128) * (H0[np.ix_(rows, nzc)].astype(np.complex128) @ u[nzc])
+        m = len(rows)
+        sigma2 = float(np.vdot(clean, clean).real) / (m * 10.0 ** (snr_db / 10.0))
+        w = (rng.standard_normal(m) + 1j * rng.standard_normal(m)) * np.sqrt(sigma2 / 2.0)
+        g = (clean + w).astype(np.complex64)
+        W[rows, s] = np.conj(ph.astype(np.complex128)) * g.astype(np.complex128)
+        tiles.append(t)
+        cuts.append(c)
+        phases.append(ph)
+        gs.append(g)
+        us.append(u)
+    # lambda_s = ratio * max_n |(H_s^H g_s)_n| with H_s = diag(phase) H0[rows]:
+    # all scenes at once as H0^H W, in FP64, streaming H0 in row chunks
+    Z = np.zeros((n, S), dtype=np.complex128)
+    for r0 in range(0, m0, 512):
+        Z += H0[r0:r0 + 512].astype(np.complex128).conj().T @ W[r0:r0 + 512]
+    lams = [float(lam_ratio * np.max(np.abs(Z[:, s]))) for s in range(S)]
+    return Batch(name or f"batch{S}_cra{tile_rows * n_f}x{H0.shape[1]}", H0, tile_rows, tiles, cuts, phases, gs,
+                 us, lams, P, rho, iters)
