@@ -45,13 +45,14 @@ def algorithmic_bytes(geo: dict, P: int, Q: int, KH: int, storage: str = "c64") 
     (not from counters).  Vectors are complex64 (8 B); H elements take
     ELEM_BYTES[storage] (+ 4 B per row of fp8 scales)."""
     m, n = geo["m"], geo["n"]
-    mi2 = geo["sum_mi2"]          # sum over blocks of m_i^2
+    ginv = geo["ginv_packed"]     # complex elements of the packed lower-tile inverses
+    gparts = geo["gram_parts"]    # 64-vectors of Gram-apply pieces (written once, read once)
     c = 8
     h = m * n * ELEM_BYTES[storage] + (4 * m * P if storage == "fp8" else 0)
     vec_rows = P * m * c          # one row-space vector (all column blocks)
     vec_cols = Q * n * c          # one column-space vector (all replicas)
     gemv_n = h + vec_cols + m * c + (P - 1) * vec_rows * (P > 1) + vec_rows * (2 if P > 1 else 1)
-    gram = mi2 * c + vec_rows * (4 if P > 1 else 3)
+    gram = ginv * c + 2 * gparts * 64 * c + vec_rows * (4 if P > 1 else 3)
     gemv_h = h + vec_rows + KH * vec_cols
     zupd = KH * vec_cols + 2 * vec_cols * 2 + 2 * n * c
     return {"k_gemv_n": gemv_n, "k_gram": gram, "k_gemv_h": gemv_h, "k_zupdate": zupd}
@@ -219,7 +220,10 @@ def main(argv=None):
     torch.cuda.synchronize()
 
     sizes = [prob.m // prob.Q + (1 if i < prob.m % prob.Q else 0) for i in range(prob.Q)]
-    geo = {"m": prob.m, "n": prob.n, "sum_mi2": int(sum(s * s for s in sizes) * prob.P)}
+    tiles = [(s_ + 63) // 64 for s_ in sizes]
+    geo = {"m": prob.m, "n": prob.n,
+           "ginv_packed": int(sum(T * (T + 1) // 2 * 4096 for T in tiles) * prob.P),
+           "gram_parts": int(sum(T * T for T in tiles) * prob.P)}
     workload = prob.name
 
     def measure(storage: str, steps: int, warmup: int):

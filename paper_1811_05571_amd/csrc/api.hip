@@ -125,7 +125,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
     return ADMM_EINVAL;
   }
   geo.blocks.clear();
-  int64_t hoff = 0, gioff = 0, foff = 0;
+  int64_t hoff = 0, gioff = 0, foff = 0, gpo = 0;
   int max_mi = 0;
   geo.max_mt = 0;
   for (int i = 0; i < Q; ++i)
@@ -158,8 +158,11 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
       d.h_off = hoff;
       d.gi_off = gioff;
       d.f_off = foff;
+      d.gpo = (int32_t)gpo;
       hoff += (int64_t)d.mi * d.ld;
-      gioff += (int64_t)d.mi * d.ldr;
+      const int64_t T = d.mt / kTile;
+      gioff += T * (T + 1) / 2 * kTile * kTile;
+      gpo += T * T;
       foff += (int64_t)d.mt * d.mt;
       max_mi = std::max(max_mi, d.mi);
       geo.max_mt = std::max(geo.max_mt, d.mt);
@@ -176,6 +179,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   geo.t_gram.clear();
   geo.t_kadj.clear();
   geo.t_hrows.clear();
+  geo.t_gtr.clear();
   const int cpl = cols_per_load(storage);
   int wg_per_chunk = 0;
   for (size_t b = 0; b < geo.blocks.size(); ++b) {
@@ -186,8 +190,10 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
     const int nl = (d.nj + cpl - 1) / cpl;
     wg_per_chunk += (nl + kColsPerWGLoads - 1) / kColsPerWGLoads;
     const int nt = d.mt / kTile;
-    for (int a = 0; a < nt; ++a)
+    for (int a = 0; a < nt; ++a) {
       for (int c = 0; c <= a; ++c) geo.t_gram.push_back(make_int4((int)b, a, c, 0));
+      geo.t_gtr.push_back(make_int4((int)b, a, 0, 0));
+    }
   }
   // Row chunks of the adjoint product: about 2048 workgroups in total, at
   // least 32 rows (8 per wave) per chunk.
@@ -246,6 +252,8 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   L.t_gram = take(16 * geo.t_gram.size());
   L.t_kadj = take(16 * geo.t_kadj.size());
   L.t_hrows = take(16 * geo.t_hrows.size());
+  L.t_gtr = take(16 * geo.t_gtr.size());
+  L.gpart = take((size_t)gpo * kTile * 8);
   L.ctl = take(sizeof(Control));
   L.redpart = take(8 * kRedCount * geo.t_z.size());
   L.row_block = take(8 * (size_t)m);
@@ -281,6 +289,8 @@ struct admm_plan {
   BlockDesc* d_blocks = nullptr;
   ColDesc* d_cols = nullptr;
   int4 *t_rows = nullptr, *t_cols = nullptr, *t_z = nullptr, *t_gram = nullptr, *t_kadj = nullptr, *t_hrows = nullptr;
+  int4* t_gtr = nullptr;
+  float2* gpart = nullptr;
   HStore hs{};
   Control* ctl = nullptr;
   double *redpart = nullptr, *kkt_max = nullptr;
@@ -364,6 +374,7 @@ IterArgs iter_args(admm_plan* p, const float2* g, double* hist) {
   a.ghat = p->ghat;
   a.r = p->r;
   a.y = p->y;
+  a.gpart = p->gpart;
   a.ctl = p->ctl;
   a.redpart = p->redpart;
   a.hist = hist;
@@ -505,6 +516,8 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   p->t_gram = at<int4>(p, L.t_gram);
   p->t_kadj = at<int4>(p, L.t_kadj);
   p->t_hrows = at<int4>(p, L.t_hrows);
+  p->t_gtr = at<int4>(p, L.t_gtr);
+  p->gpart = at<float2>(p, L.gpart);
   p->hs.storage = storage;
   p->hs.base = p->ws + L.H;
   p->hs.base_im = storage == ADMM_STORAGE_C64 ? nullptr : p->ws + L.H_im;
@@ -559,6 +572,7 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   SETUP_TRY(hipMemcpyAsync(p->t_gram, G.t_gram.data(), 16 * G.t_gram.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->t_kadj, G.t_kadj.data(), 16 * G.t_kadj.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->t_hrows, G.t_hrows.data(), 16 * G.t_hrows.size(), hipMemcpyHostToDevice, st));
+  SETUP_TRY(hipMemcpyAsync(p->t_gtr, G.t_gtr.data(), 16 * G.t_gtr.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->row_block, p->h_row_block.data(), 8 * (size_t)m, hipMemcpyHostToDevice, st));
   int max_mi = 0;
   for (auto& d : G.blocks) max_mi = std::max(max_mi, d.mi);
@@ -604,10 +618,11 @@ int admm_solve(admm_plan* p, const void* g, int iters, double tol, int check_eve
   const IterArgs a = iter_args(p, static_cast<const float2*>(g), resid_hist);
   const int nr = (int)G.t_rows.size(), nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
   const int nh = (int)G.t_hrows.size();
+  const int ngr = (int)G.t_gram.size(), ngt = (int)G.t_gtr.size();
   int done = 0;
   for (int k = 0; k < iters; ++k) {
     if ((rc = timed(p, ADMM_K_GEMV_N, st, [&] { return launch_gemv_n(a, p->t_hrows, nh, st); }))) return rc;
-    if ((rc = timed(p, ADMM_K_GRAM, st, [&] { return launch_gram(a, p->t_rows, nr, st); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GRAM, st, [&] { return launch_gram(a, p->t_gram, ngr, p->t_gtr, ngt, st); }))) return rc;
     if ((rc = timed(p, ADMM_K_GEMV_H, st, [&] { return launch_gemv_h(a, p->t_cols, nc, st); }))) return rc;
     if ((rc = timed(p, ADMM_K_ZUPDATE, st, [&] { return launch_zupdate(a, p->t_z, nz, st); }))) return rc;
     ++done;
@@ -659,6 +674,7 @@ int admm_solve_record(admm_plan* p, const void* g, int iters, int interval, void
   const IterArgs a = iter_args(p, static_cast<const float2*>(g), nullptr);
   const int nr = (int)G.t_rows.size(), nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
   const int nh = (int)G.t_hrows.size();
+  const int ngr = (int)G.t_gram.size(), ngt = (int)G.t_gtr.size();
   const size_t colv = (size_t)G.n_pad * 8, rowv = (size_t)G.m_pad * 8;
   for (int k = 0; k < iters; ++k) {
     if (k % interval == 0) {
@@ -668,7 +684,7 @@ int admm_solve_record(admm_plan* p, const void* g, int iters, int interval, void
       HIP_TRY(hipMemcpyAsync(ck + T.ghat, p->ghat, rowv * G.P, hipMemcpyDeviceToDevice, st));
     }
     if ((rc = timed(p, ADMM_K_GEMV_N, st, [&] { return launch_gemv_n(a, p->t_hrows, nh, st); }))) return rc;
-    if ((rc = timed(p, ADMM_K_GRAM, st, [&] { return launch_gram(a, p->t_rows, nr, st); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GRAM, st, [&] { return launch_gram(a, p->t_gram, ngr, p->t_gtr, ngt, st); }))) return rc;
     if ((rc = timed(p, ADMM_K_GEMV_H, st, [&] { return launch_gemv_h(a, p->t_cols, nc, st); }))) return rc;
     if ((rc = timed(p, ADMM_K_ZUPDATE, st, [&] { return launch_zupdate(a, p->t_z, nz, st); }))) return rc;
   }
@@ -732,6 +748,7 @@ int admm_backward(admm_plan* p, const void* g, const void* grad_v, const void* t
   b.yb = p->yb;
   b.rb = p->rb;
   b.part = p->part;
+  b.gpart = p->gpart;
   b.gbar = p->gbar;
   b.kpart = p->kpart;
   b.rpart = p->rpart;
@@ -746,6 +763,7 @@ int admm_backward(admm_plan* p, const void* g, const void* grad_v, const void* t
   b.cpl = a.cpl;
   const int nr = (int)G.t_rows.size(), nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
   const int nh = (int)G.t_hrows.size();
+  const int ngr = (int)G.t_gram.size(), ngt = (int)G.t_gtr.size();
   float2* yrec = reinterpret_cast<float2*>(const_cast<char*>(tp) + T.yrec);
   float2* arec = reinterpret_cast<float2*>(const_cast<char*>(tp) + T.arec);
   const size_t ystride = align256(rowv * G.P) / 8, astride = align256(colv) / 8;
@@ -760,12 +778,12 @@ int admm_backward(admm_plan* p, const void* g, const void* grad_v, const void* t
       a.y = yrec + ystride * (k - k0);
       a.arec = arec + astride * (k - k0);
       HIP_TRY(launch_gemv_n(a, p->t_hrows, nh, st));
-      HIP_TRY(launch_gram(a, p->t_rows, nr, st));
+      HIP_TRY(launch_gram(a, p->t_gram, ngr, p->t_gtr, ngt, st));
       HIP_TRY(launch_gemv_h(a, p->t_cols, nc, st));
       HIP_TRY(launch_zupdate(a, p->t_z, nz, st));
     }
     for (int k = k1 - 1; k >= k0; --k)
-      HIP_TRY(launch_adj_iteration(b, G, p->t_hrows, p->t_rows, p->t_cols, p->t_z, arec + astride * (k - k0),
+      HIP_TRY(launch_adj_iteration(b, G, p->t_hrows, p->t_gram, p->t_gtr, p->t_cols, p->t_z, arec + astride * (k - k0),
                                    yrec + ystride * (k - k0), st));
   }
   HIP_TRY(launch_adj_gflush(b, p->d_blocks, (int)G.blocks.size(), static_cast<float2*>(grad_g), st));

@@ -49,7 +49,8 @@ struct BatchGeo {
   std::vector<SceneTile> stab;        // grouped by tile f
   std::vector<int32_t> st_off;        // F+1
   std::vector<int32_t> cuts_flat, tiles_flat;
-  std::vector<int4> t_rows, t_z;
+  std::vector<int4> t_gram, t_gtr, t_z;
+  int64_t gpart_vecs = 0;
   std::vector<GemmItem> items_n[3], items_h[3];
   int64_t m_pad = 0, n_pad = 0, ldt = 0, mt0 = 0;
   int R = 0, NST = 0, max_nj = 0;
@@ -57,7 +58,7 @@ struct BatchGeo {
   size_t o_hre = 0, o_him = 0, o_tre = 0, o_tim = 0, o_ginv = 0, o_G0 = 0, o_A = 0, o_W = 0, group_bytes = 0;
   size_t o_c = 0, o_s = 0, o_v = 0, o_part = 0, o_gp = 0, o_ghat = 0, o_r = 0, o_y = 0, o_phase = 0;
   size_t o_pseudo = 0, o_cols = 0, o_blocks = 0, o_rbd = 0, o_scenes = 0, o_stab = 0, o_cuts = 0, o_tiles = 0;
-  size_t o_trows = 0, o_tz = 0, o_items_n[3] = {0, 0, 0}, o_items_h[3] = {0, 0, 0}, o_ctl = 0;
+  size_t o_tgram = 0, o_tgtr = 0, o_gpart = 0, o_tz = 0, o_items_n[3] = {0, 0, 0}, o_items_h[3] = {0, 0, 0}, o_ctl = 0;
   size_t o_gblocks = 0, o_ggram = 0, o_gtile0 = 0, g_max_blocks = 0, g_max_gram = 0, o_t0gram = 0;
   std::vector<int4> t0_gram;          // lower tiles of the pseudo blocks (G0)
   size_t total = 0;
@@ -163,7 +164,7 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
   G.scenes.clear();
   G.cuts_flat.clear();
   G.tiles_flat.clear();
-  int64_t rpad = 0, gioff = 0;
+  int64_t rpad = 0, gioff = 0, gpo = 0;
   int pslot = 0;
   std::vector<std::vector<SceneTile>> by_f(G.F);
   for (int s = 0; s < S; ++s) {
@@ -202,10 +203,13 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
         d.rpad0 = rb.rpad0;
         d.cpad0 = G.cols[j].cpad0;
         d.gi_off = gioff;
+        d.gpo = (int32_t)gpo;
         d.ld = 0;
         d.h_off = 0;
         d.f_off = 0;  // set per setup group
-        gioff += (int64_t)d.mi * d.ldr;
+        const int64_t T = d.mt / kTile;
+        gioff += T * (T + 1) / 2 * kTile * kTile;
+        gpo += T * T;
         G.blocks.push_back(d);
       }
       for (int sl = ca; sl < cb; ++sl) {
@@ -235,9 +239,16 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
   }
   G.st_off[G.F] = (int32_t)G.stab.size();
   // work tables
-  G.t_rows.clear();
-  for (size_t b = 0; b < G.blocks.size(); ++b)
-    for (int r = 0; r < G.blocks[b].mi; r += kRowsPerWG) G.t_rows.push_back(make_int4((int)b, r, 0, 0));
+  G.t_gram.clear();
+  G.t_gtr.clear();
+  for (size_t b = 0; b < G.blocks.size(); ++b) {
+    const int T = G.blocks[b].mt / kTile;
+    for (int a2 = 0; a2 < T; ++a2) {
+      for (int c2 = 0; c2 <= a2; ++c2) G.t_gram.push_back(make_int4((int)b, a2, c2, 0));
+      G.t_gtr.push_back(make_int4((int)b, a2, 0, 0));
+    }
+  }
+  G.gpart_vecs = gpo;
   G.t_z.clear();
   for (int s = 0; s < S; ++s)
     for (int j = 0; j < P; ++j)
@@ -315,7 +326,9 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
   G.o_stab = take(sizeof(SceneTile) * G.stab.size());
   G.o_cuts = take(4 * G.cuts_flat.size());
   G.o_tiles = take(4 * G.tiles_flat.size());
-  G.o_trows = take(16 * G.t_rows.size());
+  G.o_tgram = take(16 * G.t_gram.size());
+  G.o_tgtr = take(16 * G.t_gtr.size());
+  G.o_gpart = take((size_t)G.gpart_vecs * kTile * 8);
   G.o_tz = take(16 * G.t_z.size());
   for (int v = 0; v < 3; ++v) {
     G.o_items_n[v] = take(sizeof(GemmItem) * G.items_n[v].size());
@@ -399,6 +412,7 @@ IterArgs gram_args(admm_batch* b, const float2* g) {
   a.ghat = at<float2>(b, G.o_ghat);
   a.r = at<float2>(b, G.o_r);
   a.y = at<float2>(b, G.o_y);
+  a.gpart = at<float2>(b, G.o_gpart);
   a.ctl = at<Control>(b, G.o_ctl);
   a.m_pad = G.m_pad;
   a.n_pad = G.n_pad;
@@ -435,8 +449,10 @@ hipError_t launch_iteration(admm_batch* b, const float2* g, hipStream_t st, bool
                                kGemmVariants[b->var_n], st);
        })) != hipSuccess)
     return e;
-  if ((e = run(1, [&] { return launch_gram(ga, at<int4>(b, G.o_trows), (int)G.t_rows.size(), st); })) !=
-      hipSuccess)
+  if ((e = run(1, [&] {
+         return launch_gram(ga, at<int4>(b, G.o_tgram), (int)G.t_gram.size(), at<int4>(b, G.o_tgtr),
+                            (int)G.t_gtr.size(), st);
+       })) != hipSuccess)
     return e;
   if ((e = run(2, [&] {
          return launch_bgemm_h(a, at<GemmItem>(b, G.o_items_h[b->var_h]), (int)G.items_h[b->var_h].size(),
@@ -577,7 +593,8 @@ int admm_batch_setup(admm_batch** out, const void* H0, int64_t m0, int64_t n, in
   STRY(up(G.o_stab, G.stab.data(), sizeof(SceneTile) * G.stab.size()));
   STRY(up(G.o_cuts, G.cuts_flat.data(), 4 * G.cuts_flat.size()));
   STRY(up(G.o_tiles, G.tiles_flat.data(), 4 * G.tiles_flat.size()));
-  STRY(up(G.o_trows, G.t_rows.data(), 16 * G.t_rows.size()));
+  STRY(up(G.o_tgram, G.t_gram.data(), 16 * G.t_gram.size()));
+  STRY(up(G.o_tgtr, G.t_gtr.data(), 16 * G.t_gtr.size()));
   STRY(up(G.o_tz, G.t_z.data(), 16 * G.t_z.size()));
   for (int v = 0; v < 3; ++v) {
     STRY(up(G.o_items_n[v], G.items_n[v].data(), sizeof(GemmItem) * G.items_n[v].size()));

@@ -37,7 +37,9 @@ __host__ __device__ __forceinline__ int cperm(int col, int cpl) {
 // region they index.
 struct BlockDesc {
   int64_t h_off;    // H store: first element (complex) of the block
-  int64_t gi_off;   // inverse store (complex64): first element
+  int64_t gi_off;   // inverse store (complex64): first element of the block's
+                    // packed lower 64 x 64 tiles, tile (a, b), a >= b, at
+                    // gi_off + (a(a+1)/2 + b) * 4096, row-major, pads zero
   int64_t f_off;    // FP64 setup scratch (double2): first element
   int32_t i, j;     // row block, column block
   int32_t mi, nj;   // rows, columns
@@ -48,7 +50,7 @@ struct BlockDesc {
   int32_t col0;     // first global column
   int32_t rpad0;    // offset of row block i in padded row space
   int32_t cpad0;    // offset of column block j in padded column space
-  int32_t pad_;
+  int32_t gpo;      // Gram-apply partials: first of the block's (mt/64)^2 64-vectors
 };
 
 // Scalars of the per-iteration reduction (FP64).

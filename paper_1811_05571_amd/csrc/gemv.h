@@ -176,4 +176,115 @@ __device__ __forceinline__ void cols_partial(const F& f, const BlockDesc& d, con
   }
 }
 
+// One 64 x 64 tile G of a packed Hermitian matrix (lower tile (ta, tb),
+// ta >= tb) applied both ways: out_ab = G x_b and, off the diagonal,
+// out_ba = G^H x_a.  256 threads; thread (wave w, lane l) holds a 4 x 4
+// sub-block: rows 16w + 4(l >> 4) + {0..3} and columns {2b, 2b+1, 32+2b,
+// 33+2b} with b = l & 15, so each 16-byte load instruction of a wave reads
+// four contiguous 256-byte row segments.  Row sums close over the 16 lanes
+// of a row group by a reduce-scatter (xor 8, 4) and an all-reduce (xor 2, 1);
+// column sums close over the wave by a reduce-scatter (xor 32, 16) and over
+// the 4 waves through 2 KB of LDS, always in the same order.
+__device__ __forceinline__ void gram_tile_apply(const float2* __restrict__ G, const float2* __restrict__ xa,
+                                                const float2* __restrict__ xb, bool diag,
+                                                float2* __restrict__ out_ab, float2* __restrict__ out_ba,
+                                                float2 (&red)[4][64]) {
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, b = l & 15;
+  const int r0 = 16 * w + 4 * (l >> 4);
+  float4 h[4][2];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf)
+      h[rr][hf] = ldnt4(reinterpret_cast<const float4*>(G + (r0 + rr) * 64 + 32 * hf + 2 * b));
+  const float4 xb0 = *reinterpret_cast<const float4*>(xb + 2 * b);
+  const float4 xb1 = *reinterpret_cast<const float4*>(xb + 32 + 2 * b);
+  float pr[4], pi[4];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    pr[rr] = 0.f;
+    pi[rr] = 0.f;
+    cmac(pr[rr], pi[rr], h[rr][0].x, h[rr][0].y, xb0.x, xb0.y);
+    cmac(pr[rr], pi[rr], h[rr][0].z, h[rr][0].w, xb0.z, xb0.w);
+    cmac(pr[rr], pi[rr], h[rr][1].x, h[rr][1].y, xb1.x, xb1.y);
+    cmac(pr[rr], pi[rr], h[rr][1].z, h[rr][1].w, xb1.z, xb1.w);
+  }
+  {
+    // xor 8: keep rows {2s, 2s+1}, s = bit 3 of the lane
+    const bool s = (l & 8) != 0;
+    float k0r = s ? pr[2] : pr[0], k0i = s ? pi[2] : pi[0];
+    float k1r = s ? pr[3] : pr[1], k1i = s ? pi[3] : pi[1];
+    const float o0r = s ? pr[0] : pr[2], o0i = s ? pi[0] : pi[2];
+    const float o1r = s ? pr[1] : pr[3], o1i = s ? pi[1] : pi[3];
+    k0r += __shfl_xor(o0r, 8, kWave);
+    k0i += __shfl_xor(o0i, 8, kWave);
+    k1r += __shfl_xor(o1r, 8, kWave);
+    k1i += __shfl_xor(o1i, 8, kWave);
+    // xor 4: keep row 2s + t, t = bit 2
+    const bool t = (l & 4) != 0;
+    float rr_ = t ? k1r : k0r, ri_ = t ? k1i : k0i;
+    rr_ += __shfl_xor(t ? k0r : k1r, 4, kWave);
+    ri_ += __shfl_xor(t ? k0i : k1i, 4, kWave);
+    rr_ += __shfl_xor(rr_, 2, kWave);
+    ri_ += __shfl_xor(ri_, 2, kWave);
+    rr_ += __shfl_xor(rr_, 1, kWave);
+    ri_ += __shfl_xor(ri_, 1, kWave);
+    if ((l & 3) == 0) out_ab[r0 + 2 * (int)s + (int)t] = make_float2(rr_, ri_);
+  }
+  if (diag) return;
+  const float4 xa0 = *reinterpret_cast<const float4*>(xa + r0);
+  const float4 xa1 = *reinterpret_cast<const float4*>(xa + r0 + 2);
+  const float xr[4] = {xa0.x, xa0.z, xa1.x, xa1.z}, xi[4] = {xa0.y, xa0.w, xa1.y, xa1.w};
+  // column slot k: 0 -> 2b, 1 -> 2b+1, 2 -> 32+2b, 3 -> 33+2b
+  float cr[4] = {0.f, 0.f, 0.f, 0.f}, ci[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    cmacc(cr[0], ci[0], h[rr][0].x, h[rr][0].y, xr[rr], xi[rr]);
+    cmacc(cr[1], ci[1], h[rr][0].z, h[rr][0].w, xr[rr], xi[rr]);
+    cmacc(cr[2], ci[2], h[rr][1].x, h[rr][1].y, xr[rr], xi[rr]);
+    cmacc(cr[3], ci[3], h[rr][1].z, h[rr][1].w, xr[rr], xi[rr]);
+  }
+  // xor 32: keep slots {2u, 2u+1}, u = bit 5
+  const bool u = (l & 32) != 0;
+  float k0r = u ? cr[2] : cr[0], k0i = u ? ci[2] : ci[0];
+  float k1r = u ? cr[3] : cr[1], k1i = u ? ci[3] : ci[1];
+  const float o0r = u ? cr[0] : cr[2], o0i = u ? ci[0] : ci[2];
+  const float o1r = u ? cr[1] : cr[3], o1i = u ? ci[1] : ci[3];
+  k0r += __shfl_xor(o0r, 32, kWave);
+  k0i += __shfl_xor(o0i, 32, kWave);
+  k1r += __shfl_xor(o1r, 32, kWave);
+  k1i += __shfl_xor(o1i, 32, kWave);
+  // xor 16: keep slot 2u + v, v = bit 4, i.e. column 32u + 2b + v
+  const bool v = (l & 16) != 0;
+  float sr = v ? k1r : k0r, si = v ? k1i : k0i;
+  sr += __shfl_xor(v ? k0r : k1r, 16, kWave);
+  si += __shfl_xor(v ? k0i : k1i, 16, kWave);
+  red[w][32 * (int)u + 2 * b + (int)v] = make_float2(sr, si);
+  __syncthreads();
+  if (tid < 64) {
+    const float2 q0 = red[0][tid], q1 = red[1][tid], q2 = red[2][tid], q3 = red[3][tid];
+    out_ba[tid] = make_float2(((q0.x + q1.x) + q2.x) + q3.x, ((q0.y + q1.y) + q2.y) + q3.y);
+  }
+}
+
+// Sum of T strided complex partials in index order (loads issued four at a
+// time; the additions keep the sequential order).
+__device__ __forceinline__ float2 ordered_sum(const float2* __restrict__ p, int T, int64_t stride) {
+  float ar = 0.f, ai = 0.f;
+  int k = 0;
+  for (; k + 4 <= T; k += 4) {
+    const float2 q0 = p[(int64_t)k * stride], q1 = p[(int64_t)(k + 1) * stride];
+    const float2 q2 = p[(int64_t)(k + 2) * stride], q3 = p[(int64_t)(k + 3) * stride];
+    ar += q0.x; ai += q0.y;
+    ar += q1.x; ai += q1.y;
+    ar += q2.x; ai += q2.y;
+    ar += q3.x; ai += q3.y;
+  }
+  for (; k < T; ++k) {
+    const float2 q = p[(int64_t)k * stride];
+    ar += q.x; ai += q.y;
+  }
+  return make_float2(ar, ai);
+}
+
 }  // namespace admm

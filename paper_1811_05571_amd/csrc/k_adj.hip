@@ -137,34 +137,38 @@ __global__ __launch_bounds__(kBlockThreads) void k_adj_rows(AdjArgs a, const int
   }
 }
 
-// rb_ij = G_ij^{-1} yb_ij, gpb_ij = ghb_ij + rb_ij, rho_b += -Re(gpb^H y).
-__global__ __launch_bounds__(kBlockThreads) void k_adj_gram(AdjArgs a, const int4* __restrict__ tiles,
-                                                            const float2* __restrict__ yrec) {
-  const FmtC64 f{a.Ginv};
+// rb_ij = G_ij^{-1} yb_ij over the packed tiles (pieces), then per row:
+// gpb_ij = ghb_ij + rb_ij, rho_b += -Re(gpb^H y).
+__global__ __launch_bounds__(kBlockThreads) void k_adj_gram_tile(AdjArgs a, const int4* __restrict__ tiles) {
+  __shared__ float2 tt[4][64];
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = a.blocks[t.x];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int row = t.y + wave * kRowsPerWave;
+  const int T = d.mt / kTile;
+  const float2* G = a.Ginv + d.gi_off + (int64_t)(t.y * (t.y + 1) / 2 + t.z) * (kTile * kTile);
+  const float2* x = a.yb + (int64_t)d.j * a.m_pad + d.rpad0;
+  float2* part = a.gpart + (int64_t)d.gpo * kTile;
+  gram_tile_apply(G, x + t.y * kTile, x + t.z * kTile, t.y == t.z, part + (int64_t)(t.y * T + t.z) * kTile,
+                  part + (int64_t)(t.z * T + t.y) * kTile, tt);
+}
+
+__global__ __launch_bounds__(kTile) void k_adj_gram_reduce(AdjArgs a, const int4* __restrict__ tiles,
+                                                           const float2* __restrict__ yrec) {
+  const int4 t = tiles[blockIdx.x];
+  const BlockDesc d = a.blocks[t.x];
+  const int T = d.mt / kTile;
+  const int row = t.y * kTile + threadIdx.x;
   double rhob = 0.0;
   if (row < d.mi) {
-    const int nvalid = min(kRowsPerWave, d.mi - row);
-    const int64_t seg = (int64_t)d.j * a.m_pad + d.rpad0;
-    const float4* x = reinterpret_cast<const float4*>(a.yb + seg);
-    float acc[kRowsPerWave][2];
-    rows_dot<FmtC64, kRowsPerWave, 4>(f, d.gi_off + (int64_t)row * d.ldr, d.ldr, nvalid, x, (d.mi + 1) / 2, acc);
-    if (lane < nvalid) {
-      float ar = 0.f, ai = 0.f;
-#pragma unroll
-      for (int rr = 0; rr < kRowsPerWave; ++rr)
-        if (rr == lane) { ar = acc[rr][0]; ai = acc[rr][1]; }
-      const int64_t vi = seg + row + lane;
-      a.rb[vi] = make_float2(ar, ai);
-      const float2 gh = a.ghb[vi];
-      const float gr = gh.x + ar, gi = gh.y + ai;
-      a.gpb[vi] = make_float2(gr, gi);
-      const float2 y = yrec[vi];
-      rhob = -((double)gr * y.x + (double)gi * y.y);
-    }
+    const float2* part = a.gpart + ((int64_t)d.gpo + (int64_t)t.y * T) * kTile + threadIdx.x;
+    const float2 q = ordered_sum(part, T, kTile);
+    const float ar = q.x, ai = q.y;
+    const int64_t vi = (int64_t)d.j * a.m_pad + d.rpad0 + row;
+    a.rb[vi] = make_float2(ar, ai);
+    const float2 gh = a.ghb[vi];
+    const float gr = gh.x + ar, gi = gh.y + ai;
+    a.gpb[vi] = make_float2(gr, gi);
+    const float2 y = yrec[vi];
+    rhob = -((double)gr * y.x + (double)gi * y.y);
   }
   ticket_accumulate(rhob, a.rpart, &a.ctl->adj_ticket_r, &a.ctl->rbar);
 }
@@ -220,10 +224,11 @@ __global__ void k_adj_gflush(AdjArgs a, const BlockDesc* __restrict__ blocks, in
   }
 }
 
-hipError_t launch_adj_iteration(const AdjArgs& a, const Geometry& G, const int4* t_hrows, const int4* t_rows,
-                                const int4* t_cols, const int4* t_z, const float2* arec, const float2* yrec,
-                                hipStream_t st) {
-  const int nr = (int)G.t_rows.size(), nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
+hipError_t launch_adj_iteration(const AdjArgs& a, const Geometry& G, const int4* t_hrows, const int4* t_gram,
+                                const int4* t_gtr, const int4* t_cols, const int4* t_z, const float2* arec,
+                                const float2* yrec, hipStream_t st) {
+  const int nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
+  const int ng = (int)G.t_gram.size(), ngt = (int)G.t_gtr.size();
   const int nh = (int)G.t_hrows.size();
   hipLaunchKernelGGL(k_adj_z, dim3(nz), dim3(kZCols), 0, st, a, t_z, arec);
   switch (a.hs.storage) {
@@ -231,7 +236,8 @@ hipError_t launch_adj_iteration(const AdjArgs& a, const Geometry& G, const int4*
     case 1: hipLaunchKernelGGL(k_adj_rows<FmtBF16>, dim3(nh), dim3(kBlockThreads), 0, st, a, t_hrows); break;
     default: hipLaunchKernelGGL(k_adj_rows<FmtFP8>, dim3(nh), dim3(kBlockThreads), 0, st, a, t_hrows); break;
   }
-  hipLaunchKernelGGL(k_adj_gram, dim3(nr), dim3(kBlockThreads), 0, st, a, t_rows, yrec);
+  hipLaunchKernelGGL(k_adj_gram_tile, dim3(ng), dim3(kBlockThreads), 0, st, a, t_gram);
+  hipLaunchKernelGGL(k_adj_gram_reduce, dim3(ngt), dim3(kTile), 0, st, a, t_gtr, yrec);
   switch (a.hs.storage) {
     case 0: hipLaunchKernelGGL(k_adj_cols<FmtC64>, dim3(nc), dim3(kBlockThreads), 0, st, a, t_cols); break;
     case 1: hipLaunchKernelGGL(k_adj_cols<FmtBF16>, dim3(nc), dim3(kBlockThreads), 0, st, a, t_cols); break;

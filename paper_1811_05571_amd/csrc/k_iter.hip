@@ -8,10 +8,11 @@
 //     u_j^i = c + H_ij^H y_ij,   y_ij = G_ij^{-1} (g'_ij - H_ij c)
 // and the estimated data needs no third product:
 //     ghat_ij = H_ij u_j^i = g'_ij - rho y_ij.
-// One iteration is four launches:
+// One iteration is five launches:
 //   gemv_n  : r_ij = g'_ij - H_ij c_j^i  (and g'_ij from the estimated data,
 //             eq. g_rows_columns, as g_i minus the other sections' ghat)
-//   gram    : y_ij = G_ij^{-1} r_ij,  ghat_ij = g'_ij - rho y_ij
+//   gram    : y_ij = G_ij^{-1} r_ij (packed Hermitian tiles, two launches),
+//             ghat_ij = g'_ij - rho y_ij
 //   gemv_h  : row-chunk partials of H_ij^H y_ij
 //   zupdate : u = c + sum of partials, v = S_kappa(mean_i(u + s)), kappa =
 //             lambda/(Q rho) (eq. v_variable_rows_columns), s += u - v
@@ -64,31 +65,37 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4
   }
 }
 
-// y_ij = G_ij^{-1} r_ij (row-parallel over the stored Hermitian inverse) and
-// ghat_ij = g'_ij - rho y_ij.
-__global__ __launch_bounds__(kBlockThreads) void k_gram(IterArgs a, const int4* __restrict__ tiles) {
-  const FmtC64 f{a.Ginv};
+// y_ij = G_ij^{-1} r_ij over the packed lower tiles of the inverse: every
+// tile is read once and contributes to two 64-row pieces of y (gram_tile_apply);
+// k_gram_reduce adds the pieces in tile order and forms ghat_ij = g'_ij - rho y_ij.
+// tiles[x] = {block, tile row, tile col, -} (lower pairs).
+__global__ __launch_bounds__(kBlockThreads) void k_gram_tile(IterArgs a, const int4* __restrict__ tiles) {
+  __shared__ float2 tt[4][64];
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = a.blocks[t.x];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int row = t.y + wave * kRowsPerWave;
+  const int T = d.mt / kTile;
+  const float2* G = a.Ginv + d.gi_off + (int64_t)(t.y * (t.y + 1) / 2 + t.z) * (kTile * kTile);
+  const float2* x = a.r + (int64_t)d.j * a.m_pad + d.rpad0;
+  float2* part = a.gpart + (int64_t)d.gpo * kTile;
+  gram_tile_apply(G, x + t.y * kTile, x + t.z * kTile, t.y == t.z, part + (int64_t)(t.y * T + t.z) * kTile,
+                  part + (int64_t)(t.z * T + t.y) * kTile, tt);
+}
+
+// tiles[x] = {block, tile row, -, -}; 64 threads, one row each.
+__global__ __launch_bounds__(kTile) void k_gram_reduce(IterArgs a, const int4* __restrict__ tiles) {
+  const int4 t = tiles[blockIdx.x];
+  const BlockDesc d = a.blocks[t.x];
+  const int T = d.mt / kTile;
+  const int row = t.y * kTile + threadIdx.x;
   if (row >= d.mi) return;
-  const int nvalid = min(kRowsPerWave, d.mi - row);
-  const int64_t seg = (int64_t)d.j * a.m_pad + d.rpad0;
-  const float4* x = reinterpret_cast<const float4*>(a.r + seg);
-  float acc[kRowsPerWave][2];
-  rows_dot<FmtC64, kRowsPerWave, 4>(f, d.gi_off + (int64_t)row * d.ldr, d.ldr, nvalid, x, (d.mi + 1) / 2, acc);
-  if (lane < nvalid) {
-    float ar = 0.f, ai = 0.f;
-#pragma unroll
-    for (int rr = 0; rr < kRowsPerWave; ++rr)
-      if (rr == lane) { ar = acc[rr][0]; ai = acc[rr][1]; }
-    const int64_t vi = seg + row + lane;
-    a.y[vi] = make_float2(ar, ai);
-    // With one column block g'_ij is g_i itself and was not stored.
-    const float2 gpv = (a.P > 1) ? a.gp[vi] : a.g[d.row0 + row + lane];
-    a.ghat[vi] = make_float2(fmaf(-a.rho, ar, gpv.x), fmaf(-a.rho, ai, gpv.y));
-  }
+  const float2* part = a.gpart + ((int64_t)d.gpo + (int64_t)t.y * T) * kTile + threadIdx.x;
+  const float2 q = ordered_sum(part, T, kTile);
+  const float ar = q.x, ai = q.y;
+  const int64_t vi = (int64_t)d.j * a.m_pad + d.rpad0 + row;
+  a.y[vi] = make_float2(ar, ai);
+  // With one column block g'_ij is g_i itself and was not stored.
+  const float2 gpv = (a.P > 1) ? a.gp[vi] : a.g[d.row0 + row];
+  a.ghat[vi] = make_float2(fmaf(-a.rho, ar, gpv.x), fmaf(-a.rho, ai, gpv.y));
 }
 
 // Partial adjoint products: part[chunk][i][col] = sum over the chunk's rows
@@ -281,8 +288,12 @@ hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipSt
   }
   return hipGetLastError();
 }
-hipError_t launch_gram(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles);
+hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gtr, int n_gtr,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_gram_tile, dim3(n_gram), dim3(kBlockThreads), 0, st, a, t_gram);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_reduce, dim3(n_gtr), dim3(kTile), 0, st, a, t_gtr);
   return hipGetLastError();
 }
 hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st) {

@@ -450,9 +450,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_trtri_off(int dist, const Blo
       C[(int64_t)(tr + 16 * p) * d.mt + tc + 16 * q] = make_double2(-acc[p][q].x, -acc[p][q].y);
 }
 
-// G^{-1} = W^H W: tile (i,l), l <= i, = sum_{k>=i} W[k,i]^H W[k,l]; written as
-// complex64 to (i,l) and, conjugate-transposed, to (l,i).  Only the block's
-// mi x mi part is stored.  tiles[x] = {block, i, l, -}.
+// G^{-1} = W^H W: tile (i,l), l <= i, = sum_{k>=i} W[k,i]^H W[k,l], written as
+// complex64 to the block's packed lower-tile store (entries outside the
+// block's mi x mi part are zero).  tiles[x] = {block, i, l, -}.
 __global__ __launch_bounds__(kBlockThreads) void k_lauum(const int4* __restrict__ tiles,
                                                          const BlockDesc* __restrict__ blocks,
                                                          const double2* __restrict__ W,
@@ -468,16 +468,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_lauum(const int4* __restrict_
     tile_product<true, false>(sm, Wb + (int64_t)(k * T) * d.mt + i * T, Wb + (int64_t)(k * T) * d.mt + l * T,
                               d.mt, acc);
   const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
-  float2* G = Ginv + d.gi_off;
+  float2* G = Ginv + d.gi_off + (int64_t)(i * (i + 1) / 2 + l) * (T * T);
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int r = i * T + tr + 16 * p, c = l * T + tc + 16 * q;
-      if (r < d.mi && c < d.mi) {
-        G[(int64_t)r * d.ldr + c] = make_float2((float)acc[p][q].x, (float)acc[p][q].y);
-        if (i != l) G[(int64_t)c * d.ldr + r] = make_float2((float)acc[p][q].x, -(float)acc[p][q].y);
-      }
+      const int rr = tr + 16 * p, cc = tc + 16 * q;
+      const bool in = i * T + rr < d.mi && l * T + cc < d.mi;
+      G[rr * T + cc] = in ? make_float2((float)acc[p][q].x, (float)acc[p][q].y) : make_float2(0.f, 0.f);
     }
 }
 

@@ -17,7 +17,8 @@ struct ColDesc {       // one column block j
 struct Layout {
   size_t H = 0, H_im = 0, H_scale = 0, Ginv = 0, F64a = 0, F64b = 0;
   size_t c = 0, s = 0, v = 0, part = 0, gp = 0, ghat = 0, r = 0, y = 0;
-  size_t blocks = 0, cols = 0, t_rows = 0, t_cols = 0, t_z = 0, t_gram = 0, t_kadj = 0, t_hrows = 0;
+  size_t blocks = 0, cols = 0, t_rows = 0, t_cols = 0, t_z = 0, t_gram = 0, t_kadj = 0, t_hrows = 0, t_gtr = 0;
+  size_t gpart = 0;
   size_t ctl = 0, redpart = 0, row_block = 0, kkt_e = 0, kkt_v = 0, kkt_part = 0, kkt_max = 0;
   size_t vb = 0, sb = 0, ub = 0, ghb = 0, gpb = 0, yb = 0, rb = 0, gbar = 0, kpart = 0, rpart = 0;
   size_t total = 0;
@@ -33,7 +34,7 @@ struct Geometry {
   int64_t m_pad = 0, n_pad = 0;    // padded row / column space lengths
   int KH = 1;                      // row chunks of the adjoint product
   int max_mt = 0;                  // largest tile-padded block edge
-  std::vector<int4> t_rows, t_cols, t_z, t_gram, t_kadj, t_hrows;
+  std::vector<int4> t_rows, t_cols, t_z, t_gram, t_kadj, t_hrows, t_gtr;
   Layout lay;
 };
 
@@ -63,6 +64,7 @@ struct IterArgs {
   const float2* Ginv;
   const float2* g;      // caller's measurements
   float2 *c, *s, *v, *part, *gp, *ghat, *r, *y;
+  float2* gpart;        // Gram-apply pieces (BlockDesc::gpo)
   Control* ctl;
   double* redpart;
   double* hist;         // device, 2 per iteration, or null
@@ -80,7 +82,7 @@ struct AdjArgs {
   const ColDesc* cols;
   HStore hs;
   const float2* Ginv;
-  float2 *vb, *sb, *ub, *ghb, *gpb, *yb, *rb, *part;
+  float2 *vb, *sb, *ub, *ghb, *gpb, *yb, *rb, *part, *gpart;
   double2* gbar;
   double *kpart, *rpart;
   Control* ctl;
@@ -89,14 +91,15 @@ struct AdjArgs {
   float rho, kappa;
   int cpl;              // layout of ub (see cperm)
 };
-hipError_t launch_adj_iteration(const AdjArgs& a, const Geometry& G, const int4* t_hrows, const int4* t_rows,
-                                const int4* t_cols, const int4* t_z, const float2* arec, const float2* yrec,
-                                hipStream_t st);
+hipError_t launch_adj_iteration(const AdjArgs& a, const Geometry& G, const int4* t_hrows, const int4* t_gram,
+                                const int4* t_gtr, const int4* t_cols, const int4* t_z, const float2* arec,
+                                const float2* yrec, hipStream_t st);
 hipError_t launch_adj_gflush(const AdjArgs& a, const BlockDesc* blocks, int nblocks, float2* grad_g,
                              hipStream_t st);
 
 hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st);
-hipError_t launch_gram(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st);
+hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gtr, int n_gtr,
+                       hipStream_t st);
 hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st);
 hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st);
 hipError_t launch_unpad_cols(const ColDesc* cols, int P, int64_t n, const float2* src, float2* dst,

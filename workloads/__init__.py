@@ -276,14 +276,19 @@ def batch_scenes(S: int = 64, seed0: int = 1000, n_tx: int = 16, n_rx: int = 16,
     H0: the phase-free (phi = 0), row-normalised matrix of the geometry.  Scene
     s draws from seed seed0 + s, in order: the number of frequencies N_f in
     U{f_min .. n_f}; a sorted random subset of that many frequency tiles;
-    Q_s in q_choices; Q_s - 1 distinct cuts among the N_f - 1 interior tile
-    boundaries; one phase per scene row; the target patches; the noise.
+    Q_s in q_choices (raised if needed so that blocks can stay narrow);
+    Q_s - 1 distinct cuts among the N_f - 1 interior tile boundaries, redrawn
+    until every row block has fewer rows than a column block has columns (the
+    inversion-lemma x-update); one phase per scene row; the target patches;
+    the noise.
     lambda_s = lam_ratio * max|H_s^H g_s| in FP64.
     """
     tx, rx, freqs, vox = cra_geometry(n_tx, n_rx, n_f, nx, ny, nz)
     tile_rows = n_tx * n_rx
     H0 = cra_matrix(tx, rx, freqs, vox, np.zeros(tile_rows * n_f))
     m0, n = H0.shape
+    # widest row block (in tiles) that stays narrower than the narrowest column block
+    max_tiles = max(1, (n // P - 1) // tile_rows)
     tiles, cuts, phases, gs, us = [], [], [], [], []
     W = np.zeros((m0, S), dtype=np.complex128)     # conj(phase) * g at each scene's rows
     for s in range(S):
@@ -291,9 +296,13 @@ def batch_scenes(S: int = 64, seed0: int = 1000, n_tx: int = 16, n_rx: int = 16,
         nf = int(rng.integers(f_min, n_f + 1))
         t = np.sort(rng.choice(n_f, size=nf, replace=False)).astype(np.int32)
         Q = int(q_choices[rng.integers(0, len(q_choices))])
+        Q = max(Q, -(-nf // max_tiles))
         Q = min(Q, nf)
-        inner = np.sort(rng.choice(np.arange(1, nf), size=Q - 1, replace=False)) if Q > 1 else np.array([], int)
-        c = np.concatenate([[0], inner, [nf]]).astype(np.int32)
+        while True:   # cuts redrawn until every row block is narrower than its column block
+            inner = np.sort(rng.choice(np.arange(1, nf), size=Q - 1, replace=False)) if Q > 1 else np.array([], int)
+            c = np.concatenate([[0], inner, [nf]]).astype(np.int32)
+            if np.max(np.diff(c)) <= max_tiles:
+                break
         ph = np.exp(1j * rng.uniform(0.0, 2.0 * np.pi, size=nf * tile_rows)).astype(np.complex64)
         u = _patch_target(rng, nx, ny, nz, patch[0], patch[1])
         rows = (t[:, None] * tile_rows + np.arange(tile_rows)[None, :]).ravel()
