@@ -29,12 +29,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+PROFILE_EVERY = 10      # kernel events on every 10th iteration of the timed region
 PROFILES = os.path.join(ROOT, "profiles")
 
 
+ITER_SOURCES = ("k_iter.hip", "gemv.h", "hstore.h", "common.h", "plan.h")
+
+
 def kernel_source_hash() -> str:
-    src = os.path.join(ROOT, "paper_1811_05571_amd", "csrc", "k_iter.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    """Hash of the sources the per-iteration kernels are compiled from; a
+    counter summary taken on other sources is not used."""
+    h = hashlib.sha256()
+    for f in ITER_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1811_05571_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 ELEM_BYTES = {"c64": 8, "bf16": 4, "fp8": 2}   # stored bytes per complex element of H
@@ -72,6 +80,90 @@ def load_traffic(kernel: str, workload: str):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
+
+
+COPY_PROBE_KERNEL = "neg_kernel"   # torch's elementwise negation: reads and writes N bytes
+# per-iteration kernels as named in the counter output -> bench names, per storage
+TRACE_NAMES = {
+    "c64": {"k_gemv_n<FmtC64>": "k_gemv_n", "k_gemv_h<FmtC64>": "k_gemv_h"},
+    "bf16": {"k_gemv_n<FmtBF16>": "k_gemv_n", "k_gemv_h<FmtBF16>": "k_gemv_h"},
+    "fp8": {"k_gemv_n<FmtFP8>": "k_gemv_n", "k_gemv_h<FmtFP8>": "k_gemv_h"},
+}
+SHARED_NAMES = {"k_gram_tile": "k_gram", "k_gram_reduce": "k_gram", "k_zupdate<4>": "k_zupdate"}
+
+
+def _short_kernel(name: str) -> str:
+    n = name.replace("admm::(anonymous namespace)::", "").replace("admm::", "").replace("void ", "")
+    return n.split("(")[0].strip()
+
+
+def read_counter_csv(path: str, counter: str) -> dict:
+    """rocprofv3 --pmc csv -> {short kernel name: [KiB per dispatch, ...]}."""
+    import csv
+    per = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            key = (row["Dispatch_Id"], row["Kernel_Name"])
+            per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    out = {}
+    for (_, kname), val in per.items():
+        out.setdefault(_short_kernel(kname), []).append(val)
+    return out
+
+
+def summarise_traffic(fetch_csv: str, write_csv: str, probe_mib: int, workload: str, command: str):
+    """Writes profiles/traffic_<workload>_<storage>.json from a FETCH_SIZE and
+    a WRITE_SIZE counter run, each scaled by what the counter reads for the
+    copy probe (probe_mib MiB read and written)."""
+    fetch = read_counter_csv(fetch_csv, "FETCH_SIZE")
+    write = read_counter_csv(write_csv, "WRITE_SIZE")
+    probe = [k for k in fetch if COPY_PROBE_KERNEL in k]
+    if len(probe) != 1:
+        raise SystemExit(f"copy probe kernel not found once in {fetch_csv}: {probe}")
+    pk = probe[0]
+    kib = probe_mib * 1024.0
+    f_fac = kib / float(np.mean(fetch[pk]))
+    w_fac = kib / float(np.mean(write[pk]))
+    written = []
+    for storage, names in TRACE_NAMES.items():
+        kern = {}
+        for src, dst in list(names.items()) + list(SHARED_NAMES.items()):
+            if src not in fetch or src not in write:
+                continue
+            fb = float(np.mean(fetch[src])) * 1024.0 * f_fac
+            wb = float(np.mean(write[src])) * 1024.0 * w_fac
+            k = kern.setdefault(dst, {"fetch_bytes": 0.0, "write_bytes": 0.0, "parts": []})
+            k["fetch_bytes"] += fb
+            k["write_bytes"] += wb
+            k["parts"].append({"kernel": src, "dispatches": len(fetch[src]), "fetch_kib_raw": float(np.mean(fetch[src])),
+                               "write_kib_raw": float(np.mean(write[src]))})
+        if not any(n in kern for n in ("k_gemv_n", "k_gemv_h")):
+            continue
+        for k in kern.values():
+            k["bytes_per_launch"] = int(round(k["fetch_bytes"] + k["write_bytes"]))
+        rec = {"workload": f"{workload}_{storage}", "kernel_source_sha256_16": kernel_source_hash(),
+               "copy_probe": {"kernel": pk, "mib": probe_mib, "fetch_factor": f_fac, "write_factor": w_fac,
+                              "fetch_kib_raw": float(np.mean(fetch[pk])), "write_kib_raw": float(np.mean(write[pk]))},
+               "command": command, "kernels": kern}
+        path = os.path.join(PROFILES, f"traffic_{workload}_{storage}.json")
+        with open(path, "w") as f:
+            json.dump(rec, f, indent=1)
+        written.append(path)
+    return written
+
+
+def copy_probe(torch, dev, mib: int, reps: int = 3):
+    """A plain elementwise copy of known size (N bytes read, N written) that
+    calibrates the memory counters."""
+    n = mib * 1024 * 1024 // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def cpu_baseline(prob, n_iter: int):
@@ -159,21 +251,28 @@ def bench_batch(args, torch, A, W, dev):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plan = A.Plan(Hs, len(b.cuts[s]) - 1, b.P, b.rho, b.lam[s], b.row_off(s))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         vs = plan.solve(gs, K)
         torch.cuda.synchronize()
-        seq.append((time.perf_counter() - t0, float(np.linalg.norm(vs.cpu().numpy() - b.u_true[s]) ** 2 /
-                                                   np.linalg.norm(b.u_true[s]) ** 2)))
+        t2 = time.perf_counter()
+        seq.append((t2 - t0, float(np.linalg.norm(vs.cpu().numpy() - b.u_true[s]) ** 2 /
+                                   np.linalg.norm(b.u_true[s]) ** 2), t2 - t1))
         plan.close()
         del Hs, plan
     seq_t = float(np.mean([x[0] for x in seq]))
+    seq_it = float(np.mean([x[2] for x in seq]))
     res = {
-        "workload": b.name, "scenes": b.S, "iters": K, "value": round(b.S / el, 2), "unit": "scenes/s",
+        "workload": b.name, "scenes": b.S, "iters": K, "value": round(b.S / el, 2),
+        "unit": "scenes/s (300 iterations each, setup apart)",
+        "value_with_setup": round(b.S / (el + setup_s), 2),
         "ms_per_batched_iteration": round(el / K * 1e3, 3), "setup_s": round(setup_s, 2),
         "scene_tiles": NST, "tile_widths": [info["tile_n"], info["tile_h"]], "autotune": bb.tuning(),
         "kernels": kern, "ginv_gb": round(info["ginv_bytes"] / 1e9, 2),
         "nmse_mean": float(np.mean(nmse_b)),
         "plain_one_at_a_time": {
-            "scenes": len(seq), "value": round(1.0 / seq_t, 2), "unit": "scenes/s (setup + 300 iterations each)",
+            "scenes": len(seq), "value": round(1.0 / seq_it, 2), "unit": "scenes/s (300 iterations each, setup apart)",
+            "value_with_setup": round(1.0 / seq_t, 2),
             "nmse_mean": float(np.mean([x[1] for x in seq])),
             "batched_nmse_mean_same_scenes": float(np.mean(nmse_b[:len(seq)])),
         },
@@ -197,7 +296,23 @@ def main(argv=None):
     ap.add_argument("--batch-seq", type=int, default=8, help="scenes solved one at a time for comparison")
     ap.add_argument("--cpu-iters", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--batch-only", action="store_true", help="measure only the batched multi-scene form")
+    ap.add_argument("--no-kernel-events", action="store_true",
+                    help="time the region without kernel events (kernel timings from a second run)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run a plain copy of MIB MiB (counter calibration)")
+    ap.add_argument("--summarise-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_*.json from two rocprofv3 --pmc runs and exit (no GPU)")
+    ap.add_argument("--probe-mib", type=int, default=1024)
+    ap.add_argument("--command", default="", help="counter command recorded in the traffic summary")
     args = ap.parse_args(argv)
+
+    if args.summarise_traffic:
+        import workloads as W
+        for p in summarise_traffic(args.summarise_traffic[0], args.summarise_traffic[1], args.probe_mib,
+                                   W.full_imaging_name(), args.command):
+            print(p)
+        return 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver keeps every block of the split on a single "
@@ -210,6 +325,11 @@ def main(argv=None):
     import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        copy_probe(torch, dev, args.copy_probe)
+    if args.batch_only:
+        print(json.dumps({"batch": bench_batch(args, torch, A, W, dev)}), flush=True)
+        return 0
     t = time.perf_counter()
     prob = W.full_imaging(seed=args.seed)
     gen_s = time.perf_counter() - t
@@ -234,12 +354,16 @@ def main(argv=None):
         info = plan.info()
         if warmup > 0:
             plan.solve(g, warmup)
-        plan.profile(True)
+        # kernel events (on the dispatch packets) on every 10th iteration of the timed region
+        plan.profile(0 if args.no_kernel_events else PROFILE_EVERY)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         v, hist = plan.solve(g, steps, history=True)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        if args.no_kernel_events:   # kernel timings from a separate run of the same length
+            plan.profile(PROFILE_EVERY)
+            plan.solve(g, steps)
         prof = {A.KERNEL_NAMES[k]: plan.profile_read(k) for k in A.KERNEL_NAMES}
         plan.profile(False)
         algo = algorithmic_bytes(geo, prob.P, prob.Q, info["chunks"], storage)

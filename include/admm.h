@@ -211,18 +211,22 @@ int admm_get_stored_h(admm_plan* plan, void* re_out, void* im_out,
                       float* scale_out, void* stream);
 
 /*
- * Profiling.  admm_profile(plan, 1) makes later solves bracket every kernel
- * launch with HIP events on the solve's stream; admm_profile_read returns
- * the summed duration in ms and the launch count of one kernel class since
- * profiling was enabled (ADMM_K_* below).  admm_profile(plan, 0) stops and
- * clears.  Reading synchronises the recorded events.  Errors: EINVAL, EHIP.
+ * Profiling.  admm_profile(plan, every) with every >= 1 makes later solves
+ * time the kernels of every every-th iteration (iteration index k of each
+ * solve with k % every == 0) with HIP events carried by the kernels' own
+ * dispatch packets on the solve's stream; admm_profile_read returns the
+ * summed duration in ms and the number of timed launches of one kernel class
+ * since profiling was enabled (ADMM_K_* below).  admm_profile(plan, 0) stops
+ * and clears.  Reading synchronises the recorded events.  Timing adds a few
+ * microseconds between the timed kernels, so sample (every > 1) inside a
+ * throughput measurement.  Errors: EINVAL (every < 0), EHIP.
  */
 #define ADMM_K_GEMV_N   0   /* r_ij = g'_ij - H_ij c_j^i            */
 #define ADMM_K_GRAM     1   /* y_ij = G_ij^{-1} r_ij, ghat update   */
 #define ADMM_K_GEMV_H   2   /* partial H_ij^H y_ij                  */
 #define ADMM_K_ZUPDATE  3   /* mean, soft threshold, duals, norms   */
 #define ADMM_K_COUNT    4
-int admm_profile(admm_plan* plan, int enable);
+int admm_profile(admm_plan* plan, int every);
 int admm_profile_read(admm_plan* plan, int kernel, double* total_ms,
                       int64_t* launches);
 

@@ -265,8 +265,9 @@ class Plan:
         return re, im, sc
 
     # -- profiling ----------------------------------------------------------
-    def profile(self, enable: bool):
-        _check(lib().admm_profile(self._h, int(bool(enable))), "admm_profile")
+    def profile(self, every=1):
+        """every >= 1: time the kernels of every every-th iteration; 0 / False: off."""
+        _check(lib().admm_profile(self._h, int(every)), "admm_profile")
 
     def profile_read(self, kernel: int):
         ms = ctypes.c_double(0.0)

@@ -66,7 +66,7 @@ enum : int {
 // Device-side control words kept in the workspace.
 struct Control {
   int32_t iter;          // iterations done in the current solve (device counter)
-  int32_t ticket;        // arrival counter of the z-update reduction
+  int32_t zpending;      // the z-update's partial sums await their final addition
   int32_t nonfinite;     // sticky NaN/Inf flag
   int32_t notpd;         // Cholesky pivot failure flag
   int32_t kkt_ticket;    // arrival counter of the KKT reduction

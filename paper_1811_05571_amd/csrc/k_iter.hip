@@ -16,7 +16,9 @@
 //   gemv_h  : row-chunk partials of H_ij^H y_ij
 //   zupdate : u = c + sum of partials, v = S_kappa(mean_i(u + s)), kappa =
 //             lambda/(Q rho) (eq. v_variable_rows_columns), s += u - v
-//             (eq. s_variable_rows_columns), c = v - s, residual norms.
+//             (eq. s_variable_rows_columns), c = v - s, per-workgroup FP64
+//             partial sums of the residual norms; the first workgroup of the
+//             next gemv_n (or k_zfinal at the end of a solve) adds them.
 // The two H products stream H with 16-byte loads; the row-parallel products
 // reduce each row across a wavefront with xor shuffles; the adjoint product
 // keeps two columns per lane and splits the rows into chunks whose partials
@@ -26,10 +28,57 @@
 
 namespace admm {
 
+// Final FP64 sums of the previous z-update's per-workgroup partials: each
+// thread adds the partials b = tid, tid + 256, ... in order, then a fixed
+// shuffle tree and a fixed wave order; writes the residual history entry and
+// advances the iteration counter.  Run by one whole workgroup of 256 threads
+// of the next kernel on the stream, so no fence or ticket is needed.
+__device__ void zfinal(const IterArgs& a, double (&red)[kBlockThreads / kWave][kRedCount]) {
+  if (a.ctl->zpending == 0) return;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  double tot[kRedCount] = {0, 0, 0, 0, 0};
+  for (int b = tid; b < a.nz; b += kBlockThreads) {
+#pragma unroll
+    for (int q = 0; q < kRedCount; ++q) tot[q] += a.redpart[(int64_t)b * kRedCount + q];
+  }
+#pragma unroll
+  for (int q = 0; q < kRedCount; ++q) tot[q] = wave_sum_d(tot[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < kRedCount; ++q) red[wave][q] = tot[q];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double r[kRedCount];
+#pragma unroll
+    for (int q = 0; q < kRedCount; ++q) {
+      r[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+      a.ctl->red[q] = r[q];
+    }
+    const int it = a.ctl->iter;
+    if (a.hist) {
+      a.hist[2 * (int64_t)it] = r[kRedRp2];
+      a.hist[2 * (int64_t)it + 1] = r[kRedDv2] * a.rho2Q;
+    }
+    a.ctl->iter = it + 1;
+    a.ctl->zpending = 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlockThreads) void k_zfinal(IterArgs a) {
+  __shared__ double red[kBlockThreads / kWave][kRedCount];
+  zfinal(a, red);
+}
+
 // r_ij = g'_ij - H_ij c_j^i for 4 * HRows<F>::R rows of one block per workgroup.
-// tiles[x] = {block, first row, -, -}.
+// tiles[x] = {block, first row, -, -}.  Workgroup 0 first completes the
+// previous iteration's residual sums (zfinal).
 template <class F>
 __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4* __restrict__ tiles) {
+  if (blockIdx.x == 0) {
+    __shared__ double red[kBlockThreads / kWave][kRedCount];
+    zfinal(a, red);
+  }
   const F f = MakeFmt<F>::make(a.hs);
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = a.blocks[t.x];
@@ -115,12 +164,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_h(IterArgs a, const int4
 // block (one wavefront per workgroup, one column per lane).
 // tiles[x] = {column block, first column, -, -}.  Replicas stay in registers
 // when Q <= MAXQ (MAXQ = 0: any Q, partials are read twice).  Each workgroup
-// writes its five FP64 partial sums; the last workgroup to arrive (ticket)
-// adds them with a fixed assignment of partials to lanes and a fixed
-// shuffle tree, so the result does not depend on timing.
+// writes its five FP64 partial sums (a fixed shuffle tree over its lanes);
+// zfinal adds them in the next kernel.
 template <int MAXQ>
 __global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __restrict__ tiles) {
-  __shared__ int last;
   const int4 t = tiles[blockIdx.x];
   const ColDesc cd = a.cols[t.x];
   const int col = t.y + threadIdx.x;
@@ -205,31 +252,7 @@ __global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __re
   if (lane == 0) {
 #pragma unroll
     for (int q = 0; q < kRedCount; ++q) a.redpart[(int64_t)blockIdx.x * kRedCount + q] = acc[q];
-    __threadfence();
-    last = (atomicAdd(&a.ctl->ticket, 1) == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double tot[kRedCount] = {0, 0, 0, 0, 0};
-  for (unsigned b = lane; b < gridDim.x; b += kZCols) {
-#pragma unroll
-    for (int q = 0; q < kRedCount; ++q)
-      tot[q] += __hip_atomic_load(a.redpart + (int64_t)b * kRedCount + q, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-  }
-#pragma unroll
-  for (int q = 0; q < kRedCount; ++q) tot[q] = wave_sum_d(tot[q]);
-  if (lane == 0) {
-#pragma unroll
-    for (int q = 0; q < kRedCount; ++q) a.ctl->red[q] = tot[q];
-    const int it = a.ctl->iter;
-    if (a.hist) {
-      a.hist[2 * (int64_t)it] = tot[kRedRp2];
-      a.hist[2 * (int64_t)it + 1] = tot[kRedDv2] * a.rho2Q;
-    }
-    a.ctl->iter = it + 1;
-    a.ctl->ticket = 0;
+    if (blockIdx.x == 0) a.ctl->zpending = 1;
   }
 }
 
@@ -280,37 +303,51 @@ __global__ void k_fill_zero(uint4* p, size_t n16) {
 }
 
 // ---- launchers ------------------------------------------------------------
-hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st) {
+// Plain launches unless timing events are given (then on the dispatch packet).
+#define LAUNCH_TIMED(kern, grid, block, st, kt, ...)                                               \
+  do {                                                                                               \
+    const KTime kt_ = kt;                                                                            \
+    if (kt_.start || kt_.stop)                                                                       \
+      hipExtLaunchKernelGGL(kern, grid, block, 0, st, kt_.start, kt_.stop, 0, __VA_ARGS__);           \
+    else                                                                                             \
+      hipLaunchKernelGGL(kern, grid, block, 0, st, __VA_ARGS__);                                     \
+  } while (0)
+
+hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt) {
   switch (a.hs.storage) {
-    case 0: hipLaunchKernelGGL(k_gemv_n<FmtC64>, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles); break;
-    case 1: hipLaunchKernelGGL(k_gemv_n<FmtBF16>, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles); break;
-    default: hipLaunchKernelGGL(k_gemv_n<FmtFP8>, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles); break;
+    case 0: LAUNCH_TIMED(k_gemv_n<FmtC64>, dim3(ntiles), dim3(kBlockThreads), st, kt, a, tiles); break;
+    case 1: LAUNCH_TIMED(k_gemv_n<FmtBF16>, dim3(ntiles), dim3(kBlockThreads), st, kt, a, tiles); break;
+    default: LAUNCH_TIMED(k_gemv_n<FmtFP8>, dim3(ntiles), dim3(kBlockThreads), st, kt, a, tiles); break;
   }
   return hipGetLastError();
 }
 hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gtr, int n_gtr,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_tile, dim3(n_gram), dim3(kBlockThreads), 0, st, a, t_gram);
+                       hipStream_t st, KTime kt) {
+  LAUNCH_TIMED(k_gram_tile, dim3(n_gram), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gram);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gram_reduce, dim3(n_gtr), dim3(kTile), 0, st, a, t_gtr);
+  LAUNCH_TIMED(k_gram_reduce, dim3(n_gtr), dim3(kTile), st, (KTime{nullptr, kt.stop}), a, t_gtr);
   return hipGetLastError();
 }
-hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st) {
+hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt) {
   switch (a.hs.storage) {
-    case 0: hipLaunchKernelGGL(k_gemv_h<FmtC64>, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles); break;
-    case 1: hipLaunchKernelGGL(k_gemv_h<FmtBF16>, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles); break;
-    default: hipLaunchKernelGGL(k_gemv_h<FmtFP8>, dim3(ntiles), dim3(kBlockThreads), 0, st, a, tiles); break;
+    case 0: LAUNCH_TIMED(k_gemv_h<FmtC64>, dim3(ntiles), dim3(kBlockThreads), st, kt, a, tiles); break;
+    case 1: LAUNCH_TIMED(k_gemv_h<FmtBF16>, dim3(ntiles), dim3(kBlockThreads), st, kt, a, tiles); break;
+    default: LAUNCH_TIMED(k_gemv_h<FmtFP8>, dim3(ntiles), dim3(kBlockThreads), st, kt, a, tiles); break;
   }
   return hipGetLastError();
 }
-hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st) {
+hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt) {
   if (a.Q <= 4)
-    hipLaunchKernelGGL(k_zupdate<4>, dim3(ntiles), dim3(kZCols), 0, st, a, tiles);
+    LAUNCH_TIMED(k_zupdate<4>, dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
   else if (a.Q <= 8)
-    hipLaunchKernelGGL(k_zupdate<8>, dim3(ntiles), dim3(kZCols), 0, st, a, tiles);
+    LAUNCH_TIMED(k_zupdate<8>, dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
   else
-    hipLaunchKernelGGL(k_zupdate<0>, dim3(ntiles), dim3(kZCols), 0, st, a, tiles);
+    LAUNCH_TIMED(k_zupdate<0>, dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
+  return hipGetLastError();
+}
+hipError_t launch_zfinal(const IterArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_zfinal, dim3(1), dim3(kBlockThreads), 0, st, a);
   return hipGetLastError();
 }
 hipError_t launch_unpad_cols(const ColDesc* cols, int P, int64_t n, const float2* src, float2* dst,

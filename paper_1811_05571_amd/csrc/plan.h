@@ -5,6 +5,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace admm {
@@ -71,6 +73,7 @@ struct IterArgs {
   float2* arec;         // device, pre-threshold mean of this iteration (column space), or null
   int64_t m_pad, n_pad;
   int Q, P, KH;
+  int nz;               // z-update workgroups (partial sums in redpart)
   float rho, kappa;
   double rho2Q;         // rho^2 Q for the dual residual
   int cpl;              // columns per lane load of the storage (layout of c, see cperm)
@@ -97,11 +100,18 @@ hipError_t launch_adj_iteration(const AdjArgs& a, const Geometry& G, const int4*
 hipError_t launch_adj_gflush(const AdjArgs& a, const BlockDesc* blocks, int nblocks, float2* grad_g,
                              hipStream_t st);
 
-hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st);
+// Optional start / stop events carried by the dispatch packets themselves
+// (hipExtLaunchKernelGGL), so timing adds no packets between kernels.
+struct KTime {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});
 hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gtr, int n_gtr,
-                       hipStream_t st);
-hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st);
-hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st);
+                       hipStream_t st, KTime kt = {});
+hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});
+hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});
+// Final addition of a pending z-update's partial sums (one workgroup).
+hipError_t launch_zfinal(const IterArgs& a, hipStream_t st);
 hipError_t launch_unpad_cols(const ColDesc* cols, int P, int64_t n, const float2* src, float2* dst,
                              int64_t src_stride, int64_t dst_stride, int reps, int to_padded,
                              hipStream_t st);

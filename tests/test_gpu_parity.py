@@ -172,3 +172,21 @@ def test_bad_arguments_rejected(torch_gpu):
     v = torch_gpu.empty(p.n, dtype=torch_gpu.complex64, device="cuda")
     assert A.lib().admm_solve(plan.handle, g.data_ptr(), -1, 0.0, 1, v.data_ptr(), None, None, 0, None) == -1
     assert A.lib().admm_solve(plan.handle, g.data_ptr(), 1, 1e-3, 0, v.data_ptr(), None, None, 0, None) == -1
+
+
+def test_profile_sampling_counts_and_leaves_results_unchanged(torch_gpu):
+    """Kernel timing on every 3rd iteration: 9 iterations give 3 timed launches
+    per kernel class, and the iterates are bitwise those of an untimed solve."""
+    import paper_1811_05571_amd as A
+    p, _ = _case("combined_uneven")
+    plan, g, (v0, _) = gpu_solve(torch_gpu, p, 9, history=True)
+    plan.profile(3)
+    v1 = plan.solve(g, 9)
+    counts = [plan.profile_read(k)[1] for k in A.KERNEL_NAMES]
+    ms = [plan.profile_read(k)[0] for k in A.KERNEL_NAMES]
+    plan.profile(0)
+    assert counts == [3] * len(A.KERNEL_NAMES)
+    assert all(x > 0 for x in ms)
+    assert torch_gpu.equal(v0, v1)
+    with pytest.raises(A.ADMMError):
+        plan.profile(-1)

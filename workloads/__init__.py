@@ -221,9 +221,16 @@ def small_consensus() -> Problem:
 FULL_IMAGING_RHO = 6.0
 
 
+FULL_IMAGING_NAME = "cra6144x32000_Q4P8"
+
+
+def full_imaging_name() -> str:
+    return FULL_IMAGING_NAME
+
+
 def full_imaging(seed: int = 0, rho: float = FULL_IMAGING_RHO) -> Problem:
     """6144 x 32000 CRA-like consensus-and-sectioning workload (Q=4, P=8, 300 it)."""
-    return cra_problem(seed=seed, rho=rho, name="cra6144x32000_Q4P8")
+    return cra_problem(seed=seed, rho=rho, name=FULL_IMAGING_NAME)
 
 
 # --------------------------------------------------------------------------
