@@ -99,3 +99,30 @@ def test_full_size_adjoint_central_differences(torch_gpu, full):
         return L(pl=plans[r])
     kinks += _fd_check(Lr, p.rho, 1e-3 * p.rho, dr, 1e-6)
     assert kinks <= 1
+
+
+def test_full_size_batch_sampled_scenes(torch_gpu):
+    """The 64-scene batched workload in the configuration the benchmark times
+    (256-row frequency tiles, bf16 H0, autotuned MFMA tile widths, graph
+    replay): after 3 iterations, the first scene of each row split
+    Q in {2, 4, 8} matches the FP64 oracle run on that scene's stored matrix
+    diag(phase) bf16(H0)[rows] (arithmetic error only: FP32 bar 1e-5)."""
+    import paper_1811_05571_amd as A
+    from oracle import quant as QZ
+    b = W.batch_scenes(S=64)
+    bb = A.Batch(to_device(torch_gpu, b.H0), b.tile_rows, b.tiles, b.cuts, b.phases, b.P, b.rho, b.lam)
+    g = to_device(torch_gpu, np.concatenate(b.g))
+    K = 3
+    v = bb.solve(g, K, graph=True).cpu().numpy()
+    bb.close()
+    H0q = QZ.dequantise(b.H0, "bf16")
+    picked = {}
+    for s in range(b.S):
+        picked.setdefault(len(b.cuts[s]) - 1, s)
+    assert sorted(picked) == [2, 4, 8]
+    for Q, s in sorted(picked.items()):
+        Hs = b.scene_H(s, H0q)
+        ref, _, _ = O.solve(Hs, b.g[s], Q, b.P, b.rho, b.lam[s], K, b.row_off(s))
+        e = rel(v[s], ref)
+        print(f"scene {s}: {Hs.shape[0]} rows, Q={Q}, rel err vs oracle {e:.2e}", flush=True)
+        assert e <= 1e-5
