@@ -97,19 +97,29 @@ def _short_kernel(name: str) -> str:
     return n.split("(")[0].strip()
 
 
-def read_counter_csv(path: str, counter: str) -> dict:
-    """rocprofv3 --pmc csv -> {short kernel name: [KiB per dispatch, ...]}."""
+def read_counter_csv(path: str, counter: str) -> list:
+    """rocprofv3 --pmc csv -> [(dispatch id, short kernel name, KiB)] in dispatch order."""
     import csv
     per = {}
     with open(path) as f:
         for row in csv.DictReader(f):
             if row.get("Counter_Name") != counter:
                 continue
-            key = (row["Dispatch_Id"], row["Kernel_Name"])
+            key = (int(row["Dispatch_Id"]), _short_kernel(row["Kernel_Name"]))
             per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
-    out = {}
-    for (_, kname), val in per.items():
-        out.setdefault(_short_kernel(kname), []).append(val)
+    return sorted((d, k, v) for (d, k), v in per.items())
+
+
+def _by_storage(disp: list) -> dict:
+    """{storage: {kernel: [KiB, ...]}}: a kernel shared by the storages counts
+    for the storage of the last storage-typed row product dispatched before it."""
+    owner = {n: st for st, names in TRACE_NAMES.items() for n in names}
+    out, cur = {}, None
+    for _, k, v in disp:
+        if k in owner:
+            cur = owner[k]
+        if k in owner or (k in SHARED_NAMES and cur is not None):
+            out.setdefault(cur, {}).setdefault(k, []).append(v)
     return out
 
 
@@ -117,35 +127,39 @@ def summarise_traffic(fetch_csv: str, write_csv: str, probe_mib: int, workload: 
     """Writes profiles/traffic_<workload>_<storage>.json from a FETCH_SIZE and
     a WRITE_SIZE counter run, each scaled by what the counter reads for the
     copy probe (probe_mib MiB read and written)."""
-    fetch = read_counter_csv(fetch_csv, "FETCH_SIZE")
-    write = read_counter_csv(write_csv, "WRITE_SIZE")
-    probe = [k for k in fetch if COPY_PROBE_KERNEL in k]
+    fetch_d = read_counter_csv(fetch_csv, "FETCH_SIZE")
+    write_d = read_counter_csv(write_csv, "WRITE_SIZE")
+    probe = sorted({k for _, k, _ in fetch_d if COPY_PROBE_KERNEL in k})
     if len(probe) != 1:
         raise SystemExit(f"copy probe kernel not found once in {fetch_csv}: {probe}")
     pk = probe[0]
     kib = probe_mib * 1024.0
-    f_fac = kib / float(np.mean(fetch[pk]))
-    w_fac = kib / float(np.mean(write[pk]))
+    pf = [v for _, k, v in fetch_d if k == pk]
+    pw = [v for _, k, v in write_d if k == pk]
+    f_fac = kib / float(np.mean(pf))
+    w_fac = kib / float(np.mean(pw))
+    fetch, write = _by_storage(fetch_d), _by_storage(write_d)
     written = []
     for storage, names in TRACE_NAMES.items():
+        fs, ws = fetch.get(storage, {}), write.get(storage, {})
         kern = {}
         for src, dst in list(names.items()) + list(SHARED_NAMES.items()):
-            if src not in fetch or src not in write:
+            if src not in fs or src not in ws:
                 continue
-            fb = float(np.mean(fetch[src])) * 1024.0 * f_fac
-            wb = float(np.mean(write[src])) * 1024.0 * w_fac
+            fb = float(np.mean(fs[src])) * 1024.0 * f_fac
+            wb = float(np.mean(ws[src])) * 1024.0 * w_fac
             k = kern.setdefault(dst, {"fetch_bytes": 0.0, "write_bytes": 0.0, "parts": []})
             k["fetch_bytes"] += fb
             k["write_bytes"] += wb
-            k["parts"].append({"kernel": src, "dispatches": len(fetch[src]), "fetch_kib_raw": float(np.mean(fetch[src])),
-                               "write_kib_raw": float(np.mean(write[src]))})
+            k["parts"].append({"kernel": src, "dispatches": len(fs[src]), "fetch_kib_raw": float(np.mean(fs[src])),
+                               "write_kib_raw": float(np.mean(ws[src]))})
         if not any(n in kern for n in ("k_gemv_n", "k_gemv_h")):
             continue
         for k in kern.values():
             k["bytes_per_launch"] = int(round(k["fetch_bytes"] + k["write_bytes"]))
         rec = {"workload": f"{workload}_{storage}", "kernel_source_sha256_16": kernel_source_hash(),
                "copy_probe": {"kernel": pk, "mib": probe_mib, "fetch_factor": f_fac, "write_factor": w_fac,
-                              "fetch_kib_raw": float(np.mean(fetch[pk])), "write_kib_raw": float(np.mean(write[pk]))},
+                              "fetch_kib_raw": float(np.mean(pf)), "write_kib_raw": float(np.mean(pw))},
                "command": command, "kernels": kern}
         path = os.path.join(PROFILES, f"traffic_{workload}_{storage}.json")
         with open(path, "w") as f:

@@ -185,7 +185,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   for (size_t b = 0; b < geo.blocks.size(); ++b) {
     const BlockDesc& d = geo.blocks[b];
     for (int r = 0; r < d.mi; r += kRowsPerWG) geo.t_rows.push_back(make_int4((int)b, r, 0, 0));
-    const int hrows = rows_per_wave(storage) * (kBlockThreads / kWave);
+    const int hrows = rows_per_wave(storage) * kRowWaves;
     for (int r = 0; r < d.mi; r += hrows) geo.t_hrows.push_back(make_int4((int)b, r, 0, 0));
     const int nl = (d.nj + cpl - 1) / cpl;
     wg_per_chunk += (nl + kColsPerWGLoads - 1) / kColsPerWGLoads;
@@ -195,10 +195,11 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
       geo.t_gtr.push_back(make_int4((int)b, a, 0, 0));
     }
   }
-  // Row chunks of the adjoint product: about 2048 workgroups in total, at
-  // least 32 rows (8 per wave) per chunk.
+  // Row chunks of the adjoint product: about ADMM_COLS_WG_TARGET(_C64)
+  // workgroups in total, at least 32 rows (8 per wave) per chunk.
   {
-    const int want = std::max(1, (2048 + wg_per_chunk - 1) / wg_per_chunk);
+    const int target = storage == 0 ? ADMM_COLS_WG_TARGET_C64 : ADMM_COLS_WG_TARGET;
+    const int want = std::max(1, (target + wg_per_chunk - 1) / wg_per_chunk);
     const int cap = std::max(1, max_mi / 32);
     geo.KH = std::min(std::min(want, cap), 32);
   }
@@ -883,6 +884,13 @@ int admm_profile(admm_plan* p, int enable) {
   if (enable < 0) return fail(ADMM_EINVAL, "enable must be >= 0");
   p->prof = enable != 0;
   p->prof_every = enable > 0 ? enable : 1;
+  // Create the events of 64 timed iterations now, so that a timed solve does
+  // not create them between its launches.
+  while (p->prof && p->pool.size() < (size_t)2 * ADMM_K_COUNT * 64) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    p->pool.push_back(e);
+  }
   return ADMM_OK;
 }
 

@@ -40,8 +40,8 @@ template <class F> struct RowUnroll { static constexpr int U = F::CPL == 2 ? 4 :
 // H row products: rows per wave and lane loads in flight per row (narrow
 // formats reuse each lane's vector loads across 8 rows).
 template <class F> struct HRows {
-  static constexpr int R = F::CPL == 2 ? 4 : 8;
-  static constexpr int U = F::CPL == 2 ? 4 : 1;
+  static constexpr int R = F::CPL == 2 ? ADMM_ROWS_C64 : 8;
+  static constexpr int U = F::CPL == 2 ? ADMM_UNROLL_C64 : 1;
 };
 
 // Dot products of R consecutive rows of a stored matrix with the complex
@@ -185,18 +185,23 @@ __device__ __forceinline__ void cols_partial(const F& f, const BlockDesc& d, con
 // of a row group by a reduce-scatter (xor 8, 4) and an all-reduce (xor 2, 1);
 // column sums close over the wave by a reduce-scatter (xor 32, 16) and over
 // the 4 waves through 2 KB of LDS, always in the same order.
-__device__ __forceinline__ void gram_tile_apply(const float2* __restrict__ G, const float2* __restrict__ xa,
-                                                const float2* __restrict__ xb, bool diag,
-                                                float2* __restrict__ out_ab, float2* __restrict__ out_ba,
-                                                float2 (&red)[4][64]) {
+// Loads of one tile in the thread layout of gram_tile_compute.
+__device__ __forceinline__ void gram_tile_load(const float2* __restrict__ G, float4 (&h)[4][2]) {
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, b = l & 15;
   const int r0 = 16 * w + 4 * (l >> 4);
-  float4 h[4][2];
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
     for (int hf = 0; hf < 2; ++hf)
       h[rr][hf] = ldnt4(reinterpret_cast<const float4*>(G + (r0 + rr) * 64 + 32 * hf + 2 * b));
+}
+
+__device__ __forceinline__ void gram_tile_compute(const float4 (&h)[4][2], const float2* __restrict__ xa,
+                                                  const float2* __restrict__ xb, bool diag,
+                                                  float2* __restrict__ out_ab, float2* __restrict__ out_ba,
+                                                  float2 (&red)[4][64]) {
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, b = l & 15;
+  const int r0 = 16 * w + 4 * (l >> 4);
   const float4 xb0 = *reinterpret_cast<const float4*>(xb + 2 * b);
   const float4 xb1 = *reinterpret_cast<const float4*>(xb + 32 + 2 * b);
   float pr[4], pi[4];
@@ -265,6 +270,15 @@ __device__ __forceinline__ void gram_tile_apply(const float2* __restrict__ G, co
     const float2 q0 = red[0][tid], q1 = red[1][tid], q2 = red[2][tid], q3 = red[3][tid];
     out_ba[tid] = make_float2(((q0.x + q1.x) + q2.x) + q3.x, ((q0.y + q1.y) + q2.y) + q3.y);
   }
+}
+
+__device__ __forceinline__ void gram_tile_apply(const float2* __restrict__ G, const float2* __restrict__ xa,
+                                                const float2* __restrict__ xb, bool diag,
+                                                float2* __restrict__ out_ab, float2* __restrict__ out_ba,
+                                                float2 (&red)[4][64]) {
+  float4 h[4][2];
+  gram_tile_load(G, h);
+  gram_tile_compute(h, xa, xb, diag, out_ab, out_ba, red);
 }
 
 // Sum of T strided complex partials in index order (loads issued four at a

@@ -232,9 +232,9 @@ hipError_t launch_adj_iteration(const AdjArgs& a, const Geometry& G, const int4*
   const int nh = (int)G.t_hrows.size();
   hipLaunchKernelGGL(k_adj_z, dim3(nz), dim3(kZCols), 0, st, a, t_z, arec);
   switch (a.hs.storage) {
-    case 0: hipLaunchKernelGGL(k_adj_rows<FmtC64>, dim3(nh), dim3(kBlockThreads), 0, st, a, t_hrows); break;
-    case 1: hipLaunchKernelGGL(k_adj_rows<FmtBF16>, dim3(nh), dim3(kBlockThreads), 0, st, a, t_hrows); break;
-    default: hipLaunchKernelGGL(k_adj_rows<FmtFP8>, dim3(nh), dim3(kBlockThreads), 0, st, a, t_hrows); break;
+    case 0: hipLaunchKernelGGL(k_adj_rows<FmtC64>, dim3(nh), dim3(kRowWaves * kWave), 0, st, a, t_hrows); break;
+    case 1: hipLaunchKernelGGL(k_adj_rows<FmtBF16>, dim3(nh), dim3(kRowWaves * kWave), 0, st, a, t_hrows); break;
+    default: hipLaunchKernelGGL(k_adj_rows<FmtFP8>, dim3(nh), dim3(kRowWaves * kWave), 0, st, a, t_hrows); break;
   }
   hipLaunchKernelGGL(k_adj_gram_tile, dim3(ng), dim3(kBlockThreads), 0, st, a, t_gram);
   hipLaunchKernelGGL(k_adj_gram_reduce, dim3(ngt), dim3(kTile), 0, st, a, t_gtr, yrec);

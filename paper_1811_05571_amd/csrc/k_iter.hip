@@ -117,29 +117,72 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4
 // y_ij = G_ij^{-1} r_ij over the packed lower tiles of the inverse: every
 // tile is read once and contributes to two 64-row pieces of y (gram_tile_apply);
 // k_gram_reduce adds the pieces in tile order and forms ghat_ij = g'_ij - rho y_ij.
-// tiles[x] = {block, tile row, tile col, -} (lower pairs).
-__global__ __launch_bounds__(kBlockThreads) void k_gram_tile(IterArgs a, const int4* __restrict__ tiles) {
+// tiles[x] = {block, tile row, tile col, -} (lower pairs).  Each workgroup
+// takes kGramTPW consecutive tiles and issues the next tile's loads before
+// the current tile's reductions.
+__device__ __forceinline__ const float2* gram_tile_ptr(const IterArgs& a, const int4& t, const BlockDesc& d) {
+  return a.Ginv + d.gi_off + (int64_t)(t.y * (t.y + 1) / 2 + t.z) * (kTile * kTile);
+}
+__global__ __launch_bounds__(kBlockThreads) void k_gram_tile(IterArgs a, const int4* __restrict__ tiles,
+                                                             int ntiles) {
   __shared__ float2 tt[4][64];
-  const int4 t = tiles[blockIdx.x];
-  const BlockDesc d = a.blocks[t.x];
-  const int T = d.mt / kTile;
-  const float2* G = a.Ginv + d.gi_off + (int64_t)(t.y * (t.y + 1) / 2 + t.z) * (kTile * kTile);
-  const float2* x = a.r + (int64_t)d.j * a.m_pad + d.rpad0;
-  float2* part = a.gpart + (int64_t)d.gpo * kTile;
-  gram_tile_apply(G, x + t.y * kTile, x + t.z * kTile, t.y == t.z, part + (int64_t)(t.y * T + t.z) * kTile,
-                  part + (int64_t)(t.z * T + t.y) * kTile, tt);
+  const int base = blockIdx.x * kGramTPW;
+  const int cnt = min(kGramTPW, ntiles - base);
+  int4 t = tiles[base];
+  BlockDesc d = a.blocks[t.x];
+  float4 h[4][2];
+  gram_tile_load(gram_tile_ptr(a, t, d), h);
+  for (int w = 0; w < cnt; ++w) {
+    float4 hn[4][2];
+    int4 tn = t;
+    BlockDesc dn = d;
+    if (w + 1 < cnt) {
+      tn = tiles[base + w + 1];
+      dn = a.blocks[tn.x];
+      gram_tile_load(gram_tile_ptr(a, tn, dn), hn);
+    }
+    const int T = d.mt / kTile;
+    const float2* x = a.r + (int64_t)d.j * a.m_pad + d.rpad0;
+    float2* part = a.gpart + (int64_t)d.gpo * kTile;
+    gram_tile_compute(h, x + t.y * kTile, x + t.z * kTile, t.y == t.z, part + (int64_t)(t.y * T + t.z) * kTile,
+                      part + (int64_t)(t.z * T + t.y) * kTile, tt);
+    if (w + 1 < cnt) {
+      __syncthreads();   // tt is read by the previous tile's column sums
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        h[rr][0] = hn[rr][0];
+        h[rr][1] = hn[rr][1];
+      }
+      t = tn;
+      d = dn;
+    }
+  }
 }
 
-// tiles[x] = {block, tile row, -, -}; 64 threads, one row each.
-__global__ __launch_bounds__(kTile) void k_gram_reduce(IterArgs a, const int4* __restrict__ tiles) {
+// tiles[x] = {block, tile row, -, -}; 256 threads: row l = tid % 64 adds the
+// pieces k = tid / 64, tid / 64 + 4, ... in increasing k, and the four sums
+// are added in a fixed order.
+static_assert(kBlockThreads / kTile == 4, "k_gram_reduce adds four interleaved sums per row");
+__global__ __launch_bounds__(kBlockThreads) void k_gram_reduce(IterArgs a, const int4* __restrict__ tiles) {
+  __shared__ float2 red[kBlockThreads / kTile][kTile];
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = a.blocks[t.x];
   const int T = d.mt / kTile;
-  const int row = t.y * kTile + threadIdx.x;
-  if (row >= d.mi) return;
-  const float2* part = a.gpart + ((int64_t)d.gpo + (int64_t)t.y * T) * kTile + threadIdx.x;
-  const float2 q = ordered_sum(part, T, kTile);
-  const float ar = q.x, ai = q.y;
+  const int l = threadIdx.x & (kTile - 1), q = threadIdx.x / kTile;
+  const float2* part = a.gpart + ((int64_t)d.gpo + (int64_t)t.y * T) * kTile + l;
+  float sr = 0.f, si = 0.f;
+#pragma unroll 4
+  for (int k = q; k < T; k += kBlockThreads / kTile) {
+    const float2 v = part[(int64_t)k * kTile];
+    sr += v.x;
+    si += v.y;
+  }
+  red[q][l] = make_float2(sr, si);
+  __syncthreads();
+  const int row = t.y * kTile + l;
+  if (threadIdx.x >= kTile || row >= d.mi) return;
+  const float2 q0 = red[0][l], q1 = red[1][l], q2 = red[2][l], q3 = red[3][l];
+  const float ar = ((q0.x + q1.x) + q2.x) + q3.x, ai = ((q0.y + q1.y) + q2.y) + q3.y;
   const int64_t vi = (int64_t)d.j * a.m_pad + d.rpad0 + row;
   a.y[vi] = make_float2(ar, ai);
   // With one column block g'_ij is g_i itself and was not stored.
@@ -315,18 +358,19 @@ __global__ void k_fill_zero(uint4* p, size_t n16) {
 
 hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt) {
   switch (a.hs.storage) {
-    case 0: LAUNCH_TIMED(k_gemv_n<FmtC64>, dim3(ntiles), dim3(kBlockThreads), st, kt, a, tiles); break;
-    case 1: LAUNCH_TIMED(k_gemv_n<FmtBF16>, dim3(ntiles), dim3(kBlockThreads), st, kt, a, tiles); break;
-    default: LAUNCH_TIMED(k_gemv_n<FmtFP8>, dim3(ntiles), dim3(kBlockThreads), st, kt, a, tiles); break;
+    case 0: LAUNCH_TIMED(k_gemv_n<FmtC64>, dim3(ntiles), dim3(kRowWaves * kWave), st, kt, a, tiles); break;
+    case 1: LAUNCH_TIMED(k_gemv_n<FmtBF16>, dim3(ntiles), dim3(kRowWaves * kWave), st, kt, a, tiles); break;
+    default: LAUNCH_TIMED(k_gemv_n<FmtFP8>, dim3(ntiles), dim3(kRowWaves * kWave), st, kt, a, tiles); break;
   }
   return hipGetLastError();
 }
 hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gtr, int n_gtr,
                        hipStream_t st, KTime kt) {
-  LAUNCH_TIMED(k_gram_tile, dim3(n_gram), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gram);
+  const int nwg = (n_gram + kGramTPW - 1) / kGramTPW;
+  LAUNCH_TIMED(k_gram_tile, dim3(nwg), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gram, n_gram);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  LAUNCH_TIMED(k_gram_reduce, dim3(n_gtr), dim3(kTile), st, (KTime{nullptr, kt.stop}), a, t_gtr);
+  LAUNCH_TIMED(k_gram_reduce, dim3(n_gtr), dim3(kBlockThreads), st, (KTime{nullptr, kt.stop}), a, t_gtr);
   return hipGetLastError();
 }
 hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt) {

@@ -40,6 +40,30 @@ struct Geometry {
   Layout lay;
 };
 
+// Launch shapes of the H products.  Build-time constants; the defaults are the
+// measured best on MI355X at 6144 x 32000 (-D overrides serve tuning sweeps).
+#ifndef ADMM_ROW_WAVES
+#define ADMM_ROW_WAVES 4        // waves per workgroup of the H row products
+#endif
+#ifndef ADMM_ROWS_C64
+#define ADMM_ROWS_C64 8         // rows per wave of the complex64 row product
+#endif
+#ifndef ADMM_UNROLL_C64
+#define ADMM_UNROLL_C64 2       // lane loads in flight per row (complex64)
+#endif
+#ifndef ADMM_COLS_WG_TARGET
+#define ADMM_COLS_WG_TARGET 2048  // about this many workgroups of the adjoint product (bf16, fp8)
+#endif
+#ifndef ADMM_COLS_WG_TARGET_C64
+#define ADMM_COLS_WG_TARGET_C64 4096  // the same for complex64 storage
+#endif
+#ifndef ADMM_GRAM_TPW
+#define ADMM_GRAM_TPW 1         // packed inverse tiles per workgroup of the Gram apply
+#endif
+constexpr int kRowWaves = ADMM_ROW_WAVES;
+constexpr int kGramTPW = ADMM_GRAM_TPW;
+static_assert(kRowWaves >= 1 && kRowWaves <= kBlockThreads / kWave, "row waves");
+
 // Rows handled by one workgroup of the row-parallel products.
 constexpr int kRowsPerWave = 4;
 constexpr int kRowsPerWG = kRowsPerWave * (kBlockThreads / kWave);
@@ -50,7 +74,7 @@ constexpr int kColsPerWGLoads = kWave;
 inline int cols_per_load(int storage) { return storage == 0 ? 2 : (storage == 1 ? 8 : 16); }
 // Rows per wave of the H row products: narrow formats share each lane's
 // vector loads across more rows.
-inline int rows_per_wave(int storage) { return storage == 0 ? 4 : 8; }
+inline int rows_per_wave(int storage) { return storage == 0 ? ADMM_ROWS_C64 : 8; }
 // Bytes per stored complex element.
 inline int elem_bytes(int storage) { return storage == 0 ? 8 : (storage == 1 ? 4 : 2); }
 constexpr int kZCols = kWave;   // columns (lanes) per z-update workgroup
