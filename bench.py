@@ -281,7 +281,8 @@ def bench_batch(args, torch, A, W, dev):
         "unit": "scenes/s (300 iterations each, setup apart)",
         "value_with_setup": round(b.S / (el + setup_s), 2),
         "ms_per_batched_iteration": round(el / K * 1e3, 3), "setup_s": round(setup_s, 2),
-        "scene_tiles": NST, "tile_widths": [info["tile_n"], info["tile_h"]], "autotune": bb.tuning(),
+        "scene_tiles": NST, "gemm_choice": {"fwd_rows_per_wg": info["fwd_rows_per_wg"], "fwd_kchunks": info["fwd_kchunks"],
+                                  "adj_cols_per_wg": info["adj_cols_per_wg"]}, "autotune": bb.tuning(),
         "kernels": kern, "ginv_gb": round(info["ginv_bytes"] / 1e9, 2),
         "nmse_mean": float(np.mean(nmse_b)),
         "plain_one_at_a_time": {

@@ -242,8 +242,8 @@ void admm_destroy(admm_plan* plan);
  * Batched multi-scene form.
  *
  * S scenes measured by one instrument matrix H0 (m0 x n).  The rows of H0
- * come in tiles of `tile_rows` consecutive rows (one frequency each; a
- * multiple of 32 dividing m0).  Scene s measures the tiles
+ * come in tiles of `tile_rows` consecutive rows (one frequency each; 64,
+ * 128 or 256, dividing m0).  Scene s measures the tiles
  * tiles[tiles_off[s] .. tiles_off[s+1]) (strictly increasing tile indices),
  * each of its rows multiplied by a unit phase, so its sensing matrix is
  *     H_s = diag(phase_s) H0[rows of its tiles, :]
@@ -288,11 +288,14 @@ int admm_batch_profile(admm_batch* batch, int enable);
 int admm_batch_profile_read(admm_batch* batch, int kernel, double* total_ms,
                             int64_t* launches);
 /* info16: m0, n, S, P, row blocks, scene tiles, workspace bytes, inverse
- * bytes, chosen forward / adjoint tile widths (scene columns per wave),
- * their work items, packed rows, 0... */
+ * bytes, chosen forward k-chunks per column block, chosen adjoint columns per
+ * workgroup, their work items, packed rows, chosen forward rows per
+ * workgroup, 0... */
 int admm_batch_info(const admm_batch* batch, int64_t* info16);
-/* Autotuner timings (ms) of the tile widths 16, 32, 64: forward [0..2],
- * adjoint [3..5]. */
+/* Autotuner timings (ms): the three forward GEMM shapes [0..2] (rows per
+ * workgroup, k-chunks per column block: (128, 1), (128, 2), (64, 2), rows
+ * capped at tile_rows); the adjoint GEMM with 64, 128, 256 columns per
+ * workgroup [3..5]. */
 int admm_batch_tuning(const admm_batch* batch, double* ms6);
 void admm_batch_destroy(admm_batch* batch);
 

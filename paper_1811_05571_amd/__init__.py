@@ -356,14 +356,15 @@ class Batch:
     def info(self) -> dict:
         arr = (ctypes.c_int64 * 16)()
         _check(lib().admm_batch_info(self._h, arr), "admm_batch_info")
-        keys = ["m0", "n", "S", "P", "row_blocks", "scene_tiles", "workspace_bytes", "ginv_bytes", "tile_n",
-                "tile_h", "items_n", "items_h", "rows"]
+        keys = ["m0", "n", "S", "P", "row_blocks", "scene_tiles", "workspace_bytes", "ginv_bytes", "fwd_kchunks",
+                "adj_cols_per_wg", "items_n", "items_h", "rows", "fwd_rows_per_wg"]
         return {k: int(arr[i]) for i, k in enumerate(keys)}
 
     def tuning(self):
         arr = (ctypes.c_double * 6)()
         _check(lib().admm_batch_tuning(self._h, arr), "admm_batch_tuning")
-        return {"forward_ms": list(arr[:3]), "adjoint_ms": list(arr[3:]), "widths": [16, 32, 64]}
+        return {"forward_ms": list(arr[:3]), "forward_rows_kchunks": [(128, 1), (128, 2), (64, 2)],
+                "adjoint_ms": list(arr[3:]), "adjoint_cols_per_wg": [64, 128, 256]}
 
 
 def _unrolled_function():

@@ -616,7 +616,7 @@ int admm_solve(admm_plan* p, const void* g, int iters, double tol, int check_eve
   const Geometry& G = p->geo;
   int rc;
   if (!warm && (rc = reset_state(p, st))) return rc;
-  HIP_TRY(launch_fill(p->ctl, 16, st));  // iteration counter, ticket, flags
+  HIP_TRY(launch_fill(p->ctl, 16, st));  // iteration counter, pending z-sums flag, error flags
   const IterArgs a = iter_args(p, static_cast<const float2*>(g), resid_hist);
   const int nr = (int)G.t_rows.size(), nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
   const int nh = (int)G.t_hrows.size();
@@ -792,6 +792,7 @@ int admm_backward(admm_plan* p, const void* g, const void* grad_v, const void* t
                                    yrec + ystride * (k - k0), st));
   }
   HIP_TRY(launch_adj_gflush(b, p->d_blocks, (int)G.blocks.size(), static_cast<float2*>(grad_g), st));
+  HIP_TRY(launch_adj_scalars(b, (int)G.t_z.size(), (int)G.t_gtr.size(), st));
   Control hc;
   HIP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));

@@ -45,7 +45,7 @@ struct GemmItem {
   int32_t m0;      // first row (forward) / first column (adjoint) of the item
   int32_t st0;     // first scene-tile of the tile's group
   int32_t cnt;     // scene-tiles in the item (<= 64)
-  int32_t pad[3];
+  int32_t pad[3];  // forward: end k, partial slot, first row
 };
 
 struct BatchArgs {
@@ -60,13 +60,27 @@ struct BatchArgs {
   const float2* phases;            // packed per scene row
   const float2* g;                 // packed per scene row
   float2 *c, *s, *v, *part, *gp, *ghat, *r, *y;
+  // bfloat16 three-term splits of the GEMM vector operands, plane p in
+  // {Re t1, Re t2, Re t3, Im t1, Im t2, Im t3}:
+  //   cs: of c, [p][R][n_pad];  ys: of conj(phase) o y, [p][P][m_pad]
+  uint16_t *cs, *ys;
+  // forward GEMM k-chunk partials [chunk][group][tile_rows][64] and, per
+  // scene-tile entry, {first group index (add j), column in the group}
+  float2* pn;
+  const int2* st_gc;
   Control* ctl;
   int64_t m_pad, n_pad;
-  int P, tile_rows, ldt;
+  int P, tile_rows, ldt, R, NG, NST;
 };
 
-hipError_t launch_bgemm_n(const BatchArgs& a, const GemmItem* items, int nitems, int variant, hipStream_t st);
-hipError_t launch_bgemm_h(const BatchArgs& a, const GemmItem* items, int nitems, int variant, hipStream_t st);
+// Work items: forward {f, j, first k, first scene-tile, count, end k, partial
+// slot, first row}; adjoint {f, j, first column, first scene-tile, count}.
+// The forward GEMM (64 * ms rows per workgroup) over ks k-chunks, then the sum
+// of the chunks and r = g' - phase o (H0 x).
+hipError_t launch_bgemm_n(const BatchArgs& a, const GemmItem* items, int nitems, int ks, int ms, hipStream_t st);
+// The adjoint GEMM (64 * ms columns per workgroup), preceded by the split of
+// conj(phase) o y (k_bsplit_y).
+hipError_t launch_bgemm_h(const BatchArgs& a, const GemmItem* items, int nitems, int ms, hipStream_t st);
 hipError_t launch_bzupdate(const BatchArgs& a, const ColDesc* cols, const int4* tiles, int ntiles, hipStream_t st);
 hipError_t launch_btranspose(const BatchArgs& a, int P, int64_t m0, int max_nj, hipStream_t st);
 hipError_t launch_bgram_assemble(const int4* tiles, int ntiles, const BlockDesc* blocks, const int32_t* blk_tile0,

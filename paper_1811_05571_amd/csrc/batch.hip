@@ -3,6 +3,7 @@
 // block inverses in bounded FP64 groups), the MFMA tile autotuner, hipGraph
 // replay of the iteration and profiling.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -32,7 +33,21 @@ size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
     if (e_ != hipSuccess) return admm_fail(ADMM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int kGemmVariants[3] = {1, 2, 4};  // scene-tile columns per wave / 16
+// Autotuned variants: forward (rows per workgroup / 64, k-chunks per column
+// block); adjoint columns per workgroup / 64.
+#ifndef ADMM_FWD_MS
+#define ADMM_FWD_MS {2, 2, 1}
+#endif
+#ifndef ADMM_FWD_KS
+#define ADMM_FWD_KS {1, 2, 2}
+#endif
+constexpr int kFwdMS[3] = ADMM_FWD_MS;
+constexpr int kSplitVariants[3] = ADMM_FWD_KS;
+constexpr int kAdjMS[3] = {1, 2, 4};
+constexpr int max3(const int (&v)[3]) { return v[0] > v[1] ? (v[0] > v[2] ? v[0] : v[2]) : (v[1] > v[2] ? v[1] : v[2]); }
+// rows per forward workgroup / 64 of variant v for a tile height
+inline int fwd_ms(int v, int tile_rows) { return std::min(kFwdMS[v], tile_rows / 64); }
+constexpr int kGroupW = 64;   // scene-tile columns of one GEMM item
 
 struct BatchGeo {
   int64_t m0 = 0, n = 0;
@@ -56,8 +71,11 @@ struct BatchGeo {
   int R = 0, NST = 0, max_nj = 0;
   // workspace
   size_t o_hre = 0, o_him = 0, o_tre = 0, o_tim = 0, o_ginv = 0, o_G0 = 0, o_A = 0, o_W = 0, group_bytes = 0;
-  size_t o_c = 0, o_s = 0, o_v = 0, o_part = 0, o_gp = 0, o_ghat = 0, o_r = 0, o_y = 0, o_phase = 0;
+  size_t o_c = 0, o_s = 0, o_v = 0, o_part = 0, o_gp = 0, o_ghat = 0, o_r = 0, o_y = 0, o_cs = 0, o_ys = 0, o_phase = 0;
   size_t o_pseudo = 0, o_cols = 0, o_blocks = 0, o_rbd = 0, o_scenes = 0, o_stab = 0, o_cuts = 0, o_tiles = 0;
+  int NG = 0;                      // forward GEMM groups (f, scene-tile group, j)
+  std::vector<int2> st_gc;         // per scene-tile entry: first group, column in group
+  size_t o_pn = 0, o_stgc = 0;
   size_t o_tgram = 0, o_tgtr = 0, o_gpart = 0, o_tz = 0, o_items_n[3] = {0, 0, 0}, o_items_h[3] = {0, 0, 0}, o_ctl = 0;
   size_t o_gblocks = 0, o_ggram = 0, o_gtile0 = 0, g_max_blocks = 0, g_max_gram = 0, o_t0gram = 0;
   std::vector<int4> t0_gram;          // lower tiles of the pseudo blocks (G0)
@@ -68,9 +86,9 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
                 const int64_t* tiles_off, const int32_t* cuts, const int64_t* cuts_off, int P,
                 const int64_t* col_off, std::string& err) {
   char buf[256];
-  if (m0 < 1 || n < 1 || tile_rows < 32 || tile_rows % 32 || m0 % tile_rows || S < 1 || P < 1 || P > n ||
+  if (m0 < 1 || n < 1 || (tile_rows != 64 && tile_rows != 128 && tile_rows != 256) || m0 % tile_rows || S < 1 || P < 1 || P > n ||
       !tiles || !tiles_off || !cuts || !cuts_off) {
-    err = "need m0, n >= 1, tile_rows a multiple of 32 dividing m0, S >= 1, 1 <= P <= n and non-NULL scene tables";
+    err = "need m0, n >= 1, tile_rows in {64, 128, 256} dividing m0, S >= 1, 1 <= P <= n and non-NULL scene tables";
     return ADMM_EINVAL;
   }
   G.m0 = m0;
@@ -253,20 +271,53 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
   for (int s = 0; s < S; ++s)
     for (int j = 0; j < P; ++j)
       for (int c = 0; c < G.cols[j].nj; c += kZCols) G.t_z.push_back(make_int4(s, j, c, 0));
-  for (int v = 0; v < 3; ++v) {
-    const int W = 16 * kGemmVariants[v];
-    G.items_n[v].clear();
-    G.items_h[v].clear();
-    for (int f = 0; f < G.F; ++f) {
-      const int a0 = G.st_off[f], cntf = G.st_off[f + 1] - a0;
-      for (int k = 0; k < cntf; k += W)
-        for (int j = 0; j < P; ++j) {
-          for (int m = 0; m < tile_rows; m += 64)
-            G.items_n[v].push_back(GemmItem{f, j, m, a0 + k, std::min(W, cntf - k), {0, 0, 0}});
-          for (int c = 0; c < G.cols[j].nj; c += 64)
-            G.items_h[v].push_back(GemmItem{f, j, c, a0 + k, std::min(W, cntf - k), {0, 0, 0}});
-        }
+  // GEMM work items.  The items of one (tile, column block, scene group) read
+  // the same vector operand; workgroups are dealt to the 8 XCDs round-robin by
+  // index, so such items are placed at indices congruent mod 8 (windows of 8
+  // groups, item s of group g at window base + 8 s + g) to share one L2.
+  auto xcd_order = [](const std::vector<std::vector<GemmItem>>& groups, std::vector<GemmItem>& out) {
+    out.clear();
+    for (size_t w0 = 0; w0 < groups.size(); w0 += 8) {
+      const size_t w1 = std::min(groups.size(), w0 + 8);
+      size_t most = 0;
+      for (size_t g = w0; g < w1; ++g) most = std::max(most, groups[g].size());
+      for (size_t sub = 0; sub < most; ++sub)
+        for (size_t g = w0; g < w1; ++g)
+          if (sub < groups[g].size()) out.push_back(groups[g][sub]);
     }
+  };
+  // GEMM groups (f, scene-tile group of kGroupW, j) and the scene-tile -> group table
+  G.NG = 0;
+  G.st_gc.assign(G.stab.size(), make_int2(0, 0));
+  std::vector<std::array<int, 5>> groups;   // f, j, st0, cnt, g
+  for (int f = 0; f < G.F; ++f) {
+    const int a0 = G.st_off[f], cntf = G.st_off[f + 1] - a0;
+    for (int k = 0; k < cntf; k += kGroupW) {
+      for (int q = k; q < std::min(cntf, k + kGroupW); ++q) G.st_gc[a0 + q] = make_int2(G.NG, q - k);
+      for (int j = 0; j < P; ++j) groups.push_back({f, j, a0 + k, std::min(kGroupW, cntf - k), G.NG + j});
+      G.NG += P;
+    }
+  }
+  for (int v = 0; v < 3; ++v) {
+    std::vector<std::vector<GemmItem>> gn, gh;
+    for (const auto& g : groups) {
+      const int f = g[0], j = g[1], st0 = g[2], cnt = g[3], gi = g[4];
+      const int nk = (int)round_up(G.cols[j].nj, 32);
+      const int ks = kSplitVariants[v];
+      const int chunk = (int)round_up((nk + ks - 1) / ks, 32);
+      const int rows = 64 * fwd_ms(v, tile_rows);
+      gn.emplace_back();
+      for (int kc = 0; kc < ks; ++kc) {
+        const int k0 = std::min(nk, kc * chunk), k1 = std::min(nk, (kc + 1) * chunk);
+        for (int r0 = 0; r0 < tile_rows; r0 += rows)
+          gn.back().push_back(GemmItem{f, j, k0, st0, cnt, {k1, kc * G.NG + gi, r0}});
+      }
+      gh.emplace_back();
+      for (int c = 0; c < G.cols[j].nj; c += 64 * kAdjMS[v])
+        gh.back().push_back(GemmItem{f, j, c, st0, cnt, {0, 0, 0}});
+    }
+    xcd_order(gn, G.items_n[v]);
+    xcd_order(gh, G.items_h[v]);
   }
   G.t0_gram.clear();
   for (int j = 0; j < P; ++j)
@@ -317,7 +368,11 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
   G.o_ghat = take(rowv * P);
   G.o_r = take(rowv * P);
   G.o_y = take(rowv * P);
-  G.o_phase = take(8 * (size_t)G.rows_total);
+  G.o_cs = take((size_t)G.n_pad * G.R * 12);   // six bf16 planes (state: cleared with it)
+  G.o_ys = take((size_t)G.m_pad * P * 12);
+  G.o_phase = take(8 * (size_t)G.rows_total);   // from here on: not cleared per solve
+  G.o_pn = take((size_t)max3(kSplitVariants) * G.NG * G.tile_rows * kGroupW * 8);
+  G.o_stgc = take(8 * G.st_gc.size());
   G.o_pseudo = take(sizeof(BlockDesc) * P);
   G.o_cols = take(sizeof(ColDesc) * P);
   G.o_blocks = take(sizeof(BlockDesc) * G.blocks.size());
@@ -392,12 +447,19 @@ BatchArgs batch_args(admm_batch* b, const float2* g) {
   a.ghat = at<float2>(b, G.o_ghat);
   a.r = at<float2>(b, G.o_r);
   a.y = at<float2>(b, G.o_y);
+  a.cs = at<uint16_t>(b, G.o_cs);
+  a.ys = at<uint16_t>(b, G.o_ys);
+  a.pn = at<float2>(b, G.o_pn);
+  a.st_gc = at<int2>(b, G.o_stgc);
+  a.NG = G.NG;
+  a.NST = G.NST;
   a.ctl = at<Control>(b, G.o_ctl);
   a.m_pad = G.m_pad;
   a.n_pad = G.n_pad;
   a.P = G.P;
   a.tile_rows = G.tile_rows;
   a.ldt = (int)G.ldt;
+  a.R = G.R;
   return a;
 }
 
@@ -446,7 +508,7 @@ hipError_t launch_iteration(admm_batch* b, const float2* g, hipStream_t st, bool
   hipError_t e;
   if ((e = run(0, [&] {
          return launch_bgemm_n(a, at<GemmItem>(b, G.o_items_n[b->var_n]), (int)G.items_n[b->var_n].size(),
-                               kGemmVariants[b->var_n], st);
+                               kSplitVariants[b->var_n], fwd_ms(b->var_n, G.tile_rows), st);
        })) != hipSuccess)
     return e;
   if ((e = run(1, [&] {
@@ -456,7 +518,7 @@ hipError_t launch_iteration(admm_batch* b, const float2* g, hipStream_t st, bool
     return e;
   if ((e = run(2, [&] {
          return launch_bgemm_h(a, at<GemmItem>(b, G.o_items_h[b->var_h]), (int)G.items_h[b->var_h].size(),
-                               kGemmVariants[b->var_h], st);
+                               kAdjMS[b->var_h], st);
        })) != hipSuccess)
     return e;
   return run(3, [&] { return launch_bzupdate(a, at<ColDesc>(b, G.o_cols), at<int4>(b, G.o_tz), (int)G.t_z.size(), st); });
@@ -478,7 +540,7 @@ int drain(admm_batch* b) {
   return ADMM_OK;
 }
 
-// Time each tile variant of both GEMMs (3 launches, best) and keep the fastest.
+// Time each variant of both GEMMs (3 launches, best) and keep the fastest.
 int autotune(admm_batch* b, hipStream_t st) {
   static std::mutex mu;
   static std::map<std::tuple<int64_t, int64_t, int, int, int, int>, std::pair<int, int>> cache;
@@ -504,9 +566,10 @@ int autotune(admm_batch* b, hipStream_t st) {
       for (int rep = 0; rep < 3; ++rep) {
         BHIP(hipEventRecord(e0, st));
         if (which == 0)
-          BHIP(launch_bgemm_n(a, at<GemmItem>(b, G.o_items_n[v]), (int)G.items_n[v].size(), kGemmVariants[v], st));
+          BHIP(launch_bgemm_n(a, at<GemmItem>(b, G.o_items_n[v]), (int)G.items_n[v].size(), kSplitVariants[v],
+                              fwd_ms(v, G.tile_rows), st));
         else
-          BHIP(launch_bgemm_h(a, at<GemmItem>(b, G.o_items_h[v]), (int)G.items_h[v].size(), kGemmVariants[v], st));
+          BHIP(launch_bgemm_h(a, at<GemmItem>(b, G.o_items_h[v]), (int)G.items_h[v].size(), kAdjMS[v], st));
         BHIP(hipEventRecord(e1, st));
         BHIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -596,6 +659,7 @@ int admm_batch_setup(admm_batch** out, const void* H0, int64_t m0, int64_t n, in
   STRY(up(G.o_tgram, G.t_gram.data(), 16 * G.t_gram.size()));
   STRY(up(G.o_tgtr, G.t_gtr.data(), 16 * G.t_gtr.size()));
   STRY(up(G.o_tz, G.t_z.data(), 16 * G.t_z.size()));
+  STRY(up(G.o_stgc, G.st_gc.data(), 8 * G.st_gc.size()));
   for (int v = 0; v < 3; ++v) {
     STRY(up(G.o_items_n[v], G.items_n[v].data(), sizeof(GemmItem) * G.items_n[v].size()));
     STRY(up(G.o_items_h[v], G.items_h[v].data(), sizeof(GemmItem) * G.items_h[v].size()));
@@ -741,8 +805,8 @@ int admm_batch_info(const admm_batch* b, int64_t* info) {
   if (!b || !info) return admm_fail(ADMM_EINVAL, "batch plan and info must not be NULL");
   const BatchGeo& G = b->geo;
   int64_t v[16] = {G.m0, G.n, G.S, G.P, G.R, G.NST, (int64_t)G.total, (int64_t)(G.o_G0 - G.o_ginv),
-                   kGemmVariants[b->var_n], kGemmVariants[b->var_h], (int64_t)G.items_n[b->var_n].size(),
-                   (int64_t)G.items_h[b->var_h].size(), G.rows_total, 0, 0, 0};
+                   kSplitVariants[b->var_n], 64 * kAdjMS[b->var_h], (int64_t)G.items_n[b->var_n].size(),
+                   (int64_t)G.items_h[b->var_h].size(), G.rows_total, 64 * fwd_ms(b->var_n, G.tile_rows), 0, 0};
   std::memcpy(info, v, sizeof v);
   return ADMM_OK;
 }

@@ -70,13 +70,13 @@ struct Control {
   int32_t nonfinite;     // sticky NaN/Inf flag
   int32_t notpd;         // Cholesky pivot failure flag
   int32_t kkt_ticket;    // arrival counter of the KKT reduction
-  int32_t adj_ticket_k;  // arrival counters of the adjoint's scalar sums
-  int32_t adj_ticket_r;
+  int32_t unused0;
+  int32_t unused1;
   int32_t pad;
   double red[kRedCount]; // last iteration's reduction scalars
   double kkt;            // last KKT violation (unscaled)
-  double kbar;           // adjoint: d L / d kappa accumulated over iterations
-  double rbar;           // adjoint: d L / d rho through G^{-1} and ghat
+  double kbar;           // adjoint: d L / d kappa summed over iterations (k_adj_scalars)
+  double rbar;           // adjoint: d L / d rho through G^{-1} and ghat (k_adj_scalars)
 };
 static_assert(sizeof(Control) % 16 == 0, "Control size");
 

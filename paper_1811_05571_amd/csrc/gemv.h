@@ -185,25 +185,33 @@ __device__ __forceinline__ void cols_partial(const F& f, const BlockDesc& d, con
 // of a row group by a reduce-scatter (xor 8, 4) and an all-reduce (xor 2, 1);
 // column sums close over the wave by a reduce-scatter (xor 32, 16) and over
 // the 4 waves through 2 KB of LDS, always in the same order.
-// Loads of one tile in the thread layout of gram_tile_compute.
-__device__ __forceinline__ void gram_tile_load(const float2* __restrict__ G, float4 (&h)[4][2]) {
+// Operands of one tile in the thread layout of gram_tile_compute: the tile
+// entries and the thread's pieces of x_b (columns) and x_a (rows).
+struct GramOps {
+  float4 h[4][2];
+  float4 xb0, xb1, xa0, xa1;
+};
+__device__ __forceinline__ void gram_tile_load(const float2* __restrict__ G, const float2* __restrict__ xa,
+                                               const float2* __restrict__ xb, GramOps& o) {
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, b = l & 15;
   const int r0 = 16 * w + 4 * (l >> 4);
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
     for (int hf = 0; hf < 2; ++hf)
-      h[rr][hf] = ldnt4(reinterpret_cast<const float4*>(G + (r0 + rr) * 64 + 32 * hf + 2 * b));
+      o.h[rr][hf] = ldnt4(reinterpret_cast<const float4*>(G + (r0 + rr) * 64 + 32 * hf + 2 * b));
+  o.xb0 = *reinterpret_cast<const float4*>(xb + 2 * b);
+  o.xb1 = *reinterpret_cast<const float4*>(xb + 32 + 2 * b);
+  o.xa0 = *reinterpret_cast<const float4*>(xa + r0);
+  o.xa1 = *reinterpret_cast<const float4*>(xa + r0 + 2);
 }
 
-__device__ __forceinline__ void gram_tile_compute(const float4 (&h)[4][2], const float2* __restrict__ xa,
-                                                  const float2* __restrict__ xb, bool diag,
-                                                  float2* __restrict__ out_ab, float2* __restrict__ out_ba,
-                                                  float2 (&red)[4][64]) {
+__device__ __forceinline__ void gram_tile_compute(const GramOps& o, bool diag, float2* __restrict__ out_ab,
+                                                  float2* __restrict__ out_ba, float2 (&red)[4][64]) {
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, b = l & 15;
   const int r0 = 16 * w + 4 * (l >> 4);
-  const float4 xb0 = *reinterpret_cast<const float4*>(xb + 2 * b);
-  const float4 xb1 = *reinterpret_cast<const float4*>(xb + 32 + 2 * b);
+  const float4 (&h)[4][2] = o.h;
+  const float4 xb0 = o.xb0, xb1 = o.xb1;
   float pr[4], pi[4];
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
@@ -237,8 +245,7 @@ __device__ __forceinline__ void gram_tile_compute(const float4 (&h)[4][2], const
     if ((l & 3) == 0) out_ab[r0 + 2 * (int)s + (int)t] = make_float2(rr_, ri_);
   }
   if (diag) return;
-  const float4 xa0 = *reinterpret_cast<const float4*>(xa + r0);
-  const float4 xa1 = *reinterpret_cast<const float4*>(xa + r0 + 2);
+  const float4 xa0 = o.xa0, xa1 = o.xa1;
   const float xr[4] = {xa0.x, xa0.z, xa1.x, xa1.z}, xi[4] = {xa0.y, xa0.w, xa1.y, xa1.w};
   // column slot k: 0 -> 2b, 1 -> 2b+1, 2 -> 32+2b, 3 -> 33+2b
   float cr[4] = {0.f, 0.f, 0.f, 0.f}, ci[4] = {0.f, 0.f, 0.f, 0.f};
@@ -276,9 +283,9 @@ __device__ __forceinline__ void gram_tile_apply(const float2* __restrict__ G, co
                                                 const float2* __restrict__ xb, bool diag,
                                                 float2* __restrict__ out_ab, float2* __restrict__ out_ba,
                                                 float2 (&red)[4][64]) {
-  float4 h[4][2];
-  gram_tile_load(G, h);
-  gram_tile_compute(h, xa, xb, diag, out_ab, out_ba, red);
+  GramOps o;
+  gram_tile_load(G, xa, xb, o);
+  gram_tile_compute(o, diag, out_ab, out_ba, red);
 }
 
 // Sum of T strided complex partials in index order (loads issued four at a

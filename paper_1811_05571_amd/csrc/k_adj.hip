@@ -23,10 +23,13 @@
 
 namespace admm {
 
-// Ticketed FP64 sum of one value per workgroup into *total (fixed order).
-__device__ __forceinline__ void ticket_accumulate(double v, double* wgpart, int* ticket, double* total) {
+// Adds the workgroup's FP64 sum of v (fixed shuffle tree and wave order) to
+// its own slot wgpart[blockIdx.x].  Each launch of a kernel adds into the same
+// slots in stream order, so the slots hold per-workgroup sums over the
+// iterations; k_adj_scalars adds the slots once at the end of the sweep (no
+// fences or tickets between workgroups).
+__device__ __forceinline__ void slot_accumulate(double v, double* wgpart) {
   __shared__ double red[kBlockThreads / kWave];
-  __shared__ int last;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int nw = blockDim.x / kWave;
   v = wave_sum_d(v);
@@ -35,24 +38,7 @@ __device__ __forceinline__ void ticket_accumulate(double v, double* wgpart, int*
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += red[w];
-    wgpart[blockIdx.x] = s;
-    __threadfence();
-    last = (atomicAdd(ticket, 1) == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double s = 0.0;
-  for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
-    s += __hip_atomic_load(wgpart + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  s = wave_sum_d(s);
-  if (lane == 0) red[wave] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < nw; ++w) t += red[w];
-    *total += t;
-    *ticket = 0;
+    wgpart[blockIdx.x] += s;
   }
 }
 
@@ -88,7 +74,7 @@ __global__ __launch_bounds__(kZCols) void k_adj_z(AdjArgs a, const int4* __restr
       a.ub[(int64_t)i * a.n_pad + pc] = make_float2(fmaf(abr, invQ, sb.x), fmaf(abi, invQ, sb.y));
     }
   }
-  ticket_accumulate(kb, a.kpart, &a.ctl->adj_ticket_k, &a.ctl->kbar);
+  slot_accumulate(kb, a.kpart);
 }
 
 // yb_ij = H_ij ub_i - rho ghb_ij, with ghb (adjoint of the estimated data the
@@ -170,7 +156,7 @@ __global__ __launch_bounds__(kTile) void k_adj_gram_reduce(AdjArgs a, const int4
     const float2 y = yrec[vi];
     rhob = -((double)gr * y.x + (double)gi * y.y);
   }
-  ticket_accumulate(rhob, a.rpart, &a.ctl->adj_ticket_r, &a.ctl->rbar);
+  slot_accumulate(rhob, a.rpart);
 }
 
 // w = H^H rb, row-chunk partials.  tiles = adjoint-product tiles.
@@ -244,6 +230,32 @@ hipError_t launch_adj_iteration(const AdjArgs& a, const Geometry& G, const int4*
     default: hipLaunchKernelGGL(k_adj_cols<FmtFP8>, dim3(nc), dim3(kBlockThreads), 0, st, a, t_cols); break;
   }
   hipLaunchKernelGGL(k_adj_v, dim3(nz), dim3(kZCols), 0, st, a, t_z);
+  return hipGetLastError();
+}
+
+// kbar = sum of the k_adj_z slots, rbar = sum of the k_adj_gram_reduce slots
+// (each in slot order, then a fixed shuffle tree); one workgroup.
+__global__ __launch_bounds__(kBlockThreads) void k_adj_scalars(AdjArgs a, int nk, int nr) {
+  __shared__ double red[2][kBlockThreads / kWave];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  double k = 0.0, r = 0.0;
+  for (int b = threadIdx.x; b < nk; b += kBlockThreads) k += a.kpart[b];
+  for (int b = threadIdx.x; b < nr; b += kBlockThreads) r += a.rpart[b];
+  k = wave_sum_d(k);
+  r = wave_sum_d(r);
+  if (lane == 0) {
+    red[0][wave] = k;
+    red[1][wave] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.ctl->kbar = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+    a.ctl->rbar = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+  }
+}
+
+hipError_t launch_adj_scalars(const AdjArgs& a, int nk, int nr, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_scalars, dim3(1), dim3(kBlockThreads), 0, st, a, nk, nr);
   return hipGetLastError();
 }
 

@@ -7,8 +7,11 @@
 // written as one partial per (scene-tile, column) and added per row block
 // by the z-update.  Both are complex GEMMs done as real MFMA GEMMs
 // (v_mfma_f32_16x16x32_bf16, FP32 accumulation): H0 is stored in bfloat16,
-// the FP32 vector operand is split exactly enough into three bfloat16 terms
+// the FP32 vector operand is split into three bfloat16 terms
 // (x = x1 + x2 + x3 + O(2^-27 |x|)) so that the products keep FP32 accuracy.
+// The split is done once per iteration by the producer of each operand (the
+// z-update for c, k_bsplit_y for conj(phase) o y) into six bf16 planes that
+// the GEMMs load directly.
 #include "batch.h"
 
 namespace admm {
@@ -27,28 +30,45 @@ __device__ __forceinline__ f32x4 mfma(const bf16x8& a, const bf16x8& b, const f3
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// Eight complex FP32 values -> three bfloat16 terms each of Re and Im.
+// Three bfloat16 terms each of Re and Im of eight complex values.
 struct Split {
   bf16x8 r1, r2, r3, i1, i2, i3;
 };
-__device__ __forceinline__ void split8(const float (&re)[8], const float (&im)[8], Split& s) {
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    __bf16 a = (__bf16)re[e];
-    float rr = re[e] - (float)a;
-    __bf16 b = (__bf16)rr;
-    rr -= (float)b;
-    s.r1[e] = a;
-    s.r2[e] = b;
-    s.r3[e] = (__bf16)rr;
-    a = (__bf16)im[e];
-    rr = im[e] - (float)a;
-    b = (__bf16)rr;
-    rr -= (float)b;
-    s.i1[e] = a;
-    s.i2[e] = b;
-    s.i3[e] = (__bf16)rr;
-  }
+
+// x -> bf16 terms t1 + t2 + t3 (each the round-to-nearest-even bf16 of the
+// remainder), as 16-bit codes.
+__device__ __forceinline__ void split3(float x, uint16_t& t1, uint16_t& t2, uint16_t& t3) {
+  const __bf16 a = (__bf16)x;
+  float r = x - (float)a;
+  const __bf16 b = (__bf16)r;
+  r -= (float)b;
+  const __bf16 c = (__bf16)r;
+  t1 = __builtin_bit_cast(uint16_t, a);
+  t2 = __builtin_bit_cast(uint16_t, b);
+  t3 = __builtin_bit_cast(uint16_t, c);
+}
+
+// Writes the six planes of one complex value at element e (plane stride ps).
+__device__ __forceinline__ void store_split(uint16_t* __restrict__ base, int64_t ps, int64_t e, float re, float im) {
+  uint16_t t1, t2, t3;
+  split3(re, t1, t2, t3);
+  base[e] = t1;
+  base[ps + e] = t2;
+  base[2 * ps + e] = t3;
+  split3(im, t1, t2, t3);
+  base[3 * ps + e] = t1;
+  base[4 * ps + e] = t2;
+  base[5 * ps + e] = t3;
+}
+
+// Eight consecutive elements of each of the six planes (16-byte loads).
+__device__ __forceinline__ void load_split(const uint16_t* __restrict__ p, int64_t ps, Split& x) {
+  x.r1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
+  x.r2 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p + ps));
+  x.r3 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p + 2 * ps));
+  x.i1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p + 3 * ps));
+  x.i2 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p + 4 * ps));
+  x.i3 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p + 5 * ps));
 }
 
 // acc += A X for complex A = (Ar, Ai), X split:  Cr += Ar Xr - Ai Xi, Ci += Ar Xi + Ai Xr.
@@ -70,161 +90,234 @@ __device__ __forceinline__ void cmfma(const bf16x8& Ar, const bf16x8& Ai, const 
 
 __device__ __forceinline__ bf16x8 as_bf16(const u32x4& v) { return __builtin_bit_cast(bf16x8, v); }
 
-// Forward product.  One workgroup = 4 waves x 16 rows of tile f (64 rows) x
-// up to 16*NT scene-tiles.  MFMA operand layout (16x16x32): lane l holds row
-// (A) / column (B) l%16 and k = 8(l/16) .. 8(l/16)+7; the result holds
-// column l%16, rows 4(l/16) .. 4(l/16)+3.
-template <int NT>
+// ---- MFMA GEMM tiles -------------------------------------------------------
+// MFMA operand layout (16x16x32 bf16): lane l holds row (A) / column (B)
+// l%16 and k = 8(l/16) .. 8(l/16)+7; the result holds column l%16, rows
+// 4(l/16) .. 4(l/16)+3.  A workgroup of 4 waves computes (4 * 16 * MS rows) x
+// (64 scene-tile columns); wave w owns MS row subtiles and all four column
+// subtiles, so each B fragment feeds MS complex MFMA groups.  Per 32-wide
+// k-step the B operand (64 columns x 32 k x six bf16 planes, 24 KB) is staged
+// once in LDS (double buffer: the next step's pieces are loaded into registers
+// during the current step's MFMAs); A comes straight from global memory, one
+// step ahead.
+constexpr int kGN = 64;   // scene-tile columns per workgroup
+constexpr int kGK = 32;   // k per step
+
+struct __attribute__((aligned(16))) BStage {
+  uint16_t v[2][6][kGN][kGK];
+};
+static_assert(alignof(BStage) == 16, "16-byte LDS accesses");
+
+// This thread's piece of a B step: column tid/4, k offset 8 (tid % 4); six
+// 16-byte loads from plane stride ps.
+__device__ __forceinline__ void bstage_load(const uint16_t* __restrict__ src, int64_t ps, u32x4 (&r)[6]) {
+#pragma unroll
+  for (int p = 0; p < 6; ++p) r[p] = *reinterpret_cast<const u32x4*>(src + p * ps);
+}
+__device__ __forceinline__ void bstage_store(BStage& bs, int buf, const u32x4 (&r)[6]) {
+  const int col = threadIdx.x >> 2, k = 8 * (threadIdx.x & 3);
+#pragma unroll
+  for (int p = 0; p < 6; ++p) *reinterpret_cast<u32x4*>(&bs.v[buf][p][col][k]) = r[p];
+}
+__device__ __forceinline__ void bstage_frag(const BStage& bs, int buf, int nt, Split& x) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int col = 16 * nt + (lane & 15), k = 8 * (lane >> 4);
+  x.r1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&bs.v[buf][0][col][k]));
+  x.r2 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&bs.v[buf][1][col][k]));
+  x.r3 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&bs.v[buf][2][col][k]));
+  x.i1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&bs.v[buf][3][col][k]));
+  x.i2 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&bs.v[buf][4][col][k]));
+  x.i3 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&bs.v[buf][5][col][k]));
+}
+
+// Accumulates over k in [k0, k1) (multiples of kGK): a_re/a_im[m] point at
+// this lane's A row of subtile m at k = 0 (+ its 8-element k offset), bsrc at
+// this thread's B piece at k = 0, plane stride ps.  conj_a: use conj(A).
+template <int MS>
+__device__ __forceinline__ void gemm_tile(const uint16_t* const (&a_re)[MS], const uint16_t* const (&a_im)[MS],
+                                          const uint16_t* __restrict__ bsrc, int64_t ps, int k0, int k1, int ntv,
+                                          bool conj_a, BStage& bs, f32x4 (&accr)[MS][4], f32x4 (&acci)[MS][4]) {
+  const u32x4 sgn = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  u32x4 br[6];
+  u32x4 ar[MS], ai[MS];
+  bstage_load(bsrc + k0, ps, br);
+#pragma unroll
+  for (int m = 0; m < MS; ++m) {
+    ar[m] = ld16(a_re[m] + k0);
+    ai[m] = ld16(a_im[m] + k0);
+  }
+  bstage_store(bs, 0, br);
+  __syncthreads();
+  int buf = 0;
+  for (int k = k0; k < k1; k += kGK) {
+    // next step's operands (the last step reloads its own: no branch around
+    // the loads, so they stay in flight during this step's MFMAs)
+    const int kn = k + kGK < k1 ? k + kGK : k;
+    u32x4 arn[MS], ain[MS];
+    bstage_load(bsrc + kn, ps, br);
+#pragma unroll
+    for (int m = 0; m < MS; ++m) {
+      arn[m] = ld16(a_re[m] + kn);
+      ain[m] = ld16(a_im[m] + kn);
+    }
+    bf16x8 A1[MS], A2[MS], A3[MS];   // (Re, Im, -Im) of A, or (Re, -Im, Im) for conj(A)
+#pragma unroll
+    for (int m = 0; m < MS; ++m) {
+      A1[m] = as_bf16(ar[m]);
+      A2[m] = as_bf16(conj_a ? (ai[m] ^ sgn) : ai[m]);
+      A3[m] = as_bf16(conj_a ? ai[m] : (ai[m] ^ sgn));
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      if (nt < ntv) {
+        Split x;
+        bstage_frag(bs, buf, nt, x);
+#pragma unroll
+        for (int m = 0; m < MS; ++m) cmfma(A1[m], A2[m], A3[m], x, accr[m][nt], acci[m][nt]);
+      }
+    }
+    bstage_store(bs, buf ^ 1, br);   // buffer buf ^ 1 was last read before the previous barrier
+#pragma unroll
+    for (int m = 0; m < MS; ++m) {
+      ar[m] = arn[m];
+      ai[m] = ain[m];
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
+// Forward product, one k-chunk: partial sums of H0[f, C_j] X over columns
+// [it.m0, it.pad[0]) for rows [it.pad[2], it.pad[2] + 64 MS) of the tile and
+// the up to 64 scene-tiles of the item, written to partial slot it.pad[1]
+// ([slot][tile_rows][64], complex).
+template <int MS>
 __global__ __launch_bounds__(kBlockThreads) void k_bgemm_n(BatchArgs a, const GemmItem* __restrict__ items) {
+  __shared__ BStage bs;
   const GemmItem it = items[blockIdx.x];
   const BlockDesc pj = a.pseudo[it.j];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int kq = 8 * (lane >> 4);
-  const int64_t arow = (int64_t)it.f * a.tile_rows + it.m0 + 16 * wave + (lane & 15);
-  const uint16_t* are = a.h_re + pj.h_off + arow * pj.ld + kq;
-  const uint16_t* aim = a.h_im + pj.h_off + arow * pj.ld + kq;
-  const float4* xs[NT];
-  bool xv[NT];
+  const uint16_t* are[MS];
+  const uint16_t* aim[MS];
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
-    const int t = 16 * nt + (lane & 15);
-    xv[nt] = t < it.cnt;
-    const SceneTile st = a.stab[it.st0 + (xv[nt] ? t : 0)];
-    xs[nt] = reinterpret_cast<const float4*>(a.c + (int64_t)st.rep * a.n_pad + pj.cpad0 + kq);
+  for (int m = 0; m < MS; ++m) {
+    const int64_t arow = (int64_t)it.f * a.tile_rows + it.pad[2] + 16 * (wave * MS + m) + (lane & 15);
+    are[m] = a.h_re + pj.h_off + arow * pj.ld + kq;
+    aim[m] = a.h_im + pj.h_off + arow * pj.ld + kq;
   }
-  f32x4 cr[NT], ci[NT];
+  // B piece of this thread: the split planes of c (columns beyond cnt read a
+  // valid scene-tile; their results are not stored)
+  const int bcol = threadIdx.x >> 2;
+  const SceneTile stb = a.stab[it.st0 + min(bcol, it.cnt - 1)];
+  const uint16_t* bsrc = a.cs + (int64_t)stb.rep * a.n_pad + pj.cpad0 + 8 * (threadIdx.x & 3);
+  f32x4 accr[MS][4], acci[MS][4];
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const u32x4 sgn = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-  for (int k0 = 0; k0 < pj.nj; k0 += 32) {
-    const u32x4 ur = ld16(are + k0), ui = ld16(aim + k0);
-    const bf16x8 Ar = as_bf16(ur), Ai = as_bf16(ui), nAi = as_bf16(ui ^ sgn);
+  for (int m = 0; m < MS; ++m)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      float re[8], im[8];
-      if (xv[nt]) {
-        const float4* xp = xs[nt] + (k0 >> 1);
+    for (int nt = 0; nt < 4; ++nt) accr[m][nt] = acci[m][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int ntv = (it.cnt + 15) >> 4;
+  if (it.m0 < it.pad[0])   // an empty chunk writes zeros
+    gemm_tile<MS>(are, aim, bsrc, (int64_t)a.R * a.n_pad, it.m0, it.pad[0], ntv, false, bs, accr, acci);
+  float2* out = a.pn + (int64_t)it.pad[1] * a.tile_rows * kGN;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float4 v = xp[q];
-          re[2 * q] = v.x;
-          im[2 * q] = v.y;
-          re[2 * q + 1] = v.z;
-          im[2 * q + 1] = v.w;
-        }
-      } else {
+  for (int m = 0; m < MS; ++m)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) re[e] = im[e] = 0.f;
+    for (int nt = 0; nt < 4; ++nt) {
+      const int col = 16 * nt + (lane & 15);
+      if (col >= it.cnt) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = it.pad[2] + 16 * (wave * MS + m) + 4 * (lane >> 4) + e;
+        out[(int64_t)row * kGN + col] = make_float2(accr[m][nt][e], acci[m][nt][e]);
       }
-      Split x;
-      split8(re, im, x);
-      cmfma(Ar, Ai, nAi, x, cr[nt], ci[nt]);
     }
-  }
-  // epilogue: r = g' - phase * (H0 x)
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
-    const int t = 16 * nt + (lane & 15);
-    if (t >= it.cnt) continue;
-    const SceneTile st = a.stab[it.st0 + t];
-    const RowBlockDesc rb = a.rbd[st.rep];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int rr = it.m0 + 16 * wave + 4 * (lane >> 4) + e;
-      const int64_t gr = st.row0 + rr;
-      const int lr = st.lr0 + rr;
-      const float2 ph = a.phases[gr];
-      const float hr = ph.x * cr[nt][e] - ph.y * ci[nt][e];
-      const float hi = ph.x * ci[nt][e] + ph.y * cr[nt][e];
-      const int64_t vi = (int64_t)it.j * a.m_pad + rb.rpad0 + lr;
-      float2 gpv = a.g[gr];
-      if (a.P > 1) {
-        for (int q = 0; q < a.P; ++q) {
-          if (q == it.j) continue;
-          const float2 e2 = a.ghat[(int64_t)q * a.m_pad + rb.rpad0 + lr];
-          gpv.x -= e2.x;
-          gpv.y -= e2.y;
-        }
-        a.gp[vi] = gpv;
-      }
-      a.r[vi] = make_float2(gpv.x - hr, gpv.y - hi);
-    }
-  }
 }
 
-// Adjoint product.  One workgroup = 4 waves x 16 columns of block j (64
-// columns) x up to 16*NT scene-tiles; K = the tile's rows, read from the
-// transposed store so that every lane's 8 k-values are contiguous.
-template <int NT>
+// r = g' - phase o (sum of the KS k-chunk partials, in chunk order) for one
+// (scene-tile, column block): blockIdx.x = scene-tile entry, blockIdx.y = j,
+// one thread per tile row.
+__global__ __launch_bounds__(kBlockThreads) void k_bgemm_n_fin(BatchArgs a, int KS) {
+  const int p = blockIdx.x, j = blockIdx.y, rr = threadIdx.x;
+  if (rr >= a.tile_rows) return;
+  const SceneTile st = a.stab[p];
+  const int2 gc = a.st_gc[p];
+  const int64_t g = gc.x + j;
+  float hr = 0.f, hi = 0.f;
+  for (int kc = 0; kc < KS; ++kc) {
+    const float2 q = a.pn[(((int64_t)kc * a.NG + g) * a.tile_rows + rr) * kGN + gc.y];
+    hr += q.x;
+    hi += q.y;
+  }
+  const RowBlockDesc rb = a.rbd[st.rep];
+  const int64_t gr = st.row0 + rr;
+  const int lr = st.lr0 + rr;
+  const float2 ph = a.phases[gr];
+  const float pr = ph.x * hr - ph.y * hi, pi = ph.x * hi + ph.y * hr;
+  const int64_t vi = (int64_t)j * a.m_pad + rb.rpad0 + lr;
+  float2 gpv = a.g[gr];
+  if (a.P > 1) {
+    for (int q = 0; q < a.P; ++q) {
+      if (q == j) continue;
+      const float2 e2 = a.ghat[(int64_t)q * a.m_pad + rb.rpad0 + lr];
+      gpv.x -= e2.x;
+      gpv.y -= e2.y;
+    }
+    a.gp[vi] = gpv;
+  }
+  a.r[vi] = make_float2(gpv.x - pr, gpv.y - pi);
+}
+
+// Adjoint product: U = H0[f, C_j]^H Y' for 4 * 16 * MS columns of block j
+// (from it.m0) and the up to 64 scene-tiles of the item; K = the tile's rows,
+// read from the transposed store.  Writes one partial per (scene-tile, column).
+template <int MS>
 __global__ __launch_bounds__(kBlockThreads) void k_bgemm_h(BatchArgs a, const GemmItem* __restrict__ items) {
+  __shared__ BStage bs;
   const GemmItem it = items[blockIdx.x];
   const BlockDesc pj = a.pseudo[it.j];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int kq = 8 * (lane >> 4);
-  const int col = it.m0 + 16 * wave + (lane & 15);
-  const int colc = min(col, pj.nj - 1);
-  const uint16_t* are = a.t_re + pj.gi_off + (int64_t)colc * a.ldt + (int64_t)it.f * a.tile_rows + kq;
-  const uint16_t* aim = a.t_im + pj.gi_off + (int64_t)colc * a.ldt + (int64_t)it.f * a.tile_rows + kq;
-  const float4* ys[NT];
-  const float4* ps[NT];
-  bool yv[NT];
+  const uint16_t* are[MS];
+  const uint16_t* aim[MS];
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
-    const int t = 16 * nt + (lane & 15);
-    yv[nt] = t < it.cnt;
-    const SceneTile st = a.stab[it.st0 + (yv[nt] ? t : 0)];
-    const RowBlockDesc rb = a.rbd[st.rep];
-    ys[nt] = reinterpret_cast<const float4*>(a.y + (int64_t)it.j * a.m_pad + rb.rpad0 + st.lr0 + kq);
-    ps[nt] = reinterpret_cast<const float4*>(a.phases + (int64_t)st.row0 + kq);
+  for (int m = 0; m < MS; ++m) {
+    const int col = it.m0 + 16 * (wave * MS + m) + (lane & 15);
+    const int64_t colc = min(col, pj.nj - 1);
+    are[m] = a.t_re + pj.gi_off + colc * a.ldt + (int64_t)it.f * a.tile_rows + kq;
+    aim[m] = a.t_im + pj.gi_off + colc * a.ldt + (int64_t)it.f * a.tile_rows + kq;
   }
-  f32x4 cr[NT], ci[NT];
+  const int bcol = threadIdx.x >> 2;
+  const SceneTile stb = a.stab[it.st0 + min(bcol, it.cnt - 1)];
+  const RowBlockDesc rbb = a.rbd[stb.rep];
+  const uint16_t* bsrc = a.ys + (int64_t)it.j * a.m_pad + rbb.rpad0 + stb.lr0 + 8 * (threadIdx.x & 3);
+  f32x4 accr[MS][4], acci[MS][4];
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const u32x4 sgn = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-  for (int k0 = 0; k0 < a.tile_rows; k0 += 32) {
-    const u32x4 ur = ld16(are + k0), ui = ld16(aim + k0);
-    // conj(H0)^T: real part Ar, imaginary part -Ai
-    const bf16x8 Ar = as_bf16(ur), cAi = as_bf16(ui ^ sgn), Ai = as_bf16(ui);
+  for (int m = 0; m < MS; ++m)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      float re[8], im[8];
-      if (yv[nt]) {
-        const float4* yp = ys[nt] + (k0 >> 1);
-        const float4* pp = ps[nt] + (k0 >> 1);
+    for (int nt = 0; nt < 4; ++nt) accr[m][nt] = acci[m][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int ntv = (it.cnt + 15) >> 4;
+  gemm_tile<MS>(are, aim, bsrc, (int64_t)a.P * a.m_pad, 0, a.tile_rows, ntv, true, bs, accr, acci);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float4 yy = yp[q], ph = pp[q];
-          // conj(phase) * y
-          re[2 * q] = ph.x * yy.x + ph.y * yy.y;
-          im[2 * q] = ph.x * yy.y - ph.y * yy.x;
-          re[2 * q + 1] = ph.z * yy.z + ph.w * yy.w;
-          im[2 * q + 1] = ph.z * yy.w - ph.w * yy.z;
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) re[e] = im[e] = 0.f;
-      }
-      Split x;
-      split8(re, im, x);
-      // (Ar + i cAi)(Xr + i Xi) with cAi = -Ai
-      cmfma(Ar, cAi, Ai, x, cr[nt], ci[nt]);
-    }
-  }
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
+  for (int nt = 0; nt < 4; ++nt) {
     const int t = 16 * nt + (lane & 15);
     if (t >= it.cnt) continue;
-    const SceneTile st = a.stab[it.st0 + t];
-    float2* out = a.part + (int64_t)st.pslot * a.n_pad + pj.cpad0;
+    float2* out = a.part + (int64_t)a.stab[it.st0 + t].pslot * a.n_pad + pj.cpad0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int cc = it.m0 + 16 * wave + 4 * (lane >> 4) + e;
-      if (cc < pj.nj) out[cc] = make_float2(cr[nt][e], ci[nt][e]);
-    }
+    for (int m = 0; m < MS; ++m)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int cc = it.m0 + 16 * (wave * MS + m) + 4 * (lane >> 4) + e;
+        if (cc < pj.nj) out[cc] = make_float2(accr[m][nt][e], acci[m][nt][e]);
+      }
   }
 }
 
-// Per-scene z-update: tiles {scene, column block, first column}, 64 columns per workgroup.
+// Per-scene z-update: tiles {scene, column block, first column}, 64 columns
+// per workgroup.  u_i = c_i + the adjoint partials of row block i's tiles is
+// formed once and kept in registers (scenes have at most kMaxQ row blocks;
+// more are recomputed in the second pass).
+constexpr int kMaxQ = 8;
 __global__ __launch_bounds__(kZCols) void k_bzupdate(BatchArgs a, const ColDesc* __restrict__ cols,
                                                      const int4* __restrict__ tiles) {
   const int4 t = tiles[blockIdx.x];
@@ -244,13 +337,20 @@ __global__ __launch_bounds__(kZCols) void k_bzupdate(BatchArgs a, const ColDesc*
     }
     return u;
   };
+  float2 ur[kMaxQ];
   float ar = 0.f, ai = 0.f;
-  for (int i = 0; i < sd.Q; ++i) {
-    const float2 u = replica(i);
+  auto add_mean = [&](int i, const float2& u) {
     const float2 sv = a.s[(int64_t)(sd.rb0 + i) * a.n_pad + p];
     ar += u.x + sv.x;
     ai += u.y + sv.y;
-  }
+  };
+#pragma unroll
+  for (int i = 0; i < kMaxQ; ++i)
+    if (i < sd.Q) {
+      ur[i] = replica(i);
+      add_mean(i, ur[i]);
+    }
+  for (int i = kMaxQ; i < sd.Q; ++i) add_mean(i, replica(i));
   const float invQ = 1.0f / (float)sd.Q;
   ar *= invQ;
   ai *= invQ;
@@ -263,13 +363,32 @@ __global__ __launch_bounds__(kZCols) void k_bzupdate(BatchArgs a, const ColDesc*
     vi = ai * sc;
   }
   a.v[(int64_t)t.x * a.n_pad + p] = make_float2(vr, vi);
-  for (int i = 0; i < sd.Q; ++i) {
-    const float2 u = replica(i);
+  auto update = [&](int i, const float2& u) {
     const int64_t ip = (int64_t)(sd.rb0 + i) * a.n_pad + p;
     const float2 sv = a.s[ip];
     const float sr = sv.x + u.x - vr, si = sv.y + u.y - vi;
     a.s[ip] = make_float2(sr, si);
     a.c[ip] = make_float2(vr - sr, vi - si);
+    store_split(a.cs, (int64_t)a.R * a.n_pad, ip, vr - sr, vi - si);
+  };
+#pragma unroll
+  for (int i = 0; i < kMaxQ; ++i)
+    if (i < sd.Q) update(i, ur[i]);
+  for (int i = kMaxQ; i < sd.Q; ++i) update(i, replica(i));
+}
+
+// conj(phase) o y of every scene row, split into the six planes of ys.
+// Grid (row chunks, row blocks); rows beyond the block are not touched.
+__global__ __launch_bounds__(kBlockThreads) void k_bsplit_y(BatchArgs a) {
+  const RowBlockDesc rb = a.rbd[blockIdx.y];
+  const int64_t ps = (int64_t)a.P * a.m_pad;
+  for (int r = blockIdx.x * kBlockThreads + threadIdx.x; r < rb.mi; r += gridDim.x * kBlockThreads) {
+    const float2 ph = a.phases[(int64_t)rb.row0 + r];
+    for (int j = 0; j < a.P; ++j) {
+      const int64_t e = (int64_t)j * a.m_pad + rb.rpad0 + r;
+      const float2 yy = a.y[e];
+      store_split(a.ys, ps, e, ph.x * yy.x + ph.y * yy.y, ph.x * yy.y - ph.y * yy.x);
+    }
   }
 }
 
@@ -352,17 +471,21 @@ __global__ void k_bunpad_v(const ColDesc* __restrict__ cols, int64_t n, int64_t 
 
 }  // namespace
 
-hipError_t launch_bgemm_n(const BatchArgs& a, const GemmItem* items, int nitems, int variant, hipStream_t st) {
-  switch (variant) {
+hipError_t launch_bgemm_n(const BatchArgs& a, const GemmItem* items, int nitems, int ks, int ms, hipStream_t st) {
+  switch (ms) {
     case 1: hipLaunchKernelGGL(k_bgemm_n<1>, dim3(nitems), dim3(kBlockThreads), 0, st, a, items); break;
     case 2: hipLaunchKernelGGL(k_bgemm_n<2>, dim3(nitems), dim3(kBlockThreads), 0, st, a, items); break;
     default: hipLaunchKernelGGL(k_bgemm_n<4>, dim3(nitems), dim3(kBlockThreads), 0, st, a, items); break;
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bgemm_n_fin, dim3(a.NST, a.P), dim3(kBlockThreads), 0, st, a, ks);
   return hipGetLastError();
 }
 
-hipError_t launch_bgemm_h(const BatchArgs& a, const GemmItem* items, int nitems, int variant, hipStream_t st) {
-  switch (variant) {
+hipError_t launch_bgemm_h(const BatchArgs& a, const GemmItem* items, int nitems, int ms, hipStream_t st) {
+  hipLaunchKernelGGL(k_bsplit_y, dim3(8, a.R), dim3(kBlockThreads), 0, st, a);
+  switch (ms) {
     case 1: hipLaunchKernelGGL(k_bgemm_h<1>, dim3(nitems), dim3(kBlockThreads), 0, st, a, items); break;
     case 2: hipLaunchKernelGGL(k_bgemm_h<2>, dim3(nitems), dim3(kBlockThreads), 0, st, a, items); break;
     default: hipLaunchKernelGGL(k_bgemm_h<4>, dim3(nitems), dim3(kBlockThreads), 0, st, a, items); break;

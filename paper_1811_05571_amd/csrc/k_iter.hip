@@ -117,51 +117,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4
 // y_ij = G_ij^{-1} r_ij over the packed lower tiles of the inverse: every
 // tile is read once and contributes to two 64-row pieces of y (gram_tile_apply);
 // k_gram_reduce adds the pieces in tile order and forms ghat_ij = g'_ij - rho y_ij.
-// tiles[x] = {block, tile row, tile col, -} (lower pairs).  Each workgroup
-// takes kGramTPW consecutive tiles and issues the next tile's loads before
-// the current tile's reductions.
-__device__ __forceinline__ const float2* gram_tile_ptr(const IterArgs& a, const int4& t, const BlockDesc& d) {
-  return a.Ginv + d.gi_off + (int64_t)(t.y * (t.y + 1) / 2 + t.z) * (kTile * kTile);
-}
-__global__ __launch_bounds__(kBlockThreads) void k_gram_tile(IterArgs a, const int4* __restrict__ tiles,
-                                                             int ntiles) {
+// tiles[x] = {block, tile row, tile col, -} (lower pairs), one per workgroup.
+__global__ __launch_bounds__(kBlockThreads) void k_gram_tile(IterArgs a, const int4* __restrict__ tiles) {
   __shared__ float2 tt[4][64];
-  const int base = blockIdx.x * kGramTPW;
-  const int cnt = min(kGramTPW, ntiles - base);
-  int4 t = tiles[base];
-  BlockDesc d = a.blocks[t.x];
-  float4 h[4][2];
-  gram_tile_load(gram_tile_ptr(a, t, d), h);
-  for (int w = 0; w < cnt; ++w) {
-    float4 hn[4][2];
-    int4 tn = t;
-    BlockDesc dn = d;
-    if (w + 1 < cnt) {
-      tn = tiles[base + w + 1];
-      dn = a.blocks[tn.x];
-      gram_tile_load(gram_tile_ptr(a, tn, dn), hn);
-    }
-    const int T = d.mt / kTile;
-    const float2* x = a.r + (int64_t)d.j * a.m_pad + d.rpad0;
-    float2* part = a.gpart + (int64_t)d.gpo * kTile;
-    gram_tile_compute(h, x + t.y * kTile, x + t.z * kTile, t.y == t.z, part + (int64_t)(t.y * T + t.z) * kTile,
-                      part + (int64_t)(t.z * T + t.y) * kTile, tt);
-    if (w + 1 < cnt) {
-      __syncthreads();   // tt is read by the previous tile's column sums
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        h[rr][0] = hn[rr][0];
-        h[rr][1] = hn[rr][1];
-      }
-      t = tn;
-      d = dn;
-    }
-  }
+  const int4 t = tiles[blockIdx.x];
+  const BlockDesc d = a.blocks[t.x];
+  const int T = d.mt / kTile;
+  const float2* G = a.Ginv + d.gi_off + (int64_t)(t.y * (t.y + 1) / 2 + t.z) * (kTile * kTile);
+  const float2* x = a.r + (int64_t)d.j * a.m_pad + d.rpad0;
+  float2* part = a.gpart + (int64_t)d.gpo * kTile;
+  gram_tile_apply(G, x + t.y * kTile, x + t.z * kTile, t.y == t.z, part + (int64_t)(t.y * T + t.z) * kTile,
+                  part + (int64_t)(t.z * T + t.y) * kTile, tt);
 }
 
-// tiles[x] = {block, tile row, -, -}; 256 threads: row l = tid % 64 adds the
-// pieces k = tid / 64, tid / 64 + 4, ... in increasing k, and the four sums
-// are added in a fixed order.
 static_assert(kBlockThreads / kTile == 4, "k_gram_reduce adds four interleaved sums per row");
 __global__ __launch_bounds__(kBlockThreads) void k_gram_reduce(IterArgs a, const int4* __restrict__ tiles) {
   __shared__ float2 red[kBlockThreads / kTile][kTile];
@@ -366,8 +334,7 @@ hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipSt
 }
 hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gtr, int n_gtr,
                        hipStream_t st, KTime kt) {
-  const int nwg = (n_gram + kGramTPW - 1) / kGramTPW;
-  LAUNCH_TIMED(k_gram_tile, dim3(nwg), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gram, n_gram);
+  LAUNCH_TIMED(k_gram_tile, dim3(n_gram), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gram);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   LAUNCH_TIMED(k_gram_reduce, dim3(n_gtr), dim3(kBlockThreads), st, (KTime{nullptr, kt.stop}), a, t_gtr);

@@ -57,11 +57,8 @@ struct Geometry {
 #ifndef ADMM_COLS_WG_TARGET_C64
 #define ADMM_COLS_WG_TARGET_C64 4096  // the same for complex64 storage
 #endif
-#ifndef ADMM_GRAM_TPW
-#define ADMM_GRAM_TPW 1         // packed inverse tiles per workgroup of the Gram apply
-#endif
 constexpr int kRowWaves = ADMM_ROW_WAVES;
-constexpr int kGramTPW = ADMM_GRAM_TPW;
+
 static_assert(kRowWaves >= 1 && kRowWaves <= kBlockThreads / kWave, "row waves");
 
 // Rows handled by one workgroup of the row-parallel products.
@@ -121,6 +118,9 @@ struct AdjArgs {
 hipError_t launch_adj_iteration(const AdjArgs& a, const Geometry& G, const int4* t_hrows, const int4* t_gram,
                                 const int4* t_gtr, const int4* t_cols, const int4* t_z, const float2* arec,
                                 const float2* yrec, hipStream_t st);
+// Final kbar / rbar from the per-workgroup slots of nk z-workgroups and nr
+// Gram-reduce workgroups.
+hipError_t launch_adj_scalars(const AdjArgs& a, int nk, int nr, hipStream_t st);
 hipError_t launch_adj_gflush(const AdjArgs& a, const BlockDesc* blocks, int nblocks, float2* grad_g,
                              hipStream_t st);
 

@@ -103,7 +103,7 @@ def test_full_size_adjoint_central_differences(torch_gpu, full):
 
 def test_full_size_batch_sampled_scenes(torch_gpu):
     """The 64-scene batched workload in the configuration the benchmark times
-    (256-row frequency tiles, bf16 H0, autotuned MFMA tile widths, graph
+    (256-row frequency tiles, bf16 H0, autotuned MFMA GEMM shapes, graph
     replay): after 3 iterations, the first scene of each row split
     Q in {2, 4, 8} matches the FP64 oracle run on that scene's stored matrix
     diag(phase) bf16(H0)[rows] (arithmetic error only: FP32 bar 1e-5)."""
