@@ -35,13 +35,15 @@ __device__ __forceinline__ double wave_sum_d(double x) {
   return x;
 }
 
-// Loads in flight per row: the same bytes per lane for every format.
-template <class F> struct RowUnroll { static constexpr int U = F::CPL == 2 ? 4 : 2; };
+// Rows in flight per wave in the adjoint (column) product.
+template <class F> struct ColUnroll {
+  static constexpr int U = F::CPL == 2 ? ADMM_COLS_UNROLL_C64 : ADMM_COLS_UNROLL_NARROW;
+};
 // H row products: rows per wave and lane loads in flight per row (narrow
 // formats reuse each lane's vector loads across 8 rows).
 template <class F> struct HRows {
-  static constexpr int R = F::CPL == 2 ? ADMM_ROWS_C64 : 8;
-  static constexpr int U = F::CPL == 2 ? ADMM_UNROLL_C64 : 1;
+  static constexpr int R = F::CPL == 2 ? ADMM_ROWS_C64 : ADMM_ROWS_NARROW;
+  static constexpr int U = F::CPL == 2 ? ADMM_UNROLL_C64 : ADMM_UNROLL_NARROW;
 };
 
 // Dot products of R consecutive rows of a stored matrix with the complex
@@ -113,7 +115,7 @@ template <class F>
 __device__ __forceinline__ void cols_partial(const F& f, const BlockDesc& d, const int4& t, int KH,
                                              const float2* __restrict__ y, float2* __restrict__ out,
                                              float (&red)[kBlockThreads / kWave - 1][2 * F::CPL][kWave]) {
-  constexpr int CPL = F::CPL, U = RowUnroll<F>::U * 2;
+  constexpr int CPL = F::CPL, U = ColUnroll<F>::U;
   constexpr int NW = kBlockThreads / kWave;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int c = t.y + lane;

@@ -51,8 +51,20 @@ struct Geometry {
 #ifndef ADMM_UNROLL_C64
 #define ADMM_UNROLL_C64 2       // lane loads in flight per row (complex64)
 #endif
+#ifndef ADMM_ROWS_NARROW
+#define ADMM_ROWS_NARROW 8      // rows per wave of the bf16 / fp8 row product
+#endif
+#ifndef ADMM_UNROLL_NARROW
+#define ADMM_UNROLL_NARROW 1    // lane loads in flight per row (bf16 / fp8)
+#endif
+#ifndef ADMM_COLS_UNROLL_C64
+#define ADMM_COLS_UNROLL_C64 8  // rows in flight per wave of the adjoint product (complex64)
+#endif
+#ifndef ADMM_COLS_UNROLL_NARROW
+#define ADMM_COLS_UNROLL_NARROW 4  // the same for bf16 / fp8
+#endif
 #ifndef ADMM_COLS_WG_TARGET
-#define ADMM_COLS_WG_TARGET 2048  // about this many workgroups of the adjoint product (bf16, fp8)
+#define ADMM_COLS_WG_TARGET 1024  // about this many workgroups of the adjoint product (bf16, fp8)
 #endif
 #ifndef ADMM_COLS_WG_TARGET_C64
 #define ADMM_COLS_WG_TARGET_C64 4096  // the same for complex64 storage
@@ -71,7 +83,7 @@ constexpr int kColsPerWGLoads = kWave;
 inline int cols_per_load(int storage) { return storage == 0 ? 2 : (storage == 1 ? 8 : 16); }
 // Rows per wave of the H row products: narrow formats share each lane's
 // vector loads across more rows.
-inline int rows_per_wave(int storage) { return storage == 0 ? ADMM_ROWS_C64 : 8; }
+inline int rows_per_wave(int storage) { return storage == 0 ? ADMM_ROWS_C64 : ADMM_ROWS_NARROW; }
 // Bytes per stored complex element.
 inline int elem_bytes(int storage) { return storage == 0 ? 8 : (storage == 1 ? 4 : 2); }
 constexpr int kZCols = kWave;   // columns (lanes) per z-update workgroup
