@@ -48,10 +48,11 @@ def kernel_source_hash() -> str:
 ELEM_BYTES = {"c64": 8, "bf16": 4, "fp8": 2}   # stored bytes per complex element of H
 
 
-def algorithmic_bytes(geo: dict, P: int, Q: int, KH: int, storage: str = "c64") -> dict:
+def algorithmic_bytes(geo: dict, P: int, Q: int, KH: int, storage: str = "c64", inverse: str = "c64") -> dict:
     """Bytes each kernel must move per launch, from the kernel's definition
     (not from counters).  Vectors are complex64 (8 B); H elements take
-    ELEM_BYTES[storage] (+ 4 B per row of fp8 scales)."""
+    ELEM_BYTES[storage] (+ 4 B per row of fp8 scales); inverse entries 8 B
+    (4 B for the bfloat16 copy)."""
     m, n = geo["m"], geo["n"]
     ginv = geo["ginv_packed"]     # complex elements of the packed lower-tile inverses
     gparts = geo["gram_parts"]    # 64-vectors of Gram-apply pieces (written once, read once)
@@ -60,7 +61,7 @@ def algorithmic_bytes(geo: dict, P: int, Q: int, KH: int, storage: str = "c64") 
     vec_rows = P * m * c          # one row-space vector (all column blocks)
     vec_cols = Q * n * c          # one column-space vector (all replicas)
     gemv_n = h + vec_cols + m * c + (P - 1) * vec_rows * (P > 1) + vec_rows * (2 if P > 1 else 1)
-    gram = ginv * c + 2 * gparts * 64 * c + vec_rows * (4 if P > 1 else 3)
+    gram = ginv * (4 if inverse == "bf16" else c) + 2 * gparts * 64 * c + vec_rows * (4 if P > 1 else 3)
     gemv_h = h + vec_rows + KH * vec_cols
     zupd = KH * vec_cols + 2 * vec_cols * 2 + 2 * n * c
     return {"k_gemv_n": gemv_n, "k_gram": gram, "k_gemv_h": gemv_h, "k_zupdate": zupd}
@@ -293,7 +294,36 @@ def bench_batch(args, torch, A, W, dev):
         },
     }
     bb.close()
-    del H0, g
+    del bb
+    torch.cuda.empty_cache()
+    # the same batch with the bfloat16 copy of the scene inverses
+    t = time.perf_counter()
+    bb = A.Batch(H0, b.tile_rows, b.tiles, b.cuts, b.phases, b.P, b.rho, b.lam, inverse="bf16")
+    torch.cuda.synchronize()
+    setup16 = time.perf_counter() - t
+    bb.solve(g, 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v16 = bb.solve(g, K, graph=True)
+    torch.cuda.synchronize()
+    el16 = time.perf_counter() - t0
+    bb.profile(True)
+    bb.solve(g, 10, graph=False)
+    k16 = {bb.KERNELS[k]: round(bb.profile_read(k)[0] / max(bb.profile_read(k)[1], 1) * 1e3, 2) for k in bb.KERNELS}
+    bb.profile(False)
+    v16n = v16.cpu().numpy()
+    nmse16 = [float(np.linalg.norm(v16n[s] - b.u_true[s]) ** 2 / np.linalg.norm(b.u_true[s]) ** 2) for s in range(b.S)]
+    res["inverse_bf16"] = {
+        "value": round(b.S / el16, 2), "unit": "scenes/s (300 iterations each, setup apart)",
+        "value_with_setup": round(b.S / (el16 + setup16), 2), "ms_per_batched_iteration": round(el16 / K * 1e3, 3),
+        "setup_s": round(setup16, 2), "kernels_avg_us": k16,
+        "gram_gbs": round(info["ginv_bytes"] / 2 / (k16["k_gram"] * 1e-6) / 1e9, 1),
+        "nmse_mean": float(np.mean(nmse16)),
+        "rel_diff_vs_fp32_inverse": float(np.linalg.norm(v16n - vn) / np.linalg.norm(vn)),
+    }
+    print(f"[bench] batch, bf16 inverse: {res['inverse_bf16']['value']} scenes/s", file=sys.stderr, flush=True)
+    bb.close()
+    del H0, g, bb
     torch.cuda.empty_cache()
     return res
 
@@ -361,9 +391,9 @@ def main(argv=None):
            "gram_parts": int(sum(T * T for T in tiles) * prob.P)}
     workload = prob.name
 
-    def measure(storage: str, steps: int, warmup: int):
+    def measure(storage: str, steps: int, warmup: int, inverse: str = "c64"):
         t = time.perf_counter()
-        plan = A.Plan(H, prob.Q, prob.P, prob.rho, prob.lam, storage=storage)
+        plan = A.Plan(H, prob.Q, prob.P, prob.rho, prob.lam, storage=storage, inverse=inverse)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t
         info = plan.info()
@@ -381,7 +411,7 @@ def main(argv=None):
             plan.solve(g, steps)
         prof = {A.KERNEL_NAMES[k]: plan.profile_read(k) for k in A.KERNEL_NAMES}
         plan.profile(False)
-        algo = algorithmic_bytes(geo, prob.P, prob.Q, info["chunks"], storage)
+        algo = algorithmic_bytes(geo, prob.P, prob.Q, info["chunks"], storage, inverse)
         kern = {}
         for name, (ms, cnt) in prof.items():
             avg_ms = ms / max(cnt, 1)
@@ -395,14 +425,14 @@ def main(argv=None):
             "dominant": dominant,
             "roofline": {"bound": "hbm", "kernel": dominant, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(dk["gbs"] / HBM_PEAK_GBS, 4),
-                         "traffic": load_traffic(dominant, f"{workload}_{storage}"),
+                         "traffic": load_traffic(dominant, f"{workload}_{storage}") if inverse == "c64" else None,
                          "algo_bytes_per_launch": dk["algo_bytes"], "avg_launch_us": dk["avg_us"]},
             "iteration_gbs": round(sum(algo.values()) * steps / elapsed / 1e9, 1),
             "nmse": float(np.linalg.norm(v_np - prob.u_true) ** 2 / np.linalg.norm(prob.u_true) ** 2),
             "kkt": plan.kkt(g, v), "final_residuals": [float(x) for x in hist[-1].cpu().numpy()],
         }
-        print(f"[bench] {storage}: setup {setup_s * 1e3:.1f} ms, {steps} iterations in {elapsed * 1e3:.1f} ms",
-              file=sys.stderr, flush=True)
+        print(f"[bench] {storage} (inverse {inverse}): setup {setup_s * 1e3:.1f} ms, {steps} iterations in "
+              f"{elapsed * 1e3:.1f} ms", file=sys.stderr, flush=True)
         return res
 
     main = measure("c64", args.steps, args.warmup)
@@ -424,10 +454,12 @@ def main(argv=None):
     if not args.no_forms:
         forms = {}
         v_ref = main["v"].cpu().numpy()
-        for storage in ("bf16", "fp8"):
-            r = measure(storage, args.steps, args.warmup)
+        for key, storage, inverse in (("bf16", "bf16", "c64"), ("fp8", "fp8", "c64"),
+                                      ("c64_inverse_bf16", "c64", "bf16"), ("fp8_inverse_bf16", "fp8", "bf16")):
+            r = measure(storage, args.steps, args.warmup, inverse)
             vq = r["v"].cpu().numpy()
-            forms[storage] = {
+            forms[key] = {
+                "storage": storage, "inverse": inverse,
                 "value": round(args.steps / r["elapsed"], 2), "unit": "iters/s",
                 "ms_per_step": round(r["elapsed"] / args.steps * 1e3, 4), "roofline": r["roofline"],
                 "iteration_gbs": r["iteration_gbs"], "kernels": r["kern"], "setup_ms": round(r["setup_s"] * 1e3, 1),

@@ -58,6 +58,15 @@ extern "C" {
                                /* (1 for an all-zero row).  The Gram factors are built */
                                /* in FP64 from the dequantised values; products       */
                                /* accumulate in FP32.                                  */
+/* Flag OR-ed into `storage` (admm_workspace_bytes, admm_setup) or passed as
+ * `flags` to the batched setup: besides the complex64 inverses, keep a copy of
+ * each block's packed inverse G_ij^{-1} (formed in FP64, Sec. III-C, eq.
+ * inversion_lemma3) rounded to bfloat16 (nearest even, Re and Im) and apply
+ * that copy in every iteration and in the reverse sweep: half the bytes of the
+ * Gram apply, at an inverse perturbation of at most 2^-9 relative per entry.
+ * admm_backward's d/drho then differentiates through the unrounded inverse
+ * (the rounding counts as the identity). */
+#define ADMM_INVERSE_BF16  16
 
 typedef struct admm_plan admm_plan;
 
@@ -77,7 +86,7 @@ const char* admm_last_error(void);
  *   row_off   host int64[Q+1] block boundaries, strictly increasing from 0
  *             to m, or NULL for the equal split (the first m mod Q blocks
  *             get one extra row).  col_off likewise with P and n.
- *   storage   ADMM_STORAGE_*.
+ *   storage   ADMM_STORAGE_*, optionally | ADMM_INVERSE_BF16.
  *   out_bytes host, receives the size.
  * Errors: EINVAL for any bad size or split; EUNSUPPORTED when some block is
  * not wide (m_i >= n_j), since only the inversion-lemma x-update is built.
@@ -268,16 +277,17 @@ void admm_destroy(admm_plan* plan);
  * ====================================================================== */
 typedef struct admm_batch admm_batch;
 
+/* flags: 0 or ADMM_INVERSE_BF16 (the same value in both calls). */
 int admm_batch_workspace_bytes(int64_t m0, int64_t n, int tile_rows, int S,
                                const int32_t* tiles, const int64_t* tiles_off,
                                const int32_t* cuts, const int64_t* cuts_off,
-                               int P, const int64_t* col_off,
+                               int P, const int64_t* col_off, int flags,
                                size_t* out_bytes);
 int admm_batch_setup(admm_batch** out, const void* H0, int64_t m0, int64_t n,
                      int tile_rows, int S, const int32_t* tiles,
                      const int64_t* tiles_off, const int32_t* cuts,
                      const int64_t* cuts_off, const void* phases, int P,
-                     const int64_t* col_off, double rho,
+                     const int64_t* col_off, int flags, double rho,
                      const double* lambdas, void* workspace,
                      size_t workspace_bytes, void* stream);
 int admm_batch_solve(admm_batch* batch, const void* g, int iters,
@@ -287,8 +297,8 @@ int admm_batch_solve(admm_batch* batch, const void* g, int iters,
 int admm_batch_profile(admm_batch* batch, int enable);
 int admm_batch_profile_read(admm_batch* batch, int kernel, double* total_ms,
                             int64_t* launches);
-/* info16: m0, n, S, P, row blocks, scene tiles, workspace bytes, inverse
- * bytes, chosen forward k-chunks per column block, chosen adjoint columns per
+/* info16: m0, n, S, P, row blocks, scene tiles, workspace bytes, bytes of
+ * the complex64 packed inverses, chosen forward k-chunks per column block, chosen adjoint columns per
  * workgroup, their work items, packed rows, chosen forward rows per
  * workgroup, 0... */
 int admm_batch_info(const admm_batch* batch, int64_t* info16);

@@ -23,6 +23,7 @@ STATUS = {
     -5: "ADMM_ENONFINITE", -6: "ADMM_ESTATE", -7: "ADMM_EUNSUPPORTED",
 }
 STORAGE = {"c64": 0, "bf16": 1, "fp8": 2}
+INVERSE = {"c64": 0, "bf16": 16}   # ADMM_INVERSE_BF16: apply a bfloat16 copy of the block inverses
 K_GEMV_N, K_GRAM, K_GEMV_H, K_ZUPDATE = 0, 1, 2, 3
 KERNEL_NAMES = {K_GEMV_N: "k_gemv_n", K_GRAM: "k_gram", K_GEMV_H: "k_gemv_h", K_ZUPDATE: "k_zupdate"}
 
@@ -49,9 +50,10 @@ SIGNATURES = [
     ("admm_profile_read", _int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
     ("admm_plan_info", _int, [_vp, _c.POINTER(_i64)]),
     ("admm_destroy", None, [_vp]),
-    ("admm_batch_workspace_bytes", _int, [_i64, _i64, _int, _int, _vp, _vp, _vp, _vp, _int, _vp, _c.POINTER(_sz)]),
+    ("admm_batch_workspace_bytes", _int, [_i64, _i64, _int, _int, _vp, _vp, _vp, _vp, _int, _vp, _int,
+                                           _c.POINTER(_sz)]),
     ("admm_batch_setup", _int, [_c.POINTER(_vp), _vp, _i64, _i64, _int, _int, _vp, _vp, _vp, _vp, _vp, _int, _vp,
-                                _dbl, _vp, _vp, _sz, _vp]),
+                                _int, _dbl, _vp, _vp, _sz, _vp]),
     ("admm_batch_solve", _int, [_vp, _vp, _int, _vp, _int, _vp]),
     ("admm_batch_profile", _int, [_vp, _int]),
     ("admm_batch_profile_read", _int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
@@ -101,12 +103,12 @@ def _offsets(o):
 
 
 def workspace_bytes(m: int, n: int, Q: int, P: int, row_off=None, col_off=None,
-                    storage: str = "c64") -> int:
+                    storage: str = "c64", inverse: str = "c64") -> int:
     ro, rp = _offsets(row_off)
     co, cp = _offsets(col_off)
     out = ctypes.c_size_t(0)
-    _check(lib().admm_workspace_bytes(m, n, Q, rp, P, cp, STORAGE[storage], ctypes.byref(out)),
-           "admm_workspace_bytes")
+    _check(lib().admm_workspace_bytes(m, n, Q, rp, P, cp, STORAGE[storage] | INVERSE[inverse],
+                                      ctypes.byref(out)), "admm_workspace_bytes")
     return int(out.value)
 
 
@@ -126,7 +128,7 @@ class Plan:
     """
 
     def __init__(self, H, Q: int, P: int, rho: float, lam: float, row_off=None, col_off=None,
-                 storage: str = "c64"):
+                 storage: str = "c64", inverse: str = "c64"):
         import torch
         if not (H.is_cuda and H.dtype == torch.complex64 and H.dim() == 2 and H.is_contiguous()):
             raise ValueError("H must be a contiguous complex64 CUDA tensor (m, n)")
@@ -135,9 +137,9 @@ class Plan:
         self.m, self.n = H.shape
         self.Q, self.P = Q, P
         self.rho, self.lam = float(rho), float(lam)
-        self.storage = storage
+        self.storage, self.inverse = storage, inverse
         self.row_off, self.col_off = row_off, col_off
-        nbytes = workspace_bytes(self.m, self.n, Q, P, row_off, col_off, storage)
+        nbytes = workspace_bytes(self.m, self.n, Q, P, row_off, col_off, storage, inverse)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         _, rp = _offsets(row_off)
         _, cp = _offsets(col_off)
@@ -148,7 +150,7 @@ class Plan:
         cp = None if co_keep is None else co_keep.ctypes.data_as(ctypes.c_void_p)
         h = ctypes.c_void_p(0)
         _check(lib().admm_setup(ctypes.byref(h), _ptr(H), self.m, self.n, Q, rp, P, cp, self.rho,
-                                self.lam, STORAGE[storage], _ptr(self.workspace), nbytes,
+                                self.lam, STORAGE[storage] | INVERSE[inverse], _ptr(self.workspace), nbytes,
                                 _stream(torch, self.device)), "admm_setup")
         self._h = h
 
@@ -293,7 +295,8 @@ class Batch:
 
     KERNELS = {0: "k_bgemm_n", 1: "k_gram", 2: "k_bgemm_h", 3: "k_bzupdate"}
 
-    def __init__(self, H0, tile_rows: int, tiles, cuts, phases, P: int, rho: float, lambdas, col_off=None):
+    def __init__(self, H0, tile_rows: int, tiles, cuts, phases, P: int, rho: float, lambdas, col_off=None,
+                 inverse: str = "c64"):
         import torch
         self.torch = torch
         self.device = H0.device
@@ -314,10 +317,11 @@ class Batch:
         args = (self.m0, self.n, int(tile_rows), self.S, self._tiles.ctypes.data_as(v),
                 self._toff.ctypes.data_as(v), self._cuts.ctypes.data_as(v), self._coff.ctypes.data_as(v))
         out = ctypes.c_size_t(0)
-        _check(lib().admm_batch_workspace_bytes(*args, P, cp, ctypes.byref(out)), "admm_batch_workspace_bytes")
+        flags = INVERSE[inverse]
+        _check(lib().admm_batch_workspace_bytes(*args, P, cp, flags, ctypes.byref(out)), "admm_batch_workspace_bytes")
         self.workspace = torch.empty(int(out.value), dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p(0)
-        _check(lib().admm_batch_setup(ctypes.byref(h), _ptr(H0), *args[:], _ptr(self.phases), P, cp, self.rho,
+        _check(lib().admm_batch_setup(ctypes.byref(h), _ptr(H0), *args[:], _ptr(self.phases), P, cp, flags, self.rho,
                                       self._lams.ctypes.data_as(v), _ptr(self.workspace), self.workspace.numel(),
                                       _stream(torch, self.device)), "admm_batch_setup")
         self._h = h

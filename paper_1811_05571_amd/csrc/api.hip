@@ -73,10 +73,13 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
     err = buf;
     return ADMM_EINVAL;
   }
+  const bool inv16 = (storage & ADMM_INVERSE_BF16) != 0;
+  storage &= ~ADMM_INVERSE_BF16;
   if (storage != ADMM_STORAGE_C64 && storage != ADMM_STORAGE_BF16 && storage != ADMM_STORAGE_FP8) {
     err = "unknown storage";
     return ADMM_EINVAL;
   }
+  geo.inv16 = inv16;
   auto offsets = [&](int64_t total, int parts, const int64_t* given, std::vector<int64_t>& o) -> bool {
     o.assign(parts + 1, 0);
     if (given) {
@@ -234,6 +237,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   }
   L.ginv_bytes = (size_t)gioff * 8;
   L.Ginv = take(L.ginv_bytes);
+  if (geo.inv16) L.Ginv16 = take((size_t)gioff * 4);
   L.F64a = take((size_t)foff * 16);
   L.F64b = take((size_t)foff * 16);
   const size_t colv = (size_t)geo.n_pad * 8, rowv = (size_t)geo.m_pad * 8;
@@ -285,6 +289,7 @@ struct admm_plan {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   float2 *H = nullptr, *Ginv = nullptr, *c = nullptr, *s = nullptr, *v = nullptr, *part = nullptr;
+  uint32_t* Ginv16 = nullptr;
   float2 *gp = nullptr, *ghat = nullptr, *r = nullptr, *y = nullptr, *kkt_v = nullptr;
   double2 *F64a = nullptr, *F64b = nullptr, *kkt_e = nullptr, *kkt_part = nullptr;
   BlockDesc* d_blocks = nullptr;
@@ -366,6 +371,7 @@ IterArgs iter_args(admm_plan* p, const float2* g, double* hist) {
   a.cols = p->d_cols;
   a.hs = p->hs;
   a.Ginv = p->Ginv;
+  a.Ginv16 = p->Ginv16;
   a.g = g;
   a.c = p->c;
   a.s = p->s;
@@ -488,6 +494,7 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
     delete p;
     return fail(rc, "%s", err.c_str());
   }
+  storage = p->geo.storage;   // H format (the inverse flag is in geo.inv16)
   const Layout& L = p->geo.lay;
   if (!workspace || workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255)) {
     delete p;
@@ -500,6 +507,7 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   p->ws_bytes = workspace_bytes;
   p->H = at<float2>(p, L.H);
   p->Ginv = at<float2>(p, L.Ginv);
+  p->Ginv16 = p->geo.inv16 ? at<uint32_t>(p, L.Ginv16) : nullptr;
   p->F64a = at<double2>(p, L.F64a);
   p->F64b = at<double2>(p, L.F64b);
   p->c = at<float2>(p, L.c);
@@ -586,6 +594,7 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
                                 p->hs, p->ctl, st));
   SETUP_TRY(launch_gram_build(G, p->d_blocks, p->t_gram, p->hs, rho, p->F64a, st));
   SETUP_TRY(launch_cholesky_inverse(G, p->d_blocks, p->t_gram, p->F64a, p->F64b, p->Ginv, p->ctl, st));
+  if (p->Ginv16) SETUP_TRY(launch_to_bf16_pairs(p->Ginv, p->Ginv16, L.ginv_bytes / 8, st));
   Control hc;
   SETUP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
   SETUP_TRY(hipStreamSynchronize(st));
@@ -745,6 +754,7 @@ int admm_backward(admm_plan* p, const void* g, const void* grad_v, const void* t
   b.cols = p->d_cols;
   b.hs = p->hs;
   b.Ginv = p->Ginv;
+  b.Ginv16 = p->Ginv16;
   b.vb = p->vb;
   b.sb = p->sb;
   b.ub = p->ub;

@@ -70,7 +70,9 @@ struct BatchGeo {
   int64_t m_pad = 0, n_pad = 0, ldt = 0, mt0 = 0;
   int R = 0, NST = 0, max_nj = 0;
   // workspace
-  size_t o_hre = 0, o_him = 0, o_tre = 0, o_tim = 0, o_ginv = 0, o_G0 = 0, o_A = 0, o_W = 0, group_bytes = 0;
+  size_t o_hre = 0, o_him = 0, o_tre = 0, o_tim = 0, o_ginv = 0, o_ginv16 = 0, o_G0 = 0, o_A = 0, o_W = 0, group_bytes = 0;
+  bool inv16 = false;              // a bfloat16-pair copy of the inverses is kept and applied
+  int64_t ginv_elems = 0;
   size_t o_c = 0, o_s = 0, o_v = 0, o_part = 0, o_gp = 0, o_ghat = 0, o_r = 0, o_y = 0, o_cs = 0, o_ys = 0, o_phase = 0;
   size_t o_pseudo = 0, o_cols = 0, o_blocks = 0, o_rbd = 0, o_scenes = 0, o_stab = 0, o_cuts = 0, o_tiles = 0;
   int NG = 0;                      // forward GEMM groups (f, scene-tile group, j)
@@ -84,7 +86,12 @@ struct BatchGeo {
 
 int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const int32_t* tiles,
                 const int64_t* tiles_off, const int32_t* cuts, const int64_t* cuts_off, int P,
-                const int64_t* col_off, std::string& err) {
+                const int64_t* col_off, int flags, std::string& err) {
+  if (flags & ~ADMM_INVERSE_BF16) {
+    err = "unknown flags";
+    return ADMM_EINVAL;
+  }
+  G.inv16 = (flags & ADMM_INVERSE_BF16) != 0;
   char buf[256];
   if (m0 < 1 || n < 1 || (tile_rows != 64 && tile_rows != 128 && tile_rows != 256) || m0 % tile_rows || S < 1 || P < 1 || P > n ||
       !tiles || !tiles_off || !cuts || !cuts_off) {
@@ -356,6 +363,8 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
   G.o_tre = take((size_t)toff * 2);
   G.o_tim = take((size_t)toff * 2);
   G.o_ginv = take((size_t)gioff * 8);
+  G.ginv_elems = gioff;
+  if (G.inv16) G.o_ginv16 = take((size_t)gioff * 4);
   G.o_G0 = take((size_t)foff * 16);
   G.o_A = take(G.group_bytes);
   G.o_W = take(G.group_bytes);
@@ -469,6 +478,7 @@ IterArgs gram_args(admm_batch* b, const float2* g) {
   a.blocks = at<BlockDesc>(b, G.o_blocks);
   a.cols = at<ColDesc>(b, G.o_cols);
   a.Ginv = at<float2>(b, G.o_ginv);
+  a.Ginv16 = G.inv16 ? at<uint32_t>(b, G.o_ginv16) : nullptr;
   a.g = g;
   a.gp = at<float2>(b, G.o_gp);
   a.ghat = at<float2>(b, G.o_ghat);
@@ -596,11 +606,11 @@ extern "C" {
 
 int admm_batch_workspace_bytes(int64_t m0, int64_t n, int tile_rows, int S, const int32_t* tiles,
                                const int64_t* tiles_off, const int32_t* cuts, const int64_t* cuts_off, int P,
-                               const int64_t* col_off, size_t* out_bytes) {
+                               const int64_t* col_off, int flags, size_t* out_bytes) {
   if (!out_bytes) return admm_fail(ADMM_EINVAL, "out_bytes is NULL");
   BatchGeo G;
   std::string err;
-  int rc = build_batch(G, m0, n, tile_rows, S, tiles, tiles_off, cuts, cuts_off, P, col_off, err);
+  int rc = build_batch(G, m0, n, tile_rows, S, tiles, tiles_off, cuts, cuts_off, P, col_off, flags, err);
   if (rc) return admm_fail(rc, "%s", err.c_str());
   *out_bytes = G.total;
   return ADMM_OK;
@@ -608,7 +618,7 @@ int admm_batch_workspace_bytes(int64_t m0, int64_t n, int tile_rows, int S, cons
 
 int admm_batch_setup(admm_batch** out, const void* H0, int64_t m0, int64_t n, int tile_rows, int S,
                      const int32_t* tiles, const int64_t* tiles_off, const int32_t* cuts, const int64_t* cuts_off,
-                     const void* phases, int P, const int64_t* col_off, double rho, const double* lambdas,
+                     const void* phases, int P, const int64_t* col_off, int flags, double rho, const double* lambdas,
                      void* workspace, size_t workspace_bytes, void* stream) {
   if (!out) return admm_fail(ADMM_EINVAL, "out is NULL");
   *out = nullptr;
@@ -619,7 +629,7 @@ int admm_batch_setup(admm_batch** out, const void* H0, int64_t m0, int64_t n, in
       return admm_fail(ADMM_EINVAL, "lambda of scene %d must be finite and >= 0", s);
   admm_batch* b = new admm_batch;
   std::string err;
-  int rc = build_batch(b->geo, m0, n, tile_rows, S, tiles, tiles_off, cuts, cuts_off, P, col_off, err);
+  int rc = build_batch(b->geo, m0, n, tile_rows, S, tiles, tiles_off, cuts, cuts_off, P, col_off, flags, err);
   if (rc) {
     delete b;
     return admm_fail(rc, "%s", err.c_str());
@@ -721,6 +731,8 @@ int admm_batch_setup(admm_batch** out, const void* H0, int64_t m0, int64_t n, in
       i0 = i1;
     }
   }
+  if (G.inv16)
+    STRY(launch_to_bf16_pairs(at<float2>(b, G.o_ginv), at<uint32_t>(b, G.o_ginv16), (size_t)G.ginv_elems, st));
   Control hc;
   STRY(hipMemcpyAsync(&hc, ctl, sizeof hc, hipMemcpyDeviceToHost, st));
   STRY(hipStreamSynchronize(st));
@@ -804,7 +816,7 @@ int admm_batch_profile_read(admm_batch* b, int kernel, double* total_ms, int64_t
 int admm_batch_info(const admm_batch* b, int64_t* info) {
   if (!b || !info) return admm_fail(ADMM_EINVAL, "batch plan and info must not be NULL");
   const BatchGeo& G = b->geo;
-  int64_t v[16] = {G.m0, G.n, G.S, G.P, G.R, G.NST, (int64_t)G.total, (int64_t)(G.o_G0 - G.o_ginv),
+  int64_t v[16] = {G.m0, G.n, G.S, G.P, G.R, G.NST, (int64_t)G.total, G.ginv_elems * 8,
                    kSplitVariants[b->var_n], 64 * kAdjMS[b->var_h], (int64_t)G.items_n[b->var_n].size(),
                    (int64_t)G.items_h[b->var_h].size(), G.rows_total, 64 * fwd_ms(b->var_n, G.tile_rows), 0, 0};
   std::memcpy(info, v, sizeof v);

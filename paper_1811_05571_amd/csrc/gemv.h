@@ -281,6 +281,97 @@ __device__ __forceinline__ void gram_tile_compute(const GramOps& o, bool diag, f
   }
 }
 
+// The same products with the tile stored as bfloat16 pairs (32-bit word per
+// complex entry: Re in the low half, Im in the high half).  Thread (wave w,
+// lane l) holds rows 16w + 4(l >> 4) + {0..3} and the four contiguous columns
+// 4b .. 4b+3 (b = l & 15): one 16-byte load per row, 16 lanes covering a
+// 256-byte row.  The reductions are those of gram_tile_compute with column
+// slot k mapped to column 4b + k.
+__device__ __forceinline__ void bf16pair(uint32_t w, float& re, float& im) {
+  re = __uint_as_float(w << 16);
+  im = __uint_as_float(w & 0xffff0000u);
+}
+__device__ __forceinline__ void gram_tile_apply_bf16(const uint32_t* __restrict__ G, const float2* __restrict__ xa,
+                                                     const float2* __restrict__ xb, bool diag,
+                                                     float2* __restrict__ out_ab, float2* __restrict__ out_ba,
+                                                     float2 (&red)[4][64]) {
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, b = l & 15;
+  const int r0 = 16 * w + 4 * (l >> 4);
+  uint4 h[4];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const v4u_t q = __builtin_nontemporal_load(reinterpret_cast<const v4u_t*>(G + (r0 + rr) * 64 + 4 * b));
+    h[rr] = make_uint4(q.x, q.y, q.z, q.w);
+  }
+  const float4 xb0 = *reinterpret_cast<const float4*>(xb + 4 * b);
+  const float4 xb1 = *reinterpret_cast<const float4*>(xb + 4 * b + 2);
+  const float xbr[4] = {xb0.x, xb0.z, xb1.x, xb1.z}, xbi[4] = {xb0.y, xb0.w, xb1.y, xb1.w};
+  float gr[4][4], gi[4][4];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    bf16pair(h[rr].x, gr[rr][0], gi[rr][0]);
+    bf16pair(h[rr].y, gr[rr][1], gi[rr][1]);
+    bf16pair(h[rr].z, gr[rr][2], gi[rr][2]);
+    bf16pair(h[rr].w, gr[rr][3], gi[rr][3]);
+  }
+  float pr[4], pi[4];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    pr[rr] = 0.f;
+    pi[rr] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cmac(pr[rr], pi[rr], gr[rr][k], gi[rr][k], xbr[k], xbi[k]);
+  }
+  {
+    const bool s = (l & 8) != 0;
+    float k0r = s ? pr[2] : pr[0], k0i = s ? pi[2] : pi[0];
+    float k1r = s ? pr[3] : pr[1], k1i = s ? pi[3] : pi[1];
+    const float o0r = s ? pr[0] : pr[2], o0i = s ? pi[0] : pi[2];
+    const float o1r = s ? pr[1] : pr[3], o1i = s ? pi[1] : pi[3];
+    k0r += __shfl_xor(o0r, 8, kWave);
+    k0i += __shfl_xor(o0i, 8, kWave);
+    k1r += __shfl_xor(o1r, 8, kWave);
+    k1i += __shfl_xor(o1i, 8, kWave);
+    const bool t = (l & 4) != 0;
+    float rr_ = t ? k1r : k0r, ri_ = t ? k1i : k0i;
+    rr_ += __shfl_xor(t ? k0r : k1r, 4, kWave);
+    ri_ += __shfl_xor(t ? k0i : k1i, 4, kWave);
+    rr_ += __shfl_xor(rr_, 2, kWave);
+    ri_ += __shfl_xor(ri_, 2, kWave);
+    rr_ += __shfl_xor(rr_, 1, kWave);
+    ri_ += __shfl_xor(ri_, 1, kWave);
+    if ((l & 3) == 0) out_ab[r0 + 2 * (int)s + (int)t] = make_float2(rr_, ri_);
+  }
+  if (diag) return;
+  const float4 xa0 = *reinterpret_cast<const float4*>(xa + r0);
+  const float4 xa1 = *reinterpret_cast<const float4*>(xa + r0 + 2);
+  const float xr[4] = {xa0.x, xa0.z, xa1.x, xa1.z}, xi[4] = {xa0.y, xa0.w, xa1.y, xa1.w};
+  float cr[4] = {0.f, 0.f, 0.f, 0.f}, ci[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cmacc(cr[k], ci[k], gr[rr][k], gi[rr][k], xr[rr], xi[rr]);
+  const bool u = (l & 32) != 0;
+  float k0r = u ? cr[2] : cr[0], k0i = u ? ci[2] : ci[0];
+  float k1r = u ? cr[3] : cr[1], k1i = u ? ci[3] : ci[1];
+  const float o0r = u ? cr[0] : cr[2], o0i = u ? ci[0] : ci[2];
+  const float o1r = u ? cr[1] : cr[3], o1i = u ? ci[1] : ci[3];
+  k0r += __shfl_xor(o0r, 32, kWave);
+  k0i += __shfl_xor(o0i, 32, kWave);
+  k1r += __shfl_xor(o1r, 32, kWave);
+  k1i += __shfl_xor(o1i, 32, kWave);
+  const bool v = (l & 16) != 0;
+  float sr = v ? k1r : k0r, si = v ? k1i : k0i;
+  sr += __shfl_xor(v ? k0r : k1r, 16, kWave);
+  si += __shfl_xor(v ? k0i : k1i, 16, kWave);
+  red[w][4 * b + 2 * (int)u + (int)v] = make_float2(sr, si);
+  __syncthreads();
+  if (tid < 64) {
+    const float2 q0 = red[0][tid], q1 = red[1][tid], q2 = red[2][tid], q3 = red[3][tid];
+    out_ba[tid] = make_float2(((q0.x + q1.x) + q2.x) + q3.x, ((q0.y + q1.y) + q2.y) + q3.y);
+  }
+}
+
 __device__ __forceinline__ void gram_tile_apply(const float2* __restrict__ G, const float2* __restrict__ xa,
                                                 const float2* __restrict__ xb, bool diag,
                                                 float2* __restrict__ out_ab, float2* __restrict__ out_ba,

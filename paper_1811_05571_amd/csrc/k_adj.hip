@@ -130,11 +130,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_adj_gram_tile(AdjArgs a, cons
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = a.blocks[t.x];
   const int T = d.mt / kTile;
-  const float2* G = a.Ginv + d.gi_off + (int64_t)(t.y * (t.y + 1) / 2 + t.z) * (kTile * kTile);
+  const int64_t toff = d.gi_off + (int64_t)(t.y * (t.y + 1) / 2 + t.z) * (kTile * kTile);
   const float2* x = a.yb + (int64_t)d.j * a.m_pad + d.rpad0;
   float2* part = a.gpart + (int64_t)d.gpo * kTile;
-  gram_tile_apply(G, x + t.y * kTile, x + t.z * kTile, t.y == t.z, part + (int64_t)(t.y * T + t.z) * kTile,
-                  part + (int64_t)(t.z * T + t.y) * kTile, tt);
+  if (a.Ginv16)   // the forward's (rounded) inverse: the adjoint of the map actually applied
+    gram_tile_apply_bf16(a.Ginv16 + toff, x + t.y * kTile, x + t.z * kTile, t.y == t.z,
+                         part + (int64_t)(t.y * T + t.z) * kTile, part + (int64_t)(t.z * T + t.y) * kTile, tt);
+  else
+    gram_tile_apply(a.Ginv + toff, x + t.y * kTile, x + t.z * kTile, t.y == t.z,
+                    part + (int64_t)(t.y * T + t.z) * kTile, part + (int64_t)(t.z * T + t.y) * kTile, tt);
 }
 
 __global__ __launch_bounds__(kTile) void k_adj_gram_reduce(AdjArgs a, const int4* __restrict__ tiles,

@@ -117,6 +117,28 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4
 // y_ij = G_ij^{-1} r_ij over the packed lower tiles of the inverse: every
 // tile is read once and contributes to two 64-row pieces of y (gram_tile_apply);
 // k_gram_reduce adds the pieces in tile order and forms ghat_ij = g'_ij - rho y_ij.
+// The same from the bfloat16-pair copy of the inverse.
+__global__ __launch_bounds__(kBlockThreads) void k_gram_tile_bf16(IterArgs a, const int4* __restrict__ tiles) {
+  __shared__ float2 tt[4][64];
+  const int4 t = tiles[blockIdx.x];
+  const BlockDesc d = a.blocks[t.x];
+  const int T = d.mt / kTile;
+  const uint32_t* G = a.Ginv16 + d.gi_off + (int64_t)(t.y * (t.y + 1) / 2 + t.z) * (kTile * kTile);
+  const float2* x = a.r + (int64_t)d.j * a.m_pad + d.rpad0;
+  float2* part = a.gpart + (int64_t)d.gpo * kTile;
+  gram_tile_apply_bf16(G, x + t.y * kTile, x + t.z * kTile, t.y == t.z, part + (int64_t)(t.y * T + t.z) * kTile,
+                       part + (int64_t)(t.z * T + t.y) * kTile, tt);
+}
+
+// Round to nearest even of each component to bfloat16, packed as (Re | Im << 16).
+__global__ void k_to_bf16_pairs(const float2* __restrict__ src, uint32_t* __restrict__ dst, size_t n) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const float2 v = src[k];
+    const uint32_t re = __builtin_bit_cast(uint16_t, (__bf16)v.x), im = __builtin_bit_cast(uint16_t, (__bf16)v.y);
+    dst[k] = re | (im << 16);
+  }
+}
+
 // tiles[x] = {block, tile row, tile col, -} (lower pairs), one per workgroup.
 __global__ __launch_bounds__(kBlockThreads) void k_gram_tile(IterArgs a, const int4* __restrict__ tiles) {
   __shared__ float2 tt[4][64];
@@ -334,7 +356,10 @@ hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipSt
 }
 hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gtr, int n_gtr,
                        hipStream_t st, KTime kt) {
-  LAUNCH_TIMED(k_gram_tile, dim3(n_gram), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gram);
+  if (a.Ginv16)
+    LAUNCH_TIMED(k_gram_tile_bf16, dim3(n_gram), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gram);
+  else
+    LAUNCH_TIMED(k_gram_tile, dim3(n_gram), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gram);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   LAUNCH_TIMED(k_gram_reduce, dim3(n_gtr), dim3(kBlockThreads), st, (KTime{nullptr, kt.stop}), a, t_gtr);
@@ -355,6 +380,12 @@ hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipS
     LAUNCH_TIMED(k_zupdate<8>, dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
   else
     LAUNCH_TIMED(k_zupdate<0>, dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
+  return hipGetLastError();
+}
+hipError_t launch_to_bf16_pairs(const float2* src, uint32_t* dst, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_to_bf16_pairs, dim3(grid), dim3(256), 0, st, src, dst, n);
   return hipGetLastError();
 }
 hipError_t launch_zfinal(const IterArgs& a, hipStream_t st) {

@@ -17,7 +17,7 @@ struct ColDesc {       // one column block j
 
 // Workspace carve-up (byte offsets from the workspace base, 256-aligned).
 struct Layout {
-  size_t H = 0, H_im = 0, H_scale = 0, Ginv = 0, F64a = 0, F64b = 0;
+  size_t H = 0, H_im = 0, H_scale = 0, Ginv = 0, Ginv16 = 0, F64a = 0, F64b = 0;
   size_t c = 0, s = 0, v = 0, part = 0, gp = 0, ghat = 0, r = 0, y = 0;
   size_t blocks = 0, cols = 0, t_rows = 0, t_cols = 0, t_z = 0, t_gram = 0, t_kadj = 0, t_hrows = 0, t_gtr = 0;
   size_t gpart = 0;
@@ -29,7 +29,8 @@ struct Layout {
 
 struct Geometry {
   int64_t m = 0, n = 0;
-  int Q = 0, P = 0, storage = 0;
+  int Q = 0, P = 0, storage = 0;   // storage: H format (ADMM_STORAGE_*)
+  bool inv16 = false;              // a bfloat16-pair copy of the inverses is kept and applied
   std::vector<int64_t> ro, co;
   std::vector<BlockDesc> blocks;   // Q*P, index b = i*P + j
   std::vector<ColDesc> cols;       // P
@@ -97,6 +98,7 @@ struct IterArgs {
   const ColDesc* cols;
   HStore hs;
   const float2* Ginv;
+  const uint32_t* Ginv16;  // bfloat16-pair copy of Ginv (same element offsets), or null: use Ginv
   const float2* g;      // caller's measurements
   float2 *c, *s, *v, *part, *gp, *ghat, *r, *y;
   float2* gpart;        // Gram-apply pieces (BlockDesc::gpo)
@@ -118,6 +120,7 @@ struct AdjArgs {
   const ColDesc* cols;
   HStore hs;
   const float2* Ginv;
+  const uint32_t* Ginv16;  // as IterArgs::Ginv16
   float2 *vb, *sb, *ub, *ghb, *gpb, *yb, *rb, *part, *gpart;
   double2* gbar;
   double *kpart, *rpart;
@@ -148,6 +151,8 @@ hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipSt
 hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});
 // Final addition of a pending z-update's partial sums (one workgroup).
 hipError_t launch_zfinal(const IterArgs& a, hipStream_t st);
+// Round n complex64 values to bfloat16 pairs (Re low half, Im high half).
+hipError_t launch_to_bf16_pairs(const float2* src, uint32_t* dst, size_t n, hipStream_t st);
 hipError_t launch_unpad_cols(const ColDesc* cols, int P, int64_t n, const float2* src, float2* dst,
                              int64_t src_stride, int64_t dst_stride, int reps, int to_padded,
                              hipStream_t st);

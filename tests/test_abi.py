@@ -1,5 +1,6 @@
 """The C ABI library loads without a GPU and exports every entry point that
 include/admm.h declares; host-only argument checks work on the CPU."""
+import ctypes
 import os
 import re
 
@@ -38,6 +39,13 @@ def test_workspace_sizing_and_argument_errors():
     assert small > 256 * 4096 * 8            # at least the stored H
     big = A.workspace_bytes(6144, 32000, 4, 8)
     assert big > 6144 * 32000 * 8
+    # the bfloat16 copy of the packed inverses: 4 bytes per stored entry more
+    # (32 blocks of 24 x 25 / 2 tiles of 64 x 64 at full size)
+    inv16 = A.workspace_bytes(6144, 32000, 4, 8, inverse="bf16")
+    assert inv16 - big >= 32 * (24 * 25 // 2) * 4096 * 4
+    L = A.lib()
+    out = ctypes.c_size_t(0)
+    assert L.admm_workspace_bytes(256, 4096, 4, None, 1, None, 32, ctypes.byref(out)) == -1   # unknown flag
     assert A.workspace_bytes(300, 2000, 3, 5, [0, 90, 200, 300], [0, 333, 800, 1201, 1600, 2000]) > 0
     bad = [
         dict(m=0, n=10, Q=1, P=1),
@@ -81,12 +89,20 @@ def test_batch_workspace_sizing_and_errors():
     v = ctypes.c_void_p
     out = ctypes.c_size_t(0)
     rc = L.admm_batch_workspace_bytes(256, 4096, 64, 2, tiles.ctypes.data_as(v), toff.ctypes.data_as(v),
-                                      cuts.ctypes.data_as(v), coff.ctypes.data_as(v), 2, None, ctypes.byref(out))
+                                      cuts.ctypes.data_as(v), coff.ctypes.data_as(v), 2, None, 0, ctypes.byref(out))
     assert rc == 0 and out.value > 256 * 4096 * 4
+    plain = out.value
+    # the bfloat16 copy of the inverses adds 4 bytes per stored inverse entry
+    rc = L.admm_batch_workspace_bytes(256, 4096, 64, 2, tiles.ctypes.data_as(v), toff.ctypes.data_as(v),
+                                      cuts.ctypes.data_as(v), coff.ctypes.data_as(v), 2, None, 16, ctypes.byref(out))
+    assert rc == 0 and out.value > plain
+    assert L.admm_batch_workspace_bytes(256, 4096, 64, 2, tiles.ctypes.data_as(v), toff.ctypes.data_as(v),
+                                        cuts.ctypes.data_as(v), coff.ctypes.data_as(v), 2, None, 1,
+                                        ctypes.byref(out)) == -1     # unknown flag
     bad = np.array([0, 3, 2, 1, 2], np.int32)        # not increasing
     assert L.admm_batch_workspace_bytes(256, 4096, 64, 2, bad.ctypes.data_as(v), toff.ctypes.data_as(v),
-                                        cuts.ctypes.data_as(v), coff.ctypes.data_as(v), 2, None,
+                                        cuts.ctypes.data_as(v), coff.ctypes.data_as(v), 2, None, 0,
                                         ctypes.byref(out)) == -1
     assert L.admm_batch_workspace_bytes(256, 4096, 48, 2, tiles.ctypes.data_as(v), toff.ctypes.data_as(v),
-                                        cuts.ctypes.data_as(v), coff.ctypes.data_as(v), 2, None,
+                                        cuts.ctypes.data_as(v), coff.ctypes.data_as(v), 2, None, 0,
                                         ctypes.byref(out)) == -1

@@ -25,9 +25,10 @@ def _batch():
 COL_OFF = [0, 700, 1500, 2300, 3072]
 
 
-def _solve(torch, b, K, graph=True):
+def _solve(torch, b, K, graph=True, inverse="c64"):
     import paper_1811_05571_amd as A
-    bb = A.Batch(to_device(torch, b.H0), b.tile_rows, b.tiles, b.cuts, b.phases, b.P, b.rho, b.lam, COL_OFF)
+    bb = A.Batch(to_device(torch, b.H0), b.tile_rows, b.tiles, b.cuts, b.phases, b.P, b.rho, b.lam, COL_OFF,
+                 inverse=inverse)
     g = to_device(torch, np.concatenate(b.g))
     return bb, g, bb.solve(g, K, graph=graph)
 
@@ -73,6 +74,31 @@ def test_batch_nmse_equals_plain_form(torch_gpu):
         npl = np.linalg.norm(vp - b.u_true[s]) ** 2 / np.linalg.norm(b.u_true[s]) ** 2
         print(f"scene {s}: NMSE batched {nb:.5f} plain {npl:.5f}")
         assert abs(nb - npl) <= 0.01 * npl + 1e-4
+
+
+def test_batch_inverse_bf16(torch_gpu):
+    """The bfloat16 copy of the scene inverses: every scene within 2^-8 of the
+    oracle on its stored matrix (the inverse entries are perturbed by at most
+    2^-9 relative), reconstruction error unchanged to 1 %, graph replay equal
+    to plain launches."""
+    b = _batch()
+    K = 60
+    bb, g, v = _solve(torch_gpu, b, K, inverse="bf16")
+    v2 = bb.solve(g, K, graph=False)
+    assert torch_gpu.equal(v, v2)
+    v = v.cpu().numpy()
+    _, _, v32 = _solve(torch_gpu, b, K)
+    v32 = v32.cpu().numpy()
+    H0q = QZ.dequantise(b.H0, "bf16")
+    for s in range(b.S):
+        ref, _, _ = O.solve(b.scene_H(s, H0q), b.g[s], len(b.cuts[s]) - 1, b.P, b.rho, b.lam[s], K, b.row_off(s),
+                            COL_OFF)
+        e = rel(v[s], ref)
+        n16 = np.linalg.norm(v[s] - b.u_true[s]) ** 2 / np.linalg.norm(b.u_true[s]) ** 2
+        n32 = np.linalg.norm(v32[s] - b.u_true[s]) ** 2 / np.linalg.norm(b.u_true[s]) ** 2
+        print(f"scene {s}: bf16 inverse vs oracle {e:.2e}, NMSE {n32:.5f} / {n16:.5f}")
+        assert e <= 2.0 ** -8
+        assert abs(n16 - n32) <= 1e-2 * n32
 
 
 def test_batch_rejects_bad_tables(torch_gpu):

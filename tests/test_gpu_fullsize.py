@@ -126,3 +126,18 @@ def test_full_size_batch_sampled_scenes(torch_gpu):
         e = rel(v[s], ref)
         print(f"scene {s}: {Hs.shape[0]} rows, Q={Q}, rel err vs oracle {e:.2e}", flush=True)
         assert e <= 1e-5
+
+
+def test_full_size_inverse_bf16(torch_gpu, full):
+    """The full workload with the bfloat16 copy of the block inverses: after
+    the workload's 300 iterations the image is within 2^-8 of the FP32-inverse
+    image and the reconstruction error is unchanged to 1e-3."""
+    import paper_1811_05571_amd as A
+    p, H, g = full
+    v32 = A.Plan(H, p.Q, p.P, p.rho, p.lam).solve(g, 300).cpu().numpy()
+    v16 = A.Plan(H, p.Q, p.P, p.rho, p.lam, inverse="bf16").solve(g, 300).cpu().numpy()
+    e = rel(v16, v32)
+    n = lambda v: float(np.linalg.norm(v - p.u_true) ** 2 / np.linalg.norm(p.u_true) ** 2)
+    print(f"bf16 inverse vs FP32 inverse {e:.2e}, NMSE {n(v32):.5f} / {n(v16):.5f}")
+    assert e <= 2.0 ** -8
+    assert abs(n(v16) - n(v32)) <= 1e-3 * n(v32)
