@@ -331,9 +331,14 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
     for (int a = 0; a < G.mt0 / kTile; ++a)
       for (int c = 0; c <= a; ++c) G.t0_gram.push_back(make_int4(j, a, c, 0));
   // FP64 setup groups: largest block sets the minimum group size
-  size_t max_blk = 0;
-  for (auto& d : G.blocks) max_blk = std::max(max_blk, (size_t)d.mt * d.mt * 16);
-  G.group_bytes = std::max<size_t>(max_blk, (size_t)2 << 30);
+  size_t max_blk = 0, all_blk = 0;
+  for (auto& d : G.blocks) {
+    max_blk = std::max(max_blk, (size_t)d.mt * d.mt * 16);
+    all_blk += (size_t)d.mt * d.mt * 16;
+  }
+  // up to 16 GB of FP64 per group matrix (two of them), never more than all
+  // blocks need: fewer, wider setup launches
+  G.group_bytes = std::max<size_t>(max_blk, std::min<size_t>(all_blk, (size_t)16 << 30));
   {
     size_t cur = 0, nb = 0, ng = 0;
     G.g_max_blocks = G.g_max_gram = 0;

@@ -53,6 +53,18 @@ struct BlockDesc {
   int32_t gpo;      // Gram-apply partials: first of the block's (mt/64)^2 64-vectors
 };
 
+// Compensated (Neumaier) FP32 sum: s + c carries the exact running sum to
+// about twice FP32 precision; terms are added in call order.
+struct CSum {
+  float s = 0.f, c = 0.f;
+  __device__ __forceinline__ void add(float x) {
+    const float t = s + x;
+    c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ float value() const { return s + c; }
+};
+
 // Scalars of the per-iteration reduction (FP64).
 enum : int {
   kRedRp2 = 0,   // sum_ij |u_j^i - v_j|^2

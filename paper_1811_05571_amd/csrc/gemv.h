@@ -40,17 +40,20 @@ template <class F> struct ColUnroll {
   static constexpr int U = F::CPL == 2 ? ADMM_COLS_UNROLL_C64 : ADMM_COLS_UNROLL_NARROW;
 };
 // H row products: rows per wave and lane loads in flight per row (narrow
-// formats reuse each lane's vector loads across 8 rows).
+// formats reuse each lane's vector loads across 8 rows), and how the row
+// sums are closed: the reduce-scatter of rows_reduce measured faster for
+// bfloat16, one wave sum per row for the complex64 and fp8 forms.
 template <class F> struct HRows {
   static constexpr int R = F::CPL == 2 ? ADMM_ROWS_C64 : ADMM_ROWS_NARROW;
   static constexpr int U = F::CPL == 2 ? ADMM_UNROLL_C64 : ADMM_UNROLL_NARROW;
+  static constexpr bool SCATTER = F::CPL == 8;
 };
 
 // Dot products of R consecutive rows of a stored matrix with the complex
 // vector x (FP32, padded, in the lane-permuted layout of cperm).  e0: element offset of the first row, ld: row
 // stride in elements, nl: lane loads per row (ceil(ncols / CPL)), rows >=
 // nvalid are clamped.  Lane l walks lane loads l, l+64, ... with U of them
-// per row in flight.  The result (row scale not applied) is in every lane.
+// per row in flight.  Returns per-lane partial sums; rows_reduce closes them.
 template <class F, int R, int U>
 __device__ __forceinline__ void rows_dot(const F& f, int64_t e0, int64_t ld, int nvalid,
                                          const float4* __restrict__ x, int nl, float (&acc)[R][2]) {
@@ -98,11 +101,58 @@ __device__ __forceinline__ void rows_dot(const F& f, int64_t e0, int64_t ld, int
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) consume(raw[rr], xv, rr);
   }
+}
+
+// Closes R row sums held by every lane of a wave (R a power of two <= 64).
+// Afterwards every lane holds the total of row rows_reduce_row<R>(lane).
+// Scatter: a reduce-scatter over lane bits 5, 4, ... (each step a lane keeps
+// half of its rows and sends the other half across) and an all-reduce over
+// the remaining low bits, 2(R - 1) + 2(6 - log2 R) shuffles; otherwise one
+// butterfly wave sum per row, 12 R shuffles.  Both in a fixed order.
+template <int R>
+__device__ __forceinline__ int rows_reduce_row(int lane) {
+  constexpr int LR = R >= 64 ? 6 : R >= 32 ? 5 : R >= 16 ? 4 : R >= 8 ? 3 : R >= 4 ? 2 : R >= 2 ? 1 : 0;
+  return LR == 0 ? 0 : (lane >> (6 - LR)) & (R - 1);
+}
+template <int R, bool Scatter>
+__device__ __forceinline__ void rows_reduce(float (&acc)[R][2], float& outr, float& outi) {
+  static_assert(R >= 1 && R <= 64 && (R & (R - 1)) == 0, "R must be a power of two");
+  if (!Scatter) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int want = rows_reduce_row<R>(lane);
+    float r = 0.f, i = 0.f;
 #pragma unroll
-  for (int rr = 0; rr < R; ++rr) {
-    acc[rr][0] = wave_sum(acc[rr][0]);
-    acc[rr][1] = wave_sum(acc[rr][1]);
+    for (int rr = 0; rr < R; ++rr) {
+      const float sr = wave_sum(acc[rr][0]), si = wave_sum(acc[rr][1]);
+      if (rr == want) { r = sr; i = si; }
+    }
+    outr = r;
+    outi = i;
+    return;
   }
+  constexpr int LR = R >= 64 ? 6 : R >= 32 ? 5 : R >= 16 ? 4 : R >= 8 ? 3 : R >= 4 ? 2 : R >= 2 ? 1 : 0;
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int st = 0; st < LR; ++st) {
+    const int mask = 32 >> st;
+    const int half = R >> (st + 1);
+    const bool hi = (lane & mask) != 0;
+#pragma unroll
+    for (int q = 0; q < half; ++q) {
+      const float kr = hi ? acc[q + half][0] : acc[q][0], ki = hi ? acc[q + half][1] : acc[q][1];
+      const float sr = hi ? acc[q][0] : acc[q + half][0], si = hi ? acc[q][1] : acc[q + half][1];
+      acc[q][0] = kr + __shfl_xor(sr, mask, kWave);
+      acc[q][1] = ki + __shfl_xor(si, mask, kWave);
+    }
+  }
+  float r = acc[0][0], i = acc[0][1];
+#pragma unroll
+  for (int mask = 32 >> LR; mask >= 1; mask >>= 1) {
+    r += __shfl_xor(r, mask, kWave);
+    i += __shfl_xor(i, mask, kWave);
+  }
+  outr = r;
+  outi = i;
 }
 
 // Adjoint (column) product of one workgroup: columns c*CPL .. c*CPL+CPL-1 of

@@ -94,12 +94,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_adj_rows(AdjArgs a, const int
   float acc[R][2];
   rows_dot<F, R, HRows<F>::U>(f, d.h_off + (int64_t)row * d.ld, d.ld, nvalid, x, (d.nj + F::CPL - 1) / F::CPL,
                               acc);
-  if (lane < nvalid) {
-    float ar = 0.f, ai = 0.f;
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr)
-      if (rr == lane) { ar = acc[rr][0]; ai = acc[rr][1]; }
-    const int lr = row + lane;
+  float ar, ai;
+  rows_reduce<R, HRows<F>::SCATTER>(acc, ar, ai);
+  const int rw = rows_reduce_row<R>(lane);
+  if ((lane & (kWave / R - 1)) == 0 && rw < nvalid) {
+    const int lr = row + rw;
     const float sc = f.row_scale(d.row0 + lr);
     const int64_t vi = (int64_t)d.j * a.m_pad + d.rpad0 + lr;
     double tr = 0.0, ti = 0.0;

@@ -326,23 +326,30 @@ __global__ __launch_bounds__(kZCols) void k_bzupdate(BatchArgs a, const ColDesc*
   const int col = t.z + threadIdx.x;
   if (col >= cd.nj) return;
   const int64_t p = cd.cpad0 + col;
+  // compensated FP32 sums in fixed order (CSum): u = c + tile partials, and
+  // the consensus sum of u + s over the replicas
   auto replica = [&](int i) {
     const int rep = sd.rb0 + i;
-    float2 u = a.c[(int64_t)rep * a.n_pad + p];
+    const float2 c0 = a.c[(int64_t)rep * a.n_pad + p];
+    CSum ur_, ui_;
+    ur_.add(c0.x);
+    ui_.add(c0.y);
     const int s0 = a.cuts[sd.cut0 + i], s1 = a.cuts[sd.cut0 + i + 1];
     for (int sl = s0; sl < s1; ++sl) {
       const float2 q = a.part[(int64_t)(sd.pslot0 + sl) * a.n_pad + p];
-      u.x += q.x;
-      u.y += q.y;
+      ur_.add(q.x);
+      ui_.add(q.y);
     }
-    return u;
+    return make_float2(ur_.value(), ui_.value());
   };
   float2 ur[kMaxQ];
-  float ar = 0.f, ai = 0.f;
+  CSum mr, mi;
   auto add_mean = [&](int i, const float2& u) {
     const float2 sv = a.s[(int64_t)(sd.rb0 + i) * a.n_pad + p];
-    ar += u.x + sv.x;
-    ai += u.y + sv.y;
+    mr.add(u.x);
+    mr.add(sv.x);
+    mi.add(u.y);
+    mi.add(sv.y);
   };
 #pragma unroll
   for (int i = 0; i < kMaxQ; ++i)
@@ -352,8 +359,7 @@ __global__ __launch_bounds__(kZCols) void k_bzupdate(BatchArgs a, const ColDesc*
     }
   for (int i = kMaxQ; i < sd.Q; ++i) add_mean(i, replica(i));
   const float invQ = 1.0f / (float)sd.Q;
-  ar *= invQ;
-  ai *= invQ;
+  const float ar = mr.value() * invQ, ai = mi.value() * invQ;
   if (!(isfinite(ar) && isfinite(ai))) a.ctl->nonfinite = 1;
   const float mag = sqrtf(ar * ar + ai * ai);
   float vr = 0.f, vi = 0.f;

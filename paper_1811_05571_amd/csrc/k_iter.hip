@@ -91,23 +91,27 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4
   float acc[R][2];
   rows_dot<F, R, HRows<F>::U>(f, d.h_off + (int64_t)row * d.ld, d.ld, nvalid, x, (d.nj + F::CPL - 1) / F::CPL,
                               acc);
-  if (lane < nvalid) {
-    float ar = 0.f, ai = 0.f;
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr)
-      if (rr == lane) { ar = acc[rr][0]; ai = acc[rr][1]; }
-    const int lr = row + lane;                       // row inside the block
+  float ar, ai;
+  rows_reduce<R, HRows<F>::SCATTER>(acc, ar, ai);
+  const int rr = rows_reduce_row<R>(lane);
+  if ((lane & (kWave / R - 1)) == 0 && rr < nvalid) {
+    const int lr = row + rr;                         // row inside the block
     const float sc = f.row_scale(d.row0 + lr);
     const int64_t vi = (int64_t)d.j * a.m_pad + d.rpad0 + lr;
     float2 gpv = a.g[d.row0 + lr];
     if (a.P > 1) {
       // eq. g_rows_columns: subtract the other sections' estimated data
+      // (compensated sums, sections in order)
+      CSum sr, si;
+      sr.add(gpv.x);
+      si.add(gpv.y);
       for (int q = 0; q < a.P; ++q) {
         if (q == d.j) continue;
-        float2 e = a.ghat[(int64_t)q * a.m_pad + d.rpad0 + lr];
-        gpv.x -= e.x;
-        gpv.y -= e.y;
+        const float2 e = a.ghat[(int64_t)q * a.m_pad + d.rpad0 + lr];
+        sr.add(-e.x);
+        si.add(-e.y);
       }
+      gpv = make_float2(sr.value(), si.value());
       a.gp[vi] = gpv;
     }
     a.r[vi] = make_float2(fmaf(-sc, ar, gpv.x), fmaf(-sc, ai, gpv.y));
@@ -211,22 +215,26 @@ __global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __re
     const int64_t pc = cd.cpad0 + cperm(col, a.cpl);   // position of c (row-product input layout)
     const int Q = MAXQ > 0 ? MAXQ : a.Q;
     float ur[MAXQ > 0 ? MAXQ : 1], ui[MAXQ > 0 ? MAXQ : 1];
+    // u = c + the row-chunk partials, and the consensus sum of u + s over the
+    // replicas: compensated FP32 sums in fixed order
     auto replica = [&](int i, float& xr, float& xi) {
       const float2 ci = a.c[(int64_t)i * a.n_pad + pc];
-      float sr = ci.x, si = ci.y;
+      CSum sr, si;
+      sr.add(ci.x);
+      si.add(ci.y);
       const float2* pp = a.part + (int64_t)i * a.n_pad + p;
       const int64_t stride = (int64_t)a.Q * a.n_pad;
 #pragma unroll 8
       for (int k = 0; k < a.KH; ++k) {
         const float2 pk = pp[k * stride];
-        sr += pk.x;
-        si += pk.y;
+        sr.add(pk.x);
+        si.add(pk.y);
       }
-      xr = sr;
-      xi = si;
+      xr = sr.value();
+      xi = si.value();
     };
     constexpr int kUnrollQ = MAXQ > 0 ? MAXQ : 1;
-    float ar = 0.f, ai = 0.f;
+    CSum mr, mi;
 #pragma unroll kUnrollQ
     for (int i = 0; i < Q; ++i) {
       if (MAXQ > 0 && i >= a.Q) break;
@@ -237,9 +245,12 @@ __global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __re
         ui[i] = xi;
       }
       const float2 si = a.s[(int64_t)i * a.n_pad + p];
-      ar += xr + si.x;
-      ai += xi + si.y;
+      mr.add(xr);
+      mr.add(si.x);
+      mi.add(xi);
+      mi.add(si.y);
     }
+    float ar = mr.value(), ai = mi.value();
     const float invQ = 1.0f / (float)a.Q;
     ar *= invQ;
     ai *= invQ;
