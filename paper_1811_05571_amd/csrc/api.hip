@@ -396,6 +396,10 @@ IterArgs iter_args(admm_plan* p, const float2* g, double* hist) {
   a.kappa = (float)(p->lam / (p->geo.Q * p->rho));
   a.rho2Q = p->rho * p->rho * p->geo.Q;
   a.cpl = cols_per_load(p->geo.storage);
+  int64_t x4 = 0;   // float4 of c per column block in the row product's layout
+  for (const ColDesc& cd : p->geo.cols)
+    x4 = std::max<int64_t>(x4, (int64_t)(cd.nj + kWave * a.cpl - 1) / (kWave * a.cpl) * kWave * (a.cpl / 2));
+  a.xstage = x4 <= kXStage ? 1 : 0;
   return a;
 }
 

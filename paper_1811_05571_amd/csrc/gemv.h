@@ -47,6 +47,11 @@ template <class F> struct HRows {
   static constexpr int R = F::CPL == 2 ? ADMM_ROWS_C64 : ADMM_ROWS_NARROW;
   static constexpr int U = F::CPL == 2 ? ADMM_UNROLL_C64 : ADMM_UNROLL_NARROW;
   static constexpr bool SCATTER = F::CPL == 8;
+  // Load the operands of each row's epilogue (row scale, g, the other
+  // sections' estimates) before streaming the row, so that their latency
+  // overlaps the stream: this matters where a row is only a few lane loads
+  // long (narrow formats).
+  static constexpr bool PREFETCH = F::CPL == 2 ? ADMM_EPI_PREFETCH_C64 : ADMM_EPI_PREFETCH_NARROW;
 };
 
 // Dot products of R consecutive rows of a stored matrix with the complex
@@ -59,10 +64,10 @@ __device__ __forceinline__ void rows_dot(const F& f, int64_t e0, int64_t ld, int
                                          const float4* __restrict__ x, int nl, float (&acc)[R][2]) {
   constexpr int CPL = F::CPL, X4 = CPL / 2;
   const int lane = threadIdx.x & (kWave - 1);
-  int64_t rowoff[R];
+  typename F::Row rows[R];
 #pragma unroll
   for (int rr = 0; rr < R; ++rr) {
-    rowoff[rr] = e0 + (int64_t)(rr < nvalid ? rr : (nvalid - 1)) * ld;
+    rows[rr] = f.row(e0 + (int64_t)(rr < nvalid ? rr : (nvalid - 1)) * ld);
     acc[rr][0] = 0.f;
     acc[rr][1] = 0.f;
   }
@@ -81,7 +86,7 @@ __device__ __forceinline__ void rows_dot(const F& f, int64_t e0, int64_t ld, int
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int rr = 0; rr < R; ++rr) raw[u][rr] = f.load(rowoff[rr] + (int64_t)(c + u * kWave) * CPL);
+      for (int rr = 0; rr < R; ++rr) raw[u][rr] = F::load(rows[rr], (uint32_t)(c + u * kWave));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       float4 xv[X4];
@@ -94,7 +99,7 @@ __device__ __forceinline__ void rows_dot(const F& f, int64_t e0, int64_t ld, int
   for (; c < nl; c += kWave) {
     typename F::Raw raw[R];
 #pragma unroll
-    for (int rr = 0; rr < R; ++rr) raw[rr] = f.load(rowoff[rr] + (int64_t)c * CPL);
+    for (int rr = 0; rr < R; ++rr) raw[rr] = F::load(rows[rr], (uint32_t)c);
     float4 xv[X4];
 #pragma unroll
     for (int q = 0; q < X4; ++q) xv[q] = x[(((int64_t)(c >> 6) * X4 + q) << 6) + (c & 63)];

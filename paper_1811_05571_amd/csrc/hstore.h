@@ -55,11 +55,20 @@ __device__ __forceinline__ void e4m3x4_to_f32(unsigned w, float& a, float& b, fl
 // Each format: Raw = what one lane load returns (16 B per plane),
 // load(e) reads columns e .. e+CPL-1 of a row (e a multiple of CPL),
 // decode() turns it into CPL complex values (row scale not applied).
+// row(e0) is the view of one row starting at element e0 (wave-uniform
+// pointers, kept in scalar registers) and load(row, k) its k-th lane load:
+// the 32-bit byte offset k * 16 lets every row share one vector offset.
+__device__ __forceinline__ const char* lane_load_at(const char* rowp, uint32_t k) { return rowp + k * 16u; }
 struct FmtC64 {
   static constexpr int CPL = 2;
   struct Raw { float4 a; };
   const float2* p;
   __device__ __forceinline__ Raw load(int64_t e) const { return Raw{ldnt4(reinterpret_cast<const float4*>(p + e))}; }
+  struct Row { const char* p; };
+  __device__ __forceinline__ Row row(int64_t e0) const { return Row{reinterpret_cast<const char*>(p + e0)}; }
+  __device__ __forceinline__ static Raw load(const Row& r, uint32_t k) {
+    return Raw{ldnt4(reinterpret_cast<const float4*>(lane_load_at(r.p, k)))};
+  }
   __device__ __forceinline__ static void decode(const Raw& r, float (&re)[CPL], float (&im)[CPL]) {
     re[0] = r.a.x; im[0] = r.a.y; re[1] = r.a.z; im[1] = r.a.w;
   }
@@ -77,6 +86,13 @@ struct FmtBF16 {
   const uint16_t* re_p;
   const uint16_t* im_p;
   __device__ __forceinline__ Raw load(int64_t e) const { return Raw{ldnt4u(re_p + e), ldnt4u(im_p + e)}; }
+  struct Row { const char* re; const char* im; };
+  __device__ __forceinline__ Row row(int64_t e0) const {
+    return Row{reinterpret_cast<const char*>(re_p + e0), reinterpret_cast<const char*>(im_p + e0)};
+  }
+  __device__ __forceinline__ static Raw load(const Row& r, uint32_t k) {
+    return Raw{ldnt4u(lane_load_at(r.re, k)), ldnt4u(lane_load_at(r.im, k))};
+  }
   __device__ __forceinline__ static void decode(const Raw& r, float (&re)[CPL], float (&im)[CPL]) {
     const unsigned aw[4] = {r.a.x, r.a.y, r.a.z, r.a.w}, bw[4] = {r.b.x, r.b.y, r.b.z, r.b.w};
 #pragma unroll
@@ -100,6 +116,13 @@ struct FmtFP8 {
   const uint8_t* im_p;
   const float* scale;   // per global row
   __device__ __forceinline__ Raw load(int64_t e) const { return Raw{ldnt4u(re_p + e), ldnt4u(im_p + e)}; }
+  struct Row { const char* re; const char* im; };
+  __device__ __forceinline__ Row row(int64_t e0) const {
+    return Row{reinterpret_cast<const char*>(re_p + e0), reinterpret_cast<const char*>(im_p + e0)};
+  }
+  __device__ __forceinline__ static Raw load(const Row& r, uint32_t k) {
+    return Raw{ldnt4u(lane_load_at(r.re, k)), ldnt4u(lane_load_at(r.im, k))};
+  }
   __device__ __forceinline__ static void decode(const Raw& r, float (&re)[CPL], float (&im)[CPL]) {
     const unsigned aw[4] = {r.a.x, r.a.y, r.a.z, r.a.w}, bw[4] = {r.b.x, r.b.y, r.b.z, r.b.w};
 #pragma unroll

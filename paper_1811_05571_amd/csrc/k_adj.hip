@@ -85,7 +85,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_adj_rows(AdjArgs a, const int
   const F f = MakeFmt<F>::make(a.hs);
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = a.blocks[t.x];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  // wave index in a scalar register: the rows' addresses are then wave-uniform
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   constexpr int R = HRows<F>::R;
   const int row = t.y + wave * R;
   if (row >= d.mi) return;

@@ -73,7 +73,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_zfinal(IterArgs a) {
 // r_ij = g'_ij - H_ij c_j^i for 4 * HRows<F>::R rows of one block per workgroup.
 // tiles[x] = {block, first row, -, -}.  Workgroup 0 first completes the
 // previous iteration's residual sums (zfinal).
-template <class F>
+// XS: the block's c is first copied to LDS by the whole workgroup (its
+// layout unchanged), so its vector loads do not hold registers across the
+// stream's loads and the workgroup reads it from L2 once instead of per wave.
+template <class F, bool XS>
 __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4* __restrict__ tiles) {
   if (blockIdx.x == 0) {
     __shared__ double red[kBlockThreads / kWave][kRedCount];
@@ -82,34 +85,77 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4
   const F f = MakeFmt<F>::make(a.hs);
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = a.blocks[t.x];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  // wave index in a scalar register: the rows' addresses are then wave-uniform
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   constexpr int R = HRows<F>::R;
   const int row = t.y + wave * R;
+  const float4* xg = reinterpret_cast<const float4*>(a.c + (int64_t)d.i * a.n_pad + d.cpad0);
+  __shared__ float4 xs[XS ? kXStage : 1];
+  if (XS) {
+    // whole groups of 64 lane loads: inside the block's padded segment of c
+    const int n4 = (d.nj + kWave * F::CPL - 1) / (kWave * F::CPL) * kWave * (F::CPL / 2);
+    for (int k = threadIdx.x; k < n4; k += kRowWaves * kWave) xs[k] = xg[k];
+    __syncthreads();
+  }
   if (row >= d.mi) return;
   const int nvalid = min(R, d.mi - row);
-  const float4* x = reinterpret_cast<const float4*>(a.c + (int64_t)d.i * a.n_pad + d.cpad0);
+  const float4* x = XS ? xs : xg;
+  // The lane that writes row rr after the reduction (one per row).
+  const int rr = rows_reduce_row<R>(lane);
+  const bool writer = (lane & (kWave / R - 1)) == 0 && rr < nvalid;
+  const int lr = row + rr;                           // row inside the block
+  // Epilogue operands, loaded ahead of the stream where HRows asks for it and
+  // the other sections fit kEpiSections registers.
+  constexpr bool PF = HRows<F>::PREFETCH;
+  constexpr int NE = PF ? kEpiSections : 1;
+  const bool pre = PF && a.P - 1 <= kEpiSections;
+  float sc = 1.f;
+  float2 gpv = make_float2(0.f, 0.f), ev[NE];
+#pragma unroll
+  for (int q = 0; q < NE; ++q) ev[q] = make_float2(0.f, 0.f);
+  if (PF && writer) {
+    sc = f.row_scale(d.row0 + lr);
+    gpv = a.g[d.row0 + lr];
+    if (pre) {
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const int sec = q < d.j ? q : q + 1;         // the other sections in order
+        if (sec < a.P) ev[q] = a.ghat[(int64_t)sec * a.m_pad + d.rpad0 + lr];
+      }
+    }
+  }
   float acc[R][2];
   rows_dot<F, R, HRows<F>::U>(f, d.h_off + (int64_t)row * d.ld, d.ld, nvalid, x, (d.nj + F::CPL - 1) / F::CPL,
                               acc);
   float ar, ai;
   rows_reduce<R, HRows<F>::SCATTER>(acc, ar, ai);
-  const int rr = rows_reduce_row<R>(lane);
-  if ((lane & (kWave / R - 1)) == 0 && rr < nvalid) {
-    const int lr = row + rr;                         // row inside the block
-    const float sc = f.row_scale(d.row0 + lr);
+  if (writer) {
+    if (!PF) {
+      sc = f.row_scale(d.row0 + lr);
+      gpv = a.g[d.row0 + lr];
+    }
     const int64_t vi = (int64_t)d.j * a.m_pad + d.rpad0 + lr;
-    float2 gpv = a.g[d.row0 + lr];
     if (a.P > 1) {
       // eq. g_rows_columns: subtract the other sections' estimated data
       // (compensated sums, sections in order)
       CSum sr, si;
       sr.add(gpv.x);
       si.add(gpv.y);
-      for (int q = 0; q < a.P; ++q) {
-        if (q == d.j) continue;
-        const float2 e = a.ghat[(int64_t)q * a.m_pad + d.rpad0 + lr];
-        sr.add(-e.x);
-        si.add(-e.y);
+      if (pre) {
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          if (q < a.P - 1) {
+            sr.add(-ev[q].x);
+            si.add(-ev[q].y);
+          }
+        }
+      } else {
+        for (int q = 0; q < a.P; ++q) {
+          if (q == d.j) continue;
+          const float2 e = a.ghat[(int64_t)q * a.m_pad + d.rpad0 + lr];
+          sr.add(-e.x);
+          si.add(-e.y);
+        }
       }
       gpv = make_float2(sr.value(), si.value());
       a.gp[vi] = gpv;
@@ -359,9 +405,19 @@ __global__ void k_fill_zero(uint4* p, size_t n16) {
 
 hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt) {
   switch (a.hs.storage) {
-    case 0: LAUNCH_TIMED(k_gemv_n<FmtC64>, dim3(ntiles), dim3(kRowWaves * kWave), st, kt, a, tiles); break;
-    case 1: LAUNCH_TIMED(k_gemv_n<FmtBF16>, dim3(ntiles), dim3(kRowWaves * kWave), st, kt, a, tiles); break;
-    default: LAUNCH_TIMED(k_gemv_n<FmtFP8>, dim3(ntiles), dim3(kRowWaves * kWave), st, kt, a, tiles); break;
+    case 0: LAUNCH_TIMED((k_gemv_n<FmtC64, false>), dim3(ntiles), dim3(kRowWaves * kWave), st, kt, a, tiles); break;
+    case 1:
+      if (ADMM_XLDS_NARROW && a.xstage)
+        LAUNCH_TIMED((k_gemv_n<FmtBF16, true>), dim3(ntiles), dim3(kRowWaves * kWave), st, kt, a, tiles);
+      else
+        LAUNCH_TIMED((k_gemv_n<FmtBF16, false>), dim3(ntiles), dim3(kRowWaves * kWave), st, kt, a, tiles);
+      break;
+    default:
+      if (ADMM_XLDS_NARROW && a.xstage)
+        LAUNCH_TIMED((k_gemv_n<FmtFP8, true>), dim3(ntiles), dim3(kRowWaves * kWave), st, kt, a, tiles);
+      else
+        LAUNCH_TIMED((k_gemv_n<FmtFP8, false>), dim3(ntiles), dim3(kRowWaves * kWave), st, kt, a, tiles);
+      break;
   }
   return hipGetLastError();
 }

@@ -55,6 +55,12 @@ struct Geometry {
 #ifndef ADMM_ROWS_NARROW
 #define ADMM_ROWS_NARROW 8      // rows per wave of the bf16 / fp8 row product
 #endif
+#ifndef ADMM_EPI_PREFETCH_C64
+#define ADMM_EPI_PREFETCH_C64 1 // complex64 row product: load the row epilogue's operands before the stream
+#endif
+#ifndef ADMM_EPI_PREFETCH_NARROW
+#define ADMM_EPI_PREFETCH_NARROW 1  // the same for bf16 / fp8
+#endif
 #ifndef ADMM_UNROLL_NARROW
 #define ADMM_UNROLL_NARROW 1    // lane loads in flight per row (bf16 / fp8)
 #endif
@@ -71,6 +77,11 @@ struct Geometry {
 #define ADMM_COLS_WG_TARGET_C64 4096  // the same for complex64 storage
 #endif
 constexpr int kRowWaves = ADMM_ROW_WAVES;
+#ifndef ADMM_XLDS_NARROW
+#define ADMM_XLDS_NARROW 1      // bf16 / fp8 row product: stage each block's c in LDS (when it fits)
+#endif
+constexpr int kXStage = 2048;    // float4 of c staged per workgroup (32 KB: column blocks up to 4096)
+constexpr int kEpiSections = 7;  // other sections whose estimates the row epilogue prefetches (P <= 8)
 
 static_assert(kRowWaves >= 1 && kRowWaves <= kBlockThreads / kWave, "row waves");
 
@@ -112,6 +123,7 @@ struct IterArgs {
   float rho, kappa;
   double rho2Q;         // rho^2 Q for the dual residual
   int cpl;              // columns per lane load of the storage (layout of c, see cperm)
+  int xstage;           // 1: every column block's c fits kXStage float4 of LDS (row product stages it)
 };
 
 // Adjoint (reverse-mode) sweep of one iteration.
