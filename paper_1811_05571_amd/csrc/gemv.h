@@ -39,8 +39,9 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 template <class F> struct ColUnroll {
   static constexpr int U = F::CPL == 2 ? ADMM_COLS_UNROLL_C64 : ADMM_COLS_UNROLL_NARROW;
 };
-// H row products: rows per wave and lane loads in flight per row (narrow
-// formats reuse each lane's vector loads across 8 rows), and how the row
+// H row products: rows per wave and lane loads in flight per row (8 rows
+// for complex64, 4 for the narrow formats, whose wide lane loads fill more
+// registers per row; measured), and how the row
 // sums are closed: the reduce-scatter of rows_reduce measured faster for
 // bfloat16, one wave sum per row for the complex64 and fp8 forms.
 template <class F> struct HRows {

@@ -50,10 +50,10 @@ struct Geometry {
 #define ADMM_ROWS_C64 8         // rows per wave of the complex64 row product
 #endif
 #ifndef ADMM_UNROLL_C64
-#define ADMM_UNROLL_C64 2       // lane loads in flight per row (complex64)
+#define ADMM_UNROLL_C64 4       // lane loads in flight per row (complex64)
 #endif
 #ifndef ADMM_ROWS_NARROW
-#define ADMM_ROWS_NARROW 8      // rows per wave of the bf16 / fp8 row product
+#define ADMM_ROWS_NARROW 4      // rows per wave of the bf16 / fp8 row product
 #endif
 #ifndef ADMM_EPI_PREFETCH_C64
 #define ADMM_EPI_PREFETCH_C64 1 // complex64 row product: load the row epilogue's operands before the stream
@@ -93,8 +93,7 @@ constexpr int kRowsPerWG = kRowsPerWave * (kBlockThreads / kWave);
 constexpr int kColsPerWGLoads = kWave;
 // Complex columns per lane load for a storage format.
 inline int cols_per_load(int storage) { return storage == 0 ? 2 : (storage == 1 ? 8 : 16); }
-// Rows per wave of the H row products: narrow formats share each lane's
-// vector loads across more rows.
+// Rows per wave of the H row products (the tiles of k_gemv_n follow it).
 inline int rows_per_wave(int storage) { return storage == 0 ? ADMM_ROWS_C64 : ADMM_ROWS_NARROW; }
 // Bytes per stored complex element.
 inline int elem_bytes(int storage) { return storage == 0 ? 8 : (storage == 1 ? 4 : 2); }
