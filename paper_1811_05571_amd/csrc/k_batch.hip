@@ -108,6 +108,13 @@ struct __attribute__((aligned(16))) BStage {
 };
 static_assert(alignof(BStage) == 16, "16-byte LDS accesses");
 
+// LDS position of the 16-byte chunk q (k = 8q .. 8q+7) of column col: the
+// chunks of a column are permuted by an XOR with ((col >> 1) ^ (col >> 2)) & 3
+// so that the fragment reads (16 lanes = 16 consecutive columns, one chunk)
+// and the staging writes meet distinct banks in every 8- and 16-lane group;
+// unpermuted, the 64-byte column stride put 4 lanes of 8 on each bank group.
+__device__ __forceinline__ int bchunk(int col, int q) { return 8 * (q ^ (((col >> 1) ^ (col >> 2)) & 3)); }
+
 // This thread's piece of a B step: column tid/4, k offset 8 (tid % 4); six
 // 16-byte loads from plane stride ps.
 __device__ __forceinline__ void bstage_load(const uint16_t* __restrict__ src, int64_t ps, u32x4 (&r)[6]) {
@@ -115,13 +122,13 @@ __device__ __forceinline__ void bstage_load(const uint16_t* __restrict__ src, in
   for (int p = 0; p < 6; ++p) r[p] = *reinterpret_cast<const u32x4*>(src + p * ps);
 }
 __device__ __forceinline__ void bstage_store(BStage& bs, int buf, const u32x4 (&r)[6]) {
-  const int col = threadIdx.x >> 2, k = 8 * (threadIdx.x & 3);
+  const int col = threadIdx.x >> 2, k = bchunk(col, threadIdx.x & 3);
 #pragma unroll
   for (int p = 0; p < 6; ++p) *reinterpret_cast<u32x4*>(&bs.v[buf][p][col][k]) = r[p];
 }
 __device__ __forceinline__ void bstage_frag(const BStage& bs, int buf, int nt, Split& x) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int col = 16 * nt + (lane & 15), k = 8 * (lane >> 4);
+  const int col = 16 * nt + (lane & 15), k = bchunk(col, lane >> 4);
   x.r1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&bs.v[buf][0][col][k]));
   x.r2 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&bs.v[buf][1][col][k]));
   x.r3 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&bs.v[buf][2][col][k]));
