@@ -20,6 +20,7 @@ import hashlib
 import json
 import os
 import platform
+import re
 import sys
 import time
 
@@ -94,8 +95,11 @@ SHARED_NAMES = {"k_gram_tile": "k_gram", "k_gram_reduce": "k_gram", "k_zupdate<4
 
 
 def _short_kernel(name: str) -> str:
+    """Kernel name without namespace, arguments and template flags after the
+    first template argument (k_gemv_n<FmtFP8, true> -> k_gemv_n<FmtFP8>)."""
     n = name.replace("admm::(anonymous namespace)::", "").replace("admm::", "").replace("void ", "")
-    return n.split("(")[0].strip()
+    n = n.split("(")[0].strip()
+    return re.sub(r"<([^,<>]+),[^<>]*>", r"<\1>", n)
 
 
 def read_counter_csv(path: str, counter: str) -> list:
