@@ -137,42 +137,48 @@ __device__ __forceinline__ void bstage_frag(const BStage& bs, int buf, int nt, S
   x.i3 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&bs.v[buf][5][col][k]));
 }
 
-// Accumulates over k in [k0, k1) (multiples of kGK): a_re/a_im[m] point at
-// this lane's A row of subtile m at k = 0 (+ its 8-element k offset), bsrc at
-// this thread's B piece at k = 0, plane stride ps.  conj_a: use conj(A).
+// Accumulates over k in [k0, k1) (multiples of kGK, at least one step):
+// a_re/a_im[m] point at this lane's A row of subtile m at k = 0 (+ its
+// 8-element k offset), bsrc at this thread's B piece at k = 0, plane stride
+// ps.  conj_a: use conj(A).  A streams from HBM, so its loads run two steps
+// ahead in three register sets used in rotation (the loop is unrolled by
+// three, so no loop-carried copy makes a step wait for loads it does not
+// use); B comes from the cache-resident split planes one step ahead through
+// the LDS double buffer.  Loads past the last step re-read the last step.
 template <int MS>
 __device__ __forceinline__ void gemm_tile(const uint16_t* const (&a_re)[MS], const uint16_t* const (&a_im)[MS],
                                           const uint16_t* __restrict__ bsrc, int64_t ps, int k0, int k1, int ntv,
                                           bool conj_a, BStage& bs, f32x4 (&accr)[MS][4], f32x4 (&acci)[MS][4]) {
   const u32x4 sgn = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  const int klast = k1 - kGK;
   u32x4 br[6];
-  u32x4 ar[MS], ai[MS];
-  bstage_load(bsrc + k0, ps, br);
+  u32x4 a0r[MS], a0i[MS], a1r[MS], a1i[MS], a2r[MS], a2i[MS];
+  auto load_a = [&](int k, u32x4 (&r)[MS], u32x4 (&i)[MS]) {
 #pragma unroll
-  for (int m = 0; m < MS; ++m) {
-    ar[m] = ld16(a_re[m] + k0);
-    ai[m] = ld16(a_im[m] + k0);
-  }
+    for (int m = 0; m < MS; ++m) {
+      r[m] = ld16(a_re[m] + k);
+      i[m] = ld16(a_im[m] + k);
+    }
+  };
+  bstage_load(bsrc + k0, ps, br);
+  load_a(k0, a0r, a0i);
+  load_a(min(k0 + kGK, klast), a1r, a1i);
   bstage_store(bs, 0, br);
   __syncthreads();
   int buf = 0;
-  for (int k = k0; k < k1; k += kGK) {
-    // next step's operands (the last step reloads its own: no branch around
-    // the loads, so they stay in flight during this step's MFMAs)
-    const int kn = k + kGK < k1 ? k + kGK : k;
-    u32x4 arn[MS], ain[MS];
-    bstage_load(bsrc + kn, ps, br);
-#pragma unroll
-    for (int m = 0; m < MS; ++m) {
-      arn[m] = ld16(a_re[m] + kn);
-      ain[m] = ld16(a_im[m] + kn);
-    }
+  // one k-step with A operands (cr, ci); loads step k + 2's A into (nr, ni)
+  auto step = [&](int k, const u32x4 (&cr)[MS], const u32x4 (&ci)[MS], u32x4 (&nr)[MS], u32x4 (&ni)[MS]) {
+    bstage_load(bsrc + min(k + kGK, klast), ps, br);
+    // B before A in issue order: the counter wait before the LDS stores at
+    // the end of this step then does not cover the A loads two steps ahead
+    __builtin_amdgcn_sched_barrier(0);
+    load_a(min(k + 2 * kGK, klast), nr, ni);
     bf16x8 A1[MS], A2[MS], A3[MS];   // (Re, Im, -Im) of A, or (Re, -Im, Im) for conj(A)
 #pragma unroll
     for (int m = 0; m < MS; ++m) {
-      A1[m] = as_bf16(ar[m]);
-      A2[m] = as_bf16(conj_a ? (ai[m] ^ sgn) : ai[m]);
-      A3[m] = as_bf16(conj_a ? ai[m] : (ai[m] ^ sgn));
+      A1[m] = as_bf16(cr[m]);
+      A2[m] = as_bf16(conj_a ? (ci[m] ^ sgn) : ci[m]);
+      A3[m] = as_bf16(conj_a ? ci[m] : (ci[m] ^ sgn));
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -184,14 +190,17 @@ __device__ __forceinline__ void gemm_tile(const uint16_t* const (&a_re)[MS], con
       }
     }
     bstage_store(bs, buf ^ 1, br);   // buffer buf ^ 1 was last read before the previous barrier
-#pragma unroll
-    for (int m = 0; m < MS; ++m) {
-      ar[m] = arn[m];
-      ai[m] = ain[m];
-    }
     __syncthreads();
     buf ^= 1;
+  };
+  int k = k0;
+  for (; k + 3 * kGK <= k1; k += 3 * kGK) {
+    step(k, a0r, a0i, a2r, a2i);
+    step(k + kGK, a1r, a1i, a0r, a0i);
+    step(k + 2 * kGK, a2r, a2i, a1r, a1i);
   }
+  if (k < k1) step(k, a0r, a0i, a2r, a2i);
+  if (k + kGK < k1) step(k + kGK, a1r, a1i, a0r, a0i);
 }
 
 // Forward product, one k-chunk: partial sums of H0[f, C_j] X over columns
