@@ -64,7 +64,7 @@ struct BatchArgs {
   // {Re t1, Re t2, Re t3, Im t1, Im t2, Im t3}:
   //   cs: of c, [p][R][n_pad];  ys: of conj(phase) o y, [p][P][m_pad]
   uint16_t *cs, *ys;
-  // forward GEMM k-chunk partials [chunk][group][tile_rows][64] and, per
+  // forward GEMM k-chunk partials [chunk][group][64][tile_rows] and, per
   // scene-tile entry, {first group index (add j), column in the group}
   float2* pn;
   const int2* st_gc;

@@ -206,7 +206,8 @@ __device__ __forceinline__ void gemm_tile(const uint16_t* const (&a_re)[MS], con
 // Forward product, one k-chunk: partial sums of H0[f, C_j] X over columns
 // [it.m0, it.pad[0]) for rows [it.pad[2], it.pad[2] + 64 MS) of the tile and
 // the up to 64 scene-tiles of the item, written to partial slot it.pad[1]
-// ([slot][tile_rows][64], complex).
+// ([slot][64 scene-tile columns][tile_rows], complex: the finisher's threads,
+// one per row, then read consecutive entries).
 template <int MS>
 __global__ __launch_bounds__(kBlockThreads) void k_bgemm_n(BatchArgs a, const GemmItem* __restrict__ items) {
   __shared__ BStage bs;
@@ -245,7 +246,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_bgemm_n(BatchArgs a, const Ge
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int row = it.pad[2] + 16 * (wave * MS + m) + 4 * (lane >> 4) + e;
-        out[(int64_t)row * kGN + col] = make_float2(accr[m][nt][e], acci[m][nt][e]);
+        out[(int64_t)col * a.tile_rows + row] = make_float2(accr[m][nt][e], acci[m][nt][e]);
       }
     }
 }
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_bgemm_n_fin(BatchArgs a, int 
   const int64_t g = gc.x + j;
   float hr = 0.f, hi = 0.f;
   for (int kc = 0; kc < KS; ++kc) {
-    const float2 q = a.pn[(((int64_t)kc * a.NG + g) * a.tile_rows + rr) * kGN + gc.y];
+    const float2 q = a.pn[(((int64_t)kc * a.NG + g) * kGN + gc.y) * a.tile_rows + rr];
     hr += q.x;
     hi += q.y;
   }
@@ -273,12 +274,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_bgemm_n_fin(BatchArgs a, int 
   const int64_t vi = (int64_t)j * a.m_pad + rb.rpad0 + lr;
   float2 gpv = a.g[gr];
   if (a.P > 1) {
+    // the other sections' estimated data, compensated sums in section order
+    CSum sr, si;
+    sr.add(gpv.x);
+    si.add(gpv.y);
     for (int q = 0; q < a.P; ++q) {
       if (q == j) continue;
       const float2 e2 = a.ghat[(int64_t)q * a.m_pad + rb.rpad0 + lr];
-      gpv.x -= e2.x;
-      gpv.y -= e2.y;
+      sr.add(-e2.x);
+      si.add(-e2.y);
     }
+    gpv = make_float2(sr.value(), si.value());
     a.gp[vi] = gpv;
   }
   a.r[vi] = make_float2(gpv.x - pr, gpv.y - pi);
@@ -320,12 +326,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_bgemm_h(BatchArgs a, const Ge
     if (t >= it.cnt) continue;
     float2* out = a.part + (int64_t)a.stab[it.st0 + t].pslot * a.n_pad + pj.cpad0;
 #pragma unroll
-    for (int m = 0; m < MS; ++m)
+    for (int m = 0; m < MS; ++m) {
+      // four consecutive columns per lane: two 16-byte stores when all exist
+      const int cc = it.m0 + 16 * (wave * MS + m) + 4 * (lane >> 4);
+      if (cc + 3 < pj.nj) {
+        float4* o4 = reinterpret_cast<float4*>(out + cc);
+        o4[0] = make_float4(accr[m][nt][0], acci[m][nt][0], accr[m][nt][1], acci[m][nt][1]);
+        o4[1] = make_float4(accr[m][nt][2], acci[m][nt][2], accr[m][nt][3], acci[m][nt][3]);
+      } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int cc = it.m0 + 16 * (wave * MS + m) + 4 * (lane >> 4) + e;
-        if (cc < pj.nj) out[cc] = make_float2(accr[m][nt][e], acci[m][nt][e]);
+        for (int e = 0; e < 4; ++e)
+          if (cc + e < pj.nj) out[cc + e] = make_float2(accr[m][nt][e], acci[m][nt][e]);
       }
+    }
   }
 }
 
