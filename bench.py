@@ -87,7 +87,7 @@ def load_traffic(kernel: str, workload: str):
 COPY_PROBE_KERNEL = "neg_kernel"   # torch's elementwise negation: reads and writes N bytes
 # per-iteration kernels as named in the counter output -> bench names, per storage
 TRACE_NAMES = {
-    "c64": {"k_gemv_n<FmtC64>": "k_gemv_n", "k_gemv_h<FmtC64>": "k_gemv_h"},
+    "c64": {"k_gemv_n<FmtC64>": "k_gemv_n", "k_gemv_nw": "k_gemv_n", "k_gemv_h<FmtC64>": "k_gemv_h"},
     "bf16": {"k_gemv_n<FmtBF16>": "k_gemv_n", "k_gemv_h<FmtBF16>": "k_gemv_h"},
     "fp8": {"k_gemv_n<FmtFP8>": "k_gemv_n", "k_gemv_h<FmtFP8>": "k_gemv_h"},
 }

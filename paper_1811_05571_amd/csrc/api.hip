@@ -183,6 +183,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   geo.t_kadj.clear();
   geo.t_hrows.clear();
   geo.t_gtr.clear();
+  geo.t_wrows.clear();
   const int cpl = cols_per_load(storage);
   int wg_per_chunk = 0;
   for (size_t b = 0; b < geo.blocks.size(); ++b) {
@@ -190,6 +191,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
     for (int r = 0; r < d.mi; r += kRowsPerWG) geo.t_rows.push_back(make_int4((int)b, r, 0, 0));
     const int hrows = rows_per_wave(storage) * kRowWaves;
     for (int r = 0; r < d.mi; r += hrows) geo.t_hrows.push_back(make_int4((int)b, r, 0, 0));
+    for (int r = 0; r < d.mi; r += kWholeRows) geo.t_wrows.push_back(make_int4((int)b, r, 0, 0));
     const int nl = (d.nj + cpl - 1) / cpl;
     wg_per_chunk += (nl + kColsPerWGLoads - 1) / kColsPerWGLoads;
     const int nt = d.mt / kTile;
@@ -197,6 +199,13 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
       for (int c = 0; c <= a; ++c) geo.t_gram.push_back(make_int4((int)b, a, c, 0));
       geo.t_gtr.push_back(make_int4((int)b, a, 0, 0));
     }
+  }
+  // The whole-row product serves complex64 storage whose column blocks fit
+  // kWholeLoads lane loads per thread.
+  {
+    bool whole = ADMM_WHOLE_ROWS && storage == ADMM_STORAGE_C64;
+    for (const BlockDesc& d : geo.blocks) whole = whole && (d.nj + cpl - 1) / cpl <= kWholeLoads * kBlockThreads;
+    if (!whole) geo.t_wrows.clear();
   }
   // Row chunks of the adjoint product: about ADMM_COLS_WG_TARGET(_C64)
   // workgroups in total, at least 32 rows (8 per wave) per chunk.
@@ -257,6 +266,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   L.t_gram = take(16 * geo.t_gram.size());
   L.t_kadj = take(16 * geo.t_kadj.size());
   L.t_hrows = take(16 * geo.t_hrows.size());
+  L.t_wrows = take(16 * std::max<size_t>(geo.t_wrows.size(), 1));
   L.t_gtr = take(16 * geo.t_gtr.size());
   L.gpart = take((size_t)gpo * kTile * 8);
   L.ctl = take(sizeof(Control));
@@ -295,6 +305,7 @@ struct admm_plan {
   BlockDesc* d_blocks = nullptr;
   ColDesc* d_cols = nullptr;
   int4 *t_rows = nullptr, *t_cols = nullptr, *t_z = nullptr, *t_gram = nullptr, *t_kadj = nullptr, *t_hrows = nullptr;
+  int4* t_wrows = nullptr;
   int4* t_gtr = nullptr;
   float2* gpart = nullptr;
   HStore hs{};
@@ -530,6 +541,7 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   p->t_gram = at<int4>(p, L.t_gram);
   p->t_kadj = at<int4>(p, L.t_kadj);
   p->t_hrows = at<int4>(p, L.t_hrows);
+  p->t_wrows = at<int4>(p, L.t_wrows);
   p->t_gtr = at<int4>(p, L.t_gtr);
   p->gpart = at<float2>(p, L.gpart);
   p->hs.storage = storage;
@@ -586,6 +598,8 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   SETUP_TRY(hipMemcpyAsync(p->t_gram, G.t_gram.data(), 16 * G.t_gram.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->t_kadj, G.t_kadj.data(), 16 * G.t_kadj.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->t_hrows, G.t_hrows.data(), 16 * G.t_hrows.size(), hipMemcpyHostToDevice, st));
+  if (!G.t_wrows.empty())
+    SETUP_TRY(hipMemcpyAsync(p->t_wrows, G.t_wrows.data(), 16 * G.t_wrows.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->t_gtr, G.t_gtr.data(), 16 * G.t_gtr.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->row_block, p->h_row_block.data(), 8 * (size_t)m, hipMemcpyHostToDevice, st));
   int max_mi = 0;
@@ -636,7 +650,7 @@ int admm_solve(admm_plan* p, const void* g, int iters, double tol, int check_eve
   const int ngr = (int)G.t_gram.size(), ngt = (int)G.t_gtr.size();
   int done = 0;
   for (int k = 0; k < iters; ++k) {
-    if ((rc = timed(p, ADMM_K_GEMV_N, k, st, [&](KTime kt) { return launch_gemv_n(a, p->t_hrows, nh, st, kt); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GEMV_N, k, st, [&](KTime kt) { return launch_gemv_n(a, p->t_hrows, nh, p->t_wrows, (int)G.t_wrows.size(), st, kt); }))) return rc;
     if ((rc = timed(p, ADMM_K_GRAM, k, st, [&](KTime kt) { return launch_gram(a, p->t_gram, ngr, p->t_gtr, ngt, st, kt); }))) return rc;
     if ((rc = timed(p, ADMM_K_GEMV_H, k, st, [&](KTime kt) { return launch_gemv_h(a, p->t_cols, nc, st, kt); }))) return rc;
     if ((rc = timed(p, ADMM_K_ZUPDATE, k, st, [&](KTime kt) { return launch_zupdate(a, p->t_z, nz, st, kt); }))) return rc;
@@ -700,7 +714,7 @@ int admm_solve_record(admm_plan* p, const void* g, int iters, int interval, void
       HIP_TRY(hipMemcpyAsync(ck + T.s, p->s, colv * G.Q, hipMemcpyDeviceToDevice, st));
       HIP_TRY(hipMemcpyAsync(ck + T.ghat, p->ghat, rowv * G.P, hipMemcpyDeviceToDevice, st));
     }
-    if ((rc = timed(p, ADMM_K_GEMV_N, k, st, [&](KTime kt) { return launch_gemv_n(a, p->t_hrows, nh, st, kt); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GEMV_N, k, st, [&](KTime kt) { return launch_gemv_n(a, p->t_hrows, nh, p->t_wrows, (int)G.t_wrows.size(), st, kt); }))) return rc;
     if ((rc = timed(p, ADMM_K_GRAM, k, st, [&](KTime kt) { return launch_gram(a, p->t_gram, ngr, p->t_gtr, ngt, st, kt); }))) return rc;
     if ((rc = timed(p, ADMM_K_GEMV_H, k, st, [&](KTime kt) { return launch_gemv_h(a, p->t_cols, nc, st, kt); }))) return rc;
     if ((rc = timed(p, ADMM_K_ZUPDATE, k, st, [&](KTime kt) { return launch_zupdate(a, p->t_z, nz, st, kt); }))) return rc;
@@ -796,7 +810,7 @@ int admm_backward(admm_plan* p, const void* g, const void* grad_v, const void* t
     for (int k = k0; k < k1; ++k) {
       a.y = yrec + ystride * (k - k0);
       a.arec = arec + astride * (k - k0);
-      HIP_TRY(launch_gemv_n(a, p->t_hrows, nh, st));
+      HIP_TRY(launch_gemv_n(a, p->t_hrows, nh, p->t_wrows, (int)G.t_wrows.size(), st));
       HIP_TRY(launch_gram(a, p->t_gram, ngr, p->t_gtr, ngt, st));
       HIP_TRY(launch_gemv_h(a, p->t_cols, nc, st));
       HIP_TRY(launch_zupdate(a, p->t_z, nz, st));

@@ -20,6 +20,7 @@ struct Layout {
   size_t H = 0, H_im = 0, H_scale = 0, Ginv = 0, Ginv16 = 0, F64a = 0, F64b = 0;
   size_t c = 0, s = 0, v = 0, part = 0, gp = 0, ghat = 0, r = 0, y = 0;
   size_t blocks = 0, cols = 0, t_rows = 0, t_cols = 0, t_z = 0, t_gram = 0, t_kadj = 0, t_hrows = 0, t_gtr = 0;
+  size_t t_wrows = 0;
   size_t gpart = 0;
   size_t ctl = 0, redpart = 0, row_block = 0, kkt_e = 0, kkt_v = 0, kkt_part = 0, kkt_max = 0;
   size_t vb = 0, sb = 0, ub = 0, ghb = 0, gpb = 0, yb = 0, rb = 0, gbar = 0, kpart = 0, rpart = 0;
@@ -38,6 +39,7 @@ struct Geometry {
   int KH = 1;                      // row chunks of the adjoint product
   int max_mt = 0;                  // largest tile-padded block edge
   std::vector<int4> t_rows, t_cols, t_z, t_gram, t_kadj, t_hrows, t_gtr;
+  std::vector<int4> t_wrows;       // whole-row tiles of the complex64 row product (empty: not used)
   Layout lay;
 };
 
@@ -82,6 +84,11 @@ constexpr int kRowWaves = ADMM_ROW_WAVES;
 #endif
 constexpr int kXStage = 2048;    // float4 of c staged per workgroup (32 KB: column blocks up to 4096)
 constexpr int kEpiSections = 7;  // other sections whose estimates the row epilogue prefetches (P <= 8)
+#ifndef ADMM_WHOLE_ROWS
+#define ADMM_WHOLE_ROWS 1       // complex64 row product with whole rows per workgroup where blocks allow
+#endif
+constexpr int kWholeRows = 2;    // rows per workgroup of the whole-row product
+constexpr int kWholeLoads = 8;   // lane loads per thread and row: column blocks up to 8 * 256 * 2 = 4096
 
 static_assert(kRowWaves >= 1 && kRowWaves <= kBlockThreads / kWave, "row waves");
 
@@ -155,7 +162,8 @@ hipError_t launch_adj_gflush(const AdjArgs& a, const BlockDesc* blocks, int nblo
 struct KTime {
   hipEvent_t start = nullptr, stop = nullptr;
 };
-hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});
+hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, const int4* wtiles, int nwtiles,
+                          hipStream_t st, KTime kt = {});
 hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gtr, int n_gtr,
                        hipStream_t st, KTime kt = {});
 hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});

