@@ -301,6 +301,7 @@ class Batch:
         self.torch = torch
         self.device = H0.device
         self.m0, self.n = H0.shape
+        self.tile_rows = int(tile_rows)
         self.S = len(tiles)
         self.P, self.rho = P, float(rho)
         self._tiles = np.ascontiguousarray(np.concatenate([np.asarray(t, np.int32) for t in tiles]))
@@ -367,7 +368,9 @@ class Batch:
     def tuning(self):
         arr = (ctypes.c_double * 6)()
         _check(lib().admm_batch_tuning(self._h, arr), "admm_batch_tuning")
-        return {"forward_ms": list(arr[:3]), "forward_rows_kchunks": [(128, 1), (128, 2), (64, 2)],
+        # the library's candidate shapes (include/admm.h), rows capped at tile_rows
+        rows = [min(r, self.tile_rows) for r in (128, 128, 64)]
+        return {"forward_ms": list(arr[:3]), "forward_rows_kchunks": list(zip(rows, (1, 2, 2))),
                 "adjoint_ms": list(arr[3:]), "adjoint_cols_per_wg": [64, 128, 256]}
 
 
