@@ -157,22 +157,27 @@ def test_tape_errors(torch_gpu):
 
 
 def test_eight_scene_batch_gradients(torch_gpu):
-    """Eight scenes of a small CRA geometry (seeds 2000..2007), K = 100 with a
-    checkpoint every 10 iterations: every scene's adjoint matches the oracle
-    autograd gradient."""
+    """Eight scenes of a small CRA geometry (seeds 2000..2007, consensus,
+    sectioning and combined splits, uneven where Q or P is 3), K = 100 with a
+    checkpoint every 10 iterations: every scene's v^K and adjoint match the
+    oracle and its autograd gradient."""
     torch = torch_gpu
-    worst = 0.0
-    for seed in range(2000, 2008):
-        p = W.cra_problem(n_tx=4, n_rx=4, n_f=8, nx=10, ny=10, nz=5, Q=2, P=2, rho=10.0, patch=(4, 2),
+    splits = [(2, 2), (2, 4), (4, 2), (1, 2), (2, 1), (4, 4), (2, 3), (3, 2)]
+    worst_v = worst = 0.0
+    for seed, (Q, P) in zip(range(2000, 2008), splits):
+        p = W.cra_problem(n_tx=4, n_rx=4, n_f=8, nx=10, ny=10, nz=5, Q=Q, P=P, rho=10.0, patch=(4, 2),
                           iters=100, seed=seed)
         plan = _plan(torch, p)
         g = to_device(torch, p.g)
         v, tape = plan.solve_record(g, 100, 10)
-        _, gv = _loss_and_grad_v(v.cpu().numpy().astype(np.complex128), p.u_true)
+        v = v.cpu().numpy()
+        _, gv = _loss_and_grad_v(v.astype(np.complex128), p.u_true)
         gg, dl, dr = plan.backward(g, to_device(torch, gv.astype(np.complex64)), tape)
-        tg, tl, tr, _ = OT.gradients(p.H.astype(np.complex128), p.g.astype(np.complex128), p.Q, p.P, p.rho, p.lam,
-                                     100, gv)
+        tg, tl, tr, tv = OT.gradients(p.H.astype(np.complex128), p.g.astype(np.complex128), p.Q, p.P, p.rho, p.lam,
+                                      100, gv, p.row_off, p.col_off)
         e = max(rel(gg.cpu().numpy(), tg), abs(dl - tl) / abs(tl), abs(dr - tr) / abs(tr))
-        print(f"scene {seed}: max rel err {e:.2e}")
-        worst = max(worst, e)
+        print(f"scene {seed} (Q={Q}, P={P}): v {rel(v, tv):.2e}, max gradient rel err {e:.2e}")
+        worst_v, worst = max(worst_v, rel(v, tv)), max(worst, e)
+        plan.close()
+    assert worst_v <= 1e-5
     assert worst <= TOL_AUTOGRAD
