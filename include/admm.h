@@ -208,6 +208,17 @@ int admm_kkt(admm_plan* plan, const void* g, const void* v, double* out,
              void* stream);
 
 /*
+ * admm_hty_absmax -- ||H^H g||_inf over the stored H, accumulated in FP64:
+ * the scale of the regularisation weight (the lasso minimiser is 0 for
+ * lambda >= ||H^H g||_inf; workloads set lambda as a fraction of it).  Uses
+ * the same pass as admm_kkt with v = 0 (for bf16 / fp8 storage, over the
+ * dequantised H).
+ *   g    device complex64[m].   out  host double.
+ *   Synchronises `stream`.  Errors: EINVAL, EHIP.
+ */
+int admm_hty_absmax(admm_plan* plan, const void* g, double* out, void* stream);
+
+/*
  * admm_get_stored_h -- copy the plan's stored H back out as dense m x n
  * row-major planes (for checking the quantiser):
  *   C64:  re_out receives complex64[m*n]; im_out and scale_out are ignored.

@@ -45,6 +45,7 @@ SIGNATURES = [
     ("admm_get_state", _int, [_vp, _vp, _vp, _vp, _c.POINTER(_int), _vp]),
     ("admm_set_state", _int, [_vp, _vp, _vp, _vp, _int, _vp]),
     ("admm_kkt", _int, [_vp, _vp, _vp, _c.POINTER(_dbl), _vp]),
+    ("admm_hty_absmax", _int, [_vp, _vp, _c.POINTER(_dbl), _vp]),
     ("admm_get_stored_h", _int, [_vp, _vp, _vp, _vp, _vp]),
     ("admm_profile", _int, [_vp, _int]),
     ("admm_profile_read", _int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
@@ -230,6 +231,14 @@ class Plan:
         out = ctypes.c_double(0.0)
         _check(lib().admm_kkt(self._h, _ptr(g), _ptr(v), ctypes.byref(out),
                               _stream(self.torch, self.device)), "admm_kkt")
+        return float(out.value)
+
+    def hty_absmax(self, g) -> float:
+        """max_n |(H^H g)_n| over the stored H, in FP64 (the lasso minimiser is
+        zero for lambda at or above it)."""
+        out = ctypes.c_double(0.0)
+        _check(lib().admm_hty_absmax(self._h, _ptr(g), ctypes.byref(out), _stream(self.torch, self.device)),
+               "admm_hty_absmax")
         return float(out.value)
 
     def get_state(self):

@@ -885,6 +885,24 @@ int admm_kkt(admm_plan* p, const void* g, const void* v, double* out, void* stre
   return ADMM_OK;
 }
 
+int admm_hty_absmax(admm_plan* p, const void* g, double* out, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(ADMM_EINVAL, "plan is NULL");
+  if (!g || !out) return fail(ADMM_EINVAL, "g and out must not be NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Geometry& G = p->geo;
+  // the KKT pass with v = 0 and lambda = 0: its per-column value is |(H^H g)_n|
+  HIP_TRY(launch_fill(p->kkt_v, (size_t)G.n_pad * sizeof(float2), st));
+  HIP_TRY(launch_kkt_all(p->d_blocks, p->d_cols, p->row_block, p->t_kadj, (int)G.t_kadj.size(), p->t_z,
+                         (int)G.t_z.size(), G.m, G.n_pad, G.Q, G.P, G.KH, p->hs, static_cast<const float2*>(g),
+                         p->kkt_v, 0.0, p->kkt_e, p->kkt_part, p->kkt_max, p->ctl, st));
+  Control hc;
+  HIP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *out = hc.kkt;
+  return ADMM_OK;
+}
+
 int admm_get_stored_h(admm_plan* p, void* re_out, void* im_out, float* scale_out, void* stream) {
   g_last_error.clear();
   if (!p) return fail(ADMM_EINVAL, "plan is NULL");

@@ -72,6 +72,7 @@ def test_null_plan_is_rejected():
     assert L.admm_set_lambda(None, 1.0) == -1
     assert L.admm_solve(None, None, 1, 0.0, 1, None, None, None, 0, None) == -1
     assert L.admm_profile(None, 1) == -1
+    assert L.admm_hty_absmax(None, None, None, None) == -1
     L.admm_destroy(None)
 
 

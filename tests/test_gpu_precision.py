@@ -65,6 +65,22 @@ def test_c64_store_is_exact(torch_gpu):
     np.testing.assert_array_equal(plan.stored_h().cpu().numpy(), p.H)
 
 
+@pytest.mark.parametrize("storage", ["c64", "bf16", "fp8"])
+@pytest.mark.parametrize("name", ["combined_uneven", "cra_small"])
+def test_hty_absmax_matches_oracle(torch_gpu, storage, name):
+    """max|H^H g| over the stored (dequantised) H, FP64 on both sides; for
+    complex64 storage it is the workload's lambda divided by its ratio."""
+    p, _ = _problems()[name]
+    plan = _plan(torch_gpu, p, storage)
+    got = plan.hty_absmax(to_device(torch_gpu, p.g))
+    Hd = p.H if storage == "c64" else QZ.dequantise(p.H, storage)
+    want = O.lambda_max(Hd, p.g)
+    assert abs(got - want) <= 1e-10 * want, (got, want)
+    if storage == "c64":
+        ratio = 0.05 if name == "combined_uneven" else 0.02
+        assert abs(ratio * got - p.lam) <= 1e-9 * p.lam, (ratio * got, p.lam)
+
+
 @pytest.mark.parametrize("storage", ["bf16", "fp8"])
 @pytest.mark.parametrize("name", ["combined_uneven", "cra_small", "consensus256x4096"])
 def test_solve_two_way_error(torch_gpu, storage, name):
