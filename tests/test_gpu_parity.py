@@ -38,11 +38,15 @@ def _case(name):
     if name == "cra_small":
         return W.cra_problem(n_tx=8, n_rx=8, n_f=12, nx=20, ny=20, nz=10, Q=4, P=4, rho=10.0,
                              patch=(7, 3), iters=100, seed=7), 100
+    if name == "many_sections":
+        # more sections than the row epilogue keeps in registers (P - 1 > 7);
+        # rho large enough for ten Jacobi sections to converge
+        return W.iid_problem(m=200, n=3000, nnz=12, Q=2, P=10, rho=40.0, seed=8), 150
     raise KeyError(name)
 
 
 CASES = ["consensus256x4096", "combined_uneven", "sectioning", "unsplit", "ragged_consensus",
-         "cra_small"]
+         "cra_small", "many_sections"]
 
 
 @pytest.mark.parametrize("name", CASES)

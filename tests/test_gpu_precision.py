@@ -34,6 +34,7 @@ def _problems():
         "cra_small": (W.cra_problem(n_tx=8, n_rx=8, n_f=12, nx=20, ny=20, nz=10, Q=4, P=4, rho=10.0,
                                     patch=(7, 3), iters=100, seed=7), 100),
         "consensus256x4096": (W.small_consensus(), 200),
+        "many_sections": (W.iid_problem(m=200, n=3000, nnz=12, Q=2, P=10, rho=40.0, seed=8), 150),
     }
 
 
@@ -82,7 +83,7 @@ def test_hty_absmax_matches_oracle(torch_gpu, storage, name):
 
 
 @pytest.mark.parametrize("storage", ["bf16", "fp8"])
-@pytest.mark.parametrize("name", ["combined_uneven", "cra_small", "consensus256x4096"])
+@pytest.mark.parametrize("name", ["combined_uneven", "cra_small", "consensus256x4096", "many_sections"])
 def test_solve_two_way_error(torch_gpu, storage, name):
     p, K = _problems()[name]
     Hd = QZ.dequantise(p.H, storage)
