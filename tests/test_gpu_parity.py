@@ -42,11 +42,15 @@ def _case(name):
         # more sections than the row epilogue keeps in registers (P - 1 > 7);
         # rho large enough for ten Jacobi sections to converge
         return W.iid_problem(m=200, n=3000, nnz=12, Q=2, P=10, rho=40.0, seed=8), 150
+    if name == "wide_blocks":
+        # 6000-column blocks: past the whole-row complex64 product (4096 columns),
+        # so the streaming row product runs
+        return W.iid_problem(m=128, n=6000, nnz=10, Q=2, P=1, rho=1.0, seed=9), 150
     raise KeyError(name)
 
 
 CASES = ["consensus256x4096", "combined_uneven", "sectioning", "unsplit", "ragged_consensus",
-         "cra_small", "many_sections"]
+         "cra_small", "many_sections", "wide_blocks"]
 
 
 @pytest.mark.parametrize("name", CASES)

@@ -35,6 +35,8 @@ def _problems():
                                     patch=(7, 3), iters=100, seed=7), 100),
         "consensus256x4096": (W.small_consensus(), 200),
         "many_sections": (W.iid_problem(m=200, n=3000, nnz=12, Q=2, P=10, rho=40.0, seed=8), 150),
+        # blocks wider than the 32 KB LDS stage of c: the unstaged row product
+        "wide_blocks": (W.iid_problem(m=128, n=6000, nnz=10, Q=2, P=1, rho=1.0, seed=9), 150),
     }
 
 
@@ -83,7 +85,8 @@ def test_hty_absmax_matches_oracle(torch_gpu, storage, name):
 
 
 @pytest.mark.parametrize("storage", ["bf16", "fp8"])
-@pytest.mark.parametrize("name", ["combined_uneven", "cra_small", "consensus256x4096", "many_sections"])
+@pytest.mark.parametrize("name", ["combined_uneven", "cra_small", "consensus256x4096", "many_sections",
+                                  "wide_blocks"])
 def test_solve_two_way_error(torch_gpu, storage, name):
     p, K = _problems()[name]
     Hd = QZ.dequantise(p.H, storage)
