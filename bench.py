@@ -336,7 +336,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 / fp8 storage forms")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode timing")
