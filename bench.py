@@ -87,9 +87,9 @@ def load_traffic(kernel: str, workload: str):
 COPY_PROBE_KERNEL = "neg_kernel"   # torch's elementwise negation: reads and writes N bytes
 # per-iteration kernels as named in the counter output -> bench names, per storage
 TRACE_NAMES = {
-    "c64": {"k_gemv_n<FmtC64>": "k_gemv_n", "k_gemv_nw": "k_gemv_n", "k_gemv_h<FmtC64>": "k_gemv_h"},
-    "bf16": {"k_gemv_n<FmtBF16>": "k_gemv_n", "k_gemv_h<FmtBF16>": "k_gemv_h"},
-    "fp8": {"k_gemv_n<FmtFP8>": "k_gemv_n", "k_gemv_h<FmtFP8>": "k_gemv_h"},
+    "c64": {"k_gemv_n<FmtC64>": "k_gemv_n", "k_gemv_nw<FmtC64>": "k_gemv_n", "k_gemv_h<FmtC64>": "k_gemv_h"},
+    "bf16": {"k_gemv_n<FmtBF16>": "k_gemv_n", "k_gemv_nw<FmtBF16>": "k_gemv_n", "k_gemv_h<FmtBF16>": "k_gemv_h"},
+    "fp8": {"k_gemv_n<FmtFP8>": "k_gemv_n", "k_gemv_nw<FmtFP8>": "k_gemv_n", "k_gemv_h<FmtFP8>": "k_gemv_h"},
 }
 SHARED_NAMES = {"k_gram_tile": "k_gram", "k_gram_reduce": "k_gram", "k_zupdate<4>": "k_zupdate"}
 

@@ -191,7 +191,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
     for (int r = 0; r < d.mi; r += kRowsPerWG) geo.t_rows.push_back(make_int4((int)b, r, 0, 0));
     const int hrows = rows_per_wave(storage) * kRowWaves;
     for (int r = 0; r < d.mi; r += hrows) geo.t_hrows.push_back(make_int4((int)b, r, 0, 0));
-    for (int r = 0; r < d.mi; r += kWholeRows) geo.t_wrows.push_back(make_int4((int)b, r, 0, 0));
+    for (int r = 0; r < d.mi; r += whole_rows(storage)) geo.t_wrows.push_back(make_int4((int)b, r, 0, 0));
     const int nl = (d.nj + cpl - 1) / cpl;
     wg_per_chunk += (nl + kColsPerWGLoads - 1) / kColsPerWGLoads;
     const int nt = d.mt / kTile;
@@ -200,11 +200,11 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
       geo.t_gtr.push_back(make_int4((int)b, a, 0, 0));
     }
   }
-  // The whole-row product serves complex64 storage whose column blocks fit
-  // kWholeLoads lane loads per thread.
+  // The whole-row product serves column blocks of at most kWholeCols columns.
   {
-    bool whole = ADMM_WHOLE_ROWS && storage == ADMM_STORAGE_C64;
-    for (const BlockDesc& d : geo.blocks) whole = whole && (d.nj + cpl - 1) / cpl <= kWholeLoads * kBlockThreads;
+    bool whole = storage == ADMM_STORAGE_C64 ? ADMM_WHOLE_ROWS
+                 : (storage == ADMM_STORAGE_BF16 ? ADMM_WHOLE_ROWS_BF16 : ADMM_WHOLE_ROWS_FP8);
+    for (const BlockDesc& d : geo.blocks) whole = whole && d.nj <= kWholeCols;
     if (!whole) geo.t_wrows.clear();
   }
   // Row chunks of the adjoint product: about ADMM_COLS_WG_TARGET(_C64)

@@ -171,15 +171,24 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4
   }
 }
 
-// The same product for complex64 with whole rows per workgroup (column blocks
-// of at most kWholeLoads * 256 lane loads): kWholeRows rows of one block, every
-// thread issuing all of its lane loads of those rows at once, so a workgroup
-// reads whole contiguous rows and ends (measured faster than streaming eight
-// interleaved rows per wave: 7.1 vs 6.5 TB/s).  Row sums close over each wave
-// and then over the four waves in a fixed order.  tiles[x] = {block, first
-// row, -, -}.
+// The same product with whole rows per workgroup (column blocks of at most
+// K * 256 lane loads): N rows of one block, every thread issuing all of its
+// lane loads of those rows (and the matching pieces of c) at once, so a
+// workgroup reads whole contiguous rows and ends (measured faster than
+// streaming interleaved rows per wave).  Row sums close over each wave and
+// then over the four waves in a fixed order.  tiles[x] = {block, first row,
+// -, -}.  (N, K) = WholeRows<F>: about eight 16-byte loads per thread.  Used
+// for complex64 and bf16; fp8, whose rows are only 8 KB, streams faster
+// through k_gemv_n.
+template <class F>
+struct WholeRows {
+  static constexpr int N = F::CPL == 2 ? 2 : (F::CPL == 8 ? ADMM_WHOLE_N_BF16 : ADMM_WHOLE_N_FP8);
+  static constexpr int K = kWholeCols / (kBlockThreads * F::CPL);
+};
+template <class F>
 __global__ __launch_bounds__(kBlockThreads) void k_gemv_nw(IterArgs a, const int4* __restrict__ tiles) {
-  constexpr int N = kWholeRows, K = kWholeLoads, NW = kBlockThreads / kWave;
+  constexpr int N = WholeRows<F>::N, K = WholeRows<F>::K, NW = kBlockThreads / kWave;
+  constexpr int CPL = F::CPL, X4 = CPL / 2;
   __shared__ float red[NW][2 * N];
   const int4 t = tiles[blockIdx.x];   // before any store: scalar loads
   const BlockDesc d = a.blocks[t.x];
@@ -187,42 +196,44 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_nw(IterArgs a, const int
     __shared__ double zred[NW][kRedCount];
     zfinal(a, zred);
   }
-  const FmtC64 f = MakeFmt<FmtC64>::make(a.hs);
+  const F f = MakeFmt<F>::make(a.hs);
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   const int nvalid = min(N, d.mi - t.y);
-  const int nl = (d.nj + FmtC64::CPL - 1) / FmtC64::CPL;
+  const int nl = (d.nj + CPL - 1) / CPL;
   const float4* x = reinterpret_cast<const float4*>(a.c + (int64_t)d.i * a.n_pad + d.cpad0);
-  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-  // All loads first and without branches: indices past the row are clamped
-  // to its last lane load and those values replaced by zero afterwards.
-  float4 h[N][K], xv[K];
+  // All loads first and without branches: lane loads past the row are
+  // clamped to its last one and their contributions dropped afterwards.
+  typename F::Raw h[N][K];
+  float4 xv[K][X4];
 #pragma unroll
   for (int r = 0; r < N; ++r) {
-    const FmtC64::Row rp = f.row(d.h_off + (int64_t)(t.y + min(r, nvalid - 1)) * d.ld);
+    const typename F::Row rp = f.row(d.h_off + (int64_t)(t.y + min(r, nvalid - 1)) * d.ld);
 #pragma unroll
-    for (int k = 0; k < K; ++k) h[r][k] = FmtC64::load(rp, (uint32_t)min(tid + kBlockThreads * k, nl - 1)).a;
+    for (int k = 0; k < K; ++k) h[r][k] = F::load(rp, (uint32_t)min(tid + kBlockThreads * k, nl - 1));
   }
 #pragma unroll
-  for (int k = 0; k < K; ++k) xv[k] = x[min(tid + kBlockThreads * k, nl - 1)];   // lane load c is x[c] (complex64)
+  for (int k = 0; k < K; ++k) {
+    const int c = min(tid + kBlockThreads * k, nl - 1);   // c in the lane-permuted layout (cperm)
+#pragma unroll
+    for (int q = 0; q < X4; ++q) xv[k][q] = x[(((c >> 6) * X4 + q) << 6) + (c & 63)];
+  }
   // epilogue operands: wave 0, lane l for row min(l, nvalid - 1) (a uniform branch)
   RowEpi epi;
   if (wave == 0) row_epi_load(a, d, f, t.y + min(lane, nvalid - 1), epi);
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    if (tid + kBlockThreads * k >= nl) {
-      xv[k] = zero;
-#pragma unroll
-      for (int r = 0; r < N; ++r) h[r][k] = zero;
-    }
-  }
 #pragma unroll
   for (int r = 0; r < N; ++r) {
     float sr = 0.f, si = 0.f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      cmac(sr, si, h[r][k].x, h[r][k].y, xv[k].x, xv[k].y);
-      cmac(sr, si, h[r][k].z, h[r][k].w, xv[k].z, xv[k].w);
+      if (tid + kBlockThreads * k >= nl) continue;
+      float hr[CPL], hi[CPL];
+      F::decode(h[r][k], hr, hi);
+#pragma unroll
+      for (int q = 0; q < X4; ++q) {
+        cmac(sr, si, hr[2 * q], hi[2 * q], xv[k][q].x, xv[k][q].y);
+        cmac(sr, si, hr[2 * q + 1], hi[2 * q + 1], xv[k][q].z, xv[k][q].w);
+      }
     }
     sr = wave_sum(sr);
     si = wave_sum(si);
@@ -484,8 +495,12 @@ __global__ void k_fill_zero(uint4* p, size_t n16) {
 
 hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, const int4* wtiles, int nwtiles,
                           hipStream_t st, KTime kt) {
-  if (a.hs.storage == 0 && nwtiles > 0) {
-    LAUNCH_TIMED(k_gemv_nw, dim3(nwtiles), dim3(kBlockThreads), st, kt, a, wtiles);
+  if (nwtiles > 0) {
+    switch (a.hs.storage) {
+      case 0: LAUNCH_TIMED(k_gemv_nw<FmtC64>, dim3(nwtiles), dim3(kBlockThreads), st, kt, a, wtiles); break;
+      case 1: LAUNCH_TIMED(k_gemv_nw<FmtBF16>, dim3(nwtiles), dim3(kBlockThreads), st, kt, a, wtiles); break;
+      default: LAUNCH_TIMED(k_gemv_nw<FmtFP8>, dim3(nwtiles), dim3(kBlockThreads), st, kt, a, wtiles); break;
+    }
     return hipGetLastError();
   }
   switch (a.hs.storage) {

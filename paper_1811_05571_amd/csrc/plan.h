@@ -87,8 +87,21 @@ constexpr int kEpiSections = 7;  // other sections whose estimates the row epilo
 #ifndef ADMM_WHOLE_ROWS
 #define ADMM_WHOLE_ROWS 1       // complex64 row product with whole rows per workgroup where blocks allow
 #endif
-constexpr int kWholeRows = 2;    // rows per workgroup of the whole-row product
-constexpr int kWholeLoads = 8;   // lane loads per thread and row: column blocks up to 8 * 256 * 2 = 4096
+#ifndef ADMM_WHOLE_ROWS_BF16
+#define ADMM_WHOLE_ROWS_BF16 1  // the same for bf16
+#endif
+#ifndef ADMM_WHOLE_ROWS_FP8
+#define ADMM_WHOLE_ROWS_FP8 0   // the same for fp8 (measured slower: 74 vs 71 us at 6144 x 32000)
+#endif
+#ifndef ADMM_WHOLE_N_BF16
+#define ADMM_WHOLE_N_BF16 4     // rows per workgroup of the whole-row product, bf16
+#endif
+#ifndef ADMM_WHOLE_N_FP8
+#define ADMM_WHOLE_N_FP8 8      // the same for fp8
+#endif
+constexpr int kWholeCols = 4096; // widest column block of the whole-row product
+// rows per workgroup of the whole-row product (its tiles follow it)
+inline int whole_rows(int storage) { return storage == 0 ? 2 : (storage == 1 ? ADMM_WHOLE_N_BF16 : ADMM_WHOLE_N_FP8); }
 
 static_assert(kRowWaves >= 1 && kRowWaves <= kBlockThreads / kWave, "row waves");
 
