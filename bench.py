@@ -56,7 +56,9 @@ def algorithmic_bytes(geo: dict, P: int, Q: int, KH: int, storage: str = "c64", 
     (4 B for the bfloat16 copy)."""
     m, n = geo["m"], geo["n"]
     ginv = geo["ginv_packed"]     # complex elements of the packed lower-tile inverses
-    gparts = geo["gram_parts"]    # 64-vectors of Gram-apply pieces (written once, read once)
+    # 64-vectors of Gram-apply pieces (written once, read once): 4 x 4 tile
+    # patches for the complex64 inverse, single tiles for the bfloat16 copy
+    gparts = geo["gram_parts_bf16"] if inverse == "bf16" else geo["gram_parts"]
     c = 8
     h = m * n * ELEM_BYTES[storage] + (4 * m * P if storage == "fp8" else 0)
     vec_rows = P * m * c          # one row-space vector (all column blocks)
@@ -392,7 +394,8 @@ def main(argv=None):
     tiles = [(s_ + 63) // 64 for s_ in sizes]
     geo = {"m": prob.m, "n": prob.n,
            "ginv_packed": int(sum(T * (T + 1) // 2 * 4096 for T in tiles) * prob.P),
-           "gram_parts": int(sum(T * T for T in tiles) * prob.P)}
+           "gram_parts": int(sum(T * ((T + 3) // 4 + 1) for T in tiles) * prob.P),
+           "gram_parts_bf16": int(sum(T * T for T in tiles) * prob.P)}
     workload = prob.name
 
     def measure(storage: str, steps: int, warmup: int, inverse: str = "c64"):

@@ -67,6 +67,13 @@ extern "C" {
  * admm_backward's d/drho then differentiates through the unrounded inverse
  * (the rounding counts as the identity). */
 #define ADMM_INVERSE_BF16  16
+/* Flag, OR-ed in the same way: apply the complex64 inverses in patches of
+ * 4 x 4 tiles (one workgroup per patch keeps its row and column sums across
+ * the patch's tiles, so the partial stores shrink 4x) in every case.  Without
+ * it the library uses patches when a split has at least 4096 of them (fewer
+ * leave the GPU under-occupied) and single tiles otherwise.  No effect with
+ * ADMM_INVERSE_BF16, whose copy is applied per tile. */
+#define ADMM_GRAM_PATCHES  32
 
 typedef struct admm_plan admm_plan;
 
@@ -86,7 +93,7 @@ const char* admm_last_error(void);
  *   row_off   host int64[Q+1] block boundaries, strictly increasing from 0
  *             to m, or NULL for the equal split (the first m mod Q blocks
  *             get one extra row).  col_off likewise with P and n.
- *   storage   ADMM_STORAGE_*, optionally | ADMM_INVERSE_BF16.
+ *   storage   ADMM_STORAGE_*, optionally | ADMM_INVERSE_BF16 | ADMM_GRAM_PATCHES.
  *   out_bytes host, receives the size.
  * Errors: EINVAL for any bad size or split; EUNSUPPORTED when some block is
  * not wide (m_i >= n_j), since only the inversion-lemma x-update is built.
@@ -288,7 +295,8 @@ void admm_destroy(admm_plan* plan);
  * ====================================================================== */
 typedef struct admm_batch admm_batch;
 
-/* flags: 0 or ADMM_INVERSE_BF16 (the same value in both calls). */
+/* flags: 0, ADMM_INVERSE_BF16 and/or ADMM_GRAM_PATCHES (the same value in both
+ * calls). */
 int admm_batch_workspace_bytes(int64_t m0, int64_t n, int tile_rows, int S,
                                const int32_t* tiles, const int64_t* tiles_off,
                                const int32_t* cuts, const int64_t* cuts_off,

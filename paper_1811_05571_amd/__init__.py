@@ -24,6 +24,7 @@ STATUS = {
 }
 STORAGE = {"c64": 0, "bf16": 1, "fp8": 2}
 INVERSE = {"c64": 0, "bf16": 16}   # ADMM_INVERSE_BF16: apply a bfloat16 copy of the block inverses
+GRAM_PATCHES = 32                   # ADMM_GRAM_PATCHES: always apply the inverses in 4 x 4 tile patches
 K_GEMV_N, K_GRAM, K_GEMV_H, K_ZUPDATE = 0, 1, 2, 3
 KERNEL_NAMES = {K_GEMV_N: "k_gemv_n", K_GRAM: "k_gram", K_GEMV_H: "k_gemv_h", K_ZUPDATE: "k_zupdate"}
 
@@ -104,11 +105,12 @@ def _offsets(o):
 
 
 def workspace_bytes(m: int, n: int, Q: int, P: int, row_off=None, col_off=None,
-                    storage: str = "c64", inverse: str = "c64") -> int:
+                    storage: str = "c64", inverse: str = "c64", gram_patches: bool = False) -> int:
     ro, rp = _offsets(row_off)
     co, cp = _offsets(col_off)
     out = ctypes.c_size_t(0)
-    _check(lib().admm_workspace_bytes(m, n, Q, rp, P, cp, STORAGE[storage] | INVERSE[inverse],
+    _check(lib().admm_workspace_bytes(m, n, Q, rp, P, cp,
+                                      STORAGE[storage] | INVERSE[inverse] | (GRAM_PATCHES if gram_patches else 0),
                                       ctypes.byref(out)), "admm_workspace_bytes")
     return int(out.value)
 
@@ -129,7 +131,7 @@ class Plan:
     """
 
     def __init__(self, H, Q: int, P: int, rho: float, lam: float, row_off=None, col_off=None,
-                 storage: str = "c64", inverse: str = "c64"):
+                 storage: str = "c64", inverse: str = "c64", gram_patches: bool = False):
         import torch
         if not (H.is_cuda and H.dtype == torch.complex64 and H.dim() == 2 and H.is_contiguous()):
             raise ValueError("H must be a contiguous complex64 CUDA tensor (m, n)")
@@ -140,7 +142,8 @@ class Plan:
         self.rho, self.lam = float(rho), float(lam)
         self.storage, self.inverse = storage, inverse
         self.row_off, self.col_off = row_off, col_off
-        nbytes = workspace_bytes(self.m, self.n, Q, P, row_off, col_off, storage, inverse)
+        flags = STORAGE[storage] | INVERSE[inverse] | (GRAM_PATCHES if gram_patches else 0)
+        nbytes = workspace_bytes(self.m, self.n, Q, P, row_off, col_off, storage, inverse, gram_patches)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         _, rp = _offsets(row_off)
         _, cp = _offsets(col_off)
@@ -151,7 +154,7 @@ class Plan:
         cp = None if co_keep is None else co_keep.ctypes.data_as(ctypes.c_void_p)
         h = ctypes.c_void_p(0)
         _check(lib().admm_setup(ctypes.byref(h), _ptr(H), self.m, self.n, Q, rp, P, cp, self.rho,
-                                self.lam, STORAGE[storage] | INVERSE[inverse], _ptr(self.workspace), nbytes,
+                                self.lam, flags, _ptr(self.workspace), nbytes,
                                 _stream(torch, self.device)), "admm_setup")
         self._h = h
 
@@ -305,7 +308,7 @@ class Batch:
     KERNELS = {0: "k_bgemm_n", 1: "k_gram", 2: "k_bgemm_h", 3: "k_bzupdate"}
 
     def __init__(self, H0, tile_rows: int, tiles, cuts, phases, P: int, rho: float, lambdas, col_off=None,
-                 inverse: str = "c64"):
+                 inverse: str = "c64", gram_patches: bool = False):
         import torch
         self.torch = torch
         self.device = H0.device
@@ -327,7 +330,7 @@ class Batch:
         args = (self.m0, self.n, int(tile_rows), self.S, self._tiles.ctypes.data_as(v),
                 self._toff.ctypes.data_as(v), self._cuts.ctypes.data_as(v), self._coff.ctypes.data_as(v))
         out = ctypes.c_size_t(0)
-        flags = INVERSE[inverse]
+        flags = INVERSE[inverse] | (GRAM_PATCHES if gram_patches else 0)
         _check(lib().admm_batch_workspace_bytes(*args, P, cp, flags, ctypes.byref(out)), "admm_batch_workspace_bytes")
         self.workspace = torch.empty(int(out.value), dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p(0)

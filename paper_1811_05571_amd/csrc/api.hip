@@ -74,12 +74,14 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
     return ADMM_EINVAL;
   }
   const bool inv16 = (storage & ADMM_INVERSE_BF16) != 0;
-  storage &= ~ADMM_INVERSE_BF16;
+  const bool force_patches = (storage & ADMM_GRAM_PATCHES) != 0;
+  storage &= ~(ADMM_INVERSE_BF16 | ADMM_GRAM_PATCHES);
   if (storage != ADMM_STORAGE_C64 && storage != ADMM_STORAGE_BF16 && storage != ADMM_STORAGE_FP8) {
     err = "unknown storage";
     return ADMM_EINVAL;
   }
   geo.inv16 = inv16;
+  geo.force_patches = force_patches;
   auto offsets = [&](int64_t total, int parts, const int64_t* given, std::vector<int64_t>& o) -> bool {
     o.assign(parts + 1, 0);
     if (given) {
@@ -165,7 +167,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
       hoff += (int64_t)d.mi * d.ld;
       const int64_t T = d.mt / kTile;
       gioff += T * (T + 1) / 2 * kTile * kTile;
-      gpo += T * T;
+      gpo += gram_part_vecs(T);
       foff += (int64_t)d.mt * d.mt;
       max_mi = std::max(max_mi, d.mi);
       geo.max_mt = std::max(geo.max_mt, d.mt);
@@ -184,6 +186,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   geo.t_hrows.clear();
   geo.t_gtr.clear();
   geo.t_wrows.clear();
+  geo.t_gpatch.clear();
   const int cpl = cols_per_load(storage);
   int wg_per_chunk = 0;
   for (size_t b = 0; b < geo.blocks.size(); ++b) {
@@ -199,7 +202,14 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
       for (int c = 0; c <= a; ++c) geo.t_gram.push_back(make_int4((int)b, a, c, 0));
       geo.t_gtr.push_back(make_int4((int)b, a, 0, 0));
     }
+    if (ADMM_GRAM_PATCH)
+      for (int a = 0; a < (nt + 3) / 4; ++a)
+        for (int c = 0; c <= a; ++c) geo.t_gpatch.push_back(make_int4((int)b, a, c, 0));
   }
+  // 4 x 4 tile patches of the Gram apply: complex64 inverses only, when asked
+  // or when there are enough of them to fill the GPU.
+  if (!ADMM_GRAM_PATCH || geo.inv16 || !(geo.force_patches || geo.t_gpatch.size() >= kGramPatchMin))
+    geo.t_gpatch.clear();
   // The whole-row product serves column blocks of at most kWholeCols columns.
   {
     bool whole = storage == ADMM_STORAGE_C64 ? ADMM_WHOLE_ROWS
@@ -267,6 +277,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   L.t_kadj = take(16 * geo.t_kadj.size());
   L.t_hrows = take(16 * geo.t_hrows.size());
   L.t_wrows = take(16 * std::max<size_t>(geo.t_wrows.size(), 1));
+  L.t_gpatch = take(16 * std::max<size_t>(geo.t_gpatch.size(), 1));
   L.t_gtr = take(16 * geo.t_gtr.size());
   L.gpart = take((size_t)gpo * kTile * 8);
   L.ctl = take(sizeof(Control));
@@ -306,6 +317,7 @@ struct admm_plan {
   ColDesc* d_cols = nullptr;
   int4 *t_rows = nullptr, *t_cols = nullptr, *t_z = nullptr, *t_gram = nullptr, *t_kadj = nullptr, *t_hrows = nullptr;
   int4* t_wrows = nullptr;
+  int4* t_gpatch = nullptr;
   int4* t_gtr = nullptr;
   float2* gpart = nullptr;
   HStore hs{};
@@ -542,6 +554,7 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   p->t_kadj = at<int4>(p, L.t_kadj);
   p->t_hrows = at<int4>(p, L.t_hrows);
   p->t_wrows = at<int4>(p, L.t_wrows);
+  p->t_gpatch = at<int4>(p, L.t_gpatch);
   p->t_gtr = at<int4>(p, L.t_gtr);
   p->gpart = at<float2>(p, L.gpart);
   p->hs.storage = storage;
@@ -600,6 +613,8 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   SETUP_TRY(hipMemcpyAsync(p->t_hrows, G.t_hrows.data(), 16 * G.t_hrows.size(), hipMemcpyHostToDevice, st));
   if (!G.t_wrows.empty())
     SETUP_TRY(hipMemcpyAsync(p->t_wrows, G.t_wrows.data(), 16 * G.t_wrows.size(), hipMemcpyHostToDevice, st));
+  if (!G.t_gpatch.empty())
+    SETUP_TRY(hipMemcpyAsync(p->t_gpatch, G.t_gpatch.data(), 16 * G.t_gpatch.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->t_gtr, G.t_gtr.data(), 16 * G.t_gtr.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->row_block, p->h_row_block.data(), 8 * (size_t)m, hipMemcpyHostToDevice, st));
   int max_mi = 0;
@@ -651,7 +666,7 @@ int admm_solve(admm_plan* p, const void* g, int iters, double tol, int check_eve
   int done = 0;
   for (int k = 0; k < iters; ++k) {
     if ((rc = timed(p, ADMM_K_GEMV_N, k, st, [&](KTime kt) { return launch_gemv_n(a, p->t_hrows, nh, p->t_wrows, (int)G.t_wrows.size(), st, kt); }))) return rc;
-    if ((rc = timed(p, ADMM_K_GRAM, k, st, [&](KTime kt) { return launch_gram(a, p->t_gram, ngr, p->t_gtr, ngt, st, kt); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GRAM, k, st, [&](KTime kt) { return launch_gram(a, p->t_gram, ngr, p->t_gpatch, (int)G.t_gpatch.size(), p->t_gtr, ngt, st, kt); }))) return rc;
     if ((rc = timed(p, ADMM_K_GEMV_H, k, st, [&](KTime kt) { return launch_gemv_h(a, p->t_cols, nc, st, kt); }))) return rc;
     if ((rc = timed(p, ADMM_K_ZUPDATE, k, st, [&](KTime kt) { return launch_zupdate(a, p->t_z, nz, st, kt); }))) return rc;
     ++done;
@@ -715,7 +730,7 @@ int admm_solve_record(admm_plan* p, const void* g, int iters, int interval, void
       HIP_TRY(hipMemcpyAsync(ck + T.ghat, p->ghat, rowv * G.P, hipMemcpyDeviceToDevice, st));
     }
     if ((rc = timed(p, ADMM_K_GEMV_N, k, st, [&](KTime kt) { return launch_gemv_n(a, p->t_hrows, nh, p->t_wrows, (int)G.t_wrows.size(), st, kt); }))) return rc;
-    if ((rc = timed(p, ADMM_K_GRAM, k, st, [&](KTime kt) { return launch_gram(a, p->t_gram, ngr, p->t_gtr, ngt, st, kt); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GRAM, k, st, [&](KTime kt) { return launch_gram(a, p->t_gram, ngr, p->t_gpatch, (int)G.t_gpatch.size(), p->t_gtr, ngt, st, kt); }))) return rc;
     if ((rc = timed(p, ADMM_K_GEMV_H, k, st, [&](KTime kt) { return launch_gemv_h(a, p->t_cols, nc, st, kt); }))) return rc;
     if ((rc = timed(p, ADMM_K_ZUPDATE, k, st, [&](KTime kt) { return launch_zupdate(a, p->t_z, nz, st, kt); }))) return rc;
   }
@@ -811,7 +826,7 @@ int admm_backward(admm_plan* p, const void* g, const void* grad_v, const void* t
       a.y = yrec + ystride * (k - k0);
       a.arec = arec + astride * (k - k0);
       HIP_TRY(launch_gemv_n(a, p->t_hrows, nh, p->t_wrows, (int)G.t_wrows.size(), st));
-      HIP_TRY(launch_gram(a, p->t_gram, ngr, p->t_gtr, ngt, st));
+      HIP_TRY(launch_gram(a, p->t_gram, ngr, p->t_gpatch, (int)G.t_gpatch.size(), p->t_gtr, ngt, st));
       HIP_TRY(launch_gemv_h(a, p->t_cols, nc, st));
       HIP_TRY(launch_zupdate(a, p->t_z, nz, st));
     }

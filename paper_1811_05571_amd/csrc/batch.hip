@@ -64,7 +64,7 @@ struct BatchGeo {
   std::vector<SceneTile> stab;        // grouped by tile f
   std::vector<int32_t> st_off;        // F+1
   std::vector<int32_t> cuts_flat, tiles_flat;
-  std::vector<int4> t_gram, t_gtr, t_z;
+  std::vector<int4> t_gram, t_gtr, t_z, t_gpatch;
   int64_t gpart_vecs = 0;
   std::vector<GemmItem> items_n[3], items_h[3];
   int64_t m_pad = 0, n_pad = 0, ldt = 0, mt0 = 0;
@@ -78,6 +78,7 @@ struct BatchGeo {
   int NG = 0;                      // forward GEMM groups (f, scene-tile group, j)
   std::vector<int2> st_gc;         // per scene-tile entry: first group, column in group
   size_t o_pn = 0, o_stgc = 0;
+  size_t o_tgpatch = 0;
   size_t o_tgram = 0, o_tgtr = 0, o_gpart = 0, o_tz = 0, o_items_n[3] = {0, 0, 0}, o_items_h[3] = {0, 0, 0}, o_ctl = 0;
   size_t o_gblocks = 0, o_ggram = 0, o_gtile0 = 0, g_max_blocks = 0, g_max_gram = 0, o_t0gram = 0;
   std::vector<int4> t0_gram;          // lower tiles of the pseudo blocks (G0)
@@ -87,11 +88,12 @@ struct BatchGeo {
 int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const int32_t* tiles,
                 const int64_t* tiles_off, const int32_t* cuts, const int64_t* cuts_off, int P,
                 const int64_t* col_off, int flags, std::string& err) {
-  if (flags & ~ADMM_INVERSE_BF16) {
+  if (flags & ~(ADMM_INVERSE_BF16 | ADMM_GRAM_PATCHES)) {
     err = "unknown flags";
     return ADMM_EINVAL;
   }
   G.inv16 = (flags & ADMM_INVERSE_BF16) != 0;
+  const bool force_patches = (flags & ADMM_GRAM_PATCHES) != 0;
   char buf[256];
   if (m0 < 1 || n < 1 || (tile_rows != 64 && tile_rows != 128 && tile_rows != 256) || m0 % tile_rows || S < 1 || P < 1 || P > n ||
       !tiles || !tiles_off || !cuts || !cuts_off) {
@@ -234,7 +236,7 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
         d.f_off = 0;  // set per setup group
         const int64_t T = d.mt / kTile;
         gioff += T * (T + 1) / 2 * kTile * kTile;
-        gpo += T * T;
+        gpo += gram_part_vecs(T);
         G.blocks.push_back(d);
       }
       for (int sl = ca; sl < cb; ++sl) {
@@ -266,13 +268,19 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
   // work tables
   G.t_gram.clear();
   G.t_gtr.clear();
+  G.t_gpatch.clear();
   for (size_t b = 0; b < G.blocks.size(); ++b) {
     const int T = G.blocks[b].mt / kTile;
     for (int a2 = 0; a2 < T; ++a2) {
       for (int c2 = 0; c2 <= a2; ++c2) G.t_gram.push_back(make_int4((int)b, a2, c2, 0));
       G.t_gtr.push_back(make_int4((int)b, a2, 0, 0));
     }
+    if (ADMM_GRAM_PATCH)
+      for (int a2 = 0; a2 < (T + 3) / 4; ++a2)
+        for (int c2 = 0; c2 <= a2; ++c2) G.t_gpatch.push_back(make_int4((int)b, a2, c2, 0));
   }
+  // patches for the complex64 inverses when asked or when they fill the GPU
+  if (G.inv16 || !(force_patches || G.t_gpatch.size() >= kGramPatchMin)) G.t_gpatch.clear();
   G.gpart_vecs = gpo;
   G.t_z.clear();
   for (int s = 0; s < S; ++s)
@@ -396,6 +404,7 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
   G.o_cuts = take(4 * G.cuts_flat.size());
   G.o_tiles = take(4 * G.tiles_flat.size());
   G.o_tgram = take(16 * G.t_gram.size());
+  G.o_tgpatch = take(16 * std::max<size_t>(G.t_gpatch.size(), 1));
   G.o_tgtr = take(16 * G.t_gtr.size());
   G.o_gpart = take((size_t)G.gpart_vecs * kTile * 8);
   G.o_tz = take(16 * G.t_z.size());
@@ -527,8 +536,8 @@ hipError_t launch_iteration(admm_batch* b, const float2* g, hipStream_t st, bool
        })) != hipSuccess)
     return e;
   if ((e = run(1, [&] {
-         return launch_gram(ga, at<int4>(b, G.o_tgram), (int)G.t_gram.size(), at<int4>(b, G.o_tgtr),
-                            (int)G.t_gtr.size(), st);
+         return launch_gram(ga, at<int4>(b, G.o_tgram), (int)G.t_gram.size(), at<int4>(b, G.o_tgpatch),
+                            (int)G.t_gpatch.size(), at<int4>(b, G.o_tgtr), (int)G.t_gtr.size(), st);
        })) != hipSuccess)
     return e;
   if ((e = run(2, [&] {
@@ -672,6 +681,7 @@ int admm_batch_setup(admm_batch** out, const void* H0, int64_t m0, int64_t n, in
   STRY(up(G.o_cuts, G.cuts_flat.data(), 4 * G.cuts_flat.size()));
   STRY(up(G.o_tiles, G.tiles_flat.data(), 4 * G.tiles_flat.size()));
   STRY(up(G.o_tgram, G.t_gram.data(), 16 * G.t_gram.size()));
+  if (!G.t_gpatch.empty()) STRY(up(G.o_tgpatch, G.t_gpatch.data(), 16 * G.t_gpatch.size()));
   STRY(up(G.o_tgtr, G.t_gtr.data(), 16 * G.t_gtr.size()));
   STRY(up(G.o_tz, G.t_z.data(), 16 * G.t_z.size()));
   STRY(up(G.o_stgc, G.st_gc.data(), 8 * G.st_gc.size()));

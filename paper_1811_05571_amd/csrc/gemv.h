@@ -264,49 +264,26 @@ __device__ __forceinline__ void gram_tile_load(const float2* __restrict__ G, con
   o.xa1 = *reinterpret_cast<const float4*>(xa + r0 + 2);
 }
 
-__device__ __forceinline__ void gram_tile_compute(const GramOps& o, bool diag, float2* __restrict__ out_ab,
-                                                  float2* __restrict__ out_ba, float2 (&red)[4][64]) {
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, b = l & 15;
-  const int r0 = 16 * w + 4 * (l >> 4);
+// Row sums of one tile in the thread's 4 x 4 sub-block, added to (pr, pi):
+// rows r0 + rr of G x_b over this thread's four columns.
+__device__ __forceinline__ void gram_rows_acc(const GramOps& o, float (&pr)[4], float (&pi)[4]) {
   const float4 (&h)[4][2] = o.h;
   const float4 xb0 = o.xb0, xb1 = o.xb1;
-  float pr[4], pi[4];
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
-    pr[rr] = 0.f;
-    pi[rr] = 0.f;
     cmac(pr[rr], pi[rr], h[rr][0].x, h[rr][0].y, xb0.x, xb0.y);
     cmac(pr[rr], pi[rr], h[rr][0].z, h[rr][0].w, xb0.z, xb0.w);
     cmac(pr[rr], pi[rr], h[rr][1].x, h[rr][1].y, xb1.x, xb1.y);
     cmac(pr[rr], pi[rr], h[rr][1].z, h[rr][1].w, xb1.z, xb1.w);
   }
-  {
-    // xor 8: keep rows {2s, 2s+1}, s = bit 3 of the lane
-    const bool s = (l & 8) != 0;
-    float k0r = s ? pr[2] : pr[0], k0i = s ? pi[2] : pi[0];
-    float k1r = s ? pr[3] : pr[1], k1i = s ? pi[3] : pi[1];
-    const float o0r = s ? pr[0] : pr[2], o0i = s ? pi[0] : pi[2];
-    const float o1r = s ? pr[1] : pr[3], o1i = s ? pi[1] : pi[3];
-    k0r += __shfl_xor(o0r, 8, kWave);
-    k0i += __shfl_xor(o0i, 8, kWave);
-    k1r += __shfl_xor(o1r, 8, kWave);
-    k1i += __shfl_xor(o1i, 8, kWave);
-    // xor 4: keep row 2s + t, t = bit 2
-    const bool t = (l & 4) != 0;
-    float rr_ = t ? k1r : k0r, ri_ = t ? k1i : k0i;
-    rr_ += __shfl_xor(t ? k0r : k1r, 4, kWave);
-    ri_ += __shfl_xor(t ? k0i : k1i, 4, kWave);
-    rr_ += __shfl_xor(rr_, 2, kWave);
-    ri_ += __shfl_xor(ri_, 2, kWave);
-    rr_ += __shfl_xor(rr_, 1, kWave);
-    ri_ += __shfl_xor(ri_, 1, kWave);
-    if ((l & 3) == 0) out_ab[r0 + 2 * (int)s + (int)t] = make_float2(rr_, ri_);
-  }
-  if (diag) return;
+}
+// Column sums of one tile in the thread's sub-block, added to (cr, ci):
+// column slot k (k: 0 -> 2b, 1 -> 2b+1, 2 -> 32+2b, 3 -> 33+2b) of G^H x_a
+// over this thread's four rows.
+__device__ __forceinline__ void gram_cols_acc(const GramOps& o, float (&cr)[4], float (&ci)[4]) {
+  const float4 (&h)[4][2] = o.h;
   const float4 xa0 = o.xa0, xa1 = o.xa1;
   const float xr[4] = {xa0.x, xa0.z, xa1.x, xa1.z}, xi[4] = {xa0.y, xa0.w, xa1.y, xa1.w};
-  // column slot k: 0 -> 2b, 1 -> 2b+1, 2 -> 32+2b, 3 -> 33+2b
-  float cr[4] = {0.f, 0.f, 0.f, 0.f}, ci[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
     cmacc(cr[0], ci[0], h[rr][0].x, h[rr][0].y, xr[rr], xi[rr]);
@@ -314,6 +291,41 @@ __device__ __forceinline__ void gram_tile_compute(const GramOps& o, bool diag, f
     cmacc(cr[2], ci[2], h[rr][1].x, h[rr][1].y, xr[rr], xi[rr]);
     cmacc(cr[3], ci[3], h[rr][1].z, h[rr][1].w, xr[rr], xi[rr]);
   }
+}
+// Closes the row sums over the 16 lanes of each row group (reduce-scatter
+// xor 8, 4, all-reduce xor 2, 1); lanes with (l & 3) == 0 write out[row].
+__device__ __forceinline__ void gram_rows_store(const float (&pr)[4], const float (&pi)[4],
+                                                float2* __restrict__ out) {
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int r0 = 16 * w + 4 * (l >> 4);
+  // xor 8: keep rows {2s, 2s+1}, s = bit 3 of the lane
+  const bool s = (l & 8) != 0;
+  float k0r = s ? pr[2] : pr[0], k0i = s ? pi[2] : pi[0];
+  float k1r = s ? pr[3] : pr[1], k1i = s ? pi[3] : pi[1];
+  const float o0r = s ? pr[0] : pr[2], o0i = s ? pi[0] : pi[2];
+  const float o1r = s ? pr[1] : pr[3], o1i = s ? pi[1] : pi[3];
+  k0r += __shfl_xor(o0r, 8, kWave);
+  k0i += __shfl_xor(o0i, 8, kWave);
+  k1r += __shfl_xor(o1r, 8, kWave);
+  k1i += __shfl_xor(o1i, 8, kWave);
+  // xor 4: keep row 2s + t, t = bit 2
+  const bool t = (l & 4) != 0;
+  float rr_ = t ? k1r : k0r, ri_ = t ? k1i : k0i;
+  rr_ += __shfl_xor(t ? k0r : k1r, 4, kWave);
+  ri_ += __shfl_xor(t ? k0i : k1i, 4, kWave);
+  rr_ += __shfl_xor(rr_, 2, kWave);
+  ri_ += __shfl_xor(ri_, 2, kWave);
+  rr_ += __shfl_xor(rr_, 1, kWave);
+  ri_ += __shfl_xor(ri_, 1, kWave);
+  if ((l & 3) == 0) out[r0 + 2 * (int)s + (int)t] = make_float2(rr_, ri_);
+}
+// Closes the column sums over the wave (reduce-scatter xor 32, 16) and over
+// the 4 waves through `red` in a fixed order; threads < 64 write out[col].
+// Every thread of the workgroup must call it (it holds a barrier); `red` is
+// read after that barrier, so a second call needs a barrier before it.
+__device__ __forceinline__ void gram_cols_store(const float (&cr)[4], const float (&ci)[4],
+                                                float2* __restrict__ out, float2 (&red)[4][64]) {
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, b = l & 15;
   // xor 32: keep slots {2u, 2u+1}, u = bit 5
   const bool u = (l & 32) != 0;
   float k0r = u ? cr[2] : cr[0], k0i = u ? ci[2] : ci[0];
@@ -333,8 +345,19 @@ __device__ __forceinline__ void gram_tile_compute(const GramOps& o, bool diag, f
   __syncthreads();
   if (tid < 64) {
     const float2 q0 = red[0][tid], q1 = red[1][tid], q2 = red[2][tid], q3 = red[3][tid];
-    out_ba[tid] = make_float2(((q0.x + q1.x) + q2.x) + q3.x, ((q0.y + q1.y) + q2.y) + q3.y);
+    out[tid] = make_float2(((q0.x + q1.x) + q2.x) + q3.x, ((q0.y + q1.y) + q2.y) + q3.y);
   }
+}
+
+__device__ __forceinline__ void gram_tile_compute(const GramOps& o, bool diag, float2* __restrict__ out_ab,
+                                                  float2* __restrict__ out_ba, float2 (&red)[4][64]) {
+  float pr[4] = {0.f, 0.f, 0.f, 0.f}, pi[4] = {0.f, 0.f, 0.f, 0.f};
+  gram_rows_acc(o, pr, pi);
+  gram_rows_store(pr, pi, out_ab);
+  if (diag) return;
+  float cr[4] = {0.f, 0.f, 0.f, 0.f}, ci[4] = {0.f, 0.f, 0.f, 0.f};
+  gram_cols_acc(o, cr, ci);
+  gram_cols_store(cr, ci, out_ba, red);
 }
 
 // The same products with the tile stored as bfloat16 pairs (32-bit word per

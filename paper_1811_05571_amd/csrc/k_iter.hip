@@ -292,17 +292,75 @@ __global__ __launch_bounds__(kBlockThreads) void k_gram_tile(IterArgs a, const i
                   part + (int64_t)(t.z * T + t.y) * kTile, tt);
 }
 
+// y_ij = G^{-1} r over patches of up to 4 x 4 lower tiles (complex64
+// inverse).  The workgroup takes patch (R, C) = (t.y, t.z), C <= R, of block
+// t.x: tile rows 4R .. 4R+3 and columns 4C .. 4C+3 that exist (only c <= a on
+// the diagonal patch, whose diagonal tiles apply whole).  Each thread keeps
+// its sub-block's sums (the layout of gram_tile_compute) of G x_c per patch
+// row and of G^H x_a per patch column across the patch's tiles, one tile in
+// flight at a time; the workgroup then stores one 64-vector per patch row
+// (slot C of that row tile) and per patch column (slot R + 1): NS =
+// ceil(T/4) + 1 slots per row tile instead of T single-tile pieces, which
+// cuts the partial stores 4x and with them most of their cost.
+__global__ __launch_bounds__(kBlockThreads) void k_gram_patch(IterArgs a, const int4* __restrict__ tiles) {
+  __shared__ float2 red[4][64];
+  const int4 t = tiles[blockIdx.x];
+  const BlockDesc d = a.blocks[t.x];
+  const int T = d.mt / kTile, NS = (T + 3) / 4 + 1;
+  const int R = t.y, C = t.z, a0 = 4 * R, c0 = 4 * C;
+  const int na = min(4, T - a0), nc = min(4, T - c0);
+  const bool dg = R == C;
+  const float2* x = a.r + (int64_t)d.j * a.m_pad + d.rpad0;
+  const float2* G0 = a.Ginv + d.gi_off;
+  float pr[4][4], pi[4][4], cr[4][4], ci[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pr[q][k] = pi[q][k] = cr[q][k] = ci[q][k] = 0.f;
+#pragma unroll
+  for (int aa = 0; aa < 4; ++aa) {
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      if (aa >= na || cc >= nc || (dg && cc > aa)) continue;   // uniform over the workgroup
+      const int ta = a0 + aa, tc = c0 + cc;
+      GramOps o;
+      gram_tile_load(G0 + (int64_t)(ta * (ta + 1) / 2 + tc) * (kTile * kTile), x + ta * kTile, x + tc * kTile, o);
+      gram_rows_acc(o, pr[aa], pi[aa]);
+      if (!(dg && cc == aa)) gram_cols_acc(o, cr[cc], ci[cc]);
+      // the sums are materialised per tile, so the compiler cannot defer the
+      // products (and keep every tile's entries in registers) to the stores
+#pragma unroll
+      for (int k = 0; k < 4; ++k) asm volatile("" : "+v"(pr[aa][k]), "+v"(pi[aa][k]), "+v"(cr[cc][k]), "+v"(ci[cc][k]));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  float2* part = a.gpart + (int64_t)d.gpo * kTile;
+#pragma unroll
+  for (int aa = 0; aa < 4; ++aa)
+    if (aa < na) gram_rows_store(pr[aa], pi[aa], part + ((int64_t)(a0 + aa) * NS + C) * kTile);
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc) {
+    if (cc >= nc) continue;
+    if (cc > 0) __syncthreads();   // red is read by the previous store
+    gram_cols_store(cr[cc], ci[cc], part + ((int64_t)(c0 + cc) * NS + R + 1) * kTile, red);
+  }
+}
+
+// PATCH: pieces laid out by k_gram_patch (NS = ceil(T/4) + 1 slots per row
+// tile), else by k_gram_tile / k_gram_tile_bf16 (T slots).
 static_assert(kBlockThreads / kTile == 4, "k_gram_reduce adds four interleaved sums per row");
+template <bool PATCH>
 __global__ __launch_bounds__(kBlockThreads) void k_gram_reduce(IterArgs a, const int4* __restrict__ tiles) {
   __shared__ float2 red[kBlockThreads / kTile][kTile];
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = a.blocks[t.x];
   const int T = d.mt / kTile;
+  const int NS = PATCH ? (T + 3) / 4 + 1 : T;
   const int l = threadIdx.x & (kTile - 1), q = threadIdx.x / kTile;
-  const float2* part = a.gpart + ((int64_t)d.gpo + (int64_t)t.y * T) * kTile + l;
+  const float2* part = a.gpart + ((int64_t)d.gpo + (int64_t)t.y * NS) * kTile + l;
   float sr = 0.f, si = 0.f;
 #pragma unroll 4
-  for (int k = q; k < T; k += kBlockThreads / kTile) {
+  for (int k = q; k < NS; k += kBlockThreads / kTile) {
     const float2 v = part[(int64_t)k * kTile];
     sr += v.x;
     si += v.y;
@@ -520,15 +578,21 @@ hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, const
   }
   return hipGetLastError();
 }
-hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gtr, int n_gtr,
-                       hipStream_t st, KTime kt) {
+hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gpatch, int n_gpatch,
+                       const int4* t_gtr, int n_gtr, hipStream_t st, KTime kt) {
+  const bool patch = !a.Ginv16 && n_gpatch > 0;
   if (a.Ginv16)
     LAUNCH_TIMED(k_gram_tile_bf16, dim3(n_gram), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gram);
+  else if (patch)
+    LAUNCH_TIMED(k_gram_patch, dim3(n_gpatch), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gpatch);
   else
     LAUNCH_TIMED(k_gram_tile, dim3(n_gram), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gram);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  LAUNCH_TIMED(k_gram_reduce, dim3(n_gtr), dim3(kBlockThreads), st, (KTime{nullptr, kt.stop}), a, t_gtr);
+  if (patch)
+    LAUNCH_TIMED(k_gram_reduce<true>, dim3(n_gtr), dim3(kBlockThreads), st, (KTime{nullptr, kt.stop}), a, t_gtr);
+  else
+    LAUNCH_TIMED(k_gram_reduce<false>, dim3(n_gtr), dim3(kBlockThreads), st, (KTime{nullptr, kt.stop}), a, t_gtr);
   return hipGetLastError();
 }
 hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt) {

@@ -2,6 +2,8 @@
 // exports to the C ABI layer.
 #pragma once
 
+#include <algorithm>
+
 #include <string>
 #include <vector>
 
@@ -20,7 +22,7 @@ struct Layout {
   size_t H = 0, H_im = 0, H_scale = 0, Ginv = 0, Ginv16 = 0, F64a = 0, F64b = 0;
   size_t c = 0, s = 0, v = 0, part = 0, gp = 0, ghat = 0, r = 0, y = 0;
   size_t blocks = 0, cols = 0, t_rows = 0, t_cols = 0, t_z = 0, t_gram = 0, t_kadj = 0, t_hrows = 0, t_gtr = 0;
-  size_t t_wrows = 0;
+  size_t t_wrows = 0, t_gpatch = 0;
   size_t gpart = 0;
   size_t ctl = 0, redpart = 0, row_block = 0, kkt_e = 0, kkt_v = 0, kkt_part = 0, kkt_max = 0;
   size_t vb = 0, sb = 0, ub = 0, ghb = 0, gpb = 0, yb = 0, rb = 0, gbar = 0, kpart = 0, rpart = 0;
@@ -32,6 +34,7 @@ struct Geometry {
   int64_t m = 0, n = 0;
   int Q = 0, P = 0, storage = 0;   // storage: H format (ADMM_STORAGE_*)
   bool inv16 = false;              // a bfloat16-pair copy of the inverses is kept and applied
+  bool force_patches = false;      // ADMM_GRAM_PATCHES
   std::vector<int64_t> ro, co;
   std::vector<BlockDesc> blocks;   // Q*P, index b = i*P + j
   std::vector<ColDesc> cols;       // P
@@ -39,7 +42,8 @@ struct Geometry {
   int KH = 1;                      // row chunks of the adjoint product
   int max_mt = 0;                  // largest tile-padded block edge
   std::vector<int4> t_rows, t_cols, t_z, t_gram, t_kadj, t_hrows, t_gtr;
-  std::vector<int4> t_wrows;       // whole-row tiles of the complex64 row product (empty: not used)
+  std::vector<int4> t_wrows;       // whole-row tiles of the row product (empty: not used)
+  std::vector<int4> t_gpatch;      // 4 x 4 tile patches of the Gram apply (empty: single tiles)
   Layout lay;
 };
 
@@ -99,6 +103,13 @@ constexpr int kEpiSections = 7;  // other sections whose estimates the row epilo
 #ifndef ADMM_WHOLE_N_FP8
 #define ADMM_WHOLE_N_FP8 8      // the same for fp8
 #endif
+#ifndef ADMM_GRAM_PATCH
+#define ADMM_GRAM_PATCH 1       // complex64 inverses applied in 4 x 4 tile patches
+#endif
+// Gram-apply pieces per block (64-vectors): single tiles use T per row tile,
+// 4 x 4 patches ceil(T/4) + 1; the region holds either layout.
+inline int64_t gram_part_vecs(int64_t T) { return std::max(T * T, T * ((T + 3) / 4 + 1)); }
+constexpr size_t kGramPatchMin = 4096;   // patches used by default from this many on
 constexpr int kWholeCols = 4096; // widest column block of the whole-row product
 // rows per workgroup of the whole-row product (its tiles follow it)
 inline int whole_rows(int storage) { return storage == 0 ? 2 : (storage == 1 ? ADMM_WHOLE_N_BF16 : ADMM_WHOLE_N_FP8); }
@@ -177,8 +188,8 @@ struct KTime {
 };
 hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, const int4* wtiles, int nwtiles,
                           hipStream_t st, KTime kt = {});
-hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gtr, int n_gtr,
-                       hipStream_t st, KTime kt = {});
+hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gpatch, int n_gpatch,
+                       const int4* t_gtr, int n_gtr, hipStream_t st, KTime kt = {});
 hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});
 hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});
 // Final addition of a pending z-update's partial sums (one workgroup).

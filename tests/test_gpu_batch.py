@@ -25,18 +25,19 @@ def _batch():
 COL_OFF = [0, 700, 1500, 2300, 3072]
 
 
-def _solve(torch, b, K, graph=True, inverse="c64"):
+def _solve(torch, b, K, graph=True, inverse="c64", gram_patches=False):
     import paper_1811_05571_amd as A
     bb = A.Batch(to_device(torch, b.H0), b.tile_rows, b.tiles, b.cuts, b.phases, b.P, b.rho, b.lam, COL_OFF,
-                 inverse=inverse)
+                 inverse=inverse, gram_patches=gram_patches)
     g = to_device(torch, np.concatenate(b.g))
     return bb, g, bb.solve(g, K, graph=graph)
 
 
-def test_batch_matches_oracle_per_scene(torch_gpu):
+@pytest.mark.parametrize("gram_patches", [False, True])
+def test_batch_matches_oracle_per_scene(torch_gpu, gram_patches):
     b = _batch()
     K = 60
-    bb, g, v = _solve(torch_gpu, b, K)
+    bb, g, v = _solve(torch_gpu, b, K, gram_patches=gram_patches)
     v = v.cpu().numpy()
     H0q = QZ.dequantise(b.H0, "bf16")
     worst = 0.0

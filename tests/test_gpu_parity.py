@@ -77,6 +77,27 @@ def test_image_matches_oracle(torch_gpu, name):
     assert rel(ghg.cpu().numpy(), st_ref.ghat) <= 10 * TOL
 
 
+@pytest.mark.parametrize("name", ["combined_uneven", "ragged_consensus", "cra_small", "gram_patches"])
+def test_gram_patches_match_oracle(torch_gpu, name):
+    """The Gram apply in 4 x 4 tile patches (forced; by default only splits
+    with thousands of patches use them): single-tile-row blocks, partial edge
+    patches and several full patches per block."""
+    import paper_1811_05571_amd as A
+    if name == "gram_patches":
+        # 600-row blocks: 10 tile rows, patches (R, C) for R, C < 3 with a partial last row
+        p, K = W.iid_problem(m=1200, n=6000, nnz=20, Q=2, P=2, rho=10.0, seed=12), 80
+    else:
+        p, K = _case(name)
+    v_ref, _, st_ref = _oracle(p, K)
+    plan = A.Plan(to_device(torch_gpu, p.H), p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off, gram_patches=True)
+    v = plan.solve(to_device(torch_gpu, p.g), K).cpu().numpy()
+    err = rel(v, v_ref)
+    print(f"case {name} with patches: rel err {err:.3e}", flush=True)
+    assert err <= TOL
+    k, _, _, ghg = plan.get_state()
+    assert rel(ghg.cpu().numpy(), st_ref.ghat) <= 10 * TOL
+
+
 def test_deterministic(torch_gpu):
     p, K = _case("combined_uneven")
     plan, g, v1 = gpu_solve(torch_gpu, p, 60)
