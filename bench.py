@@ -49,16 +49,17 @@ def kernel_source_hash() -> str:
 ELEM_BYTES = {"c64": 8, "bf16": 4, "fp8": 2}   # stored bytes per complex element of H
 
 
-def algorithmic_bytes(geo: dict, P: int, Q: int, KH: int, storage: str = "c64", inverse: str = "c64") -> dict:
+def algorithmic_bytes(geo: dict, P: int, Q: int, KH: int, storage: str = "c64", inverse: str = "c64",
+                      patches: bool = False) -> dict:
     """Bytes each kernel must move per launch, from the kernel's definition
     (not from counters).  Vectors are complex64 (8 B); H elements take
     ELEM_BYTES[storage] (+ 4 B per row of fp8 scales); inverse entries 8 B
     (4 B for the bfloat16 copy)."""
     m, n = geo["m"], geo["n"]
     ginv = geo["ginv_packed"]     # complex elements of the packed lower-tile inverses
-    # 64-vectors of Gram-apply pieces (written once, read once): 4 x 4 tile
-    # patches for the complex64 inverse, single tiles for the bfloat16 copy
-    gparts = geo["gram_parts_bf16"] if inverse == "bf16" else geo["gram_parts"]
+    # 64-vectors of Gram-apply pieces (written once, read once): one per tile
+    # and row or column, or, with 4 x 4 tile patches, one per patch and row or column
+    gparts = geo["gram_parts_patch"] if patches else geo["gram_parts"]
     c = 8
     h = m * n * ELEM_BYTES[storage] + (4 * m * P if storage == "fp8" else 0)
     vec_rows = P * m * c          # one row-space vector (all column blocks)
@@ -93,7 +94,8 @@ TRACE_NAMES = {
     "bf16": {"k_gemv_n<FmtBF16>": "k_gemv_n", "k_gemv_nw<FmtBF16>": "k_gemv_n", "k_gemv_h<FmtBF16>": "k_gemv_h"},
     "fp8": {"k_gemv_n<FmtFP8>": "k_gemv_n", "k_gemv_nw<FmtFP8>": "k_gemv_n", "k_gemv_h<FmtFP8>": "k_gemv_h"},
 }
-SHARED_NAMES = {"k_gram_tile": "k_gram", "k_gram_reduce": "k_gram", "k_zupdate<4>": "k_zupdate"}
+SHARED_NAMES = {"k_gram_tile": "k_gram", "k_gram_patch": "k_gram", "k_gram_reduce<false>": "k_gram",
+                "k_gram_reduce<true>": "k_gram", "k_zupdate<4>": "k_zupdate"}
 
 
 def _short_kernel(name: str) -> str:
@@ -394,8 +396,8 @@ def main(argv=None):
     tiles = [(s_ + 63) // 64 for s_ in sizes]
     geo = {"m": prob.m, "n": prob.n,
            "ginv_packed": int(sum(T * (T + 1) // 2 * 4096 for T in tiles) * prob.P),
-           "gram_parts": int(sum(T * ((T + 3) // 4 + 1) for T in tiles) * prob.P),
-           "gram_parts_bf16": int(sum(T * T for T in tiles) * prob.P)}
+           "gram_parts": int(sum(T * T for T in tiles) * prob.P),
+           "gram_parts_patch": int(sum(T * ((T + 3) // 4 + 1) for T in tiles) * prob.P)}
     workload = prob.name
 
     def measure(storage: str, steps: int, warmup: int, inverse: str = "c64"):
@@ -418,7 +420,7 @@ def main(argv=None):
             plan.solve(g, steps)
         prof = {A.KERNEL_NAMES[k]: plan.profile_read(k) for k in A.KERNEL_NAMES}
         plan.profile(False)
-        algo = algorithmic_bytes(geo, prob.P, prob.Q, info["chunks"], storage, inverse)
+        algo = algorithmic_bytes(geo, prob.P, prob.Q, info["chunks"], storage, inverse, info["gram_patches"] > 0)
         kern = {}
         for name, (ms, cnt) in prof.items():
             avg_ms = ms / max(cnt, 1)

@@ -259,7 +259,9 @@ int admm_profile_read(admm_plan* plan, int kernel, double* total_ms,
 
 /* Static description of the plan: fills host int64 info[16] with
  * m, n, Q, P, storage, chunks of the adjoint product, workspace bytes,
- * bytes of stored H, bytes of stored inverses, iterations done, 0... */
+ * bytes of stored H, bytes of stored inverses, iterations done, padded row
+ * and column space lengths, 4 x 4 tile patches of the Gram apply (0: one
+ * tile per workgroup), 0... */
 int admm_plan_info(const admm_plan* plan, int64_t* info16);
 
 /* Release the plan (host memory only; the workspace stays the caller's). */
@@ -319,7 +321,8 @@ int admm_batch_profile_read(admm_batch* batch, int kernel, double* total_ms,
 /* info16: m0, n, S, P, row blocks, scene tiles, workspace bytes, bytes of
  * the complex64 packed inverses, chosen forward k-chunks per column block, chosen adjoint columns per
  * workgroup, their work items, packed rows, chosen forward rows per
- * workgroup, 0... */
+ * workgroup, 4 x 4 tile patches of the Gram apply (0: one tile per
+ * workgroup), 0 */
 int admm_batch_info(const admm_batch* batch, int64_t* info16);
 /* Autotuner timings (ms): the three forward GEMM shapes [0..2] (rows per
  * workgroup, k-chunks per column block: (128, 1), (128, 2), (64, 2), rows

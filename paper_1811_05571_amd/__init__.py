@@ -294,7 +294,7 @@ class Plan:
         arr = (ctypes.c_int64 * 16)()
         _check(lib().admm_plan_info(self._h, arr), "admm_plan_info")
         keys = ["m", "n", "Q", "P", "storage", "chunks", "workspace_bytes", "h_bytes", "ginv_bytes",
-                "iters_done", "m_pad", "n_pad"]
+                "iters_done", "m_pad", "n_pad", "gram_patches"]
         return {k: int(arr[i]) for i, k in enumerate(keys)}
 
 
@@ -374,7 +374,7 @@ class Batch:
         arr = (ctypes.c_int64 * 16)()
         _check(lib().admm_batch_info(self._h, arr), "admm_batch_info")
         keys = ["m0", "n", "S", "P", "row_blocks", "scene_tiles", "workspace_bytes", "ginv_bytes", "fwd_kchunks",
-                "adj_cols_per_wg", "items_n", "items_h", "rows", "fwd_rows_per_wg"]
+                "adj_cols_per_wg", "items_n", "items_h", "rows", "fwd_rows_per_wg", "gram_patches"]
         return {k: int(arr[i]) for i, k in enumerate(keys)}
 
     def tuning(self):

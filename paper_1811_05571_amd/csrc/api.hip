@@ -972,7 +972,7 @@ int admm_plan_info(const admm_plan* p, int64_t* info) {
   if (!p || !info) return fail(ADMM_EINVAL, "plan and info must not be NULL");
   const Geometry& G = p->geo;
   int64_t v[16] = {G.m, G.n, G.Q, G.P, G.storage, G.KH, (int64_t)G.lay.total, (int64_t)G.lay.h_bytes,
-                   (int64_t)G.lay.ginv_bytes, p->k_done, G.m_pad, G.n_pad, 0, 0, 0, 0};
+                   (int64_t)G.lay.ginv_bytes, p->k_done, G.m_pad, G.n_pad, (int64_t)G.t_gpatch.size(), 0, 0, 0};
   std::memcpy(info, v, sizeof v);
   return ADMM_OK;
 }

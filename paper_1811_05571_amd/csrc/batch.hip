@@ -833,7 +833,7 @@ int admm_batch_info(const admm_batch* b, int64_t* info) {
   const BatchGeo& G = b->geo;
   int64_t v[16] = {G.m0, G.n, G.S, G.P, G.R, G.NST, (int64_t)G.total, G.ginv_elems * 8,
                    kSplitVariants[b->var_n], 64 * kAdjMS[b->var_h], (int64_t)G.items_n[b->var_n].size(),
-                   (int64_t)G.items_h[b->var_h].size(), G.rows_total, 64 * fwd_ms(b->var_n, G.tile_rows), 0, 0};
+                   (int64_t)G.items_h[b->var_h].size(), G.rows_total, 64 * fwd_ms(b->var_n, G.tile_rows), (int64_t)G.t_gpatch.size(), 0};
   std::memcpy(info, v, sizeof v);
   return ADMM_OK;
 }

@@ -38,6 +38,7 @@ def test_batch_matches_oracle_per_scene(torch_gpu, gram_patches):
     b = _batch()
     K = 60
     bb, g, v = _solve(torch_gpu, b, K, gram_patches=gram_patches)
+    assert (bb.info()["gram_patches"] > 0) == gram_patches   # the small batch is below the size threshold
     v = v.cpu().numpy()
     H0q = QZ.dequantise(b.H0, "bf16")
     worst = 0.0

@@ -90,6 +90,7 @@ def test_gram_patches_match_oracle(torch_gpu, name):
         p, K = _case(name)
     v_ref, _, st_ref = _oracle(p, K)
     plan = A.Plan(to_device(torch_gpu, p.H), p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off, gram_patches=True)
+    assert plan.info()["gram_patches"] > 0
     v = plan.solve(to_device(torch_gpu, p.g), K).cpu().numpy()
     err = rel(v, v_ref)
     print(f"case {name} with patches: rel err {err:.3e}", flush=True)
