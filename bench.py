@@ -219,6 +219,74 @@ def cpu_baseline(prob, n_iter: int):
 MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16
 
 
+def block_geometry(m: int, n: int, Q: int, P: int) -> dict:
+    """Sizes the algorithmic byte counts need for equal splits (the first m % Q
+    row blocks one row longer)."""
+    sizes = [m // Q + (1 if i < m % Q else 0) for i in range(Q)]
+    tiles = [(s_ + 63) // 64 for s_ in sizes]
+    return {"m": m, "n": n,
+            "ginv_packed": int(sum(T * (T + 1) // 2 * 4096 for T in tiles) * P),
+            "gram_parts": int(sum(T * T for T in tiles) * P),
+            "gram_parts_patch": int(sum(T * ((T + 3) // 4 + 1) for T in tiles) * P)}
+
+
+# The paper's timing table (Sec. VI): per splitting, inversion time (ms), 50
+# iterations (ms) and total imaging time (s), one Titan V under MATLAB R2017b
+# at 2160 x 22500 (precision not stated).  Quoted as context only.
+PAPER_TABLE_TIMES = {(4, 1): (196.0, 616.0, 0.812), (1, 3): (381.0, 639.0, 1.020), (4, 3): (248.0, 1171.0, 1.419)}
+
+
+def bench_paper_table(args, torch, A, W, dev, reps: int = 5):
+    """The paper's timing-table workload on one MI355X: 2160 x 22500, the three
+    splittings, setup (FP64 Gram, Cholesky and inverse, the paper's inversion
+    step) and 50 iterations timed apart, complex64."""
+    p = W.paper_table_imaging(seed=args.seed)
+    H = torch.from_numpy(p.H).to(dev)
+    g = torch.from_numpy(p.g).to(dev)
+    K = W.PAPER_TABLE_ITERS
+    rows = []
+    for Q, P in W.PAPER_TABLE_SPLITS:
+        A.Plan(H, Q, P, p.rho, p.lam).close()   # first build of this split, untimed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = A.Plan(H, Q, P, p.rho, p.lam)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        plan.solve(g, K)
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            v, hist = plan.solve(g, K, history=True)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        it = float(np.median(times))
+        info = plan.info()
+        algo = algorithmic_bytes(block_geometry(p.m, p.n, Q, P), P, Q, info["chunks"], "c64", "c64",
+                                 info["gram_patches"] > 0)
+        vn = v.cpu().numpy()
+        hs = hist.cpu().numpy()
+        ps, pi, pt = PAPER_TABLE_TIMES[(Q, P)]
+        mi, nj = -(-p.m // Q), -(-p.n // P)
+        rows.append({
+            "split": f"{Q}x{P}", "block": f"{mi}x{nj}", "inverse": f"{mi}x{mi}",
+            "setup_ms": round(setup * 1e3, 2), "iters_ms": round(it * 1e3, 3),
+            "total_ms": round((setup + it) * 1e3, 2), "iters_per_s": round(K / it, 1),
+            "iteration_gbs": round(sum(algo.values()) * K / it / 1e9, 1),
+            "nmse_vs_truth": float(np.linalg.norm(vn - p.u_true) ** 2 / np.linalg.norm(p.u_true) ** 2),
+            "residuals_first_last": [[float(x) for x in hs[0]], [float(x) for x in hs[-1]]],
+            "paper_titan_v": {"inversion_ms": ps, "iters_ms": pi, "total_s": pt},
+        })
+        plan.close()
+        print(f"[bench] paper table {Q}x{P}: setup {setup * 1e3:.1f} ms, {K} iterations {it * 1e3:.2f} ms",
+              file=sys.stderr, flush=True)
+    del H, g
+    torch.cuda.empty_cache()
+    return {"workload": "cra2160x22500", "m": p.m, "n": p.n, "rho": p.rho, "lam_ratio": 0.02, "iters": K,
+            "dtype": "c64", "timing": f"setup of a second build; iterations: median of {reps} solves from zero",
+            "paper_hardware": "one Titan V, MATLAB R2017b (context, not a target)", "splits": rows}
+
+
 def bench_batch(args, torch, A, W, dev):
     """Batched multi-scene form: S scenes (seeds 1000..) sharing the 6144 x
     32000 instrument, frequency subsets of 12..24 tiles, Q in {2,4,8}, P=8,
@@ -345,6 +413,8 @@ def main(argv=None):
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 / fp8 storage forms")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched multi-scene form")
+    ap.add_argument("--no-paper-table", action="store_true", help="skip the paper's timing-table workload")
+    ap.add_argument("--paper-table-only", action="store_true", help="measure only the paper's timing-table workload")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-seq", type=int, default=8, help="scenes solved one at a time for comparison")
     ap.add_argument("--cpu-iters", type=int, default=4)
@@ -383,6 +453,9 @@ def main(argv=None):
     if args.batch_only:
         print(json.dumps({"batch": bench_batch(args, torch, A, W, dev)}), flush=True)
         return 0
+    if args.paper_table_only:
+        print(json.dumps({"paper_table": bench_paper_table(args, torch, A, W, dev)}), flush=True)
+        return 0
     t = time.perf_counter()
     prob = W.full_imaging(seed=args.seed)
     gen_s = time.perf_counter() - t
@@ -392,12 +465,7 @@ def main(argv=None):
     g = torch.from_numpy(prob.g).to(dev)
     torch.cuda.synchronize()
 
-    sizes = [prob.m // prob.Q + (1 if i < prob.m % prob.Q else 0) for i in range(prob.Q)]
-    tiles = [(s_ + 63) // 64 for s_ in sizes]
-    geo = {"m": prob.m, "n": prob.n,
-           "ginv_packed": int(sum(T * (T + 1) // 2 * 4096 for T in tiles) * prob.P),
-           "gram_parts": int(sum(T * T for T in tiles) * prob.P),
-           "gram_parts_patch": int(sum(T * ((T + 3) // 4 + 1) for T in tiles) * prob.P)}
+    geo = block_geometry(prob.m, prob.n, prob.Q, prob.P)
     workload = prob.name
 
     def measure(storage: str, steps: int, warmup: int, inverse: str = "c64"):
@@ -508,6 +576,8 @@ def main(argv=None):
     del H
     if not args.no_batch:
         out["batch"] = bench_batch(args, torch, A, W, dev)
+    if not args.no_paper_table:
+        out["paper_table"] = bench_paper_table(args, torch, A, W, dev)
 
     if not args.no_cpu:
         print(f"[bench] oracle CPU baseline: setup + {args.cpu_iters} iterations", file=sys.stderr, flush=True)

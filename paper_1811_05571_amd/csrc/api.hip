@@ -210,11 +210,12 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   // or when there are enough of them to fill the GPU.
   if (!ADMM_GRAM_PATCH || geo.inv16 || !(geo.force_patches || geo.t_gpatch.size() >= kGramPatchMin))
     geo.t_gpatch.clear();
-  // The whole-row product serves column blocks of at most kWholeCols columns.
+  // The whole-row product reads rows of up to kWholeCols columns in one
+  // chunk, longer ones chunk by chunk (ADMM_WHOLE_WIDE).
   {
     bool whole = storage == ADMM_STORAGE_C64 ? ADMM_WHOLE_ROWS
                  : (storage == ADMM_STORAGE_BF16 ? ADMM_WHOLE_ROWS_BF16 : ADMM_WHOLE_ROWS_FP8);
-    for (const BlockDesc& d : geo.blocks) whole = whole && d.nj <= kWholeCols;
+    for (const BlockDesc& d : geo.blocks) whole = whole && (d.nj <= kWholeCols || ADMM_WHOLE_WIDE);
     if (!whole) geo.t_wrows.clear();
   }
   // Row chunks of the adjoint product: about ADMM_COLS_WG_TARGET(_C64)
@@ -423,6 +424,8 @@ IterArgs iter_args(admm_plan* p, const float2* g, double* hist) {
   for (const ColDesc& cd : p->geo.cols)
     x4 = std::max<int64_t>(x4, (int64_t)(cd.nj + kWave * a.cpl - 1) / (kWave * a.cpl) * kWave * (a.cpl / 2));
   a.xstage = x4 <= kXStage ? 1 : 0;
+  a.wide = 0;
+  for (const ColDesc& cd : p->geo.cols) a.wide |= cd.nj > kWholeCols ? 1 : 0;
   return a;
 }
 

@@ -185,7 +185,9 @@ struct WholeRows {
   static constexpr int N = F::CPL == 2 ? 2 : (F::CPL == 8 ? ADMM_WHOLE_N_BF16 : ADMM_WHOLE_N_FP8);
   static constexpr int K = kWholeCols / (kBlockThreads * F::CPL);
 };
-template <class F>
+// WIDE: the rows are longer than one chunk of kBlockThreads * K lane loads;
+// the workgroup streams them chunk by chunk, the row sums carried in registers.
+template <class F, bool WIDE>
 __global__ __launch_bounds__(kBlockThreads) void k_gemv_nw(IterArgs a, const int4* __restrict__ tiles) {
   constexpr int N = WholeRows<F>::N, K = WholeRows<F>::K, NW = kBlockThreads / kWave;
   constexpr int CPL = F::CPL, X4 = CPL / 2;
@@ -202,44 +204,91 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_nw(IterArgs a, const int
   const int nvalid = min(N, d.mi - t.y);
   const int nl = (d.nj + CPL - 1) / CPL;
   const float4* x = reinterpret_cast<const float4*>(a.c + (int64_t)d.i * a.n_pad + d.cpad0);
-  // All loads first and without branches: lane loads past the row are
-  // clamped to its last one and their contributions dropped afterwards.
-  typename F::Raw h[N][K];
-  float4 xv[K][X4];
-#pragma unroll
-  for (int r = 0; r < N; ++r) {
-    const typename F::Row rp = f.row(d.h_off + (int64_t)(t.y + min(r, nvalid - 1)) * d.ld);
-#pragma unroll
-    for (int k = 0; k < K; ++k) h[r][k] = F::load(rp, (uint32_t)min(tid + kBlockThreads * k, nl - 1));
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int c = min(tid + kBlockThreads * k, nl - 1);   // c in the lane-permuted layout (cperm)
-#pragma unroll
-    for (int q = 0; q < X4; ++q) xv[k][q] = x[(((c >> 6) * X4 + q) << 6) + (c & 63)];
-  }
-  // epilogue operands: wave 0, lane l for row min(l, nvalid - 1) (a uniform branch)
   RowEpi epi;
-  if (wave == 0) row_epi_load(a, d, f, t.y + min(lane, nvalid - 1), epi);
+  if constexpr (!WIDE) {
+    // All loads first and without branches: lane loads past the row are
+    // clamped to its last one and their contributions dropped afterwards.
+    typename F::Raw h[N][K];
+    float4 xv[K][X4];
 #pragma unroll
-  for (int r = 0; r < N; ++r) {
-    float sr = 0.f, si = 0.f;
+    for (int r = 0; r < N; ++r) {
+      const typename F::Row rp = f.row(d.h_off + (int64_t)(t.y + min(r, nvalid - 1)) * d.ld);
+#pragma unroll
+      for (int k = 0; k < K; ++k) h[r][k] = F::load(rp, (uint32_t)min(tid + kBlockThreads * k, nl - 1));
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      if (tid + kBlockThreads * k >= nl) continue;
-      float hr[CPL], hi[CPL];
-      F::decode(h[r][k], hr, hi);
+      const int c = min(tid + kBlockThreads * k, nl - 1);   // c in the lane-permuted layout (cperm)
 #pragma unroll
-      for (int q = 0; q < X4; ++q) {
-        cmac(sr, si, hr[2 * q], hi[2 * q], xv[k][q].x, xv[k][q].y);
-        cmac(sr, si, hr[2 * q + 1], hi[2 * q + 1], xv[k][q].z, xv[k][q].w);
+      for (int q = 0; q < X4; ++q) xv[k][q] = x[(((c >> 6) * X4 + q) << 6) + (c & 63)];
+    }
+    // epilogue operands: wave 0, lane l for row min(l, nvalid - 1) (a uniform branch)
+    if (wave == 0) row_epi_load(a, d, f, t.y + min(lane, nvalid - 1), epi);
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (tid + kBlockThreads * k >= nl) continue;
+        float hr[CPL], hi[CPL];
+        F::decode(h[r][k], hr, hi);
+#pragma unroll
+        for (int q = 0; q < X4; ++q) {
+          cmac(sr, si, hr[2 * q], hi[2 * q], xv[k][q].x, xv[k][q].y);
+          cmac(sr, si, hr[2 * q + 1], hi[2 * q + 1], xv[k][q].z, xv[k][q].w);
+        }
+      }
+      sr = wave_sum(sr);
+      si = wave_sum(si);
+      if (lane == 0) {
+        red[wave][2 * r] = sr;
+        red[wave][2 * r + 1] = si;
       }
     }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    if (lane == 0) {
-      red[wave][2 * r] = sr;
-      red[wave][2 * r + 1] = si;
+  } else {
+    // The same chunk by chunk, the epilogue operands loaded first; each
+    // thread's row sums run on across the chunks in the same order.
+    if (wave == 0) row_epi_load(a, d, f, t.y + min(lane, nvalid - 1), epi);
+    float sr[N], si[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) sr[r] = si[r] = 0.f;
+    for (int c0 = 0; c0 < nl; c0 += kBlockThreads * K) {
+      typename F::Raw h[N][K];
+      float4 xv[K][X4];
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        const typename F::Row rp = f.row(d.h_off + (int64_t)(t.y + min(r, nvalid - 1)) * d.ld);
+#pragma unroll
+        for (int k = 0; k < K; ++k) h[r][k] = F::load(rp, (uint32_t)min(c0 + tid + kBlockThreads * k, nl - 1));
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int c = min(c0 + tid + kBlockThreads * k, nl - 1);
+#pragma unroll
+        for (int q = 0; q < X4; ++q) xv[k][q] = x[(((c >> 6) * X4 + q) << 6) + (c & 63)];
+      }
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          if (c0 + tid + kBlockThreads * k >= nl) continue;
+          float hr[CPL], hi[CPL];
+          F::decode(h[r][k], hr, hi);
+#pragma unroll
+          for (int q = 0; q < X4; ++q) {
+            cmac(sr[r], si[r], hr[2 * q], hi[2 * q], xv[k][q].x, xv[k][q].y);
+            cmac(sr[r], si[r], hr[2 * q + 1], hi[2 * q + 1], xv[k][q].z, xv[k][q].w);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const float wr = wave_sum(sr[r]), wi = wave_sum(si[r]);
+      if (lane == 0) {
+        red[wave][2 * r] = wr;
+        red[wave][2 * r + 1] = wi;
+      }
     }
   }
   __syncthreads();
@@ -554,10 +603,18 @@ __global__ void k_fill_zero(uint4* p, size_t n16) {
 hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, const int4* wtiles, int nwtiles,
                           hipStream_t st, KTime kt) {
   if (nwtiles > 0) {
-    switch (a.hs.storage) {
-      case 0: LAUNCH_TIMED(k_gemv_nw<FmtC64>, dim3(nwtiles), dim3(kBlockThreads), st, kt, a, wtiles); break;
-      case 1: LAUNCH_TIMED(k_gemv_nw<FmtBF16>, dim3(nwtiles), dim3(kBlockThreads), st, kt, a, wtiles); break;
-      default: LAUNCH_TIMED(k_gemv_nw<FmtFP8>, dim3(nwtiles), dim3(kBlockThreads), st, kt, a, wtiles); break;
+    if (a.wide) {
+      switch (a.hs.storage) {
+        case 0: LAUNCH_TIMED((k_gemv_nw<FmtC64, true>), dim3(nwtiles), dim3(kBlockThreads), st, kt, a, wtiles); break;
+        case 1: LAUNCH_TIMED((k_gemv_nw<FmtBF16, true>), dim3(nwtiles), dim3(kBlockThreads), st, kt, a, wtiles); break;
+        default: LAUNCH_TIMED((k_gemv_nw<FmtFP8, true>), dim3(nwtiles), dim3(kBlockThreads), st, kt, a, wtiles); break;
+      }
+    } else {
+      switch (a.hs.storage) {
+        case 0: LAUNCH_TIMED((k_gemv_nw<FmtC64, false>), dim3(nwtiles), dim3(kBlockThreads), st, kt, a, wtiles); break;
+        case 1: LAUNCH_TIMED((k_gemv_nw<FmtBF16, false>), dim3(nwtiles), dim3(kBlockThreads), st, kt, a, wtiles); break;
+        default: LAUNCH_TIMED((k_gemv_nw<FmtFP8, false>), dim3(nwtiles), dim3(kBlockThreads), st, kt, a, wtiles); break;
+      }
     }
     return hipGetLastError();
   }

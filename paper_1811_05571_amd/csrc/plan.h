@@ -97,6 +97,9 @@ constexpr int kEpiSections = 7;  // other sections whose estimates the row epilo
 #ifndef ADMM_WHOLE_ROWS_FP8
 #define ADMM_WHOLE_ROWS_FP8 0   // the same for fp8 (measured slower: 74 vs 71 us at 6144 x 32000)
 #endif
+#ifndef ADMM_WHOLE_WIDE
+#define ADMM_WHOLE_WIDE 1       // whole-row product also for column blocks wider than kWholeCols (in chunks)
+#endif
 #ifndef ADMM_WHOLE_N_BF16
 #define ADMM_WHOLE_N_BF16 4     // rows per workgroup of the whole-row product, bf16
 #endif
@@ -110,7 +113,7 @@ constexpr int kEpiSections = 7;  // other sections whose estimates the row epilo
 // 4 x 4 patches ceil(T/4) + 1; the region holds either layout.
 inline int64_t gram_part_vecs(int64_t T) { return std::max(T * T, T * ((T + 3) / 4 + 1)); }
 constexpr size_t kGramPatchMin = 4096;   // patches used by default from this many on
-constexpr int kWholeCols = 4096; // widest column block of the whole-row product
+constexpr int kWholeCols = 4096; // columns per chunk of the whole-row product
 // rows per workgroup of the whole-row product (its tiles follow it)
 inline int whole_rows(int storage) { return storage == 0 ? 2 : (storage == 1 ? ADMM_WHOLE_N_BF16 : ADMM_WHOLE_N_FP8); }
 
@@ -154,6 +157,7 @@ struct IterArgs {
   double rho2Q;         // rho^2 Q for the dual residual
   int cpl;              // columns per lane load of the storage (layout of c, see cperm)
   int xstage;           // 1: every column block's c fits kXStage float4 of LDS (row product stages it)
+  int wide;             // 1: some column block is wider than kWholeCols (the whole-row product loops over chunks)
 };
 
 // Adjoint (reverse-mode) sweep of one iteration.

@@ -141,3 +141,24 @@ def test_full_size_inverse_bf16(torch_gpu, full):
     print(f"bf16 inverse vs FP32 inverse {e:.2e}, NMSE {n(v32):.5f} / {n(v16):.5f}")
     assert e <= 2.0 ** -8
     assert abs(n(v16) - n(v32)) <= 1e-3 * n(v32)
+
+
+@pytest.mark.parametrize("split", [(4, 1), (1, 3), (4, 3)])
+def test_paper_table_workload_parity(torch_gpu, split):
+    """2160 x 22500 (the paper's timing-table shape), its three splittings:
+    parity with the oracle after 10 iterations and decreasing residuals over
+    the table's 50."""
+    import paper_1811_05571_amd as A
+    Q, P = split
+    p = W.paper_table_imaging(Q=Q, P=P)
+    H, g = to_device(torch_gpu, p.H), to_device(torch_gpu, p.g)
+    plan = A.Plan(H, Q, P, p.rho, p.lam)
+    K = 10
+    v = plan.solve(g, K).cpu().numpy()
+    v_ref, _, _ = O.solve(p.H, p.g, Q, P, p.rho, p.lam, K)
+    err = rel(v, v_ref)
+    print(f"paper table {Q}x{P}: rel err after {K} iterations {err:.2e}", flush=True)
+    assert err <= 1e-5
+    _, hist = plan.solve(g, W.PAPER_TABLE_ITERS, history=True)
+    h = hist.cpu().numpy()
+    assert np.all(np.isfinite(h)) and h[-1, 0] < 1e-3 * h[0, 0] and h[-1, 1] < h[1, 1]

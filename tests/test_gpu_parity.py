@@ -43,8 +43,8 @@ def _case(name):
         # rho large enough for ten Jacobi sections to converge
         return W.iid_problem(m=200, n=3000, nnz=12, Q=2, P=10, rho=40.0, seed=8), 150
     if name == "wide_blocks":
-        # 6000-column blocks: past the whole-row complex64 product (4096 columns),
-        # so the streaming row product runs
+        # 6000-column blocks: longer than one 4096-column chunk of the whole-row
+        # product, which streams them in two (the second partial)
         return W.iid_problem(m=128, n=6000, nnz=10, Q=2, P=1, rho=1.0, seed=9), 150
     raise KeyError(name)
 

@@ -35,7 +35,9 @@ def _problems():
                                     patch=(7, 3), iters=100, seed=7), 100),
         "consensus256x4096": (W.small_consensus(), 200),
         "many_sections": (W.iid_problem(m=200, n=3000, nnz=12, Q=2, P=10, rho=40.0, seed=8), 150),
-        # blocks wider than the 32 KB LDS stage of c: the unstaged row product
+        # 6000-column blocks, wider than one whole-row chunk and than the 32 KB
+        # LDS stage of c: the chunked whole-row product (bf16), the unstaged
+        # streaming one (fp8)
         "wide_blocks": (W.iid_problem(m=128, n=6000, nnz=10, Q=2, P=1, rho=1.0, seed=9), 150),
     }
 

@@ -274,6 +274,19 @@ def test_partition_matches_paper_timing_table():
         assert sp["woodbury"] == [sp["block"][0]] * 2
 
 
+def test_paper_table_workload_shapes():
+    """The timing-table workload has the table's measurement and pixel counts,
+    its splits, unit rows and the two-patch target."""
+    gold = json.load(open(os.path.join(GOLDEN, "tab_timing.json")))
+    p = W.paper_table_imaging()
+    assert p.H.shape == (gold["N_m"], gold["N_p"])
+    assert [(sp["M"], sp["N"]) for sp in gold["splits"]] == list(W.PAPER_TABLE_SPLITS)
+    np.testing.assert_allclose(np.linalg.norm(p.H.astype(np.complex128), axis=1), 1.0, rtol=1e-5)
+    assert np.count_nonzero(p.u_true) == 150 and p.lam > 0
+    # same seed, same matrix for every split
+    assert np.array_equal(W.paper_table_imaging(Q=1, P=3).H, p.H)
+
+
 def test_uneven_split_offsets():
     np.testing.assert_array_equal(O.split_offsets(10, 3), [0, 4, 7, 10])
     np.testing.assert_array_equal(O.split_offsets(9, 3), [0, 3, 6, 9])

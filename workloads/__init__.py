@@ -103,12 +103,13 @@ def iid_problem(m: int = 256, n: int = 4096, nnz: int = 20, snr_db: float = 30.0
 def cra_geometry(n_tx: int = 16, n_rx: int = 16, n_f: int = 24,
                  nx: int = 40, ny: int = 40, nz: int = 20,
                  aperture: float = 0.3, f_lo: float = 70e9, f_hi: float = 77e9,
-                 spacing: float = 5e-3, z0: float = 0.5):
+                 spacing: float = 5e-3, z0: float = 0.5, spacing_z: float | None = None):
     """Antenna, frequency and voxel coordinates of the CRA-like imaging model.
 
     Tx on the x axis, Rx on the y axis (two orthogonal linear arrays at z=0,
     as in the paper's imaging set-up, Sec. VI).  Frequencies uniform in
-    [f_lo, f_hi].  Voxel grid centred at (0, 0, z0); column index
+    [f_lo, f_hi].  Voxel grid centred at (0, 0, z0), `spacing` in x and y and
+    `spacing_z` (default: `spacing`) in z; column index
     iz + nz*(iy + ny*ix) (x slowest), so equal column blocks are x slabs.
     Row index rx + n_rx*(tx + n_tx*f) (frequency slowest).
     """
@@ -119,7 +120,7 @@ def cra_geometry(n_tx: int = 16, n_rx: int = 16, n_f: int = 24,
     freqs = f_lo + (f_hi - f_lo) * np.arange(n_f) / max(n_f - 1, 1)
     xs = (np.arange(nx) - (nx - 1) / 2) * spacing
     ys = (np.arange(ny) - (ny - 1) / 2) * spacing
-    zs = z0 + (np.arange(nz) - (nz - 1) / 2) * spacing
+    zs = z0 + (np.arange(nz) - (nz - 1) / 2) * (spacing if spacing_z is None else spacing_z)
     X, Y, Z = np.meshgrid(xs, ys, zs, indexing="ij")
     vox = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)  # (nx*ny*nz, 3), x slowest
     return tx, rx, freqs, vox
@@ -188,15 +189,16 @@ def _patch_target(rng: np.random.Generator, nx: int, ny: int, nz: int,
 def cra_problem(n_tx: int = 16, n_rx: int = 16, n_f: int = 24, nx: int = 40, ny: int = 40,
                 nz: int = 20, Q: int = 4, P: int = 8, rho: float = 1.0, lam_ratio: float = 0.02,
                 snr_db: float = 25.0, iters: int = 300, seed: int = 0, patch=(15, 5),
-                row_off=None, col_off=None, name: str | None = None) -> Problem:
+                row_off=None, col_off=None, name: str | None = None, geometry: dict | None = None) -> Problem:
     """CRA-like imaging problem.  Defaults are the full imaging workload:
     m = 16*16*24 = 6144 measurements, n = 40*40*20 = 32000 voxels, Q=4, P=8,
     rho=1, lambda = 0.02 max|H^H g|, 25 dB SNR, 300 iterations, seed 0.
+    `geometry` passes spacing, spacing_z, z0 or aperture to cra_geometry.
 
     Draw order: phi (m values, row order), patch positions, Re w, Im w.
     """
     rng = np.random.default_rng(seed)
-    tx, rx, freqs, vox = cra_geometry(n_tx, n_rx, n_f, nx, ny, nz)
+    tx, rx, freqs, vox = cra_geometry(n_tx, n_rx, n_f, nx, ny, nz, **(geometry or {}))
     m = n_tx * n_rx * n_f
     phi = rng.uniform(0.0, 2.0 * np.pi, size=m)
     H = cra_matrix(tx, rx, freqs, vox, phi)
@@ -231,6 +233,29 @@ def full_imaging_name() -> str:
 def full_imaging(seed: int = 0, rho: float = FULL_IMAGING_RHO) -> Problem:
     """6144 x 32000 CRA-like consensus-and-sectioning workload (Q=4, P=8, 300 it)."""
     return cra_problem(seed=seed, rho=rho, name=FULL_IMAGING_NAME)
+
+
+# The imaging set-up of the paper's timing table (Sec. VI, parameter and
+# timing tables): 12 Tx x 12 Rx x 15 frequencies in 70-77 GHz = 2160
+# measurements; 75 x 75 x 4 = 22500 pixels of lambda_c x lambda_c x 5 lambda_c
+# (lambda_c = c / 73.5 GHz) centred 86 cm from the arrays; 50 iterations of
+# each of the three splittings, consensus 4 x 1, sectioning 1 x 3 and both
+# 4 x 3.  The paper's rho = 1e5 belongs to its own scaling of H; with rows of
+# unit norm the iterates do not move in 50 iterations at that value, while
+# rho = 10 is the smallest of {1, 3, 10, 1e5} at which all three splittings
+# converge within them (1 x 3 and 4 x 3 diverge at 1; at 3 the 1 x 3 primal
+# residual only halves).
+PAPER_TABLE_SPLITS = ((4, 1), (1, 3), (4, 3))
+PAPER_TABLE_RHO = 10.0
+PAPER_TABLE_ITERS = 50
+_LAMBDA_C = C0 / 73.5e9
+
+
+def paper_table_imaging(Q: int = 4, P: int = 3, seed: int = 0, rho: float = PAPER_TABLE_RHO) -> Problem:
+    """2160 x 22500 CRA-like workload of the paper's timing table (one H for all splits of a seed)."""
+    return cra_problem(n_tx=12, n_rx=12, n_f=15, nx=75, ny=75, nz=4, Q=Q, P=P, rho=rho,
+                       iters=PAPER_TABLE_ITERS, seed=seed, name=f"cra2160x22500_Q{Q}P{P}",
+                       geometry=dict(spacing=_LAMBDA_C, spacing_z=5 * _LAMBDA_C, z0=0.86))
 
 
 # --------------------------------------------------------------------------
