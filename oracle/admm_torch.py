@@ -3,7 +3,9 @@
 TEST INFRASTRUCTURE ONLY (same rule as oracle/admm.py).
 
 The same iteration as oracle/admm.py (paper Sec. III-C, combined scheme, in
-the paper's order with the literal inversion lemma of eq. inversion_lemma3),
+the paper's order with the literal inversion lemma of eq. inversion_lemma3 for
+blocks with fewer rows than columns and, as the paper remarks for the others,
+a direct factor of H_ij^* H_ij + rho I),
 written with torch complex128 CPU operations so that torch's autograd gives
 d v^K / d(g, lambda, rho) for K unrolled iterations from the zero state.
 
@@ -42,10 +44,12 @@ def unrolled(H: torch.Tensor, g: torch.Tensor, Q: int, P: int, rho: torch.Tensor
         for j in range(P):
             Hij = H[ro[i]:ro[i + 1], co[j]:co[j + 1]]
             mb, nb = Hij.shape
-            if mb >= nb:
-                raise ValueError("the twin carries the inversion-lemma branch only")
-            A = torch.eye(mb, dtype=H.dtype) + (Hij @ Hij.conj().T) / rho
-            blocks[i, j] = (Hij, torch.linalg.cholesky(A))
+            if mb < nb:
+                A = torch.eye(mb, dtype=H.dtype) + (Hij @ Hij.conj().T) / rho
+                blocks[i, j] = (Hij, True, torch.linalg.cholesky(A))
+            else:
+                B = Hij.conj().T @ Hij + rho * torch.eye(nb, dtype=H.dtype)
+                blocks[i, j] = (Hij, False, torch.linalg.cholesky(B))
     zc = lambda k: torch.zeros(k, dtype=H.dtype)
     v = zc(n)
     s = [zc(n) for _ in range(Q)]
@@ -58,14 +62,17 @@ def unrolled(H: torch.Tensor, g: torch.Tensor, Q: int, P: int, rho: torch.Tensor
             gi = g[ro[i]:ro[i + 1]]
             for j in range(P):
                 c0, c1 = co[j], co[j + 1]
-                Hij, L = blocks[i, j]
+                Hij, lemma, L = blocks[i, j]
                 g_ij = gi
                 for q in range(P):
                     if q != j:
                         g_ij = g_ij - ghat[i][q]
                 b = Hij.conj().T @ g_ij + rho * (v[c0:c1] - s[i][c0:c1])
-                t = torch.cholesky_solve((Hij @ b).unsqueeze(1), L).squeeze(1)
-                u[i][j] = b / rho - (Hij.conj().T @ t) / rho ** 2
+                if lemma:
+                    t = torch.cholesky_solve((Hij @ b).unsqueeze(1), L).squeeze(1)
+                    u[i][j] = b / rho - (Hij.conj().T @ t) / rho ** 2
+                else:
+                    u[i][j] = torch.cholesky_solve(b.unsqueeze(1), L).squeeze(1)
                 ghat_new[i][j] = Hij @ u[i][j]
         ghat = ghat_new
         ui = [torch.cat(u[i]) for i in range(Q)]

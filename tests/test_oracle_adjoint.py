@@ -25,7 +25,7 @@ def test_torch_gradient_convention():
     assert torch.allclose(z.grad, torch.tensor([2.0 + 4.0j], dtype=torch.complex128))
 
 
-@pytest.mark.parametrize("Q,P", [(1, 1), (2, 1), (2, 2), (1, 2)])
+@pytest.mark.parametrize("Q,P", [(1, 1), (2, 1), (2, 2), (1, 2), (1, 4)])   # (1, 4): 40 x 30, direct
 def test_twin_forward_equals_oracle(Q, P):
     H, g, u, _, _, rho, lam = _problem(Q=Q, P=P)
     v_ref, _, _ = O.solve(H, g, Q, P, rho, lam, 30)
@@ -34,7 +34,7 @@ def test_twin_forward_equals_oracle(Q, P):
     assert np.linalg.norm(v - v_ref) <= 1e-12 * np.linalg.norm(v_ref)
 
 
-@pytest.mark.parametrize("Q,P", [(2, 1), (2, 2)])
+@pytest.mark.parametrize("Q,P", [(2, 1), (2, 2), (1, 4)])
 def test_twin_gradients_match_central_differences(Q, P):
     H, g, u_true, _, _, rho, lam = _problem(seed=1, Q=Q, P=P)
     K = 20
