@@ -230,6 +230,42 @@ def block_geometry(m: int, n: int, Q: int, P: int) -> dict:
             "gram_parts_patch": int(sum(T * ((T + 3) // 4 + 1) for T in tiles) * P)}
 
 
+def bench_full_splits(args, torch, A, prob, H, g, steps: int = 300, warmup: int = 300):
+    """The other two methods on the full matrix: consensus only (Q = 4, P = 1,
+    1536 x 32000 blocks) and sectioning only (Q = 1, P = 8, 6144 x 4000
+    blocks, taller than wide), complex64, same rho and lambda."""
+    rows = []
+    for Q, P in ((4, 1), (1, 8)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = A.Plan(H, Q, P, prob.rho, prob.lam)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        plan.solve(g, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v, hist = plan.solve(g, steps, history=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        info = plan.info()
+        algo = algorithmic_bytes(block_geometry(prob.m, prob.n, Q, P), P, Q, info["chunks"], "c64", "c64",
+                                 info["gram_patches"] > 0)
+        vn = v.cpu().numpy()
+        hs = hist.cpu().numpy()
+        mi, nj = -(-prob.m // Q), -(-prob.n // P)
+        rows.append({
+            "split": f"{Q}x{P}", "block": f"{mi}x{nj}", "value": round(steps / el, 1), "unit": "iters/s",
+            "setup_ms": round(setup * 1e3, 1), "iteration_gbs": round(sum(algo.values()) * steps / el / 1e9, 1),
+            "algo_bytes_per_iteration": int(sum(algo.values())), "inverse_gb": round(info["ginv_bytes"] / 1e9, 3),
+            "nmse_vs_truth": float(np.linalg.norm(vn - prob.u_true) ** 2 / np.linalg.norm(prob.u_true) ** 2),
+            "residuals_last": [float(x) for x in hs[-1]],
+        })
+        plan.close()
+        print(f"[bench] full matrix {Q}x{P}: setup {setup * 1e3:.1f} ms, {steps / el:.1f} iterations/s",
+              file=sys.stderr, flush=True)
+    return {"workload": prob.name.split("_")[0], "iters": steps, "warmup": warmup, "splits": rows}
+
+
 # The paper's timing table (Sec. VI): per splitting, inversion time (ms), 50
 # iterations (ms) and total imaging time (s), one Titan V under MATLAB R2017b
 # at 2160 x 22500 (precision not stated).  Quoted as context only.
@@ -414,6 +450,7 @@ def main(argv=None):
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched multi-scene form")
     ap.add_argument("--no-paper-table", action="store_true", help="skip the paper's timing-table workload")
+    ap.add_argument("--no-splits", action="store_true", help="skip the consensus-only and sectioning-only splits")
     ap.add_argument("--paper-table-only", action="store_true", help="measure only the paper's timing-table workload")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-seq", type=int, default=8, help="scenes solved one at a time for comparison")
@@ -573,6 +610,8 @@ def main(argv=None):
         }
         print(f"[bench] adjoint: forward {out['adjoint']['forward_ms']} ms, backward "
               f"{out['adjoint']['backward_ms']} ms", file=sys.stderr, flush=True)
+    if not args.no_splits:
+        out["full_splits"] = bench_full_splits(args, torch, A, prob, H, g)
     del H
     if not args.no_batch:
         out["batch"] = bench_batch(args, torch, A, W, dev)

@@ -95,8 +95,12 @@ const char* admm_last_error(void);
  *             get one extra row).  col_off likewise with P and n.
  *   storage   ADMM_STORAGE_*, optionally | ADMM_INVERSE_BF16 | ADMM_GRAM_PATCHES.
  *   out_bytes host, receives the size.
- * Errors: EINVAL for any bad size or split; EUNSUPPORTED when some block is
- * not wide (m_i >= n_j), since only the inversion-lemma x-update is built.
+ * Errors: EINVAL for any bad size or split; EUNSUPPORTED when some block has
+ * m_i >= (1 + sqrt 2) n_j (exactly: m_i^2 >= 2 m_i n_j + n_j^2).  Every block
+ * takes the inversion-lemma (push-through) x-update, which streams the packed
+ * m_i x m_i inverse each iteration; for blocks that tall the direct form of
+ * Sec. III (an n_j x n_j inverse plus a third product with H_ij) would stream
+ * less, and it is not built.
  */
 int admm_workspace_bytes(int64_t m, int64_t n, int Q, const int64_t* row_off,
                          int P, const int64_t* col_off, int storage,
@@ -292,7 +296,8 @@ void admm_destroy(admm_plan* plan);
  *   g        device complex64, packed like phases.
  *   v_out    device complex64 S x n (scene s at s*n).
  *   use_graph  1: replay one captured hipGraph of the iteration per step.
- * Errors: EINVAL, EUNSUPPORTED (a block not wide), EWORKSPACE, ENONFINITE,
+ * Errors: EINVAL, EUNSUPPORTED (a block with m_i >= (1 + sqrt 2) n_j, as for
+ * admm_workspace_bytes), EWORKSPACE, ENONFINITE,
  * ENOTPD, EHIP.  setup and solve synchronise `stream`.
  * ====================================================================== */
 typedef struct admm_batch admm_batch;

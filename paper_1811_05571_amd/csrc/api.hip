@@ -140,10 +140,16 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
       d.j = j;
       d.mi = (int32_t)(geo.ro[i + 1] - geo.ro[i]);
       d.nj = (int32_t)(geo.co[j + 1] - geo.co[j]);
-      if (d.mi >= d.nj) {
+      // The push-through x-update serves any block shape.  Per iteration it
+      // streams the packed m_i x m_i inverse; the direct form of tall blocks
+      // (Sec. III) would stream an n_j x n_j one plus a third pass over H_ij
+      // (for its estimated data).  The first is the smaller stream while
+      // m_i^2 < 2 m_i n_j + n_j^2, i.e. m_i < (1 + sqrt 2) n_j; taller blocks
+      // would need the direct form, which is not built.
+      if ((int64_t)d.mi * d.mi >= 2 * (int64_t)d.mi * d.nj + (int64_t)d.nj * d.nj) {
         snprintf(buf, sizeof buf,
-                 "block (%d,%d) is %d x %d: only wide blocks (rows < columns) use the inversion-lemma "
-                 "x-update that is built",
+                 "block (%d,%d) is %d x %d: at least (1 + sqrt 2) times taller than wide, where the direct "
+                 "x-update that is not built would stream less than the inversion-lemma one",
                  i, j, d.mi, d.nj);
         err = buf;
         return ADMM_EUNSUPPORTED;

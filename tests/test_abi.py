@@ -62,10 +62,13 @@ def test_workspace_sizing_and_argument_errors():
         with pytest.raises(A.ADMMError) as ei:
             A.workspace_bytes(**kw)
         assert ei.value.status == "ADMM_EINVAL", kw
-    # tall blocks use the direct x-update, which is not built
-    with pytest.raises(A.ADMMError) as ei:
-        A.workspace_bytes(6144, 32000, 1, 8)
-    assert ei.value.status == "ADMM_EUNSUPPORTED"
+    # tall blocks take the inversion-lemma x-update while m_i < (1 + sqrt 2) n_j
+    assert A.workspace_bytes(6144, 32000, 1, 8) > 0          # 6144 x 4000
+    assert A.workspace_bytes(480, 1000, 1, 5) > 0            # 480 x 200: 480^2 < 2*480*200 + 200^2
+    for m, n, P in ((500, 1000, 5), (6144, 32000, 32)):      # 500 x 200 and 6144 x 1000: beyond
+        with pytest.raises(A.ADMMError) as ei:
+            A.workspace_bytes(m, n, 1, P)
+        assert ei.value.status == "ADMM_EUNSUPPORTED"
 
 
 def test_null_plan_is_rejected():

@@ -27,6 +27,8 @@ def _cases():
                                           col_off=[0, 333, 800, 1201, 1600, 2000]), 40),
         "cra_small": (W.cra_problem(n_tx=6, n_rx=6, n_f=8, nx=12, ny=12, nz=6, Q=2, P=2, rho=10.0,
                                     patch=(5, 2), iters=50, seed=22), 50),
+        # 150 x 125 blocks, taller than wide: the twin differentiates the direct solve
+        "tall_sectioning": (W.iid_problem(m=150, n=500, nnz=8, Q=1, P=4, rho=10.0, seed=23), 40),
     }
 
 
@@ -40,7 +42,7 @@ def _loss_and_grad_v(v, u_true):
     return float(np.sum(np.abs(v - u_true) ** 2)), 2 * (v - u_true)
 
 
-@pytest.mark.parametrize("name", ["consensus", "combined_uneven", "cra_small"])
+@pytest.mark.parametrize("name", ["consensus", "combined_uneven", "cra_small", "tall_sectioning"])
 def test_adjoint_matches_oracle_autograd(torch_gpu, name):
     torch = torch_gpu
     p, K = _cases()[name]

@@ -52,6 +52,28 @@ def test_batch_matches_oracle_per_scene(torch_gpu, gram_patches):
     assert worst <= 1e-5
 
 
+def test_batch_tall_blocks_match_oracle(torch_gpu):
+    """Eight equal column blocks of 384: scene 1's 576-row block is taller than
+    wide and scene 3 (one row block) square; the oracle solves those blocks
+    directly, the batch keeps the inversion lemma."""
+    import paper_1811_05571_amd as A
+    b = _batch()
+    b.cuts[3] = np.array([0, len(b.tiles[3])], dtype=np.int32)
+    P, K = 8, 60
+    bb = A.Batch(to_device(torch_gpu, b.H0), b.tile_rows, b.tiles, b.cuts, b.phases, P, b.rho, b.lam)
+    v = bb.solve(to_device(torch_gpu, np.concatenate(b.g)), K).cpu().numpy()
+    H0q = QZ.dequantise(b.H0, "bf16")
+    tall = 0
+    worst = 0.0
+    for s in range(b.S):
+        Hs = b.scene_H(s, H0q)
+        tall += int(np.diff(b.row_off(s)).max() >= 384)
+        ref, _, _ = O.solve(Hs, b.g[s], len(b.cuts[s]) - 1, P, b.rho, b.lam[s], K, b.row_off(s), None)
+        worst = max(worst, rel(v[s], ref))
+    print(f"tall-block batch: {tall} scenes with blocks of m_i >= n_j, worst rel err {worst:.2e}", flush=True)
+    assert tall >= 2 and worst <= 1e-5
+
+
 def test_batch_graph_equals_plain_launches(torch_gpu):
     b = _batch()
     bb, g, v1 = _solve(torch_gpu, b, 20, graph=True)

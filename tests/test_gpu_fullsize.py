@@ -31,6 +31,20 @@ def test_full_size_parity_first_iterations(torch_gpu, full):
     assert rel(ghat.cpu().numpy(), st.ghat) <= 1e-4
 
 
+def test_full_size_sectioning_only_parity(torch_gpu, full):
+    """The sectioning-only split of the full matrix (Q = 1, P = 8): 6144 x 4000
+    blocks, taller than wide; the oracle solves them directly."""
+    import paper_1811_05571_amd as A
+    p, H, g = full
+    plan = A.Plan(H, 1, 8, p.rho, p.lam)
+    K = 3
+    v = plan.solve(g, K).cpu().numpy()
+    v_ref, _, _ = O.solve(p.H, p.g, 1, 8, p.rho, p.lam, K)
+    err = rel(v, v_ref)
+    print(f"sectioning only 1x8: rel err after {K} iterations {err:.2e}", flush=True)
+    assert err <= 1e-5
+
+
 def test_full_size_300_iterations_properties(torch_gpu, full):
     """After the workload's 300 iterations: residuals decrease, the FP64 KKT
     violation decreases, both runs of the same input agree bit for bit."""

@@ -46,11 +46,22 @@ def _case(name):
         # 6000-column blocks: longer than one 4096-column chunk of the whole-row
         # product, which streams them in two (the second partial)
         return W.iid_problem(m=128, n=6000, nnz=10, Q=2, P=1, rho=1.0, seed=9), 150
+    # Blocks with m_i >= n_j: the GPU keeps the inversion-lemma x-update, the
+    # oracle takes the direct solve of (H^H H + rho I) for them.
+    if name == "tall_sectioning":      # 300 x 250 blocks
+        return W.iid_problem(m=300, n=1000, nnz=10, Q=1, P=4, rho=10.0, seed=21), 150
+    if name == "square_blocks":        # 256 x 256
+        return W.iid_problem(m=256, n=512, nnz=10, Q=1, P=2, rho=10.0, seed=22), 150
+    if name == "mixed_tall":           # 120 x 100 next to wide blocks
+        return W.iid_problem(m=240, n=900, nnz=10, Q=2, P=3, rho=10.0, seed=23, col_off=[0, 100, 400, 900]), 150
+    if name == "tall_near_limit":      # 480 x 200: just under (1 + sqrt 2) n_j
+        return W.iid_problem(m=480, n=1000, nnz=10, Q=1, P=5, rho=10.0, seed=24), 150
     raise KeyError(name)
 
 
 CASES = ["consensus256x4096", "combined_uneven", "sectioning", "unsplit", "ragged_consensus",
-         "cra_small", "many_sections", "wide_blocks"]
+         "cra_small", "many_sections", "wide_blocks", "tall_sectioning", "square_blocks", "mixed_tall",
+         "tall_near_limit"]
 
 
 @pytest.mark.parametrize("name", CASES)
