@@ -230,6 +230,20 @@ def block_geometry(m: int, n: int, Q: int, P: int) -> dict:
             "gram_parts_patch": int(sum(T * ((T + 3) // 4 + 1) for T in tiles) * P)}
 
 
+# rates of the split cost model (measured on MI355X: streaming reads, the FP64
+# setup, the fixed cost of one iteration's launches and small kernels)
+MODEL_RATES = {"hbm_gbs": 6800.0, "fp64_tflops": 45.0, "latency_us": 25.0}
+
+
+def split_model(A, m: int, n: int, Q: int, P: int) -> dict:
+    """admm_split_cost priced at MODEL_RATES: modelled setup and iteration times."""
+    c = A.split_cost(m, n, Q, P)
+    return {"exchange_elements": int(c["exchange_elements"]),
+            "model_setup_ms": round(c["setup_fp64_flops"] / (MODEL_RATES["fp64_tflops"] * 1e12) * 1e3, 2),
+            "model_iter_us": round((c["bytes_per_iteration"] / (MODEL_RATES["hbm_gbs"] * 1e9)
+                                    + MODEL_RATES["latency_us"] * 1e-6) * 1e6, 1)}
+
+
 def bench_full_splits(args, torch, A, prob, H, g, steps: int = 300, warmup: int = 300):
     """The other two methods on the full matrix: consensus only (Q = 4, P = 1,
     1536 x 32000 blocks) and sectioning only (Q = 1, P = 8, 6144 x 4000
@@ -259,6 +273,7 @@ def bench_full_splits(args, torch, A, prob, H, g, steps: int = 300, warmup: int 
             "algo_bytes_per_iteration": int(sum(algo.values())), "inverse_gb": round(info["ginv_bytes"] / 1e9, 3),
             "nmse_vs_truth": float(np.linalg.norm(vn - prob.u_true) ** 2 / np.linalg.norm(prob.u_true) ** 2),
             "residuals_last": [float(x) for x in hs[-1]],
+            "iter_us": round(el / steps * 1e6, 1), **split_model(A, prob.m, prob.n, Q, P),
         })
         plan.close()
         print(f"[bench] full matrix {Q}x{P}: setup {setup * 1e3:.1f} ms, {steps / el:.1f} iterations/s",
@@ -275,13 +290,20 @@ PAPER_TABLE_TIMES = {(4, 1): (196.0, 616.0, 0.812), (1, 3): (381.0, 639.0, 1.020
 def bench_paper_table(args, torch, A, W, dev, reps: int = 5):
     """The paper's timing-table workload on one MI355X: 2160 x 22500, the three
     splittings, setup (FP64 Gram, Cholesky and inverse, the paper's inversion
-    step) and 50 iterations timed apart, complex64."""
+    step) and 50 iterations timed apart, complex64; then the splits the cost
+    model chooses for 50 iterations, without and with a limit of 10000
+    exchanged elements per node."""
     p = W.paper_table_imaging(seed=args.seed)
     H = torch.from_numpy(p.H).to(dev)
     g = torch.from_numpy(p.g).to(dev)
     K = W.PAPER_TABLE_ITERS
     rows = []
-    for Q, P in W.PAPER_TABLE_SPLITS:
+    chosen = [A.choose_split(p.m, p.n, K, max_exchange=lim, **MODEL_RATES)[:2] for lim in (0.0, 10000.0)]
+    splits = list(W.PAPER_TABLE_SPLITS)
+    for s in chosen:
+        if s not in splits:
+            splits.append(s)
+    for Q, P in splits:
         A.Plan(H, Q, P, p.rho, p.lam).close()   # first build of this split, untimed
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -302,7 +324,6 @@ def bench_paper_table(args, torch, A, W, dev, reps: int = 5):
                                  info["gram_patches"] > 0)
         vn = v.cpu().numpy()
         hs = hist.cpu().numpy()
-        ps, pi, pt = PAPER_TABLE_TIMES[(Q, P)]
         mi, nj = -(-p.m // Q), -(-p.n // P)
         rows.append({
             "split": f"{Q}x{P}", "block": f"{mi}x{nj}", "inverse": f"{mi}x{mi}",
@@ -311,8 +332,13 @@ def bench_paper_table(args, torch, A, W, dev, reps: int = 5):
             "iteration_gbs": round(sum(algo.values()) * K / it / 1e9, 1),
             "nmse_vs_truth": float(np.linalg.norm(vn - p.u_true) ** 2 / np.linalg.norm(p.u_true) ** 2),
             "residuals_first_last": [[float(x) for x in hs[0]], [float(x) for x in hs[-1]]],
-            "paper_titan_v": {"inversion_ms": ps, "iters_ms": pi, "total_s": pt},
+            **split_model(A, p.m, p.n, Q, P),
         })
+        if (Q, P) in PAPER_TABLE_TIMES:
+            ps, pi, pt = PAPER_TABLE_TIMES[(Q, P)]
+            rows[-1]["paper_titan_v"] = {"inversion_ms": ps, "iters_ms": pi, "total_s": pt}
+        else:
+            rows[-1]["chosen_by_model"] = {"max_exchange": 0 if (Q, P) == chosen[0] else 10000}
         plan.close()
         print(f"[bench] paper table {Q}x{P}: setup {setup * 1e3:.1f} ms, {K} iterations {it * 1e3:.2f} ms",
               file=sys.stderr, flush=True)

@@ -107,6 +107,49 @@ int admm_workspace_bytes(int64_t m, int64_t n, int Q, const int64_t* row_off,
                          size_t* out_bytes);
 
 /*
+ * admm_split_cost -- cost model of one split (host computation, no GPU call).
+ *   m..storage  as for admm_workspace_bytes, with the same errors.
+ *   out16     host double[16]:
+ *     [0] elements one computational node sends and receives per iteration
+ *         when each block is its own node (Sec. IV, table of exchanged
+ *         elements): 2 n with row blocks only, P m with column blocks only,
+ *         P m_i + 2 n_j with both (the largest blocks when uneven), 0 unsplit;
+ *     [1] HBM bytes one iteration of this library moves (algorithmic: H read
+ *         twice, the packed inverses once, the block vectors; with Q > 32 the
+ *         z-update's second read of c and the partials), for the kernels this
+ *         split gets;
+ *     [2] FP64 flops of the setup (lower half of H_ij H_ij^H, Cholesky,
+ *         triangular inverse and W^H W, 8 per complex multiply-add);
+ *     [3] bytes of the packed complex64 inverses, [4] bytes of stored H,
+ *     [5] workspace bytes, [6] largest m_i, [7] largest n_j, [8] row chunks
+ *     of the adjoint product, [9] 4 x 4 tile patches of the Gram apply (0:
+ *     single tiles), [10..15] 0.
+ */
+int admm_split_cost(int64_t m, int64_t n, int Q, const int64_t* row_off,
+                    int P, const int64_t* col_off, int storage, double* out16);
+
+/*
+ * admm_choose_split -- equal split (Q, P), Q and P from {1, 2, 3, 4, 5, 6,
+ * 8, 10, 12, 16, 20, 24, 32}, that minimises the modelled time of setup
+ * plus `iters` iterations,
+ *   flops[2] / (fp64_tflops 1e12) + iters (bytes[1] / (hbm_gbs 1e9) + latency_us 1e-6),
+ * among the splits admm_workspace_bytes accepts whose exchange count [0]
+ * is at most max_exchange (<= 0: no limit; the limit stands for the link
+ * budget of a distributed run, Sec. IV).  The rates are the caller's
+ * measurements: on MI355X about 6800 GB/s for streaming reads, 40-50
+ * TFLOP/s for the FP64 setup, 20-35 us of fixed cost per iteration.  The
+ * model prices a fixed number of iterations; how many a split needs to
+ * converge depends on the problem and is the caller's input.
+ *   Q_out, P_out  host, receive the split; model_s host or NULL, receives
+ *                 the modelled seconds.
+ * Errors: EINVAL (NULL outputs, iters < 0, rates not > 0, latency < 0),
+ * EUNSUPPORTED (no candidate meets the exchange limit).
+ */
+int admm_choose_split(int64_t m, int64_t n, int iters, int storage,
+                      double max_exchange, double hbm_gbs, double fp64_tflops,
+                      double latency_us, int* Q_out, int* P_out, double* model_s);
+
+/*
  * admm_setup -- build a plan: copy/quantise H into the workspace and factor
  * every block's Gram matrix G_ij = rho I + H_ij H_ij^H once (FP64 Gram,
  * Cholesky and inverse on the GPU, stored as an FP32 Hermitian inverse).

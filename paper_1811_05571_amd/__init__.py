@@ -36,6 +36,9 @@ SIGNATURES = [
     ("admm_strerror", _c.c_char_p, [_int]),
     ("admm_last_error", _c.c_char_p, []),
     ("admm_workspace_bytes", _int, [_i64, _i64, _int, _vp, _int, _vp, _int, _c.POINTER(_sz)]),
+    ("admm_split_cost", _int, [_i64, _i64, _int, _vp, _int, _vp, _int, _c.POINTER(_dbl)]),
+    ("admm_choose_split", _int, [_i64, _i64, _int, _int, _dbl, _dbl, _dbl, _dbl, _c.POINTER(_int), _c.POINTER(_int),
+                                 _c.POINTER(_dbl)]),
     ("admm_setup", _int, [_c.POINTER(_vp), _vp, _i64, _i64, _int, _vp, _int, _vp, _dbl, _dbl, _int,
                           _vp, _sz, _vp]),
     ("admm_set_lambda", _int, [_vp, _dbl]),
@@ -113,6 +116,31 @@ def workspace_bytes(m: int, n: int, Q: int, P: int, row_off=None, col_off=None,
                                       STORAGE[storage] | INVERSE[inverse] | (GRAM_PATCHES if gram_patches else 0),
                                       ctypes.byref(out)), "admm_workspace_bytes")
     return int(out.value)
+
+
+SPLIT_COST_KEYS = ["exchange_elements", "bytes_per_iteration", "setup_fp64_flops", "inverse_bytes", "h_bytes",
+                   "workspace_bytes", "max_block_rows", "max_block_cols", "chunks", "gram_patches"]
+
+
+def split_cost(m: int, n: int, Q: int, P: int, row_off=None, col_off=None, storage: str = "c64",
+               inverse: str = "c64", gram_patches: bool = False) -> dict:
+    ro, rp = _offsets(row_off)
+    co, cp = _offsets(col_off)
+    out = (ctypes.c_double * 16)()
+    _check(lib().admm_split_cost(m, n, Q, rp, P, cp,
+                                 STORAGE[storage] | INVERSE[inverse] | (GRAM_PATCHES if gram_patches else 0), out),
+           "admm_split_cost")
+    return {k: float(out[i]) for i, k in enumerate(SPLIT_COST_KEYS)}
+
+
+def choose_split(m: int, n: int, iters: int, storage: str = "c64", max_exchange: float = 0.0,
+                 hbm_gbs: float = 6800.0, fp64_tflops: float = 45.0, latency_us: float = 25.0):
+    """(Q, P, modelled seconds) of admm_choose_split."""
+    q, p, t = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    _check(lib().admm_choose_split(m, n, int(iters), STORAGE[storage], float(max_exchange), float(hbm_gbs),
+                                   float(fp64_tflops), float(latency_us), ctypes.byref(q), ctypes.byref(p),
+                                   ctypes.byref(t)), "admm_choose_split")
+    return int(q.value), int(p.value), float(t.value)
 
 
 def _ptr(t) -> int:

@@ -514,6 +514,96 @@ int admm_workspace_bytes(int64_t m, int64_t n, int Q, const int64_t* row_off, in
   return ADMM_OK;
 }
 
+namespace {
+// Cost model of one split (host only; see admm_split_cost).
+void split_cost(const Geometry& geo, double* out) {
+  const int64_t m = geo.m, n = geo.n;
+  const int Q = geo.Q, P = geo.P;
+  int64_t mi = 0, nj = 0;
+  for (int i = 0; i < Q; ++i) mi = std::max(mi, geo.ro[i + 1] - geo.ro[i]);
+  for (int j = 0; j < P; ++j) nj = std::max(nj, geo.co[j + 1] - geo.co[j]);
+  // elements one node sends and receives per iteration (Sec. IV, table of
+  // exchanged elements; with uneven blocks the largest ones)
+  double exch = 0.0;
+  if (Q > 1 && P == 1) exch = 2.0 * (double)n;
+  else if (Q == 1 && P > 1) exch = (double)P * (double)m;
+  else if (Q > 1 && P > 1) exch = (double)P * (double)mi + 2.0 * (double)nj;
+  // HBM bytes of one iteration: the four per-iteration kernels' algorithmic bytes
+  const double e = elem_bytes(geo.storage), c = 8.0;
+  const double h = (double)m * (double)n * e + (geo.storage == ADMM_STORAGE_FP8 ? 4.0 * (double)m * P : 0.0);
+  const double vrows = c * P * (double)m, vcols = c * Q * (double)n;
+  const bool patch = !geo.t_gpatch.empty();
+  double ginv = 0.0, parts = 0.0, flops = 0.0;
+  for (const BlockDesc& d : geo.blocks) {
+    const double T = d.mt / kTile;
+    ginv += T * (T + 1) / 2 * kTile * kTile;
+    parts += T * (patch ? std::ceil(T / 4) + 1 : T);
+    // FP64 setup: lower half of H H^H (m_i (m_i + 1) / 2 n_j complex
+    // multiply-adds), Cholesky, triangular inverse and W^H W (m_i^3 / 3 each),
+    // 8 real flops per complex multiply-add
+    const double a = d.mi, b = d.nj;
+    flops += 8.0 * (a * (a + 1) / 2 * b + a * a * a);
+  }
+  const double gemv_n = h + vcols + c * m + (P > 1 ? (P - 1) * vrows + 2 * vrows : vrows);
+  const double gram = ginv * (geo.inv16 ? 4.0 : c) + 2 * parts * kTile * c + vrows * (P > 1 ? 4 : 3);
+  const double gemv_h = h + vrows + geo.KH * vcols;
+  // more than 32 replicas do not stay in registers: the z-update reads c and
+  // the row-chunk partials a second time
+  const double zupd = geo.KH * vcols + 4 * vcols + 2 * c * n + (Q > 32 ? (geo.KH + 1) * vcols : 0.0);
+  for (int k = 0; k < 16; ++k) out[k] = 0.0;
+  out[0] = exch;
+  out[1] = gemv_n + gram + gemv_h + zupd;
+  out[2] = flops;
+  out[3] = (double)geo.lay.ginv_bytes;
+  out[4] = (double)geo.lay.h_bytes;
+  out[5] = (double)geo.lay.total;
+  out[6] = (double)mi;
+  out[7] = (double)nj;
+  out[8] = geo.KH;
+  out[9] = (double)geo.t_gpatch.size();
+}
+}  // namespace
+
+int admm_split_cost(int64_t m, int64_t n, int Q, const int64_t* row_off, int P, const int64_t* col_off, int storage,
+                    double* out16) {
+  g_last_error.clear();
+  if (!out16) return fail(ADMM_EINVAL, "out is NULL");
+  Geometry geo;
+  std::string err;
+  const int rc = build_geometry(geo, m, n, Q, row_off, P, col_off, storage, err);
+  if (rc) return fail(rc, "%s", err.c_str());
+  split_cost(geo, out16);
+  return ADMM_OK;
+}
+
+int admm_choose_split(int64_t m, int64_t n, int iters, int storage, double max_exchange, double hbm_gbs,
+                      double fp64_tflops, double latency_us, int* Q_out, int* P_out, double* model_s) {
+  g_last_error.clear();
+  if (!Q_out || !P_out) return fail(ADMM_EINVAL, "Q_out and P_out must not be NULL");
+  if (iters < 0 || !(hbm_gbs > 0.0) || !(fp64_tflops > 0.0) || !(latency_us >= 0.0))
+    return fail(ADMM_EINVAL, "iters >= 0, hbm_gbs > 0, fp64_tflops > 0 and latency_us >= 0 required");
+  static const int cand[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32};
+  double best = HUGE_VAL;
+  int bq = 0, bp = 0;
+  for (int Q : cand)
+    for (int P : cand) {
+      if (Q > m || P > n) continue;
+      Geometry geo;
+      std::string err;
+      if (build_geometry(geo, m, n, Q, nullptr, P, nullptr, storage, err) != ADMM_OK) continue;   // e.g. too tall
+      double c[16];
+      split_cost(geo, c);
+      if (max_exchange > 0.0 && c[0] > max_exchange) continue;
+      const double t = c[2] / (fp64_tflops * 1e12) + iters * (c[1] / (hbm_gbs * 1e9) + latency_us * 1e-6);
+      if (t < best) best = t, bq = Q, bp = P;
+    }
+  if (!bq) return fail(ADMM_EUNSUPPORTED, "no candidate split meets the exchange limit");
+  *Q_out = bq;
+  *P_out = bp;
+  if (model_s) *model_s = best;
+  return ADMM_OK;
+}
+
 int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, const int64_t* row_off, int P,
                const int64_t* col_off, double rho, double lambda, int storage, void* workspace,
                size_t workspace_bytes, void* stream) {

@@ -665,6 +665,8 @@ hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipS
     LAUNCH_TIMED(k_zupdate<4>, dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
   else if (a.Q <= 8)
     LAUNCH_TIMED(k_zupdate<8>, dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
+  else if (a.Q <= 32)
+    LAUNCH_TIMED(k_zupdate<32>, dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
   else
     LAUNCH_TIMED(k_zupdate<0>, dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
   return hipGetLastError();

@@ -56,12 +56,20 @@ def _case(name):
         return W.iid_problem(m=240, n=900, nnz=10, Q=2, P=3, rho=10.0, seed=23, col_off=[0, 100, 400, 900]), 150
     if name == "tall_near_limit":      # 480 x 200: just under (1 + sqrt 2) n_j
         return W.iid_problem(m=480, n=1000, nnz=10, Q=1, P=5, rho=10.0, seed=24), 150
+    # more than 8 row blocks: up to 32 replicas in registers, beyond that the
+    # z-update reads them twice
+    if name == "forty_row_blocks":     # 40 blocks of 30 rows
+        return W.iid_problem(m=1200, n=3000, nnz=10, Q=40, P=1, rho=1.0, seed=27), 100
+    if name == "many_row_blocks":      # 12 blocks of 40 rows
+        return W.iid_problem(m=480, n=2000, nnz=10, Q=12, P=1, rho=1.0, seed=25), 150
+    if name == "many_rows_and_sections":   # 10 x 2, ragged rows
+        return W.iid_problem(m=501, n=3000, nnz=10, Q=10, P=2, rho=10.0, seed=26), 150
     raise KeyError(name)
 
 
 CASES = ["consensus256x4096", "combined_uneven", "sectioning", "unsplit", "ragged_consensus",
          "cra_small", "many_sections", "wide_blocks", "tall_sectioning", "square_blocks", "mixed_tall",
-         "tall_near_limit"]
+         "tall_near_limit", "many_row_blocks", "many_rows_and_sections", "forty_row_blocks"]
 
 
 @pytest.mark.parametrize("name", CASES)

@@ -1,0 +1,89 @@
+"""The split cost model and chooser of the C ABI (host computations, no GPU):
+the exchange counts against the paper's tables (Sec. IV and VI), the bytes
+per iteration against the benchmark's own algorithmic byte count, and the
+chooser against a brute-force search over the same candidates."""
+import json
+import os
+
+import pytest
+
+import bench
+import paper_1811_05571_amd as A
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+CANDIDATES = (1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32)
+
+
+def test_exchange_counts_match_the_paper():
+    gold = json.load(open(os.path.join(GOLDEN, "tab_communications.json")))
+    m, n = gold["N_m"], gold["N_p"]
+    by = {r["name"]: r for r in gold["printed"]}
+    ex = {name: A.split_cost(m, n, r["M"], r["N"])["exchange_elements"] for name, r in by.items()}
+    assert ex["consensus"] == by["consensus"]["elements"] == 2 * n
+    assert ex["sectioning"] == by["sectioning"]["elements"] == 3 * m
+    assert round(100 * (1 - ex["sectioning"] / ex["consensus"]), 1) == by["sectioning"]["reduction_percent"]
+    # the combined entry of the example table does not follow the paper's own
+    # formula N N_m / M + 2 N_p / N = 3 * 540 + 2 * 7500 (the model keeps the formula)
+    assert ex["consensus and sectioning"] == 3 * 540 + 2 * 7500 == 16620 != by["consensus and sectioning"]["elements"]
+    assert A.split_cost(m, n, 1, 1)["exchange_elements"] == 0
+
+
+def test_column_wise_beats_row_wise_below_the_paper_bound():
+    """Sec. IV: dividing by columns exchanges less than by rows iff N N_m < 2 N_p."""
+    m, n = 2160, 22500
+    rows = A.split_cost(m, n, 4, 1)["exchange_elements"]
+    for P in (2, 10, 20, 21, 24):
+        cols = A.split_cost(m, n, 1, P)["exchange_elements"]
+        assert (cols < rows) == (P * m < 2 * n)
+
+
+@pytest.mark.parametrize("Q,P", [(4, 8), (1, 8), (4, 1), (2, 3)])
+def test_bytes_per_iteration_match_the_benchmark_count(Q, P):
+    m, n = 6144, 32000
+    c = A.split_cost(m, n, Q, P)
+    algo = bench.algorithmic_bytes(bench.block_geometry(m, n, Q, P), P, Q, int(c["chunks"]), "c64", "c64",
+                                   c["gram_patches"] > 0)
+    assert c["bytes_per_iteration"] == sum(algo.values())
+    assert c["max_block_rows"] == -(-m // Q) and c["max_block_cols"] == -(-n // P)
+
+
+def test_setup_flops_closed_form():
+    # one 100 x 300 block: 8 (m(m+1)/2 n + m^3) real flops
+    c = A.split_cost(100, 300, 1, 1)
+    assert c["setup_fp64_flops"] == 8 * (100 * 101 / 2 * 300 + 100 ** 3)
+
+
+def test_chooser_is_the_argmin_under_the_exchange_limit():
+    m, n, K = 2160, 22500, 50
+    bw, fl, lat = 6800.0, 45.0, 25.0
+    for limit in (0.0, 20000.0, 7000.0):
+        q, p, t = A.choose_split(m, n, K, max_exchange=limit, hbm_gbs=bw, fp64_tflops=fl, latency_us=lat)
+        best = None
+        for Q in CANDIDATES:
+            for P in CANDIDATES:
+                try:
+                    c = A.split_cost(m, n, Q, P)
+                except A.ADMMError:
+                    continue
+                if limit > 0 and c["exchange_elements"] > limit:
+                    continue
+                tt = c["setup_fp64_flops"] / (fl * 1e12) + K * (c["bytes_per_iteration"] / (bw * 1e9) + lat * 1e-6)
+                if best is None or tt < best[2]:
+                    best = (Q, P, tt)
+        assert (q, p) == best[:2] and t == pytest.approx(best[2], rel=1e-12)
+        if limit > 0:
+            assert A.split_cost(m, n, q, p)["exchange_elements"] <= limit
+
+
+def test_chooser_errors():
+    # the unsplit problem exchanges nothing, but 1000 x 300 is too tall for it
+    assert A.choose_split(2160, 22500, 50, max_exchange=1.0)[:2] == (1, 1)
+    with pytest.raises(A.ADMMError) as ei:
+        A.choose_split(1000, 300, 50, max_exchange=1.0)
+    assert ei.value.status == "ADMM_EUNSUPPORTED"
+    for kw in (dict(hbm_gbs=0.0), dict(fp64_tflops=-1.0), dict(latency_us=-1.0)):
+        with pytest.raises(A.ADMMError) as ei:
+            A.choose_split(2160, 22500, 50, **kw)
+        assert ei.value.status == "ADMM_EINVAL"
+    with pytest.raises(A.ADMMError):
+        A.choose_split(2160, 22500, -1)
