@@ -6,8 +6,9 @@
 //
 // Every FP64 matrix is padded to a multiple of kTile with identity rows, so
 // the tiled algorithms never see a ragged tile.  Tiles are 64 x 64 double2;
-// each workgroup (256 threads) owns one output tile and every thread a 4 x 4
-// sub-block of it.  All blocks of the split are processed by the same launch.
+// each workgroup (256 threads) owns one output tile, whose products run on
+// the FP64 matrix cores (AccM) or on vector FMAs (AccV).  All blocks of the
+// split are processed by the same launch.
 #include <algorithm>
 #include <cmath>
 
@@ -31,42 +32,113 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
 
-// acc[a][b] += sum_kk A[tr+16a][kk] * B[kk][tc+16b]
-__device__ __forceinline__ void mma_chunk(const Smem& sm, double2 (&acc)[4][4], int tr, int tc) {
-#pragma unroll 4
-  for (int kk = 0; kk < KC; ++kk) {
-    double2 av[4], bv[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      av[q] = sm.A[tr + 16 * q][kk];
-      bv[q] = sm.B[kk][tc + 16 * q];
-    }
+// Accumulators of one 64 x 64 complex tile product C += A B over K chunks of
+// KC staged in LDS (sm.A: 64 x KC, sm.B: KC x 64).  Both kinds give
+// zero(), chunk(sm) and each(fn): fn(row, col, value) once for every element
+// the calling thread holds.
+//
+// AccV: FP64 vector FMAs, thread t holds rows t/16 + 16p, columns t%16 + 16q.
+struct AccV {
+  double2 v[4][4];
+  __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        acc[p][q].x = fma(av[p].x, bv[q].x, acc[p][q].x);
-        acc[p][q].x = fma(-av[p].y, bv[q].y, acc[p][q].x);
-        acc[p][q].y = fma(av[p].x, bv[q].y, acc[p][q].y);
-        acc[p][q].y = fma(av[p].y, bv[q].x, acc[p][q].y);
-      }
+      for (int q = 0; q < 4; ++q) v[p][q] = make_double2(0.0, 0.0);
   }
-}
+  __device__ __forceinline__ void chunk(const Smem& sm) {
+    const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+#pragma unroll 4
+    for (int kk = 0; kk < KC; ++kk) {
+      double2 av[4], bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        av[q] = sm.A[tr + 16 * q][kk];
+        bv[q] = sm.B[kk][tc + 16 * q];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          v[p][q].x = fma(av[p].x, bv[q].x, v[p][q].x);
+          v[p][q].x = fma(-av[p].y, bv[q].y, v[p][q].x);
+          v[p][q].y = fma(av[p].x, bv[q].y, v[p][q].y);
+          v[p][q].y = fma(av[p].y, bv[q].x, v[p][q].y);
+        }
+    }
+  }
+  template <class Fn>
+  __device__ __forceinline__ void each(Fn fn) const {
+    const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) fn(tr + 16 * p, tc + 16 * q, v[p][q]);
+  }
+};
 
-__device__ __forceinline__ void zero_acc(double2 (&acc)[4][4]) {
+// AccM: the FP64 matrix cores (v_mfma_f64_16x16x4f64: D[16x16] += A[16x4]
+// B[4x16]; lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds D rows
+// l/16 + 4r, r = 0..3, of column l%16 -- the layout measured on gfx950).  Wave w computes the 32 x 32
+// quarter at rows 32(w/2), columns 32(w%2) as 2 x 2 blocks of 16 x 16, each
+// complex block as four real products: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
+typedef double v4d __attribute__((ext_vector_type(4)));
+struct AccM {
+  v4d re[2][2], im[2][2];
+  __device__ __forceinline__ void zero() {
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[p][q] = make_double2(0.0, 0.0);
-}
+      for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  __device__ __forceinline__ void chunk(const Smem& sm) {
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    const int r0 = 32 * (w / 2), c0 = 32 * (w % 2), i = l % 16, k = l / 16;
+#pragma unroll 2
+    for (int k4 = 0; k4 < KC; k4 += 4) {
+      double2 av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = sm.A[r0 + 16 * a + i][k4 + k];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = sm.B[k4 + k][c0 + 16 * b + i];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, re[a][b], 0, 0, 0);
+          re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[a].y, bv[b].y, re[a][b], 0, 0, 0);
+          im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, im[a][b], 0, 0, 0);
+          im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, im[a][b], 0, 0, 0);
+        }
+    }
+  }
+  template <class Fn>
+  __device__ __forceinline__ void each(Fn fn) const {
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    const int r0 = 32 * (w / 2) + l / 16, c0 = 32 * (w % 2) + l % 16;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fn(r0 + 16 * a + 4 * r, c0 + 16 * b, make_double2(re[a][b][r], im[a][b][r]));
+  }
+};
+
+#if ADMM_SETUP_MFMA
+using Acc = AccM;
+#else
+using Acc = AccV;
+#endif
+static_assert(kBlockThreads == 4 * kWave, "the tile accumulators assume four waves");
 
 // acc += opA(X) opB(Y) over one 64-wide K range of FP64 tiles.
 // X, Y point at tile origins in an ld-strided double2 matrix.
 // conjTA: use X^H instead of X.  conjTB: use Y^H instead of Y.
 template <bool conjTA, bool conjTB>
 __device__ void tile_product(Smem& sm, const double2* __restrict__ X, const double2* __restrict__ Y,
-                            int64_t ld, double2 (&acc)[4][4]) {
-  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+                            int64_t ld, Acc& acc) {
+  const int tid = threadIdx.x;
   for (int k0 = 0; k0 < T; k0 += KC) {
     __syncthreads();
     for (int e = tid; e < T * KC; e += kBlockThreads) {
@@ -76,7 +148,7 @@ __device__ void tile_product(Smem& sm, const double2* __restrict__ X, const doub
       sm.B[kb][c] = conjTB ? conjd(Y[(int64_t)c * ld + k0 + kb]) : Y[(int64_t)(k0 + kb) * ld + c];
     }
     __syncthreads();
-    mma_chunk(sm, acc, tr, tc);
+    acc.chunk(sm);
   }
 }
 
@@ -114,10 +186,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_gram_build(const int4* __rest
   const F f = MakeFmt<F>::make(hs);
   const int4 t = tiles[blockIdx.x];
   const BlockDesc d = blocks[t.x];
-  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+  const int tid = threadIdx.x;
   const int r0 = t.y * T, c0 = t.z * T;
-  double2 acc[4][4];
-  zero_acc(acc);
+  Acc acc;
+  acc.zero();
   for (int k0 = 0; k0 < d.nj; k0 += KC) {
     __syncthreads();
     for (int e = tid; e < T * KC; e += kBlockThreads) {
@@ -130,19 +202,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_gram_build(const int4* __rest
       sm.B[kb][c] = make_double2(b.x, -b.y);
     }
     __syncthreads();
-    mma_chunk(sm, acc, tr, tc);
+    acc.chunk(sm);
   }
   double2* Ab = A + d.f_off;
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = r0 + tr + 16 * p, c = c0 + tc + 16 * q;
-      double2 val = acc[p][q];
-      if (r >= d.mi || c >= d.mi) val = make_double2(r == c ? 1.0 : 0.0, 0.0);
-      else if (r == c) val.x += rho;
-      Ab[(int64_t)r * d.mt + c] = val;
-    }
+  acc.each([&](int rr, int cc, double2 val) {
+    const int r = r0 + rr, c = c0 + cc;
+    if (r >= d.mi || c >= d.mi) val = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    else if (r == c) val.x += rho;
+    Ab[(int64_t)r * d.mt + c] = val;
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -349,20 +417,16 @@ __global__ __launch_bounds__(kBlockThreads) void k_herk_trail(int k, const Block
   if (ia >= nt) return;
   const int i = k + 1 + ia, l = k + 1 + la;
   double2* Ab = A + d.f_off;
-  double2 acc[4][4];
-  zero_acc(acc);
+  Acc acc;
+  acc.zero();
   tile_product<false, true>(sm, Ab + (int64_t)(i * T) * d.mt + k * T, Ab + (int64_t)(l * T) * d.mt + k * T,
                             d.mt, acc);
-  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
   double2* C = Ab + (int64_t)(i * T) * d.mt + l * T;
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double2& o = C[(int64_t)(tr + 16 * p) * d.mt + tc + 16 * q];
-      o.x -= acc[p][q].x;
-      o.y -= acc[p][q].y;
-    }
+  acc.each([&](int r, int c, double2 v) {
+    double2& o = C[(int64_t)r * d.mt + c];
+    o.x -= v.x;
+    o.y -= v.y;
+  });
 }
 
 // W[k,k] = L[k,k]^{-1} (lower).  grid = (tiles of the largest block, blocks).
@@ -417,19 +481,16 @@ __global__ __launch_bounds__(kBlockThreads) void k_trtri_off(int dist, const Blo
   const BlockDesc d = blocks[blockIdx.y];
   const int k = blockIdx.x, i = k + dist;
   if (i * T >= d.mt) return;
-  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+  const int tid = threadIdx.x;
   const double2* Ab = A + d.f_off;
   double2* Wb = W + d.f_off;
-  double2 acc[4][4];
-  zero_acc(acc);
+  Acc acc;
+  acc.zero();
   for (int l = k; l < i; ++l)
     tile_product<false, false>(sm, Ab + (int64_t)(i * T) * d.mt + l * T, Wb + (int64_t)(l * T) * d.mt + k * T,
                                d.mt, acc);
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) Sx[tr + 16 * p][tc + 16 * q] = acc[p][q];
-  zero_acc(acc);
+  acc.each([&](int r, int c, double2 v) { Sx[r][c] = v; });
+  acc.zero();
   const double2* Wii = Wb + (int64_t)(i * T) * d.mt + i * T;
   for (int k0 = 0; k0 < T; k0 += KC) {
     __syncthreads();
@@ -440,14 +501,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_trtri_off(int dist, const Blo
       sm.B[kb][c] = Sx[k0 + kb][c];
     }
     __syncthreads();
-    mma_chunk(sm, acc, tr, tc);
+    acc.chunk(sm);
   }
   double2* C = Wb + (int64_t)(i * T) * d.mt + k * T;
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      C[(int64_t)(tr + 16 * p) * d.mt + tc + 16 * q] = make_double2(-acc[p][q].x, -acc[p][q].y);
+  acc.each([&](int r, int c, double2 v) { C[(int64_t)r * d.mt + c] = make_double2(-v.x, -v.y); });
 }
 
 // G^{-1} = W^H W: tile (i,l), l <= i, = sum_{k>=i} W[k,i]^H W[k,l], written as
@@ -462,21 +519,16 @@ __global__ __launch_bounds__(kBlockThreads) void k_lauum(const int4* __restrict_
   const BlockDesc d = blocks[t.x];
   const int i = t.y, l = t.z, nt = d.mt / T;
   const double2* Wb = W + d.f_off;
-  double2 acc[4][4];
-  zero_acc(acc);
+  Acc acc;
+  acc.zero();
   for (int k = i; k < nt; ++k)
     tile_product<true, false>(sm, Wb + (int64_t)(k * T) * d.mt + i * T, Wb + (int64_t)(k * T) * d.mt + l * T,
                               d.mt, acc);
-  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
   float2* G = Ginv + d.gi_off + (int64_t)(i * (i + 1) / 2 + l) * (T * T);
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int rr = tr + 16 * p, cc = tc + 16 * q;
-      const bool in = i * T + rr < d.mi && l * T + cc < d.mi;
-      G[rr * T + cc] = in ? make_float2((float)acc[p][q].x, (float)acc[p][q].y) : make_float2(0.f, 0.f);
-    }
+  acc.each([&](int rr, int cc, double2 v) {
+    const bool in = i * T + rr < d.mi && l * T + cc < d.mi;
+    G[rr * T + cc] = in ? make_float2((float)v.x, (float)v.y) : make_float2(0.f, 0.f);
+  });
 }
 
 }  // namespace

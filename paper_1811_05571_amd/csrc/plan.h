@@ -106,6 +106,9 @@ constexpr int kEpiSections = 7;  // other sections whose estimates the row epilo
 #ifndef ADMM_WHOLE_N_FP8
 #define ADMM_WHOLE_N_FP8 8      // the same for fp8
 #endif
+#ifndef ADMM_SETUP_MFMA
+#define ADMM_SETUP_MFMA 1       // FP64 setup tile products on the matrix cores (0: vector FMAs)
+#endif
 #ifndef ADMM_GRAM_PATCH
 #define ADMM_GRAM_PATCH 1       // complex64 inverses applied in 4 x 4 tile patches
 #endif
