@@ -33,8 +33,9 @@ Pins (tests/test_oracle_*.py): prox characterisation of S by brute force,
 inversion lemma vs direct solve, unitary-H closed form, lasso KKT at the
 fixed point, equality of the limits of all splittings and an independent
 FISTA minimiser, the lambda >= max|H^H g| zero solution, textbook lasso ADMM
-for Q=P=1, the real special case against scikit-learn's Lasso, and the
-block shapes of the paper's timing table.
+for Q=P=1, the real special case against scikit-learn's Lasso, the block
+shapes of the paper's timing table, the stop rule on states with hand-computed
+norms, and the push-through form against the literal one.
 """
 
 from __future__ import annotations
@@ -176,33 +177,116 @@ def step(H, g, row_off, col_off, rho, lam, blocks, st: State):
     return State(st.k + 1, u_new, v_new, s_new, ghat_new), rp2, rd2
 
 
+# --------------------------------------------------------------------------
+# The same iteration in push-through form (for timing on the host)
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class PushBlock:
+    """x-update of one block with two products per iteration.
+
+    With G = rho I + H H^* the inversion lemma (eq. inversion_lemma3) turns
+    the x-update of eq. x_solution_rows_columns, for c = v_j - s_j^i, into
+        y = G^{-1} (g' - H c),    u = c + H^* y,
+    and since H H^* = G - rho I the estimated data is H u = g' - rho y.  One
+    product with H, one Cholesky solve with G and one product with H^* per
+    iteration, against three products and a solve in the literal form.
+    Blocks with m_b >= n_b keep the direct factor of H^*H + rho I and form
+    H u explicitly, as the literal form does.
+    """
+    H: np.ndarray
+    rho: float
+    wide: bool
+    factor: tuple
+
+    @classmethod
+    def build(cls, H: np.ndarray, rho: float) -> "PushBlock":
+        mb, nb = H.shape
+        if mb < nb:
+            G = H @ H.conj().T + rho * np.eye(mb, dtype=np.complex128)
+            return cls(H, rho, True, sla.cho_factor(G, lower=True))
+        B = H.conj().T @ H + rho * np.eye(nb, dtype=np.complex128)
+        return cls(H, rho, False, sla.cho_factor(B, lower=True))
+
+    def adjoint(self, y: np.ndarray) -> np.ndarray:
+        """H^* y, as the conjugate of y^* H (no conjugated copy of H is formed)."""
+        return np.conj(np.conj(y) @ self.H)
+
+    def update(self, gp: np.ndarray, c: np.ndarray):
+        """(u, H u) for local data gp and c = v_j - s_j^i."""
+        H = self.H
+        if self.wide:
+            y = sla.cho_solve(self.factor, gp - H @ c)
+            return c + self.adjoint(y), gp - self.rho * y
+        u = sla.cho_solve(self.factor, self.adjoint(gp) + self.rho * c)
+        return u, H @ u
+
+
+def setup_push_through(H: np.ndarray, row_off: np.ndarray, col_off: np.ndarray, rho: float):
+    H = np.asarray(H, dtype=np.complex128)
+    Q, P = len(row_off) - 1, len(col_off) - 1
+    return [[PushBlock.build(H[row_off[i]:row_off[i + 1], col_off[j]:col_off[j + 1]].copy(), rho)
+             for j in range(P)] for i in range(Q)]
+
+
+def step_push_through(g, row_off, col_off, rho, lam, pblocks, st: State):
+    """The iteration of step() with the x-update of PushBlock (same order,
+    same Jacobi local data, same z- and dual updates)."""
+    g = np.asarray(g, dtype=np.complex128)
+    Q, P = len(row_off) - 1, len(col_off) - 1
+    u_new = np.empty_like(st.u)
+    ghat_new = np.empty_like(st.ghat)
+    for i in range(Q):
+        r0, r1 = row_off[i], row_off[i + 1]
+        total = st.ghat[:, r0:r1].sum(axis=0)
+        for j in range(P):
+            c0, c1 = col_off[j], col_off[j + 1]
+            gp = g[r0:r1] - (total - st.ghat[j, r0:r1]) if P > 1 else g[r0:r1]
+            u, hu = pblocks[i][j].update(gp, st.v[c0:c1] - st.s[i, c0:c1])
+            u_new[i, c0:c1] = u
+            ghat_new[j, r0:r1] = hu
+    kappa = lam / (Q * rho)
+    v_new = soft_threshold(u_new.mean(axis=0) + st.s.mean(axis=0), kappa)
+    s_new = st.s + u_new - v_new[None, :]
+    rp2 = float(np.sum(np.abs(u_new - v_new[None, :]) ** 2))
+    rd2 = float(rho ** 2 * Q * np.sum(np.abs(v_new - st.v) ** 2))
+    return State(st.k + 1, u_new, v_new, s_new, ghat_new), rp2, rd2
+
+
 def converged(st: State, rp2: float, rd2: float, rho: float, tol: float) -> bool:
     """Relative stopping rule (absolute tolerance zero):
     |r_p| <= tol max(|(u^i)|, sqrt(Q)|v|) and |r_d| <= tol rho |(s^i)|."""
     Q = st.u.shape[0]
     pri = tol * max(np.linalg.norm(st.u), np.sqrt(Q) * np.linalg.norm(st.v))
     dual = tol * rho * np.linalg.norm(st.s)
-    return np.sqrt(rp2) <= pri and np.sqrt(rd2) <= dual
+    return bool(np.sqrt(rp2) <= pri and np.sqrt(rd2) <= dual)
 
 
 def solve(H, g, Q: int, P: int, rho: float, lam: float, iters: int, row_off=None, col_off=None,
-          tol: float = 0.0, check_every: int = 10, state: State | None = None, blocks=None):
+          tol: float = 0.0, check_every: int = 10, state: State | None = None, blocks=None,
+          form: str = "literal"):
     """Run up to `iters` iterations from `state` (zeros by default).
 
     Returns (v, history (k, 2) of [|r_p|^2, |r_d|^2], final state).
     With tol <= 0 exactly `iters` iterations run; otherwise the stop rule is
-    tested after every `check_every`-th iteration.
+    tested after every `check_every`-th iteration.  form="push_through" runs
+    step_push_through (two products per block and iteration) instead of the
+    literal step; `blocks` must then come from setup_push_through.
     """
+    if form not in ("literal", "push_through"):
+        raise ValueError("form must be 'literal' or 'push_through'")
     H = np.asarray(H, dtype=np.complex128)
     m, n = H.shape
     ro = split_offsets(m, Q, row_off)
     co = split_offsets(n, P, col_off)
     if blocks is None:
-        blocks = setup(H, ro, co, rho)
+        blocks = (setup if form == "literal" else setup_push_through)(H, ro, co, rho)
     st = state.copy() if state is not None else State.zeros(m, n, Q, P)
     hist = []
     for it in range(iters):
-        st, rp2, rd2 = step(H, g, ro, co, rho, lam, blocks, st)
+        if form == "literal":
+            st, rp2, rd2 = step(H, g, ro, co, rho, lam, blocks, st)
+        else:
+            st, rp2, rd2 = step_push_through(g, ro, co, rho, lam, blocks, st)
         hist.append((rp2, rd2))
         if tol > 0 and (it + 1) % check_every == 0 and converged(st, rp2, rd2, rho, tol):
             break
@@ -226,12 +310,6 @@ def kkt_violation(H, g, v, lam: float) -> float:
     viol = np.maximum(np.abs(z) - lam, 0.0)
     viol[on] = np.abs(z[on] - lam * v[on] / mag[on])
     return float(np.max(viol) / lam)
-
-
-def objective(H, g, v, lam: float) -> float:
-    H = np.asarray(H, dtype=np.complex128)
-    r = H @ np.asarray(v, dtype=np.complex128) - np.asarray(g, dtype=np.complex128)
-    return float(0.5 * np.vdot(r, r).real + lam * np.sum(np.abs(v)))
 
 
 def lambda_max(H, g) -> float:

@@ -480,4 +480,94 @@ __device__ __forceinline__ float2 ordered_sum(const float2* __restrict__ p, int 
   return make_float2(ar, ai);
 }
 
+
+// Final FP64 sums of the previous z-update's per-workgroup partials: each
+// thread adds the partials b = tid, tid + 256, ... in order, then a fixed
+// shuffle tree and a fixed wave order; writes the residual history entry and
+// advances the iteration counter.  Run by one whole workgroup of 256 threads
+// of the next kernel on the stream, so no fence or ticket is needed.
+__device__ void zfinal(const IterArgs& a, double (&red)[kBlockThreads / kWave][kRedCount]) {
+  if (a.ctl->zpending == 0) return;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  double tot[kRedCount] = {0, 0, 0, 0, 0};
+  for (int b = tid; b < a.nz; b += kBlockThreads) {
+#pragma unroll
+    for (int q = 0; q < kRedCount; ++q) tot[q] += a.redpart[(int64_t)b * kRedCount + q];
+  }
+#pragma unroll
+  for (int q = 0; q < kRedCount; ++q) tot[q] = wave_sum_d(tot[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < kRedCount; ++q) red[wave][q] = tot[q];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double r[kRedCount];
+#pragma unroll
+    for (int q = 0; q < kRedCount; ++q) {
+      r[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+      a.ctl->red[q] = r[q];
+    }
+    const int it = a.ctl->iter;
+    if (a.hist) {
+      a.hist[2 * (int64_t)it] = r[kRedRp2];
+      a.hist[2 * (int64_t)it + 1] = r[kRedDv2] * a.rho2Q;
+    }
+    a.ctl->iter = it + 1;
+    a.ctl->zpending = 0;
+  }
+}
+
+// Operands of one row's epilogue: the row scale, g, and the other sections'
+// estimated data when they fit kEpiSections registers (else read at the end).
+struct RowEpi {
+  float sc;
+  float2 g;
+  float2 e[kEpiSections];
+  bool pre;
+};
+template <class F>
+__device__ __forceinline__ void row_epi_load(const IterArgs& a, const BlockDesc& d, const F& f, int lr, RowEpi& o) {
+  o.sc = f.row_scale(d.row0 + lr);
+  o.g = a.g[d.row0 + lr];
+  o.pre = a.P - 1 <= kEpiSections;
+#pragma unroll
+  for (int q = 0; q < kEpiSections; ++q) {
+    const int sec = q < d.j ? q : q + 1;             // the other sections in order
+    o.e[q] = (o.pre && sec < a.P) ? a.ghat[(int64_t)sec * a.m_pad + d.rpad0 + lr] : make_float2(0.f, 0.f);
+  }
+}
+// r_ij = g'_ij - s (H c) for row lr of block (i, j), with (ar, ai) the row's
+// product; eq. g_rows_columns: g'_ij = g_i minus the other sections'
+// estimated data (compensated sums, sections in order), stored when P > 1.
+__device__ __forceinline__ void row_epi_store(const IterArgs& a, const BlockDesc& d, int lr, float ar, float ai,
+                                              const RowEpi& o) {
+  const int64_t vi = (int64_t)d.j * a.m_pad + d.rpad0 + lr;
+  float2 gpv = o.g;
+  if (a.P > 1) {
+    CSum sr, si;
+    sr.add(gpv.x);
+    si.add(gpv.y);
+    if (o.pre) {
+#pragma unroll
+      for (int q = 0; q < kEpiSections; ++q) {
+        if (q < a.P - 1) {
+          sr.add(-o.e[q].x);
+          si.add(-o.e[q].y);
+        }
+      }
+    } else {
+      for (int q = 0; q < a.P; ++q) {
+        if (q == d.j) continue;
+        const float2 e = a.ghat[(int64_t)q * a.m_pad + d.rpad0 + lr];
+        sr.add(-e.x);
+        si.add(-e.y);
+      }
+    }
+    gpv = make_float2(sr.value(), si.value());
+    a.gp[vi] = gpv;
+  }
+  a.r[vi] = make_float2(fmaf(-o.sc, ar, gpv.x), fmaf(-o.sc, ai, gpv.y));
+}
+
 }  // namespace admm

@@ -294,3 +294,85 @@ def test_uneven_split_offsets():
         O.split_offsets(10, 3, [0, 5, 5, 10])
     with pytest.raises(ValueError):
         O.split_offsets(3, 4)
+
+
+# --------------------------------------------------------------------------
+# stop rule (relative tolerance) on states whose norms are known by hand
+# --------------------------------------------------------------------------
+def _uniform_state(Q, n, u, v, s):
+    """Every replica entry u, every image entry v, every dual entry s."""
+    st = O.State.zeros(1, n, Q, 1)
+    st.u[:] = u
+    st.v[:] = v
+    st.s[:] = s
+    return st
+
+
+def test_stop_rule_on_hand_computed_norms():
+    # Q = 2 replicas of n = 4 entries.  u = 3, v = 4, s = 1 (rho = 2):
+    #   |(u^i)| = sqrt(2*4*9) = 6 sqrt 2,  sqrt(Q)|v| = sqrt 2 * sqrt(4*16) = 8 sqrt 2
+    #   primal scale = tol * 8 sqrt 2,  |(s^i)| = sqrt 8 = 2 sqrt 2,  dual scale = tol * 2 * 2 sqrt 2
+    # With |r_p|^2 = 8 (|r_p| = 2 sqrt 2) the primal test holds iff tol >= 1/4;
+    # with |r_d|^2 = 8 the dual test holds iff tol >= 1/2.
+    st = _uniform_state(2, 4, 3.0, 4.0, 1.0)
+    for tol, want in [(0.2, False), (0.3, False), (0.49, False), (0.51, True), (2.0, True)]:
+        assert O.converged(st, 8.0, 8.0, 2.0, tol) is want, tol
+    # the dual test alone decides when the primal residual is zero
+    assert O.converged(st, 0.0, 8.0, 2.0, 0.49) is False
+    assert O.converged(st, 0.0, 8.0, 2.0, 0.51) is True
+    # and the primal test alone when the dual residual is zero: tol >= 1/4
+    assert O.converged(st, 8.0, 0.0, 2.0, 0.24) is False
+    assert O.converged(st, 8.0, 0.0, 2.0, 0.26) is True
+
+
+def test_stop_rule_takes_the_larger_primal_scale():
+    # u = 5, v = 1 (Q = 3, n = 2): |(u^i)| = sqrt(3*2*25) = 5 sqrt 6 beats
+    # sqrt(3)|v| = sqrt 3 * sqrt 2 = sqrt 6.  |r_p|^2 = 6 (|r_p| = sqrt 6):
+    # primal holds iff tol >= 1/5 (with the smaller scale it would need tol >= 1).
+    st = _uniform_state(3, 2, 5.0, 1.0, 1.0)
+    assert O.converged(st, 6.0, 0.0, 1.0, 0.19) is False
+    assert O.converged(st, 6.0, 0.0, 1.0, 0.21) is True
+    # the complex modulus counts, not the real part: u = 3 + 4j has |u| = 5
+    st2 = _uniform_state(3, 2, 3.0 + 4.0j, 1.0, 1.0)
+    assert O.converged(st2, 6.0, 0.0, 1.0, 0.21) is True
+
+
+def test_solve_stops_at_the_first_check_that_passes():
+    H, g, lam = _random_problem(12)
+    Q, P, rho, tol, every = 2, 2, 4.0, 1e-3, 7
+    m, n = H.shape
+    v, hist, st = O.solve(H, g, Q, P, rho, lam, 400, tol=tol, check_every=every)
+    k = len(hist)
+    assert 0 < k < 400 and k % every == 0
+    # replay the same iterations: the rule holds at iteration k and fails at
+    # every earlier multiple of check_every
+    ro, co = O.split_offsets(m, Q), O.split_offsets(n, P)
+    blocks = O.setup(H, ro, co, rho)
+    s2 = O.State.zeros(m, n, Q, P)
+    for it in range(1, k + 1):
+        s2, rp2, rd2 = O.step(H, g, ro, co, rho, lam, blocks, s2)
+        if it % every == 0:
+            assert O.converged(s2, rp2, rd2, rho, tol) is (it == k)
+    assert np.array_equal(s2.v, v)
+
+
+# --------------------------------------------------------------------------
+# push-through form of the x-update against the literal one
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n,Q,P,rho,ro", [
+    (48, 160, 1, 1, 1.0, None),       # unsplit, wide
+    (48, 160, 4, 1, 1.0, None),       # consensus
+    (48, 160, 1, 3, 6.0, None),       # sectioning
+    (48, 160, 3, 2, 4.0, None),       # combined
+    (60, 40, 2, 2, 8.0, None),        # tall blocks 30 x 20 (direct factor)
+    (50, 90, 2, 3, 9.0, [0, 35, 50]), # uneven rows: 35 x 30 tall beside 15 x 30 wide
+])
+def test_push_through_form_matches_literal(m, n, Q, P, rho, ro):
+    H, g, lam = _random_problem(13, m=m, n=n)
+    v1, h1, s1 = O.solve(H, g, Q, P, rho, lam, 40, row_off=ro)
+    v2, h2, s2 = O.solve(H, g, Q, P, rho, lam, 40, row_off=ro, form="push_through")
+    scale = max(1.0, np.linalg.norm(v1))
+    assert np.linalg.norm(v2 - v1) <= 1e-12 * scale
+    assert np.linalg.norm(s2.s - s1.s) <= 1e-12 * max(1.0, np.linalg.norm(s1.s))
+    assert np.linalg.norm(s2.ghat - s1.ghat) <= 1e-12 * max(1.0, np.linalg.norm(s1.ghat))
+    np.testing.assert_allclose(h2, h1, rtol=1e-9, atol=1e-24)
