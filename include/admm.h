@@ -262,6 +262,26 @@ int admm_kkt(admm_plan* plan, const void* g, const void* v, double* out,
              void* stream);
 
 /*
+ * admm_kkt_noalloc -- admm_kkt for callers that cannot allocate device memory
+ * at the call (code near HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): the same check and result, but its scratch (v in the
+ * padded column space, the FP64 residual, the FP64 adjoint partials and the
+ * per-workgroup maxima) lives in one static device array of the library,
+ * 16 MiB per GPU, held until the process ends, instead of in the plan's
+ * workspace.  It calls no allocating routine.  All calls on one GPU share
+ * that array: calls that overlap in time on one GPU (two streams, two
+ * threads) race and must be serialised by the caller.
+ *   Arguments, synchronisation and result as admm_kkt.
+ *   Errors: EINVAL, EHIP; EWORKSPACE when the plan's check needs more than
+ *   the 16 MiB: 8 n_pad + 16 m + 16 n_pad Q KH + 8 T bytes, each term
+ *   rounded up to 256 (n_pad, KH = "chunks" of admm_plan_info, T = 64-column
+ *   tiles of the column blocks); 6144 x 32000 with Q = 4, P = 8 needs
+ *   8.8 MB.  EUNSUPPORTED on a device index of 64 or more.
+ */
+int admm_kkt_noalloc(admm_plan* plan, const void* g, const void* v, double* out,
+                     void* stream);
+
+/*
  * admm_hty_absmax -- ||H^H g||_inf over the stored H, accumulated in FP64:
  * the scale of the regularisation weight (the lasso minimiser is 0 for
  * lambda >= ||H^H g||_inf; workloads set lambda as a fraction of it).  Uses

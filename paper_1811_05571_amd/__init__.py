@@ -49,6 +49,7 @@ SIGNATURES = [
     ("admm_get_state", _int, [_vp, _vp, _vp, _vp, _c.POINTER(_int), _vp]),
     ("admm_set_state", _int, [_vp, _vp, _vp, _vp, _int, _vp]),
     ("admm_kkt", _int, [_vp, _vp, _vp, _c.POINTER(_dbl), _vp]),
+    ("admm_kkt_noalloc", _int, [_vp, _vp, _vp, _c.POINTER(_dbl), _vp]),
     ("admm_hty_absmax", _int, [_vp, _vp, _c.POINTER(_dbl), _vp]),
     ("admm_get_stored_h", _int, [_vp, _vp, _vp, _vp, _vp]),
     ("admm_profile", _int, [_vp, _int]),
@@ -262,6 +263,14 @@ class Plan:
         out = ctypes.c_double(0.0)
         _check(lib().admm_kkt(self._h, _ptr(g), _ptr(v), ctypes.byref(out),
                               _stream(self.torch, self.device)), "admm_kkt")
+        return float(out.value)
+
+    def kkt_noalloc(self, g, v) -> float:
+        """kkt() with the library's static device scratch instead of the
+        plan's workspace (admm_kkt_noalloc)."""
+        out = ctypes.c_double(0.0)
+        _check(lib().admm_kkt_noalloc(self._h, _ptr(g), _ptr(v), ctypes.byref(out),
+                                      _stream(self.torch, self.device)), "admm_kkt_noalloc")
         return float(out.value)
 
     def hty_absmax(self, g) -> float:

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -310,6 +311,37 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
 }
 
 }  // namespace admm
+
+// Device scratch of admm_kkt_noalloc: one array per GPU, held until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address on the current GPU comes from hipGetSymbolAddress (static_scratch).
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call per device and kept.
+int static_scratch(char** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(ADMM_EUNSUPPORTED, "device %d is beyond the %d devices of the static scratch table", dev,
+                kScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(ADMM_EHIP, "hipGetSymbolAddress returned no address for the static scratch");
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return ADMM_OK;
+}
+}  // namespace
 
 struct admm_plan {
   Geometry geo;
@@ -992,6 +1024,41 @@ int admm_kkt(admm_plan* p, const void* g, const void* v, double* out, void* stre
   HIP_TRY(launch_kkt_all(p->d_blocks, p->d_cols, p->row_block, p->t_kadj, (int)G.t_kadj.size(), p->t_z,
                          (int)G.t_z.size(), G.m, G.n_pad, G.Q, G.P, G.KH, p->hs, static_cast<const float2*>(g),
                          p->kkt_v, p->lam, p->kkt_e, p->kkt_part, p->kkt_max, p->ctl, st));
+  Control hc;
+  HIP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *out = hc.kkt / p->lam;
+  return ADMM_OK;
+}
+
+int admm_kkt_noalloc(admm_plan* p, const void* g, const void* v, double* out, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(ADMM_EINVAL, "plan is NULL");
+  if (!g || !v || !out) return fail(ADMM_EINVAL, "g, v and out must not be NULL");
+  if (!(p->lam > 0.0)) return fail(ADMM_EINVAL, "the KKT check needs lambda > 0");
+  const Geometry& G = p->geo;
+  // the scratch admm_kkt takes from the plan's workspace: v in the padded
+  // column space, the FP64 residual g - H v, the FP64 adjoint partials per
+  // row chunk and replica, one maximum per final workgroup.  Every entry a
+  // kernel reads was written earlier in the same call, so nothing is cleared.
+  const size_t colv = (size_t)G.n_pad * 8;
+  const size_t off_e = align256(colv);
+  const size_t off_part = off_e + align256(16 * (size_t)G.m);
+  const size_t off_max = off_part + align256(2 * colv * (size_t)G.Q * (size_t)G.KH);
+  const size_t need = off_max + align256(8 * G.t_z.size());
+  if (need > kStaticScratchBytes)
+    return fail(ADMM_EWORKSPACE, "the KKT check of this plan needs %zu bytes of scratch; the static scratch holds %zu",
+                need, kStaticScratchBytes);
+  char* sb = nullptr;
+  int rc = static_scratch(&sb);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float2* vpad = reinterpret_cast<float2*>(sb);
+  HIP_TRY(launch_unpad_cols(p->d_cols, G.P, G.n, static_cast<const float2*>(v), vpad, 0, 0, 1, 1, st));
+  HIP_TRY(launch_kkt_all(p->d_blocks, p->d_cols, p->row_block, p->t_kadj, (int)G.t_kadj.size(), p->t_z,
+                         (int)G.t_z.size(), G.m, G.n_pad, G.Q, G.P, G.KH, p->hs, static_cast<const float2*>(g), vpad,
+                         p->lam, reinterpret_cast<double2*>(sb + off_e), reinterpret_cast<double2*>(sb + off_part),
+                         reinterpret_cast<double*>(sb + off_max), p->ctl, st));
   Control hc;
   HIP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
