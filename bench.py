@@ -34,7 +34,7 @@ PROFILE_EVERY = 10      # kernel events on every 10th iteration of the timed reg
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-ITER_SOURCES = ("k_iter.hip", "gemv.h", "hstore.h", "common.h", "plan.h")
+ITER_SOURCES = ("k_iter.hip", "k_fused.hip", "gemv.h", "hstore.h", "common.h", "plan.h")
 
 
 def kernel_source_hash() -> str:
@@ -50,11 +50,13 @@ ELEM_BYTES = {"c64": 8, "bf16": 4, "fp8": 2}   # stored bytes per complex elemen
 
 
 def algorithmic_bytes(geo: dict, P: int, Q: int, KH: int, storage: str = "c64", inverse: str = "c64",
-                      patches: bool = False) -> dict:
+                      patches: bool = False, slab_wgs: int = 0) -> dict:
     """Bytes each kernel must move per launch, from the kernel's definition
     (not from counters).  Vectors are complex64 (8 B); H elements take
     ELEM_BYTES[storage] (+ 4 B per row of fp8 scales); inverse entries 8 B
-    (4 B for the bfloat16 copy)."""
+    (4 B for the bfloat16 copy).  slab_wgs: workgroups of the single-pass
+    slab kernel, each of which writes (and the row kernel reads) its part of
+    H c for every row."""
     m, n = geo["m"], geo["n"]
     ginv = geo["ginv_packed"]     # complex elements of the packed lower-tile inverses
     # 64-vectors of Gram-apply pieces (written once, read once): one per tile
@@ -68,7 +70,22 @@ def algorithmic_bytes(geo: dict, P: int, Q: int, KH: int, storage: str = "c64", 
     gram = ginv * (4 if inverse == "bf16" else c) + 2 * gparts * 64 * c + vec_rows * (4 if P > 1 else 3)
     gemv_h = h + vec_rows + KH * vec_cols
     zupd = KH * vec_cols + 2 * vec_cols * 2 + 2 * n * c
-    return {"k_gemv_n": gemv_n, "k_gram": gram, "k_gemv_h": gemv_h, "k_zupdate": zupd}
+    parts = slab_wgs * m * c
+    # single pass: H once, y of every column block, c and s read and written,
+    # v read and written, the row parts written; the row kernel reads the
+    # parts, g and the other sections' estimates, and writes r (and g')
+    fz_slab = h + vec_rows + 4 * vec_cols + 2 * n * c + parts
+    fz_rows = parts + m * c + (P - 1) * vec_rows * (P > 1) + vec_rows * (2 if P > 1 else 1)
+    return {"k_gemv_n": gemv_n, "k_gram": gram, "k_gemv_h": gemv_h, "k_zupdate": zupd,
+            "k_fz_rows": fz_rows, "k_fz_slab": fz_slab}
+
+
+def iteration_bytes(algo: dict, info: dict) -> int:
+    """Algorithmic bytes of one iteration on the plan's path (single pass:
+    row kernel, Gram apply, slab kernel; else the four two-pass kernels)."""
+    names = (("k_fz_rows", "k_gram", "k_fz_slab") if info.get("single_pass")
+             else ("k_gemv_n", "k_gram", "k_gemv_h", "k_zupdate"))
+    return int(sum(algo[k] for k in names))
 
 
 def load_traffic(kernel: str, workload: str):
@@ -90,7 +107,8 @@ def load_traffic(kernel: str, workload: str):
 COPY_PROBE_KERNEL = "neg_kernel"   # torch's elementwise negation: reads and writes N bytes
 # per-iteration kernels as named in the counter output -> bench names, per storage
 TRACE_NAMES = {
-    "c64": {"k_gemv_n<FmtC64>": "k_gemv_n", "k_gemv_nw<FmtC64>": "k_gemv_n", "k_gemv_h<FmtC64>": "k_gemv_h"},
+    "c64": {"k_gemv_n<FmtC64>": "k_gemv_n", "k_gemv_nw<FmtC64>": "k_gemv_n", "k_gemv_h<FmtC64>": "k_gemv_h",
+            "k_fz_slab<FmtC64>": "k_fz_slab", "k_fz_rows<FmtC64>": "k_fz_rows"},
     "bf16": {"k_gemv_n<FmtBF16>": "k_gemv_n", "k_gemv_nw<FmtBF16>": "k_gemv_n", "k_gemv_h<FmtBF16>": "k_gemv_h"},
     "fp8": {"k_gemv_n<FmtFP8>": "k_gemv_n", "k_gemv_nw<FmtFP8>": "k_gemv_n", "k_gemv_h<FmtFP8>": "k_gemv_h"},
 }
@@ -263,14 +281,14 @@ def bench_full_splits(args, torch, A, prob, H, g, steps: int = 300, warmup: int 
         el = time.perf_counter() - t0
         info = plan.info()
         algo = algorithmic_bytes(block_geometry(prob.m, prob.n, Q, P), P, Q, info["chunks"], "c64", "c64",
-                                 info["gram_patches"] > 0)
+                                 info["gram_patches"] > 0, info["slab_workgroups"])
         vn = v.cpu().numpy()
         hs = hist.cpu().numpy()
         mi, nj = -(-prob.m // Q), -(-prob.n // P)
         rows.append({
             "split": f"{Q}x{P}", "block": f"{mi}x{nj}", "value": round(steps / el, 1), "unit": "iters/s",
-            "setup_ms": round(setup * 1e3, 1), "iteration_gbs": round(sum(algo.values()) * steps / el / 1e9, 1),
-            "algo_bytes_per_iteration": int(sum(algo.values())), "inverse_gb": round(info["ginv_bytes"] / 1e9, 3),
+            "setup_ms": round(setup * 1e3, 1), "iteration_gbs": round(iteration_bytes(algo, info) * steps / el / 1e9, 1),
+            "algo_bytes_per_iteration": iteration_bytes(algo, info), "single_pass": info["single_pass"], "inverse_gb": round(info["ginv_bytes"] / 1e9, 3),
             "nmse_vs_truth": float(np.linalg.norm(vn - prob.u_true) ** 2 / np.linalg.norm(prob.u_true) ** 2),
             "residuals_last": [float(x) for x in hs[-1]],
             "iter_us": round(el / steps * 1e6, 1), **split_model(A, prob.m, prob.n, Q, P),
@@ -321,7 +339,7 @@ def bench_paper_table(args, torch, A, W, dev, reps: int = 5):
         it = float(np.median(times))
         info = plan.info()
         algo = algorithmic_bytes(block_geometry(p.m, p.n, Q, P), P, Q, info["chunks"], "c64", "c64",
-                                 info["gram_patches"] > 0)
+                                 info["gram_patches"] > 0, info["slab_workgroups"])
         vn = v.cpu().numpy()
         hs = hist.cpu().numpy()
         mi, nj = -(-p.m // Q), -(-p.n // P)
@@ -329,7 +347,8 @@ def bench_paper_table(args, torch, A, W, dev, reps: int = 5):
             "split": f"{Q}x{P}", "block": f"{mi}x{nj}", "inverse": f"{mi}x{mi}",
             "setup_ms": round(setup * 1e3, 2), "iters_ms": round(it * 1e3, 3),
             "total_ms": round((setup + it) * 1e3, 2), "iters_per_s": round(K / it, 1),
-            "iteration_gbs": round(sum(algo.values()) * K / it / 1e9, 1),
+            "iteration_gbs": round(iteration_bytes(algo, info) * K / it / 1e9, 1),
+            "single_pass": info["single_pass"],
             "nmse_vs_truth": float(np.linalg.norm(vn - p.u_true) ** 2 / np.linalg.norm(p.u_true) ** 2),
             "residuals_first_last": [[float(x) for x in hs[0]], [float(x) for x in hs[-1]]],
             **split_model(A, p.m, p.n, Q, P),
@@ -551,9 +570,12 @@ def main(argv=None):
             plan.solve(g, steps)
         prof = {A.KERNEL_NAMES[k]: plan.profile_read(k) for k in A.KERNEL_NAMES}
         plan.profile(False)
-        algo = algorithmic_bytes(geo, prob.P, prob.Q, info["chunks"], storage, inverse, info["gram_patches"] > 0)
+        algo = algorithmic_bytes(geo, prob.P, prob.Q, info["chunks"], storage, inverse, info["gram_patches"] > 0,
+                                 info["slab_workgroups"])
         kern = {}
         for name, (ms, cnt) in prof.items():
+            if cnt == 0:
+                continue
             avg_ms = ms / max(cnt, 1)
             kern[name] = {"avg_us": round(avg_ms * 1e3, 3), "launches": cnt, "algo_bytes": algo[name],
                           "gbs": round(algo[name] / (avg_ms * 1e-3) / 1e9, 1)}
@@ -567,7 +589,7 @@ def main(argv=None):
                          "unit": "GB/s", "frac": round(dk["gbs"] / HBM_PEAK_GBS, 4),
                          "traffic": load_traffic(dominant, f"{workload}_{storage}") if inverse == "c64" else None,
                          "algo_bytes_per_launch": dk["algo_bytes"], "avg_launch_us": dk["avg_us"]},
-            "iteration_gbs": round(sum(algo.values()) * steps / elapsed / 1e9, 1),
+            "iteration_gbs": round(iteration_bytes(algo, info) * steps / elapsed / 1e9, 1),
             "nmse": float(np.linalg.norm(v_np - prob.u_true) ** 2 / np.linalg.norm(prob.u_true) ** 2),
             "kkt": plan.kkt(g, v), "final_residuals": [float(x) for x in hist[-1].cpu().numpy()],
         }

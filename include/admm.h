@@ -74,6 +74,18 @@ extern "C" {
  * leave the GPU under-occupied) and single tiles otherwise.  No effect with
  * ADMM_INVERSE_BF16, whose copy is applied per tile. */
 #define ADMM_GRAM_PATCHES  32
+/* Flag, OR-ed in the same way (single plan only): always iterate with the
+ * two-pass kernels, which read H once for the forward products H_ij c and
+ * once for the adjoint products H_ij^H y.  Without it, complex64 plans with
+ * at most 32 row blocks and at most 6144 padded rows (row blocks padded to
+ * multiples of 64) iterate in a single pass over H: the plan also keeps a
+ * copy of H cut into slabs of two columns over all rows, and one kernel
+ * visit of a slab forms u = c + H^H y on its columns, applies the z- and
+ * dual updates there (eqs. v_variable_rows_columns, s_variable_rows_columns)
+ * and accumulates the next iteration's H c from the same registers.  Both
+ * give the same iterates up to FP32 rounding order; the single pass reads
+ * each element of H once per iteration instead of twice. */
+#define ADMM_TWO_PASS      64
 
 typedef struct admm_plan admm_plan;
 
@@ -93,7 +105,8 @@ const char* admm_last_error(void);
  *   row_off   host int64[Q+1] block boundaries, strictly increasing from 0
  *             to m, or NULL for the equal split (the first m mod Q blocks
  *             get one extra row).  col_off likewise with P and n.
- *   storage   ADMM_STORAGE_*, optionally | ADMM_INVERSE_BF16 | ADMM_GRAM_PATCHES.
+ *   storage   ADMM_STORAGE_*, optionally | ADMM_INVERSE_BF16 | ADMM_GRAM_PATCHES
+ *             | ADMM_TWO_PASS.
  *   out_bytes host, receives the size.
  * Errors: EINVAL for any bad size or split; EUNSUPPORTED when some block has
  * m_i >= (1 + sqrt 2) n_j (exactly: m_i^2 >= 2 m_i n_j + n_j^2).  Every block
@@ -114,16 +127,19 @@ int admm_workspace_bytes(int64_t m, int64_t n, int Q, const int64_t* row_off,
  *         when each block is its own node (Sec. IV, table of exchanged
  *         elements): 2 n with row blocks only, P m with column blocks only,
  *         P m_i + 2 n_j with both (the largest blocks when uneven), 0 unsplit;
- *     [1] HBM bytes one iteration of this library moves (algorithmic: H read
- *         twice, the packed inverses once, the block vectors; with Q > 32 the
- *         z-update's second read of c and the partials), for the kernels this
- *         split gets;
+ *     [1] HBM bytes one iteration of this library moves (algorithmic), for
+ *         the kernels this split gets: with the single pass H once, the
+ *         packed inverses once, the block vectors and the slab workgroups'
+ *         row parts of H c (written and read once); with the two-pass
+ *         kernels H twice, the inverses, the vectors and, with Q > 32, the
+ *         z-update's second read of c and the partials;
  *     [2] FP64 flops of the setup (lower half of H_ij H_ij^H, Cholesky,
  *         triangular inverse and W^H W, 8 per complex multiply-add);
  *     [3] bytes of the packed complex64 inverses, [4] bytes of stored H,
  *     [5] workspace bytes, [6] largest m_i, [7] largest n_j, [8] row chunks
  *     of the adjoint product, [9] 4 x 4 tile patches of the Gram apply (0:
- *     single tiles), [10..15] 0.
+ *     single tiles), [10] 1 if the split iterates in a single pass over H,
+ *     [11] workgroups of the single-pass slab kernel, [12..15] 0.
  */
 int admm_split_cost(int64_t m, int64_t n, int Q, const int64_t* row_off,
                     int P, const int64_t* col_off, int storage, double* out16);
@@ -315,11 +331,13 @@ int admm_get_stored_h(admm_plan* plan, void* re_out, void* im_out,
  * microseconds between the timed kernels, so sample (every > 1) inside a
  * throughput measurement.  Errors: EINVAL (every < 0), EHIP.
  */
-#define ADMM_K_GEMV_N   0   /* r_ij = g'_ij - H_ij c_j^i            */
-#define ADMM_K_GRAM     1   /* y_ij = G_ij^{-1} r_ij, ghat update   */
-#define ADMM_K_GEMV_H   2   /* partial H_ij^H y_ij                  */
-#define ADMM_K_ZUPDATE  3   /* mean, soft threshold, duals, norms   */
-#define ADMM_K_COUNT    4
+#define ADMM_K_GEMV_N   0   /* r_ij = g'_ij - H_ij c_j^i (two-pass)             */
+#define ADMM_K_GRAM     1   /* y_ij = G_ij^{-1} r_ij, ghat update               */
+#define ADMM_K_GEMV_H   2   /* partial H_ij^H y_ij (two-pass)                   */
+#define ADMM_K_ZUPDATE  3   /* mean, soft threshold, duals, norms (two-pass)    */
+#define ADMM_K_FZ_ROWS  4   /* single pass: r_ij from the slab parts of H c      */
+#define ADMM_K_FZ_SLAB  5   /* single pass: H^H y, z- and dual update, next H c */
+#define ADMM_K_COUNT    6
 int admm_profile(admm_plan* plan, int every);
 int admm_profile_read(admm_plan* plan, int kernel, double* total_ms,
                       int64_t* launches);
@@ -328,7 +346,8 @@ int admm_profile_read(admm_plan* plan, int kernel, double* total_ms,
  * m, n, Q, P, storage, chunks of the adjoint product, workspace bytes,
  * bytes of stored H, bytes of stored inverses, iterations done, padded row
  * and column space lengths, 4 x 4 tile patches of the Gram apply (0: one
- * tile per workgroup), 0... */
+ * tile per workgroup), 1 if the plan iterates in a single pass over H (else
+ * 0), workgroups of the single-pass slab kernel, 0. */
 int admm_plan_info(const admm_plan* plan, int64_t* info16);
 
 /* Release the plan (host memory only; the workspace stays the caller's). */

@@ -76,7 +76,8 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   }
   const bool inv16 = (storage & ADMM_INVERSE_BF16) != 0;
   const bool force_patches = (storage & ADMM_GRAM_PATCHES) != 0;
-  storage &= ~(ADMM_INVERSE_BF16 | ADMM_GRAM_PATCHES);
+  const bool two_pass = (storage & ADMM_TWO_PASS) != 0;
+  storage &= ~(ADMM_INVERSE_BF16 | ADMM_GRAM_PATCHES | ADMM_TWO_PASS);
   if (storage != ADMM_STORAGE_C64 && storage != ADMM_STORAGE_BF16 && storage != ADMM_STORAGE_FP8) {
     err = "unknown storage";
     return ADMM_EINVAL;
@@ -243,6 +244,85 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   for (int j = 0; j < P; ++j)
     for (int c = 0; c < geo.cols[j].nj; c += kZCols) geo.t_z.push_back(make_int4(j, c, 0, 0));
 
+  // Single-pass iteration (k_fused.hip): complex64 storage, at most kFzMaxQ
+  // row blocks, each row block on a whole number of waves: 512-thread
+  // workgroups (8 waves, two per CU) with RPL from kFzRpl, else 1024 threads
+  // (16 waves, one per CU) with RPL <= 6.  Otherwise, or with ADMM_TWO_PASS,
+  // the two-pass kernels.
+  geo.fz = false;
+  geo.t_fz.clear();
+  geo.fz_colwg.clear();
+  geo.t_fzr.clear();
+  geo.fzt = FzArgs{};
+  if (!two_pass && storage == ADMM_STORAGE_C64 && Q <= kFzMaxQ) {
+    std::vector<int> gi(Q);   // 64-row groups of each row block
+    for (int i = 0; i < Q; ++i) gi[i] = (int)(ldr[i] / kWave);
+    auto waves = [&](int rpl) {
+      int w = 0;
+      for (int i = 0; i < Q; ++i) w += (gi[i] + rpl - 1) / rpl;
+      return w;
+    };
+    int nt = 0, rpl = 0;
+    const char* ent = getenv("ADMM_FZ_NT");
+    const int want_nt = ent ? atoi(ent) : 0;
+    if (want_nt != 1024)
+      for (int r : kFzRpl)
+        if (waves(r) <= 8) {
+          nt = 512;
+          rpl = r;
+          break;
+        }
+    if (!nt)
+      for (int r : {1, 2, 3, 4, 6})
+        if (waves(r) <= 16) {
+          nt = 1024;
+          rpl = r;
+          break;
+        }
+    if (nt) {
+      FzArgs& z = geo.fzt;
+      int w = 0;
+      for (int i = 0; i < Q; ++i) {
+        z.bw[i] = w;
+        for (int g = 0; g < gi[i]; g += rpl, ++w) {
+          z.ngw[w] = std::min(rpl, gi[i] - g);
+          z.g0[w] = (int)(rpad0[i] / kWave) + g;
+          z.wblk[w] = i;
+        }
+        z.rpad0[i] = (int)rpad0[i];
+        z.mi[i] = (int)(geo.ro[i + 1] - geo.ro[i]);
+        z.row0[i] = (int)geo.ro[i];
+      }
+      z.bw[Q] = w;
+      // slabs of CPL columns per column block, spread over about
+      // ADMM_FZ_WGS workgroups in proportion to the block widths; workgroup
+      // w of a block with N workgroups takes slabs w, w + N, w + 2N, ..., so
+      // the workgroups read neighbouring slabs at the same time
+      const int cplz = cols_per_load(storage);
+      std::vector<int64_t> ns(P);
+      int64_t tot = 0;
+      for (int j = 0; j < P; ++j) tot += (ns[j] = (geo.cols[j].nj + cplz - 1) / cplz);
+      int target = nt == 512 ? ADMM_FZ_WGS : ADMM_FZ_WGS / 2;
+      if (const char* e = getenv("ADMM_FZ_WGS")) target = std::max(1, atoi(e));
+      int64_t sgb = 0;
+      for (int j = 0; j < P; ++j) {
+        const int nwj = (int)std::max<int64_t>(
+            1, std::min<int64_t>(ns[j], std::llround((double)target * (double)ns[j] / (double)tot)));
+        const int w0 = (int)geo.t_fz.size();
+        for (int q = 0; q < nwj; ++q) geo.t_fz.push_back(make_int4(j, q, (int)ns[j], (int)sgb));
+        geo.fz_colwg.push_back(make_int2(w0, (int)geo.t_fz.size()));
+        sgb += ns[j];
+      }
+      geo.fz_slabs = sgb;
+      for (size_t b = 0; b < geo.blocks.size(); ++b)
+        for (int r = 0; r < geo.blocks[b].mi; r += kBlockThreads) geo.t_fzr.push_back(make_int4((int)b, r, 0, 0));
+      z.nwg = (int)geo.t_fz.size();
+      geo.fz = true;
+      geo.fz_nt = nt;
+      geo.fz_rpl = rpl;
+    }
+  }
+
   // workspace layout
   Layout& L = geo.lay;
   size_t off = 0;
@@ -262,6 +342,9 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
     L.H_scale = take(4 * (size_t)m);
     L.h_bytes += 4 * (size_t)m;
   }
+  // column-slab copy of H for the single-pass iteration (zeroed with H at setup)
+  L.hs_bytes = geo.fz ? (size_t)geo.fz_slabs * (size_t)geo.m_pad * (size_t)cols_per_load(storage) * 8 : 0;
+  L.Hs = take(L.hs_bytes);
   L.ginv_bytes = (size_t)gioff * 8;
   L.Ginv = take(L.ginv_bytes);
   if (geo.inv16) L.Ginv16 = take((size_t)gioff * 4);
@@ -276,6 +359,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   L.ghat = take(rowv * P);
   L.r = take(rowv * P);
   L.y = take(rowv * P);
+  L.fpart = take((size_t)geo.t_fz.size() * rowv);   // in the state region: zeroed with it
   L.blocks = take(sizeof(BlockDesc) * geo.blocks.size());
   L.cols = take(sizeof(ColDesc) * P);
   L.t_rows = take(16 * geo.t_rows.size());
@@ -287,9 +371,12 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   L.t_wrows = take(16 * std::max<size_t>(geo.t_wrows.size(), 1));
   L.t_gpatch = take(16 * std::max<size_t>(geo.t_gpatch.size(), 1));
   L.t_gtr = take(16 * geo.t_gtr.size());
+  L.t_fz = take(16 * std::max<size_t>(geo.t_fz.size(), 1));
+  L.fz_colwg = take(8 * std::max<size_t>(geo.fz_colwg.size(), 1));
+  L.t_fzr = take(16 * std::max<size_t>(geo.t_fzr.size(), 1));
   L.gpart = take((size_t)gpo * kTile * 8);
   L.ctl = take(sizeof(Control));
-  L.redpart = take(8 * kRedCount * geo.t_z.size());
+  L.redpart = take(8 * kRedCount * std::max(geo.t_z.size(), geo.t_fz.size()));
   L.row_block = take(8 * (size_t)m);
   L.kkt_e = take(16 * (size_t)m);
   L.kkt_v = take(colv);
@@ -369,13 +456,20 @@ struct admm_plan {
   float2 *vb = nullptr, *sb = nullptr, *ub = nullptr, *ghb = nullptr, *gpb = nullptr, *yb = nullptr, *rb = nullptr;
   double2* gbar = nullptr;
   double *kpart = nullptr, *rpart = nullptr;
+  // single-pass iteration: tables, arguments, and whether the workgroup parts
+  // of H c in the workspace belong to the current c (else a forward-only slab
+  // pass recomputes them before the first iteration)
+  int4 *t_fz = nullptr, *t_fzr = nullptr;
+  int2* fz_colwg = nullptr;
+  FzArgs fz{};
+  bool fz_valid = true;
   // profiling
   bool prof = false;
   int prof_every = 1;    // time the kernels of every prof_every-th iteration
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[ADMM_K_COUNT];
   std::vector<hipEvent_t> pool;
-  double prof_ms[ADMM_K_COUNT] = {0, 0, 0, 0};
-  int64_t prof_n[ADMM_K_COUNT] = {0, 0, 0, 0};
+  double prof_ms[ADMM_K_COUNT] = {};
+  int64_t prof_n[ADMM_K_COUNT] = {};
 };
 
 namespace {
@@ -473,6 +567,7 @@ int reset_state(admm_plan* p, hipStream_t st) {
   const size_t bytes = L.blocks - L.c;
   HIP_TRY(launch_fill(p->ws + L.c, bytes, st));
   p->k_done = 0;
+  p->fz_valid = true;   // zero parts of H c for c = 0
   return ADMM_OK;
 }
 
@@ -585,6 +680,14 @@ void split_cost(const Geometry& geo, double* out) {
   for (int k = 0; k < 16; ++k) out[k] = 0.0;
   out[0] = exch;
   out[1] = gemv_n + gram + gemv_h + zupd;
+  if (geo.fz) {
+    // single pass: the slab kernel reads H once, y, c and s, writes c, s, v
+    // and its row parts of H c; the row kernel reads the parts and forms r
+    const double parts = (double)geo.t_fz.size() * (double)m * c;
+    const double fz_slab = h + vrows + 4 * vcols + 2 * c * n + parts;
+    const double fz_rows = parts + c * m + (P > 1 ? (P - 1) * vrows + 2 * vrows : vrows);
+    out[1] = fz_rows + gram + fz_slab;
+  }
   out[2] = flops;
   out[3] = (double)geo.lay.ginv_bytes;
   out[4] = (double)geo.lay.h_bytes;
@@ -593,6 +696,8 @@ void split_cost(const Geometry& geo, double* out) {
   out[7] = (double)nj;
   out[8] = geo.KH;
   out[9] = (double)geo.t_gpatch.size();
+  out[10] = geo.fz ? 1.0 : 0.0;
+  out[11] = (double)geo.t_fz.size();
 }
 }  // namespace
 
@@ -709,6 +814,15 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   p->gbar = at<double2>(p, L.gbar);
   p->kpart = at<double>(p, L.kpart);
   p->rpart = at<double>(p, L.rpart);
+  p->t_fz = at<int4>(p, L.t_fz);
+  p->t_fzr = at<int4>(p, L.t_fzr);
+  p->fz_colwg = at<int2>(p, L.fz_colwg);
+  p->fz = p->geo.fzt;
+  p->fz.hsl = HStore{p->ws + L.Hs, nullptr, nullptr, ADMM_STORAGE_C64};
+  p->fz.fpart = at<float2>(p, L.fpart);
+  p->fz.work = p->t_fz;
+  p->fz.colwg = p->fz_colwg;
+  p->fz.mode = 0;
   {
     static std::atomic<uint64_t> next_serial{1};
     p->serial = next_serial++;
@@ -747,6 +861,11 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   if (!G.t_gpatch.empty())
     SETUP_TRY(hipMemcpyAsync(p->t_gpatch, G.t_gpatch.data(), 16 * G.t_gpatch.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->t_gtr, G.t_gtr.data(), 16 * G.t_gtr.size(), hipMemcpyHostToDevice, st));
+  if (G.fz) {
+    SETUP_TRY(hipMemcpyAsync(p->t_fz, G.t_fz.data(), 16 * G.t_fz.size(), hipMemcpyHostToDevice, st));
+    SETUP_TRY(hipMemcpyAsync(p->fz_colwg, G.fz_colwg.data(), 8 * G.fz_colwg.size(), hipMemcpyHostToDevice, st));
+    SETUP_TRY(hipMemcpyAsync(p->t_fzr, G.t_fzr.data(), 16 * G.t_fzr.size(), hipMemcpyHostToDevice, st));
+  }
   SETUP_TRY(hipMemcpyAsync(p->row_block, p->h_row_block.data(), 8 * (size_t)m, hipMemcpyHostToDevice, st));
   int max_mi = 0;
   for (auto& d : G.blocks) max_mi = std::max(max_mi, d.mi);
@@ -756,6 +875,7 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   else
     SETUP_TRY(launch_pack_quant(static_cast<const float2*>(H), m, n, p->d_blocks, (int)G.blocks.size(), max_mi,
                                 p->hs, p->ctl, st));
+  if (G.fz) SETUP_TRY(launch_pack_slabs(p->hs, p->fz.hsl, p->d_blocks, G.Q, G.P, G.m_pad, p->fz, st));
   SETUP_TRY(launch_gram_build(G, p->d_blocks, p->t_gram, p->hs, rho, p->F64a, st));
   SETUP_TRY(launch_cholesky_inverse(G, p->d_blocks, p->t_gram, p->F64a, p->F64b, p->Ginv, p->ctl, st));
   if (p->Ginv16) SETUP_TRY(launch_to_bf16_pairs(p->Ginv, p->Ginv16, L.ginv_bytes / 8, st));
@@ -790,16 +910,35 @@ int admm_solve(admm_plan* p, const void* g, int iters, double tol, int check_eve
   int rc;
   if (!warm && (rc = reset_state(p, st))) return rc;
   HIP_TRY(launch_fill(p->ctl, 16, st));  // iteration counter, pending z-sums flag, error flags
-  const IterArgs a = iter_args(p, static_cast<const float2*>(g), resid_hist);
-  const int nr = (int)G.t_rows.size(), nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
+  IterArgs a = iter_args(p, static_cast<const float2*>(g), resid_hist);
+  const int nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
   const int nh = (int)G.t_hrows.size();
   const int ngr = (int)G.t_gram.size(), ngt = (int)G.t_gtr.size();
   int done = 0;
+  FzArgs z = p->fz;
+  if (G.fz) {
+    a.nz = (int)G.t_fz.size();   // residual partials: one per slab-pass workgroup
+    if (!p->fz_valid && iters > 0) {
+      // the workspace's parts of H c belong to another c (state import,
+      // recorded solve): one forward-only slab pass
+      z.mode = 1;
+      HIP_TRY(launch_fz_slab(a, z, G.fz_nt, G.fz_rpl, st));
+      z.mode = 0;
+      p->fz_valid = true;
+    }
+  }
+  const int nfr = (int)G.t_fzr.size();
   for (int k = 0; k < iters; ++k) {
-    if ((rc = timed(p, ADMM_K_GEMV_N, k, st, [&](KTime kt) { return launch_gemv_n(a, p->t_hrows, nh, p->t_wrows, (int)G.t_wrows.size(), st, kt); }))) return rc;
-    if ((rc = timed(p, ADMM_K_GRAM, k, st, [&](KTime kt) { return launch_gram(a, p->t_gram, ngr, p->t_gpatch, (int)G.t_gpatch.size(), p->t_gtr, ngt, st, kt); }))) return rc;
-    if ((rc = timed(p, ADMM_K_GEMV_H, k, st, [&](KTime kt) { return launch_gemv_h(a, p->t_cols, nc, st, kt); }))) return rc;
-    if ((rc = timed(p, ADMM_K_ZUPDATE, k, st, [&](KTime kt) { return launch_zupdate(a, p->t_z, nz, st, kt); }))) return rc;
+    if (G.fz) {
+      if ((rc = timed(p, ADMM_K_FZ_ROWS, k, st, [&](KTime kt) { return launch_fz_rows(a, z, p->t_fzr, nfr, st, kt); }))) return rc;
+      if ((rc = timed(p, ADMM_K_GRAM, k, st, [&](KTime kt) { return launch_gram(a, p->t_gram, ngr, p->t_gpatch, (int)G.t_gpatch.size(), p->t_gtr, ngt, st, kt); }))) return rc;
+      if ((rc = timed(p, ADMM_K_FZ_SLAB, k, st, [&](KTime kt) { return launch_fz_slab(a, z, G.fz_nt, G.fz_rpl, st, kt); }))) return rc;
+    } else {
+      if ((rc = timed(p, ADMM_K_GEMV_N, k, st, [&](KTime kt) { return launch_gemv_n(a, p->t_hrows, nh, p->t_wrows, (int)G.t_wrows.size(), st, kt); }))) return rc;
+      if ((rc = timed(p, ADMM_K_GRAM, k, st, [&](KTime kt) { return launch_gram(a, p->t_gram, ngr, p->t_gpatch, (int)G.t_gpatch.size(), p->t_gtr, ngt, st, kt); }))) return rc;
+      if ((rc = timed(p, ADMM_K_GEMV_H, k, st, [&](KTime kt) { return launch_gemv_h(a, p->t_cols, nc, st, kt); }))) return rc;
+      if ((rc = timed(p, ADMM_K_ZUPDATE, k, st, [&](KTime kt) { return launch_zupdate(a, p->t_z, nz, st, kt); }))) return rc;
+    }
     ++done;
     if (tol > 0 && (k + 1) % check_every == 0) {
       HIP_TRY(launch_zfinal(a, st));
@@ -847,6 +986,7 @@ int admm_solve_record(admm_plan* p, const void* g, int iters, int interval, void
   char* tp = static_cast<char*>(tape);
   int rc;
   if ((rc = reset_state(p, st))) return rc;
+  p->fz_valid = false;   // the two-pass kernels below move c
   HIP_TRY(launch_fill(p->ctl, 16, st));
   const IterArgs a = iter_args(p, static_cast<const float2*>(g), nullptr);
   const int nr = (int)G.t_rows.size(), nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
@@ -907,6 +1047,7 @@ int admm_backward(admm_plan* p, const void* g, const void* grad_v, const void* t
   const int K = h.iters, C = h.interval;
   const TapeLayout T = tape_layout(G, K, C);
   const size_t colv = (size_t)G.n_pad * 8, rowv = (size_t)G.m_pad * 8;
+  p->fz_valid = false;   // the recomputed forward moves c
   // adjoint state: vb = grad_v, everything else zero
   HIP_TRY(launch_fill(p->ws + G.lay.vb, G.lay.total - G.lay.vb, st));
   HIP_TRY(launch_fill(&p->ctl->kbar, 16, st));
@@ -1010,6 +1151,7 @@ int admm_set_state(admm_plan* p, const void* v, const void* s, const void* ghat,
   HIP_TRY(launch_make_c(p->d_cols, G.P, G.Q, G.n_pad, cols_per_load(G.storage), p->v, p->s, p->c, st));
   HIP_TRY(hipStreamSynchronize(st));
   p->k_done = k;
+  p->fz_valid = false;
   return ADMM_OK;
 }
 
@@ -1138,7 +1280,8 @@ int admm_plan_info(const admm_plan* p, int64_t* info) {
   if (!p || !info) return fail(ADMM_EINVAL, "plan and info must not be NULL");
   const Geometry& G = p->geo;
   int64_t v[16] = {G.m, G.n, G.Q, G.P, G.storage, G.KH, (int64_t)G.lay.total, (int64_t)G.lay.h_bytes,
-                   (int64_t)G.lay.ginv_bytes, p->k_done, G.m_pad, G.n_pad, (int64_t)G.t_gpatch.size(), 0, 0, 0};
+                   (int64_t)G.lay.ginv_bytes, p->k_done, G.m_pad, G.n_pad, (int64_t)G.t_gpatch.size(),
+                   G.fz ? 1 : 0, (int64_t)G.t_fz.size(), 0};
   std::memcpy(info, v, sizeof v);
   return ADMM_OK;
 }

@@ -1,0 +1,423 @@
+// Single-pass iteration of the split-lasso ADMM (arXiv 1811.05571, Sec. III-C)
+// over a column-slab copy of H.
+//
+// The two-pass iteration (k_iter.hip) reads H twice per iteration: once for
+// the forward products H_ij c and once for the adjoint products H_ij^H y.  The
+// z-update of a column needs only that column of every replica (the mean over
+// the row blocks and the element-wise threshold of eqs. v_variable_rows_columns
+// and softhresholding), so a workgroup holding a slab of CPL columns over all
+// rows can, in one visit of the slab:
+//   1. form u_j^i = c_j^i + H_ij^H y_ij on the slab's columns for every i
+//      (the x-update of eq. x_solution_rows_columns in push-through form),
+//   2. apply the z-update and the dual update (eq. s_variable_rows_columns)
+//      to those columns, giving the next c = v - s, and
+//   3. accumulate the next iteration's forward products H_ij c_j^i from the
+//      slab it still holds in registers.
+// Every element of H then comes from HBM once per iteration.  A workgroup owns
+// a run of slabs of one column block and keeps, for every row, its part of
+// H c over its slabs; k_fz_rows adds the parts of a column block's workgroups
+// in a fixed order and forms r_ij = g'_ij - H_ij c (g'_ij by eq.
+// g_rows_columns).  One iteration is k_fz_rows, the Gram apply of k_iter.hip
+// (y = G^{-1} r, ghat = g' - rho y) and k_fz_slab.  Sums run in a fixed order
+// (no atomics), so runs are bitwise reproducible.
+#include "gemv.h"
+
+namespace admm {
+
+// Workgroup barrier for data exchanged through LDS: the wave's own LDS
+// accesses complete (lgkmcnt 0), then s_barrier; the empty asm statements
+// keep the compiler from moving memory accesses across it.  Unlike
+// __syncthreads it leaves global loads in flight, including the loads into
+// LDS of the next slab (a workgroup fence would wait for those).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt, expcnt not waited for
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Rows rb + 64 k (k < ngw) of a slab (16 bytes each, slab base sp) into the
+// same rows of the LDS array hl, one 16-byte load into LDS per lane and row:
+// lane l of the wave writes hl[64 g + l] for the wave-uniform row 64 g.
+template <int RPL>
+__device__ __forceinline__ void stage_rows(const char* sp, float4* hl, int rb, int lane, int ngw) {
+#pragma unroll
+  for (int k = 0; k < RPL; ++k)
+    if (k < ngw)
+      __builtin_amdgcn_global_load_lds(sp + (size_t)(rb + kWave * k) * 16, hl + (rb - lane + kWave * k), 16, 0, 0);
+}
+
+// a + b = s + e exactly (Knuth's two-sum; the same s and e for (b, a)).
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// r_ij = g'_ij - s_row (H_ij c) for 256 rows of one block, H_ij c the ordered
+// sum of the column block's workgroup parts (s_row: fp8 row scale).
+// tiles[x] = {block, first row, -, -}.  Workgroup 0 first completes the
+// previous iteration's residual sums.
+template <class F>
+__global__ __launch_bounds__(kBlockThreads) void k_fz_rows(IterArgs a, FzArgs z, const int4* __restrict__ tiles) {
+  const int4 t = tiles[blockIdx.x];   // descriptors before any store: scalar loads
+  const BlockDesc d = a.blocks[t.x];
+  const int2 wr = z.colwg[d.j];
+  if (blockIdx.x == 0) {
+    __shared__ double red[kBlockThreads / kWave][kRedCount];
+    zfinal(a, red);
+  }
+  const F f = MakeFmt<F>::make(a.hs);
+  const int lr = t.y + threadIdx.x;
+  if (lr >= d.mi) return;
+  RowEpi epi;
+  row_epi_load(a, d, f, lr, epi);
+  const float2 hc = ordered_sum(z.fpart + (int64_t)wr.x * a.m_pad + d.rpad0 + lr, wr.y - wr.x, a.m_pad);
+  row_epi_store(a, d, lr, hc.x, hc.y, epi);
+}
+
+// The slab pass.  Workgroup w takes slabs sl0, sl0 + N, ... < sl1 of column
+// block j (work[w], N the block's workgroups); wave v holds the ngw[v] 64-row groups g0[v] .. of one row block
+// wblk[v] (a row block spans whole waves), lane l row 64 g + l of group g, one
+// 16-byte lane load per row: RPL lane loads of the current slab stay in
+// registers.  Per slab:
+//   adjoint : per-lane sums of conj(H) y over the lane's rows, closed over
+//             the wave (reduce-scatter) into red[wave];
+//   z-update: lane i*CPL + t of wave 0 owns replica i of column t of the
+//             slab: u^i = c^i + the sums of block i's waves (compensated), the
+//             mean over the replicas by a compensated butterfly, the
+//             threshold, the duals and c, residual partial sums in FP64;
+//   forward : every lane adds H[row, slab] c^{i(row)}[slab] to its row sums.
+// The lane loads alternate between two register sets: the next slab's are
+// issued as a slab's processing starts.
+// mode 1 skips the first two steps (forward products of the state's c).
+// YL: y of the column block in LDS instead of RPL registers per lane.
+template <class F, int NT, int RPL, bool YL>
+__global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // >= 4 waves per SIMD: <= 128 VGPRs
+  constexpr int CPL = F::CPL, NW = NT / kWave;
+  static_assert(NW <= kFzMaxWaves && RPL <= 32, "slab kernel shape");
+  static_assert(kFzMaxQ * CPL <= kWave, "the z-update takes one lane of wave 0 per replica and column");
+  __shared__ float2 ys[YL ? NT * RPL : 1];
+  __shared__ float4 hl[NT * RPL];   // the slab's rows in flight (16 bytes per padded row)
+  __shared__ float red[NW][2 * CPL];
+  __shared__ float2 zc[kFzMaxQ * CPL], zs[kFzMaxQ * CPL], zv[CPL], cn[kFzMaxQ * CPL];
+  __shared__ double racc[kRedCount][kWave];   // residual partial sums of the z-update lanes
+  __shared__ int bws[kFzMaxQ + 1];            // waves of each row block (read per lane)
+  const int4 wk = z.work[blockIdx.x];
+  const int j = wk.x, sl0 = wk.y, sl1 = wk.z, sgb = wk.w;
+  const int2 cw = z.colwg[j];
+  const int step = cw.y - cw.x;   // the column block's workgroups take every step-th slab
+  const ColDesc cd = a.cols[j];
+  const F f = MakeFmt<F>::make(z.hsl);
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int ngw = z.ngw[wave], blk = z.wblk[wave];
+  const int rb = kWave * z.g0[wave] + lane;   // this lane's row in its first group
+  const int Q = a.Q, QC = a.Q * CPL;
+  const int64_t mp = a.m_pad, np = a.n_pad;
+  const bool full = z.mode == 0;
+
+  // The slab's lane loads go from HBM straight into LDS (one 16-byte load
+  // per lane and row into the wave's own rows of hl); a wave copies its rows
+  // to registers when a slab's processing starts and at once issues the next
+  // slab's loads into the same rows, which then stay in flight through the
+  // slab's adjoint step, z-update and forward step.
+  typename F::Raw h[RPL];
+  float2 yv[YL ? 1 : RPL];
+  float fr[RPL], fi[RPL];
+  auto stage = [&](int sl) {   // the next slab's rows of this wave -> hl
+    stage_rows<RPL>(reinterpret_cast<const char*>(z.hsl.base) + ((int64_t)(sgb + sl) * mp * CPL) * 8, hl, rb, lane,
+                    ngw);
+  };
+  // hl -> registers (the wave's own rows).  The compiler does not see the
+  // lane-wise LDS writes of the loads into LDS: the empty asm tells it that
+  // hl may have changed.
+  auto unstage = [&]() {
+    asm volatile("" ::"v"(hl) : "memory");
+#pragma unroll
+    for (int k = 0; k < RPL; ++k)
+      if (k < ngw) h[k] = typename F::Raw{hl[rb + kWave * k]};
+  };
+  {
+    const float2* yj = a.y + (int64_t)j * mp;
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+      fr[k] = fi[k] = 0.f;
+      if (!YL) yv[k] = make_float2(0.f, 0.f);
+      h[k] = typename F::Raw{};
+      if (k < ngw) {
+        const int rp = rb + kWave * k;
+        float2 yy = yj[rp];
+        if constexpr (CPL == 16) {   // fp8: (diag(s) Hq)^H y = Hq^H (s o y)
+          const int lr = rp - z.rpad0[blk];
+          const float sc = lr < z.mi[blk] ? f.row_scale(z.row0[blk] + lr) : 0.f;
+          yy = make_float2(sc * yy.x, sc * yy.y);
+        }
+        if (YL)
+          ys[rp] = yy;
+        else
+          yv[k] = yy;
+      }
+    }
+  }
+  stage(sl0);
+  // c, s and the previous v of the slab's columns: thread t < Q*CPL holds
+  // replica t / CPL of column t % CPL; issued one slab ahead.
+  float2 pc = make_float2(0.f, 0.f), ps = pc, pv = pc;
+  auto prefetch = [&](int sl) {
+    if (tid < QC) {
+      const int i = tid / CPL, q = tid - i * CPL;
+      const int col = sl * CPL + q;
+      pc = ps = pv = make_float2(0.f, 0.f);
+      if (col < cd.nj) {
+        pc = a.c[(int64_t)i * np + cd.cpad0 + cperm(col, a.cpl)];
+        if (full) {
+          ps = a.s[(int64_t)i * np + cd.cpad0 + col];
+          if (tid < CPL) pv = a.v[cd.cpad0 + col];
+        }
+      }
+    }
+  };
+  prefetch(sl0);
+  if (tid < kWave) {
+#pragma unroll
+    for (int q = 0; q < kRedCount; ++q) racc[q][tid] = 0.0;
+  }
+  if (tid <= Q) bws[tid] = z.bw[tid];
+  lds_barrier();   // ys and bws complete
+
+  for (int sl = sl0; sl < sl1; sl += step) {
+    const bool more = sl + step < sl1;
+    // this slab's rows in hl (loaded a slab ago), the prefetched c, s, v and
+    // the previous slab's stores: all complete
+    __builtin_amdgcn_s_waitcnt(0);
+    unstage();
+    if (tid < QC) {   // read after this slab's first barrier
+      zc[tid] = pc;
+      zs[tid] = ps;
+      if (tid < CPL) zv[tid] = pv;
+    }
+    if (more) {
+      // the copies must have left the wave's rows of hl before they are refilled
+      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+      stage(sl + step);
+    }
+    if (full) {
+      float ar[CPL][2];
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) ar[q][0] = ar[q][1] = 0.f;
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) {
+        if (k < ngw) {
+          float hr[CPL], hi[CPL];
+          F::decode(h[k], hr, hi);
+          const float2 yk = YL ? ys[rb + kWave * k] : yv[k];
+#pragma unroll
+          for (int q = 0; q < CPL; ++q) cmacc(ar[q][0], ar[q][1], hr[q], hi[q], yk.x, yk.y);
+        }
+      }
+      if (ngw > 0) {
+        float outr, outi;
+        rows_reduce<CPL, true>(ar, outr, outi);
+        if ((lane & (kWave / CPL - 1)) == 0) {
+          const int q = rows_reduce_row<CPL>(lane);
+          red[wave][2 * q] = outr;
+          red[wave][2 * q + 1] = outi;
+        }
+      }
+      lds_barrier();
+      if (wave == 0) {
+        // lane i*CPL + t: replica i of the slab's column t
+        const int i = lane / CPL, t = lane - i * CPL, col = sl * CPL + t;
+        const bool act = i < Q, valid = act && col < cd.nj;
+        float xr = 0.f, xi = 0.f, sr0 = 0.f, si0 = 0.f;
+        if (valid) {
+          // u^i = c^i + H_ij^H y_ij: block i's wave sums, compensated, in order
+          const float2 ci = zc[lane];
+          CSum ur, ui;
+          ur.add(ci.x);
+          ui.add(ci.y);
+#pragma unroll 1
+          for (int w = bws[i]; w < bws[i + 1]; ++w) {
+            ur.add(red[w][2 * t]);
+            ui.add(red[w][2 * t + 1]);
+          }
+          xr = ur.value();
+          xi = ui.value();
+          const float2 sv = zs[lane];
+          sr0 = sv.x;
+          si0 = sv.y;
+        }
+        // consensus sum of u^i + s^i over the replicas (lanes t, t + CPL, ...):
+        // a compensated butterfly, so every lane of the column ends with the
+        // same total
+        float mr, er, mi, ei;
+        two_sum(xr, sr0, mr, er);
+        two_sum(xi, si0, mi, ei);
+#pragma unroll
+        for (int msk = CPL; msk < kWave; msk <<= 1) {
+          const float omr = __shfl_xor(mr, msk, kWave), oer = __shfl_xor(er, msk, kWave);
+          const float omi = __shfl_xor(mi, msk, kWave), oei = __shfl_xor(ei, msk, kWave);
+          float e1, e2;
+          two_sum(mr, omr, mr, e1);
+          two_sum(mi, omi, mi, e2);
+          er = (er + oer) + e1;
+          ei = (ei + oei) + e2;
+        }
+        if (valid) {
+          const float invQ = 1.0f / (float)Q;
+          const float mar = (mr + er) * invQ, mai = (mi + ei) * invQ;
+          if (!(isfinite(mar) && isfinite(mai))) a.ctl->nonfinite = 1;
+          // eq. softhresholding with sign(a) = a/|a|
+          const float mag = sqrtf(mar * mar + mai * mai);
+          float vr = 0.f, vi = 0.f;
+          if (mag > a.kappa) {
+            const float sc = 1.0f - a.kappa / mag;
+            vr = mar * sc;
+            vi = mai * sc;
+          }
+          const int64_t p = cd.cpad0 + col;
+          const float dr = xr - vr, di = xi - vi;
+          const float sr = sr0 + dr, sim = si0 + di;
+          const float2 cnew = make_float2(vr - sr, vi - sim);
+          a.s[(int64_t)i * np + p] = make_float2(sr, sim);
+          a.c[(int64_t)i * np + cd.cpad0 + cperm(col, a.cpl)] = cnew;
+          cn[lane] = cnew;
+          racc[kRedRp2][lane] += (double)dr * dr + (double)di * di;
+          racc[kRedU2][lane] += (double)xr * xr + (double)xi * xi;
+          racc[kRedS2][lane] += (double)sr * sr + (double)sim * sim;
+          if (i == 0) {
+            a.v[p] = make_float2(vr, vi);
+            const float2 vo = zv[t];
+            const double dvr = (double)vr - vo.x, dvi = (double)vi - vo.y;
+            racc[kRedDv2][lane] += dvr * dvr + dvi * dvi;
+            racc[kRedV2][lane] += (double)vr * vr + (double)vi * vi;
+          }
+        } else if (act) {
+          cn[lane] = make_float2(0.f, 0.f);
+        }
+      }
+      lds_barrier();
+    } else {
+      lds_barrier();   // the previous slab's forward step has read cn
+      if (tid < QC) cn[tid] = zc[tid];
+      lds_barrier();
+    }
+    if (more) prefetch(sl + step);   // into LDS at the next slab's start
+    float2 cb[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) cb[q] = cn[blk * CPL + q];
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+      if (k < ngw) {
+        float hr[CPL], hi[CPL];
+        F::decode(h[k], hr, hi);
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) cmac(fr[k], fi[k], hr[q], hi[q], cb[q].x, cb[q].y);
+      }
+    }
+  }
+  float2* fp = z.fpart + (int64_t)blockIdx.x * mp;
+#pragma unroll
+  for (int k = 0; k < RPL; ++k)
+    if (k < ngw) fp[rb + kWave * k] = make_float2(fr[k], fi[k]);
+  if (full && wave == 0) {
+    double acc[kRedCount];
+#pragma unroll
+    for (int q = 0; q < kRedCount; ++q) acc[q] = wave_sum_d(racc[q][lane]);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < kRedCount; ++q) a.redpart[(int64_t)blockIdx.x * kRedCount + q] = acc[q];
+      if (blockIdx.x == 0) a.ctl->zpending = 1;
+    }
+  }
+}
+
+// Slab store from the H store (setup): row rp of slab sl of column block j
+// holds lane load sl of row rp - rpad0_i of block (i, j); pad rows stay zero.
+// grid = (ceil(m_pad / 256), P).
+template <class F>
+__global__ __launch_bounds__(kBlockThreads) void k_pack_slabs(HStore src, HStore dst,
+                                                              const BlockDesc* __restrict__ blocks, int Q, int P,
+                                                              int64_t m_pad, FzArgs z) {
+  constexpr int CPL = F::CPL;
+  constexpr int ES = CPL == 2 ? 8 : (CPL == 8 ? 2 : 1);   // bytes per element of a plane
+  constexpr int NPL = CPL == 2 ? 1 : 2;                    // planes
+  const int j = blockIdx.y;
+  const int64_t rp = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  if (rp >= m_pad) return;
+  int i = 0;
+  while (i + 1 < Q && rp >= z.rpad0[i + 1]) ++i;
+  const int lr = (int)(rp - z.rpad0[i]);
+  if (lr >= z.mi[i]) return;
+  const BlockDesc d = blocks[i * P + j];
+  const int ns = (d.nj + CPL - 1) / CPL;
+  const int64_t sgb = z.work[z.colwg[j].x].w;
+  const char* sp[2] = {static_cast<const char*>(src.base), static_cast<const char*>(src.base_im)};
+  char* dp[2] = {static_cast<char*>(const_cast<void*>(dst.base)), static_cast<char*>(const_cast<void*>(dst.base_im))};
+  for (int sl = 0; sl < ns; ++sl) {
+    const int64_t se = (d.h_off + (int64_t)lr * d.ld + (int64_t)sl * CPL) * ES;
+    const int64_t de = ((sgb + sl) * m_pad + rp) * CPL * ES;
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl)
+      *reinterpret_cast<uint4*>(dp[pl] + de) = *reinterpret_cast<const uint4*>(sp[pl] + se);
+  }
+}
+
+// ---- launchers ------------------------------------------------------------
+hipError_t launch_fz_rows(const IterArgs& a, const FzArgs& z, const int4* tiles, int ntiles, hipStream_t st,
+                          KTime kt) {
+  switch (a.hs.storage) {
+    case 0: LAUNCH_TIMED(k_fz_rows<FmtC64>, dim3(ntiles), dim3(kBlockThreads), st, kt, a, z, tiles); break;
+    case 1: LAUNCH_TIMED(k_fz_rows<FmtBF16>, dim3(ntiles), dim3(kBlockThreads), st, kt, a, z, tiles); break;
+    default: LAUNCH_TIMED(k_fz_rows<FmtFP8>, dim3(ntiles), dim3(kBlockThreads), st, kt, a, z, tiles); break;
+  }
+  return hipGetLastError();
+}
+
+namespace {
+template <class F, int NT, int RPL, bool YL>
+hipError_t fz_go(const IterArgs& a, const FzArgs& z, hipStream_t st, KTime kt) {
+  LAUNCH_TIMED((k_fz_slab<F, NT, RPL, YL>), dim3(z.nwg), dim3(NT), st, kt, a, z);
+  return hipGetLastError();
+}
+}  // namespace
+
+// Shapes built (complex64 storage): 512 threads (8 waves of rows, two
+// workgroups per CU, y in LDS) and 1024 threads (16 waves, one workgroup per
+// CU, y in registers), each with RPL 1..6 groups of 64 rows per wave.  bf16 / fp8 lane loads decode into four times the registers per row
+// and take the two-pass kernels.
+hipError_t launch_fz_slab(const IterArgs& a, const FzArgs& z, int nt, int rpl, hipStream_t st, KTime kt) {
+  if (a.hs.storage != 0) return hipErrorInvalidValue;
+  if (nt == 512) {
+    switch (rpl) {
+      case 1: return fz_go<FmtC64, 512, 1, true>(a, z, st, kt);
+      case 2: return fz_go<FmtC64, 512, 2, true>(a, z, st, kt);
+      case 3: return fz_go<FmtC64, 512, 3, true>(a, z, st, kt);
+      case 4: return fz_go<FmtC64, 512, 4, true>(a, z, st, kt);
+      case 6: return fz_go<FmtC64, 512, 6, true>(a, z, st, kt);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (nt == 1024) {
+    switch (rpl) {
+      case 1: return fz_go<FmtC64, 1024, 1, true>(a, z, st, kt);
+      case 2: return fz_go<FmtC64, 1024, 2, true>(a, z, st, kt);
+      case 3: return fz_go<FmtC64, 1024, 3, true>(a, z, st, kt);
+      case 4: return fz_go<FmtC64, 1024, 4, true>(a, z, st, kt);
+      case 6: return fz_go<FmtC64, 1024, 6, true>(a, z, st, kt);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_pack_slabs(const HStore& src, const HStore& dst, const BlockDesc* blocks, int Q, int P,
+                             int64_t m_pad, const FzArgs& z, hipStream_t st) {
+  const dim3 grid((unsigned)((m_pad + kBlockThreads - 1) / kBlockThreads), (unsigned)P);
+  if (src.storage != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pack_slabs<FmtC64>, grid, dim3(kBlockThreads), 0, st, src, dst, blocks, Q, P, m_pad, z);
+  return hipGetLastError();
+}
+
+}  // namespace admm

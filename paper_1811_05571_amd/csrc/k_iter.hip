@@ -501,15 +501,6 @@ __global__ void k_fill_zero(uint4* p, size_t n16) {
 }
 
 // ---- launchers ------------------------------------------------------------
-// Plain launches unless timing events are given (then on the dispatch packet).
-#define LAUNCH_TIMED(kern, grid, block, st, kt, ...)                                               \
-  do {                                                                                               \
-    const KTime kt_ = kt;                                                                            \
-    if (kt_.start || kt_.stop)                                                                       \
-      hipExtLaunchKernelGGL(kern, grid, block, 0, st, kt_.start, kt_.stop, 0, __VA_ARGS__);           \
-    else                                                                                             \
-      hipLaunchKernelGGL(kern, grid, block, 0, st, __VA_ARGS__);                                     \
-  } while (0)
 
 hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, const int4* wtiles, int nwtiles,
                           hipStream_t st, KTime kt) {

@@ -17,13 +17,38 @@ struct ColDesc {       // one column block j
   int32_t nj, cpad0, col0, ld;
 };
 
-// Workspace carve-up (byte offsets from the workspace base, 256-aligned).
+// Single-pass iteration over a column-slab copy of H (k_fused.hip).  A slab
+// is CPL consecutive columns of one column block over every row of the
+// padded row space; in the slab store it is m_pad x CPL elements, row-major,
+// so one 16-byte lane load per plane reads one row of it.  A workgroup owns a
+// strided set of slabs of one column block; each of its waves owns up to RPL
+// consecutive 64-row groups of one row block (a row block spans whole waves).
+constexpr int kFzMaxWaves = 16;     // waves per workgroup
+constexpr int kFzMaxQ = 16;         // row blocks (each needs at least one wave)
+struct FzArgs {
+  HStore hsl;                       // slab store (same formats as the H store; row scales by global row)
+  float2* fpart;                    // [workgroup][m_pad]: that workgroup's part of H c for every row
+  const int4* work;                 // per workgroup {column block, first slab, slabs of the block, slab base of the block}
+  const int2* colwg;                // per column block {first workgroup, end workgroup}
+  int nwg, mode;                    // mode 0: full iteration step, 1: forward products only (c of the state)
+  int ngw[kFzMaxWaves];             // 64-row groups of each wave
+  int g0[kFzMaxWaves];              // first group of each wave (padded row 64 g0)
+  int wblk[kFzMaxWaves];            // row block of each wave
+  int bw[kFzMaxQ + 1];              // waves of row block i: [bw[i], bw[i+1])
+  int rpad0[kFzMaxQ], mi[kFzMaxQ], row0[kFzMaxQ];   // row blocks (row scales of fp8)
+};
+constexpr int kFzRpl[] = {1, 2, 3, 4, 6};   // row groups per wave built (512 and 1024 threads)
+#ifndef ADMM_FZ_WGS
+#define ADMM_FZ_WGS 512                 // about this many slab-pass workgroups (two per CU)
+#endif
+
 struct Layout {
   size_t H = 0, H_im = 0, H_scale = 0, Ginv = 0, Ginv16 = 0, F64a = 0, F64b = 0;
   size_t c = 0, s = 0, v = 0, part = 0, gp = 0, ghat = 0, r = 0, y = 0;
   size_t blocks = 0, cols = 0, t_rows = 0, t_cols = 0, t_z = 0, t_gram = 0, t_kadj = 0, t_hrows = 0, t_gtr = 0;
   size_t t_wrows = 0, t_gpatch = 0;
   size_t gpart = 0;
+  size_t Hs = 0, Hs_im = 0, fpart = 0, t_fz = 0, fz_colwg = 0, t_fzr = 0, hs_bytes = 0;
   size_t ctl = 0, redpart = 0, row_block = 0, kkt_e = 0, kkt_v = 0, kkt_part = 0, kkt_max = 0;
   size_t vb = 0, sb = 0, ub = 0, ghb = 0, gpb = 0, yb = 0, rb = 0, gbar = 0, kpart = 0, rpart = 0;
   size_t total = 0;
@@ -44,6 +69,14 @@ struct Geometry {
   std::vector<int4> t_rows, t_cols, t_z, t_gram, t_kadj, t_hrows, t_gtr;
   std::vector<int4> t_wrows;       // whole-row tiles of the row product (empty: not used)
   std::vector<int4> t_gpatch;      // 4 x 4 tile patches of the Gram apply (empty: single tiles)
+  // single-pass iteration (empty t_fz: the two-pass kernels run)
+  bool fz = false;
+  int fz_nt = 0, fz_rpl = 0;       // threads per workgroup, 64-row groups per wave
+  int64_t fz_slabs = 0;            // slabs in the slab store
+  std::vector<int4> t_fz;          // per workgroup {j, first slab, slabs of block j, slab base of block j}
+  std::vector<int2> fz_colwg;      // per column block {first, end workgroup}
+  std::vector<int4> t_fzr;         // row kernel: {block, first row, -, -}, 256 rows each
+  FzArgs fzt{};                    // the host part of the single-pass arguments (tables)
   Layout lay;
 };
 
@@ -193,12 +226,27 @@ hipError_t launch_adj_gflush(const AdjArgs& a, const BlockDesc* blocks, int nblo
 struct KTime {
   hipEvent_t start = nullptr, stop = nullptr;
 };
+// Plain launch unless timing events are given (then on the dispatch packet).
+#define LAUNCH_TIMED(kern, grid, block, st, kt, ...)                                               \
+  do {                                                                                               \
+    const KTime kt_ = kt;                                                                            \
+    if (kt_.start || kt_.stop)                                                                       \
+      hipExtLaunchKernelGGL(kern, grid, block, 0, st, kt_.start, kt_.stop, 0, __VA_ARGS__);           \
+    else                                                                                             \
+      hipLaunchKernelGGL(kern, grid, block, 0, st, __VA_ARGS__);                                     \
+  } while (0)
 hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, const int4* wtiles, int nwtiles,
                           hipStream_t st, KTime kt = {});
 hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gpatch, int n_gpatch,
                        const int4* t_gtr, int n_gtr, hipStream_t st, KTime kt = {});
 hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});
 hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});
+// Single-pass iteration (k_fused.hip).
+hipError_t launch_fz_rows(const IterArgs& a, const FzArgs& z, const int4* tiles, int ntiles, hipStream_t st,
+                          KTime kt = {});
+hipError_t launch_fz_slab(const IterArgs& a, const FzArgs& z, int nt, int rpl, hipStream_t st, KTime kt = {});
+hipError_t launch_pack_slabs(const HStore& src, const HStore& dst, const BlockDesc* blocks, int Q, int P,
+                             int64_t m_pad, const FzArgs& z, hipStream_t st);
 // Final addition of a pending z-update's partial sums (one workgroup).
 hipError_t launch_zfinal(const IterArgs& a, hipStream_t st);
 // Round n complex64 values to bfloat16 pairs (Re low half, Im high half).

@@ -45,7 +45,7 @@ def test_workspace_sizing_and_argument_errors():
     assert inv16 - big >= 32 * (24 * 25 // 2) * 4096 * 4
     L = A.lib()
     out = ctypes.c_size_t(0)
-    assert L.admm_workspace_bytes(256, 4096, 4, None, 1, None, 64, ctypes.byref(out)) == -1   # unknown flag
+    assert L.admm_workspace_bytes(256, 4096, 4, None, 1, None, 128, ctypes.byref(out)) == -1   # unknown flag
     # ADMM_GRAM_PATCHES (32) is known; it only adds the patch table
     assert L.admm_workspace_bytes(256, 4096, 4, None, 1, None, 32, ctypes.byref(out)) == 0
     assert A.workspace_bytes(300, 2000, 3, 5, [0, 90, 200, 300], [0, 333, 800, 1201, 1600, 2000]) > 0

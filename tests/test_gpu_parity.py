@@ -7,12 +7,14 @@ widths, rows not a multiple of the row tile), uneven block splits and the
 three splittings (consensus P=1, sectioning Q=1, combined), plus the
 degenerate ones (Q=P=1, zero iterations, lambda above max|H^H g|).
 """
+import functools
+
 import numpy as np
 import pytest
 
 import workloads as W
 from oracle import admm as O
-from tests._gpu import gpu_solve, rel, to_device
+from tests._gpu import check_image, gpu_solve, rel, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -64,24 +66,41 @@ def _case(name):
         return W.iid_problem(m=480, n=2000, nnz=10, Q=12, P=1, rho=1.0, seed=25), 150
     if name == "many_rows_and_sections":   # 10 x 2, ragged rows
         return W.iid_problem(m=501, n=3000, nnz=10, Q=10, P=2, rho=10.0, seed=26), 150
+    # degenerate block shapes and weights
+    if name == "one_row_blocks":       # m_i = 1: 8 blocks of one row, two sections
+        return W.iid_problem(m=8, n=300, nnz=4, Q=8, P=2, rho=10.0, seed=31), 150
+    if name == "one_column_blocks":    # n_j = 1: blocks of 2 x 1 (a single column each)
+        return W.iid_problem(m=6, n=12, nnz=3, Q=3, P=12, rho=40.0, seed=32), 150
+    if name == "lambda_zero":          # lambda = 0: kappa = 0, the least-squares iteration
+        return W.iid_problem(m=200, n=1200, nnz=10, Q=2, P=2, rho=10.0, lam_ratio=0.0, seed=33), 150
     raise KeyError(name)
 
 
 CASES = ["consensus256x4096", "combined_uneven", "sectioning", "unsplit", "ragged_consensus",
          "cra_small", "many_sections", "wide_blocks", "tall_sectioning", "square_blocks", "mixed_tall",
-         "tall_near_limit", "many_row_blocks", "many_rows_and_sections", "forty_row_blocks"]
+         "tall_near_limit", "many_row_blocks", "many_rows_and_sections", "forty_row_blocks",
+         "one_row_blocks", "one_column_blocks", "lambda_zero"]
 
 
-@pytest.mark.parametrize("name", CASES)
-def test_image_matches_oracle(torch_gpu, name):
+@functools.lru_cache(maxsize=None)
+def _reference(name):
+    """(problem, K, oracle result) of a named case, computed once per session."""
     p, K = _case(name)
-    print(f"case {name} m={p.m} n={p.n} Q={p.Q} P={p.P} K={K}", flush=True)
-    v_ref, hist_ref, st_ref = _oracle(p, K)
-    plan, g, (v, hist) = gpu_solve(torch_gpu, p, K, history=True)
+    return p, K, _oracle(p, K)
+
+
+@pytest.mark.parametrize("path", ["single_pass", "two_pass"])
+@pytest.mark.parametrize("name", CASES)
+def test_image_matches_oracle(torch_gpu, name, path):
+    p, K, (v_ref, hist_ref, st_ref) = _reference(name)
+    print(f"case {name} ({path}) m={p.m} n={p.n} Q={p.Q} P={p.P} K={K}", flush=True)
+    plan, g, (v, hist) = gpu_solve(torch_gpu, p, K, history=True, two_pass=(path == "two_pass"))
+    if path == "two_pass":
+        assert plan.info()["single_pass"] == 0
     v = v.cpu().numpy()
-    err = rel(v, v_ref)
-    print(f"  rel err {err:.3e}", flush=True)
-    assert err <= TOL, f"{name}: relative error {err:.3e} > {TOL}"
+    err, emax, nd = check_image(v, v_ref, st_ref.s, p.lam / (p.Q * p.rho))
+    print(f"  single pass {plan.info()['single_pass']}: rel err {err:.3e}, max element err {emax:.3e}, "
+          f"zero pattern on {nd} entries", flush=True)
     hist = hist.cpu().numpy()
     assert hist.shape == hist_ref.shape
     # residual histories: relative agreement where they are well above rounding
@@ -92,7 +111,12 @@ def test_image_matches_oracle(torch_gpu, name):
     # full state (duals, estimated data) after K iterations
     k, vg, sg, ghg = plan.get_state()
     assert k == K
-    assert rel(sg.cpu().numpy(), st_ref.s) <= 10 * TOL
+    # duals relative to their size, floored at 1e-3 |u|: with lambda = 0 and
+    # more columns than rows every block's data is fitted exactly and the
+    # duals converge to 0 (|s| = 2e-9 at K = 150 beside |u| = 1.9), so only
+    # FP32 rounding of u is left in them
+    s_scale = max(np.linalg.norm(st_ref.s), 1e-3 * np.linalg.norm(st_ref.u))
+    assert np.linalg.norm(sg.cpu().numpy() - st_ref.s) <= 10 * TOL * s_scale
     assert rel(ghg.cpu().numpy(), st_ref.ghat) <= 10 * TOL
 
 
@@ -146,6 +170,25 @@ def test_state_roundtrip_matches_oracle(torch_gpu):
                    to_device(torch, st40.ghat.astype(np.complex64)))
     v = plan.solve(g, 30, warm=True).cpu().numpy()
     assert rel(v, v70) <= TOL
+
+
+def test_warm_start_after_record_and_import(torch_gpu):
+    """The single pass keeps the forward parts of H c between solves; a state
+    import or a recorded solve (two-pass kernels) makes the next warm solve
+    recompute them first: all three continuations equal an uninterrupted run."""
+    p, _ = _case("combined_uneven")
+    torch = torch_gpu
+    plan, g, v_full = gpu_solve(torch, p, 70)
+    assert plan.info()["single_pass"] == 1
+    plan.solve(g, 40)
+    k, v40, s40, gh40 = plan.get_state()
+    plan.solve_record(g, 5)                   # moves the state with the two-pass kernels
+    plan.set_state(k, v40, s40, gh40)
+    v_imp = plan.solve(g, 30, warm=True)
+    assert rel(v_imp.cpu().numpy(), v_full.cpu().numpy()) <= 1e-6
+    plan.solve(g, 40)
+    plan.solve(g, 30, warm=True)              # parts kept from the previous solve
+    assert torch.equal(plan.get_state()[1], v_full)
 
 
 def test_zero_iterations_gives_zero_image(torch_gpu):
@@ -223,19 +266,24 @@ def test_bad_arguments_rejected(torch_gpu):
     assert A.lib().admm_solve(plan.handle, g.data_ptr(), 1, 1e-3, 0, v.data_ptr(), None, None, 0, None) == -1
 
 
-def test_profile_sampling_counts_and_leaves_results_unchanged(torch_gpu):
+@pytest.mark.parametrize("path", ["single_pass", "two_pass"])
+def test_profile_sampling_counts_and_leaves_results_unchanged(torch_gpu, path):
     """Kernel timing on every 3rd iteration: 9 iterations give 3 timed launches
-    per kernel class, and the iterates are bitwise those of an untimed solve."""
+    per kernel class of the path, and the iterates are bitwise those of an
+    untimed solve."""
     import paper_1811_05571_amd as A
     p, _ = _case("combined_uneven")
-    plan, g, (v0, _) = gpu_solve(torch_gpu, p, 9, history=True)
+    plan, g, (v0, _) = gpu_solve(torch_gpu, p, 9, history=True, two_pass=(path == "two_pass"))
+    used = ([A.K_FZ_ROWS, A.K_GRAM, A.K_FZ_SLAB] if path == "single_pass"
+            else [A.K_GEMV_N, A.K_GRAM, A.K_GEMV_H, A.K_ZUPDATE])
+    assert plan.info()["single_pass"] == (1 if path == "single_pass" else 0)
     plan.profile(3)
     v1 = plan.solve(g, 9)
-    counts = [plan.profile_read(k)[1] for k in A.KERNEL_NAMES]
-    ms = [plan.profile_read(k)[0] for k in A.KERNEL_NAMES]
+    counts = {k: plan.profile_read(k)[1] for k in A.KERNEL_NAMES}
+    ms = {k: plan.profile_read(k)[0] for k in A.KERNEL_NAMES}
     plan.profile(0)
-    assert counts == [3] * len(A.KERNEL_NAMES)
-    assert all(x > 0 for x in ms)
+    assert counts == {k: (3 if k in used else 0) for k in A.KERNEL_NAMES}
+    assert all(ms[k] > 0 for k in used)
     assert torch_gpu.equal(v0, v1)
     with pytest.raises(A.ADMMError):
         plan.profile(-1)

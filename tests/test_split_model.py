@@ -37,13 +37,15 @@ def test_column_wise_beats_row_wise_below_the_paper_bound():
         assert (cols < rows) == (P * m < 2 * n)
 
 
+@pytest.mark.parametrize("two_pass", [False, True])
 @pytest.mark.parametrize("Q,P", [(4, 8), (1, 8), (4, 1), (2, 3)])
-def test_bytes_per_iteration_match_the_benchmark_count(Q, P):
+def test_bytes_per_iteration_match_the_benchmark_count(Q, P, two_pass):
     m, n = 6144, 32000
-    c = A.split_cost(m, n, Q, P)
+    c = A.split_cost(m, n, Q, P, two_pass=two_pass)
     algo = bench.algorithmic_bytes(bench.block_geometry(m, n, Q, P), P, Q, int(c["chunks"]), "c64", "c64",
-                                   c["gram_patches"] > 0)
-    assert c["bytes_per_iteration"] == sum(algo.values())
+                                   c["gram_patches"] > 0, int(c["slab_workgroups"]))
+    assert c["single_pass"] == (0 if two_pass else 1)
+    assert c["bytes_per_iteration"] == bench.iteration_bytes(algo, {"single_pass": c["single_pass"]})
     assert c["max_block_rows"] == -(-m // Q) and c["max_block_cols"] == -(-n // P)
 
 
