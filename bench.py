@@ -180,7 +180,7 @@ def summarise_traffic(fetch_csv: str, write_csv: str, probe_mib: int, workload: 
             k["write_bytes"] += wb
             k["parts"].append({"kernel": src, "dispatches": len(fs[src]), "fetch_kib_raw": float(np.mean(fs[src])),
                                "write_kib_raw": float(np.mean(ws[src]))})
-        if not any(n in kern for n in ("k_gemv_n", "k_gemv_h")):
+        if not any(n in kern for n in ("k_gemv_n", "k_gemv_h", "k_fz_slab")):
             continue
         for k in kern.values():
             k["bytes_per_launch"] = int(round(k["fetch_bytes"] + k["write_bytes"]))
@@ -207,34 +207,104 @@ def copy_probe(torch, dev, mib: int, reps: int = 3):
     del src, dst
 
 
-def cpu_baseline(prob, n_iter: int):
-    """The FP64 oracle on the host cores: setup once, then n_iter iterations."""
-    from oracle import admm as O
+def attainable_bandwidth(torch, dev, gib: int = 2, reps: int = 5) -> dict:
+    """Reference rates of plain streaming on this GPU: a read-only sum over
+    `gib` GiB (torch's reduction, read once) and a copy of the same size
+    (read and written), best of `reps` timed runs each (HIP events)."""
+    n = gib * (1 << 30) // 4
+    x = torch.ones(n, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    out = {}
+    for name, fn, nbytes in (("read", lambda: torch.sum(x), x.numel() * 4),
+                             ("copy", lambda: y.copy_(x), 2 * x.numel() * 4)):
+        fn()
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e-3)
+        out[f"{name}_gbs"] = round(nbytes / best / 1e9, 1)
+    del x, y
+    torch.cuda.empty_cache()
+    out["bytes"] = gib * (1 << 30)
+    return out
+
+
+def _blas_info():
     try:
         from threadpoolctl import threadpool_info
-        threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
-        blas = ",".join(sorted({d.get("internal_api", "?") for d in threadpool_info()}))
+        info = threadpool_info()
+        threads = max((d.get("num_threads", 1) for d in info), default=1)
+        blas = ",".join(sorted({f"{d.get('internal_api', '?')}" for d in info}))
     except Exception:
         threads, blas = os.cpu_count(), "?"
-    H = prob.H.astype(np.complex128)
+    return threads, blas
+
+
+def cpu_baseline(prob, n_iter: int, keep=(), H=None):
+    """The FP64 oracle on the host cores in its push-through form (two
+    products with each block per iteration, the form a host solver would
+    run): setup once, then n_iter iterations timed.  Returns the timing and
+    the image after each iteration count in `keep`.  H: the matrix to run on
+    (default the workload's complex64 H)."""
+    from oracle import admm as O
+    threads, blas = _blas_info()
+    H = prob.H.astype(np.complex128) if H is None else H
     ro = O.split_offsets(prob.m, prob.Q)
     co = O.split_offsets(prob.n, prob.P)
     t0 = time.perf_counter()
-    blocks = O.setup(H, ro, co, prob.rho)
+    blocks = O.setup_push_through(H, ro, co, prob.rho)
     t1 = time.perf_counter()
     st = O.State.zeros(prob.m, prob.n, prob.Q, prob.P)
     g = prob.g.astype(np.complex128)
-    for _ in range(n_iter):
-        st, _, _ = O.step(H, g, ro, co, prob.rho, prob.lam, blocks, st)
+    kept = {}
+    for k in range(n_iter):
+        st, _, _ = O.step_push_through(g, ro, co, prob.rho, prob.lam, blocks, st)
+        if k + 1 in keep:
+            kept[k + 1] = st.v.copy()
     t2 = time.perf_counter()
     return {
-        "setup_s": t1 - t0, "iter_s": (t2 - t1) / n_iter, "iters": n_iter, "threads": threads,
-        "blas": blas, "v": st.v, "cpu": platform.processor() or platform.machine(),
+        "setup_s": t1 - t0, "iter_s": (t2 - t1) / max(n_iter, 1), "iters": n_iter, "threads": threads,
+        "blas": blas, "v": st.v, "kept": kept, "cpu": platform.processor() or platform.machine(),
         "affinity": len(os.sched_getaffinity(0)),
     }
 
 
+def bench_small(args, torch, A, W, dev, reps: int = 5) -> dict:
+    """The 256 x 4096 consensus workload (Q = 4 row blocks of 64, P = 1, 200
+    iterations): H is 8.4 MB and stays in the caches, so an iteration is
+    bound by launches and latency, not HBM (no roofline claim).  Median of
+    `reps` 200-iteration solves with plain launches and with graph replay."""
+    p = W.small_consensus()
+    H, g = torch.from_numpy(p.H).to(dev), torch.from_numpy(p.g).to(dev)
+    plan = A.Plan(H, p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off)
+    out = {"workload": p.name, "m": p.m, "n": p.n, "Q": p.Q, "P": p.P, "iters": p.iters,
+           "single_pass": plan.info()["single_pass"]}
+    for key, graphs in (("plain_launches", False), ("graph_replay", True)):
+        plan.set_graphs(graphs)
+        plan.solve(g, p.iters)
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            v = plan.solve(g, p.iters)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        it = float(np.median(times))
+        out[key] = {"iters_per_s": round(p.iters / it, 1), "us_per_iter": round(it / p.iters * 1e6, 2)}
+    vn = v.cpu().numpy()
+    out["nmse_vs_truth"] = float(np.linalg.norm(vn - p.u_true) ** 2 / np.linalg.norm(p.u_true) ** 2)
+    print(f"[bench] 256x4096: plain {out['plain_launches']['iters_per_s']} it/s, graphs "
+          f"{out['graph_replay']['iters_per_s']} it/s", file=sys.stderr, flush=True)
+    plan.close()
+    return out
+
+
 MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16
+PARITY_ITERS = 4                 # iterations of the full-size parity points of the precision forms
 
 
 def block_geometry(m: int, n: int, Q: int, P: int) -> dict:
@@ -499,7 +569,10 @@ def main(argv=None):
     ap.add_argument("--paper-table-only", action="store_true", help="measure only the paper's timing-table workload")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-seq", type=int, default=8, help="scenes solved one at a time for comparison")
-    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--no-small", action="store_true", help="skip the 256 x 4096 workload")
+    ap.add_argument("--no-form-oracle", action="store_true",
+                    help="skip the oracle runs on the dequantised bf16 / fp8 matrices")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--batch-only", action="store_true", help="measure only the batched multi-scene form")
     ap.add_argument("--no-kernel-events", action="store_true",
@@ -599,6 +672,13 @@ def main(argv=None):
 
     main = measure("c64", args.steps, args.warmup)
     plan = main["plan"]
+    # the same solve replaying captured graphs of 10 iterations (no kernel events)
+    plan.solve(g, max(args.steps, 10), history=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.solve(g, args.steps, history=True)
+    torch.cuda.synchronize()
+    graph_el = time.perf_counter() - t0
     out = {
         "metric": "ADMM iters/s", "value": round(args.steps / main["elapsed"], 2), "unit": "iters/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -608,11 +688,15 @@ def main(argv=None):
                    "rho": prob.rho, "lam_ratio": 0.02, "storage": "c64", "parallelism": "single-gpu"},
         "roofline": main["roofline"],
         "iteration_gbs": main["iteration_gbs"],
+        "graph_replay": {"value": round(args.steps / graph_el, 2), "ms_per_step": round(graph_el / args.steps * 1e3, 4),
+                         "note": "same solve replaying captured graphs of 10 iterations, no kernel events"},
+        "single_pass": main["info"]["single_pass"],
         "kernels": main["kern"],
         "setup_ms": round(main["setup_s"] * 1e3, 1),
         "nmse_vs_truth": main["nmse"], "kkt_violation": main["kkt"],
         "final_residuals": main["final_residuals"],
     }
+    form_plans = {}
     if not args.no_forms:
         forms = {}
         v_ref = main["v"].cpu().numpy()
@@ -620,14 +704,23 @@ def main(argv=None):
                                       ("c64_inverse_bf16", "c64", "bf16"), ("fp8_inverse_bf16", "fp8", "bf16")):
             r = measure(storage, args.steps, args.warmup, inverse)
             vq = r["v"].cpu().numpy()
+            # reconstruction quality after the workload's 300 iterations
+            v300 = r["plan"].solve(g, prob.iters)
+            v300n = v300.cpu().numpy()
             forms[key] = {
                 "storage": storage, "inverse": inverse,
                 "value": round(args.steps / r["elapsed"], 2), "unit": "iters/s",
                 "ms_per_step": round(r["elapsed"] / args.steps * 1e3, 4), "roofline": r["roofline"],
                 "iteration_gbs": r["iteration_gbs"], "kernels": r["kern"], "setup_ms": round(r["setup_s"] * 1e3, 1),
-                "nmse_vs_truth": r["nmse"], "kkt_violation": r["kkt"],
+                "after_300_iterations": {
+                    "nmse_vs_truth": float(np.linalg.norm(v300n - prob.u_true) ** 2
+                                           / np.linalg.norm(prob.u_true) ** 2),
+                    "kkt_violation": r["plan"].kkt(g, v300)},
                 "rel_diff_vs_c64_image": float(np.linalg.norm(vq - v_ref) / max(np.linalg.norm(v_ref), 1e-300)),
             }
+            if storage != "c64" and inverse == "c64":
+                form_plans[storage] = r["plan"]
+                continue
             r["plan"].close()
             del r
         out["forms"] = forms
@@ -658,6 +751,8 @@ def main(argv=None):
         }
         print(f"[bench] adjoint: forward {out['adjoint']['forward_ms']} ms, backward "
               f"{out['adjoint']['backward_ms']} ms", file=sys.stderr, flush=True)
+    if not args.no_small:
+        out["small_256x4096"] = bench_small(args, torch, A, W, dev)
     if not args.no_splits:
         out["full_splits"] = bench_full_splits(args, torch, A, prob, H, g)
     del H
@@ -666,20 +761,39 @@ def main(argv=None):
     if not args.no_paper_table:
         out["paper_table"] = bench_paper_table(args, torch, A, W, dev)
 
+    out["attainable"] = attainable_bandwidth(torch, dev)
     if not args.no_cpu:
         print(f"[bench] oracle CPU baseline: setup + {args.cpu_iters} iterations", file=sys.stderr, flush=True)
-        cb = cpu_baseline(prob, args.cpu_iters)
-        # parity at full size on the same sample: GPU from zero, same iteration count
+        kp = min(PARITY_ITERS, args.cpu_iters)
+        cb = cpu_baseline(prob, args.cpu_iters, keep=(kp,))
+        # parity at full size on the same sample: GPU from zero, same iteration counts
         vg = plan.solve(g, args.cpu_iters).cpu().numpy()
         err = float(np.linalg.norm(vg - cb["v"]) / max(np.linalg.norm(cb["v"]), 1e-300))
         out["cpu_baseline"] = {
             "value": round(1.0 / cb["iter_s"], 4), "unit": "iters/s", "cores": cb["threads"], "kind": "oracle",
+            "form": "push-through (two products with each block per iteration)",
             "sample": f"{prob.name}: oracle setup ({cb['setup_s']:.1f} s, not in value) then "
-                      f"{cb['iters']} iterations from zero, FP64 complex128, {cb['blas']} BLAS with "
-                      f"{cb['threads']} threads on {cb['affinity']} available cores",
+                      f"{cb['iters']} iterations from zero, FP64 complex128, push-through form, {cb['blas']} "
+                      f"BLAS with {cb['threads']} threads on {cb['affinity']} available cores",
             "setup_s": round(cb["setup_s"], 2),
         }
         out["parity_at_full_size"] = {"iters": args.cpu_iters, "rel_err_vs_oracle": err}
+        # precision forms against the oracle after kp iterations: on the
+        # dequantised H (arithmetic error) and on the complex64 H (total)
+        if form_plans and not args.no_form_oracle:
+            from oracle import quant as QZ
+            v64 = cb["kept"][kp]
+            fe = {}
+            for storage, fplan in form_plans.items():
+                vq = fplan.solve(g, kp).cpu().numpy()
+                print(f"[bench] oracle on the dequantised {storage} H: {kp} iterations", file=sys.stderr,
+                      flush=True)
+                cq = cpu_baseline(prob, kp, keep=(kp,), H=QZ.dequantise(prob.H, storage))
+                rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+                fe[storage] = {"iters": kp, "rel_err_vs_oracle_dequantised_H": rel(vq, cq["kept"][kp]),
+                               "rel_err_vs_oracle_c64_H": rel(vq, v64)}
+                fplan.close()
+            out["forms_vs_oracle"] = fe
     print(json.dumps(out), flush=True)
     return 0
 

@@ -77,8 +77,9 @@ extern "C" {
 /* Flag, OR-ed in the same way (single plan only): always iterate with the
  * two-pass kernels, which read H once for the forward products H_ij c and
  * once for the adjoint products H_ij^H y.  Without it, complex64 plans with
- * at most 32 row blocks and at most 6144 padded rows (row blocks padded to
- * multiples of 64) iterate in a single pass over H: the plan also keeps a
+ * at most 16 row blocks that fit 16 waves of at most six 64-row groups each,
+ * every row block on whole waves (so at most 6144 rows, row blocks padded to
+ * multiples of 64), iterate in a single pass over H: the plan also keeps a
  * copy of H cut into slabs of two columns over all rows, and one kernel
  * visit of a slab forms u = c + H^H y on its columns, applies the z- and
  * dual updates there (eqs. v_variable_rows_columns, s_variable_rows_columns)
@@ -217,6 +218,18 @@ int admm_solve(admm_plan* plan, const void* g, int iters, double tol,
                double* resid_hist, int warm, void* stream);
 
 /*
+ * admm_set_graphs -- graph replay in admm_solve on (enable != 0, the default)
+ * or off.  When on, and no kernel timing is enabled (admm_profile), a solve
+ * captures the launches of a run of iterations (10, or check_every when
+ * tol > 0) once as a HIP graph on a stream of the plan (default priority)
+ * and replays it; the captured launches depend on g, resid_hist and lambda,
+ * so a solve with other values captures again.  The solve's work is ordered
+ * after earlier work on `stream` and before later work on it by events.
+ * Results are bitwise those of plain launches.  Errors: EINVAL.
+ */
+int admm_set_graphs(admm_plan* plan, int enable);
+
+/*
  * Reverse mode of K unrolled iterations (the differentiable map
  * (g, lambda, rho) -> v^K from the zero state).
  *
@@ -237,7 +250,12 @@ int admm_solve(admm_plan* plan, const void* g, int iters, double tol,
  *                      soft-threshold Jacobian, H u, G^{-1} (its rho
  *                      derivative -G^{-2}), H^H r, estimated-data and
  *                      local-data adjoints.  FP32 vectors, FP64 scalar sums.
- *                      Overwrites the plan's iteration state.
+ *                      The tape is also the sweep's scratch: backward writes
+ *                      the recomputed y and a records into it (the
+ *                      checkpoints stay), so a tape serves any number of
+ *                      backward calls.  Leaves the plan's iteration state at
+ *                      the end of the first checkpoint interval (iteration
+ *                      min(interval, iters), reported by admm_get_state).
  * Errors: EINVAL; EWORKSPACE (tape too small); ESTATE (tape not recorded by
  * this plan, or lambda changed since); ENONFINITE; EHIP.  All synchronise
  * `stream`.
@@ -248,7 +266,7 @@ int admm_solve_record(admm_plan* plan, const void* g, int iters, int interval,
                       void* tape, size_t tape_bytes, void* v_out,
                       void* stream);
 int admm_backward(admm_plan* plan, const void* g, const void* grad_v,
-                  const void* tape, void* grad_g, double* grad_lambda,
+                  void* tape, void* grad_g, double* grad_lambda,
                   double* grad_rho, void* stream);
 
 /*

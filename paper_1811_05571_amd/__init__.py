@@ -44,6 +44,7 @@ SIGNATURES = [
     ("admm_setup", _int, [_c.POINTER(_vp), _vp, _i64, _i64, _int, _vp, _int, _vp, _dbl, _dbl, _int,
                           _vp, _sz, _vp]),
     ("admm_set_lambda", _int, [_vp, _dbl]),
+    ("admm_set_graphs", _int, [_vp, _int]),
     ("admm_solve", _int, [_vp, _vp, _int, _dbl, _int, _vp, _c.POINTER(_int), _vp, _int, _vp]),
     ("admm_tape_bytes", _int, [_vp, _int, _int, _c.POINTER(_sz)]),
     ("admm_solve_record", _int, [_vp, _vp, _int, _int, _vp, _sz, _vp, _vp]),
@@ -215,6 +216,10 @@ class Plan:
         _check(lib().admm_set_lambda(self._h, float(lam)), "admm_set_lambda")
         self.lam = float(lam)
 
+    def set_graphs(self, enable: bool):
+        """Graph replay of runs of iterations in solve (on by default)."""
+        _check(lib().admm_set_graphs(self._h, int(bool(enable))), "admm_set_graphs")
+
     def solve(self, g, iters: int, tol: float = 0.0, check_every: int = 10, warm: bool = False,
               history: bool = False, out=None):
         """Run `iters` iterations on g (complex64 CUDA, length m); returns v
@@ -224,14 +229,20 @@ class Plan:
         if not (g.is_cuda and g.dtype == torch.complex64 and g.numel() == self.m and g.is_contiguous()):
             raise ValueError("g must be a contiguous complex64 CUDA tensor of length m")
         v = out if out is not None else torch.empty(self.n, dtype=torch.complex64, device=self.device)
-        hist = torch.zeros((max(iters, 1), 2), dtype=torch.float64, device=self.device) if history else None
+        hist = None
+        if history:
+            # one device buffer kept across solves (a stable pointer lets the
+            # library replay its captured graph); the caller gets a copy
+            if getattr(self, "_hist", None) is None or self._hist.shape[0] < max(iters, 1):
+                self._hist = torch.empty((max(iters, 1), 2), dtype=torch.float64, device=self.device)
+            hist = self._hist
         done = ctypes.c_int(0)
         _check(lib().admm_solve(self._h, _ptr(g), int(iters), float(tol), int(check_every), _ptr(v),
                                 ctypes.byref(done), None if hist is None else _ptr(hist), int(bool(warm)),
                                 _stream(torch, self.device)), "admm_solve")
         self.iters_done = int(done.value)
         if history:
-            return v, hist[: self.iters_done]
+            return v, hist[: self.iters_done].clone()
         return v
 
     # -- reverse mode -------------------------------------------------------

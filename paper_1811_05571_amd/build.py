@@ -61,23 +61,5 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-def build_probe(verbose: bool = False) -> str:
-    """The HBM read-bandwidth probe (probe/hbm_read.hip), a standalone program."""
-    os.makedirs(BUILD, exist_ok=True)
-    src = os.path.join(HERE, "probe", "hbm_read.hip")
-    exe = os.path.join(BUILD, "hbm_read")
-    cmd = [HIPCC, "-O3", "-std=c++17", f"--offload-arch={ARCH}",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", src, "-o", exe]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed on {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    if verbose:
-        print("built", exe)
-    return exe
-
-
 if __name__ == "__main__":
-    if "--probe" in sys.argv[1:]:
-        build_probe(verbose=True)
-    else:
-        build(verbose=True)
+    build(verbose=True)

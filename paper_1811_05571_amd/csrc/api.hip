@@ -463,6 +463,16 @@ struct admm_plan {
   int2* fz_colwg = nullptr;
   FzArgs fz{};
   bool fz_valid = true;
+  // graph replay of fixed-length runs of iterations (admm_solve): captured on
+  // an internal stream, keyed by what the captured launches depend on
+  bool graphs = true;
+  hipStream_t gs = nullptr;
+  hipEvent_t gin = nullptr, gout = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void* gkey_g = nullptr;
+  const void* gkey_hist = nullptr;
+  float gkey_kappa = 0.f;
+  int gkey_chunk = 0;
   // profiling
   bool prof = false;
   int prof_every = 1;    // time the kernels of every prof_every-th iteration
@@ -897,6 +907,70 @@ int admm_set_lambda(admm_plan* p, double lambda) {
   return ADMM_OK;
 }
 
+namespace {
+
+// The launches of one iteration on stream st (kernel events when profiling
+// samples iteration k).
+int launch_iteration(admm_plan* p, const IterArgs& a, const FzArgs& z, int k, hipStream_t st) {
+  const Geometry& G = p->geo;
+  int rc;
+  const int ngr = (int)G.t_gram.size(), ngt = (int)G.t_gtr.size();
+  auto gram = [&](KTime kt) {
+    return launch_gram(a, p->t_gram, ngr, p->t_gpatch, (int)G.t_gpatch.size(), p->t_gtr, ngt, st, kt);
+  };
+  if (G.fz) {
+    if ((rc = timed(p, ADMM_K_FZ_ROWS, k, st, [&](KTime kt) { return launch_fz_rows(a, z, p->t_fzr, (int)G.t_fzr.size(), st, kt); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GRAM, k, st, gram))) return rc;
+    if ((rc = timed(p, ADMM_K_FZ_SLAB, k, st, [&](KTime kt) { return launch_fz_slab(a, z, G.fz_nt, G.fz_rpl, st, kt); }))) return rc;
+  } else {
+    if ((rc = timed(p, ADMM_K_GEMV_N, k, st, [&](KTime kt) { return launch_gemv_n(a, p->t_hrows, (int)G.t_hrows.size(), p->t_wrows, (int)G.t_wrows.size(), st, kt); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GRAM, k, st, gram))) return rc;
+    if ((rc = timed(p, ADMM_K_GEMV_H, k, st, [&](KTime kt) { return launch_gemv_h(a, p->t_cols, (int)G.t_cols.size(), st, kt); }))) return rc;
+    if ((rc = timed(p, ADMM_K_ZUPDATE, k, st, [&](KTime kt) { return launch_zupdate(a, p->t_z, (int)G.t_z.size(), st, kt); }))) return rc;
+  }
+  return ADMM_OK;
+}
+
+// A graph of `chunk` iterations for these arguments (captured again when g,
+// the residual history, kappa or the chunk change).
+constexpr int kGraphChunk = 10;
+int ensure_graph(admm_plan* p, const IterArgs& a, const FzArgs& z, int chunk) {
+  if (p->gexec && p->gkey_g == a.g && p->gkey_hist == a.hist && p->gkey_kappa == a.kappa && p->gkey_chunk == chunk)
+    return ADMM_OK;
+  if (!p->gs) {
+    HIP_TRY(hipStreamCreateWithFlags(&p->gs, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&p->gin, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&p->gout, hipEventDisableTiming));
+  }
+  if (p->gexec) {
+    HIP_TRY(hipGraphExecDestroy(p->gexec));
+    p->gexec = nullptr;
+  }
+  HIP_TRY(hipStreamBeginCapture(p->gs, hipStreamCaptureModeThreadLocal));
+  int rc = ADMM_OK;
+  for (int c = 0; c < chunk && rc == ADMM_OK; ++c) rc = launch_iteration(p, a, z, c, p->gs);
+  hipGraph_t gr = nullptr;
+  const hipError_t e = hipStreamEndCapture(p->gs, &gr);
+  if (rc) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(ADMM_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+  const hipError_t e2 = hipGraphInstantiate(&p->gexec, gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  if (e2 != hipSuccess) {
+    p->gexec = nullptr;
+    return fail(ADMM_EHIP, "graph instantiation failed: %s", hipGetErrorString(e2));
+  }
+  p->gkey_g = a.g;
+  p->gkey_hist = a.hist;
+  p->gkey_kappa = a.kappa;
+  p->gkey_chunk = chunk;
+  return ADMM_OK;
+}
+
+}  // namespace
+
 int admm_solve(admm_plan* p, const void* g, int iters, double tol, int check_every, void* v_out, int* iters_done,
                double* resid_hist, int warm, void* stream) {
   g_last_error.clear();
@@ -911,10 +985,6 @@ int admm_solve(admm_plan* p, const void* g, int iters, double tol, int check_eve
   if (!warm && (rc = reset_state(p, st))) return rc;
   HIP_TRY(launch_fill(p->ctl, 16, st));  // iteration counter, pending z-sums flag, error flags
   IterArgs a = iter_args(p, static_cast<const float2*>(g), resid_hist);
-  const int nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
-  const int nh = (int)G.t_hrows.size();
-  const int ngr = (int)G.t_gram.size(), ngt = (int)G.t_gtr.size();
-  int done = 0;
   FzArgs z = p->fz;
   if (G.fz) {
     a.nz = (int)G.t_fz.size();   // residual partials: one per slab-pass workgroup
@@ -927,24 +997,31 @@ int admm_solve(admm_plan* p, const void* g, int iters, double tol, int check_eve
       p->fz_valid = true;
     }
   }
-  const int nfr = (int)G.t_fzr.size();
-  for (int k = 0; k < iters; ++k) {
-    if (G.fz) {
-      if ((rc = timed(p, ADMM_K_FZ_ROWS, k, st, [&](KTime kt) { return launch_fz_rows(a, z, p->t_fzr, nfr, st, kt); }))) return rc;
-      if ((rc = timed(p, ADMM_K_GRAM, k, st, [&](KTime kt) { return launch_gram(a, p->t_gram, ngr, p->t_gpatch, (int)G.t_gpatch.size(), p->t_gtr, ngt, st, kt); }))) return rc;
-      if ((rc = timed(p, ADMM_K_FZ_SLAB, k, st, [&](KTime kt) { return launch_fz_slab(a, z, G.fz_nt, G.fz_rpl, st, kt); }))) return rc;
+  // Runs of `chunk` iterations (check_every with a tolerance) replay one
+  // captured graph when graphs are on and no kernel timing is sampled.
+  const int chunk = tol > 0 ? check_every : kGraphChunk;
+  const bool use_graph = p->graphs && !p->prof && iters >= chunk;
+  hipStream_t ws = st;
+  if (use_graph) {
+    if ((rc = ensure_graph(p, a, z, chunk))) return rc;
+    HIP_TRY(hipEventRecord(p->gin, st));
+    HIP_TRY(hipStreamWaitEvent(p->gs, p->gin, 0));
+    ws = p->gs;
+  }
+  int done = 0;
+  while (done < iters) {
+    if (use_graph && iters - done >= chunk) {
+      HIP_TRY(hipGraphLaunch(p->gexec, ws));
+      done += chunk;
     } else {
-      if ((rc = timed(p, ADMM_K_GEMV_N, k, st, [&](KTime kt) { return launch_gemv_n(a, p->t_hrows, nh, p->t_wrows, (int)G.t_wrows.size(), st, kt); }))) return rc;
-      if ((rc = timed(p, ADMM_K_GRAM, k, st, [&](KTime kt) { return launch_gram(a, p->t_gram, ngr, p->t_gpatch, (int)G.t_gpatch.size(), p->t_gtr, ngt, st, kt); }))) return rc;
-      if ((rc = timed(p, ADMM_K_GEMV_H, k, st, [&](KTime kt) { return launch_gemv_h(a, p->t_cols, nc, st, kt); }))) return rc;
-      if ((rc = timed(p, ADMM_K_ZUPDATE, k, st, [&](KTime kt) { return launch_zupdate(a, p->t_z, nz, st, kt); }))) return rc;
+      if ((rc = launch_iteration(p, a, z, done, ws))) return rc;
+      ++done;
     }
-    ++done;
-    if (tol > 0 && (k + 1) % check_every == 0) {
-      HIP_TRY(launch_zfinal(a, st));
+    if (tol > 0 && done % check_every == 0) {
+      HIP_TRY(launch_zfinal(a, ws));
       Control hc;
-      HIP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
+      HIP_TRY(hipMemcpyAsync(&hc, p->ctl, sizeof hc, hipMemcpyDeviceToHost, ws));
+      HIP_TRY(hipStreamSynchronize(ws));
       if (hc.nonfinite) break;
       const double Q = G.Q;
       const double rp = std::sqrt(hc.red[kRedRp2]), rd = p->rho * std::sqrt(Q * hc.red[kRedDv2]);
@@ -952,6 +1029,10 @@ int admm_solve(admm_plan* p, const void* g, int iters, double tol, int check_eve
       const double dua = tol * p->rho * std::sqrt(hc.red[kRedS2]);
       if (rp <= pri && rd <= dua) break;
     }
+  }
+  if (use_graph) {
+    HIP_TRY(hipEventRecord(p->gout, p->gs));
+    HIP_TRY(hipStreamWaitEvent(st, p->gout, 0));
   }
   p->k_done += done;
   HIP_TRY(launch_zfinal(a, st));
@@ -961,6 +1042,13 @@ int admm_solve(admm_plan* p, const void* g, int iters, double tol, int check_eve
   HIP_TRY(hipStreamSynchronize(st));
   if (iters_done) *iters_done = done;
   if (hc.nonfinite) return fail(ADMM_ENONFINITE, "a NaN or Inf reached the iterates (check g and rho)");
+  return ADMM_OK;
+}
+
+int admm_set_graphs(admm_plan* p, int enable) {
+  g_last_error.clear();
+  if (!p) return fail(ADMM_EINVAL, "plan is NULL");
+  p->graphs = enable != 0;
   return ADMM_OK;
 }
 
@@ -1029,7 +1117,7 @@ int admm_solve_record(admm_plan* p, const void* g, int iters, int interval, void
   return ADMM_OK;
 }
 
-int admm_backward(admm_plan* p, const void* g, const void* grad_v, const void* tape, void* grad_g,
+int admm_backward(admm_plan* p, const void* g, const void* grad_v, void* tape, void* grad_g,
                   double* grad_lambda, double* grad_rho, void* stream) {
   g_last_error.clear();
   if (!p) return fail(ADMM_EINVAL, "plan is NULL");
@@ -1037,7 +1125,7 @@ int admm_backward(admm_plan* p, const void* g, const void* grad_v, const void* t
     return fail(ADMM_EINVAL, "g, grad_v, tape, grad_g, grad_lambda and grad_rho must not be NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Geometry& G = p->geo;
-  const char* tp = static_cast<const char*>(tape);
+  char* tp = static_cast<char*>(tape);
   TapeHeader h{};
   HIP_TRY(hipMemcpyAsync(&h, tp, sizeof h, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -1084,8 +1172,8 @@ int admm_backward(admm_plan* p, const void* g, const void* grad_v, const void* t
   const int nr = (int)G.t_rows.size(), nc = (int)G.t_cols.size(), nz = (int)G.t_z.size();
   const int nh = (int)G.t_hrows.size();
   const int ngr = (int)G.t_gram.size(), ngt = (int)G.t_gtr.size();
-  float2* yrec = reinterpret_cast<float2*>(const_cast<char*>(tp) + T.yrec);
-  float2* arec = reinterpret_cast<float2*>(const_cast<char*>(tp) + T.arec);
+  float2* yrec = reinterpret_cast<float2*>(tp + T.yrec);
+  float2* arec = reinterpret_cast<float2*>(tp + T.arec);
   const size_t ystride = align256(rowv * G.P) / 8, astride = align256(colv) / 8;
   for (int seg = h.nseg - 1; seg >= 0; --seg) {
     const int k0 = seg * C, k1 = std::min(K, k0 + C);
@@ -1114,7 +1202,7 @@ int admm_backward(admm_plan* p, const void* g, const void* grad_v, const void* t
   const double Q = G.Q;
   *grad_lambda = hc.kbar / (Q * p->rho);
   *grad_rho = hc.rbar - hc.kbar * p->lam / (Q * p->rho * p->rho);
-  p->k_done = 0;
+  p->k_done = std::min(K, C);   // the state the last recomputed interval ends in
   if (hc.nonfinite) return fail(ADMM_ENONFINITE, "a NaN or Inf reached the recomputed iterates");
   return ADMM_OK;
 }
@@ -1289,6 +1377,10 @@ int admm_plan_info(const admm_plan* p, int64_t* info) {
 void admm_destroy(admm_plan* p) {
   if (!p) return;
   drain_profile(p);
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->gin) (void)hipEventDestroy(p->gin);
+  if (p->gout) (void)hipEventDestroy(p->gout);
+  if (p->gs) (void)hipStreamDestroy(p->gs);
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   delete p;
 }

@@ -29,6 +29,8 @@ def _cases():
                                     patch=(5, 2), iters=50, seed=22), 50),
         # 150 x 125 blocks, taller than wide: the twin differentiates the direct solve
         "tall_sectioning": (W.iid_problem(m=150, n=500, nnz=8, Q=1, P=4, rho=10.0, seed=23), 40),
+        # lambda = 0: no threshold, the unrolled map is smooth in g and rho
+        "lambda_zero": (W.iid_problem(m=128, n=600, nnz=8, Q=2, P=2, rho=10.0, lam_ratio=0.0, seed=24), 40),
     }
 
 
@@ -42,7 +44,7 @@ def _loss_and_grad_v(v, u_true):
     return float(np.sum(np.abs(v - u_true) ** 2)), 2 * (v - u_true)
 
 
-@pytest.mark.parametrize("name", ["consensus", "combined_uneven", "cra_small", "tall_sectioning"])
+@pytest.mark.parametrize("name", ["consensus", "combined_uneven", "cra_small", "tall_sectioning", "lambda_zero"])
 def test_adjoint_matches_oracle_autograd(torch_gpu, name):
     torch = torch_gpu
     p, K = _cases()[name]
@@ -83,21 +85,74 @@ def test_adjoint_reduced_storage_vs_oracle(torch_gpu, storage):
     assert eg <= TOL_AUTOGRAD and el <= TOL_AUTOGRAD and er <= TOL_AUTOGRAD
 
 
-def _fd_check(f, x0, h, ad, scale):
-    """Central difference of f at x0 with step h against the adjoint value ad.
-    Soft-threshold kinks inside [x0 - h, x0 + h] make the map's left and right
-    slopes differ and the central difference meaningless; the derivative at x0
-    of the piecewise-smooth map, which the adjoint computes, still lies
-    between the two one-sided difference quotients (up to the tolerance).
-    Returns True when the central difference missed (a kink was crossed)."""
-    fp, f0, fm = f(x0 + h), f(x0), f(x0 - h)
+def _trace(plan, g, K):
+    """(v^K, zero pattern of v after each of the K iterations from zero): one
+    warm single-iteration solve at a time, the same iterates as one solve."""
+    plan.solve(g, 0)
+    pats = []
+    for _ in range(K):
+        v = plan.solve(g, 1, warm=True)
+        pats.append((v == 0).cpu().numpy())
+    return v.cpu().numpy(), np.stack(pats)
+
+
+def _fd_check(E, x0, h, ad, scale):
+    """Central difference of the loss at x0 (step h) against the adjoint value
+    ad.  E(x) -> (loss, zero patterns of v over the iterations).  A soft-
+    threshold kink is crossed inside [x0 - h, x0 + h] exactly when some
+    iteration's zero pattern differs between x0 - h, x0 and x0 + h; without
+    one the map is smooth there and the central difference must match
+    (TOL_FD); with one the derivative at x0 of the piecewise-smooth map,
+    which the adjoint computes, lies between the two one-sided quotients.
+    Returns True when a kink was crossed."""
+    (fp, sp), (f0, s0), (fm, sm) = E(x0 + h), E(x0), E(x0 - h)
     c = (fp - fm) / (2 * h)
     tol = TOL_FD * (abs(c) + scale)
-    if abs(c - ad) <= tol:
+    if np.array_equal(sp, s0) and np.array_equal(sm, s0):
+        assert abs(c - ad) <= tol, ("no kink crossed, yet the central difference misses", c, ad)
         return False
     fwd, bwd = (fp - f0) / h, (f0 - fm) / h
     assert min(fwd, bwd) - tol <= ad <= max(fwd, bwd) + tol, ("adjoint outside the one-sided slopes", fwd, bwd, ad)
     return True
+
+
+def _fd_all(torch, p, K, interval, inverse="c64", directions=4, seed=5, check_lambda=True):
+    """The adjoint of K recorded iterations against central differences in
+    `directions` random unit directions of g, in lambda and (FP32 inverses) in
+    rho.  Returns (kinks crossed, checks)."""
+    g = to_device(torch, p.g)
+    u_true = p.u_true.astype(np.complex128)
+
+    def E(gg=None, lam=None, rho=None):
+        plan = _plan(torch, p, rho=rho, inverse=inverse)
+        if lam is not None:
+            plan.set_lambda(lam)
+        v, pats = _trace(plan, to_device(torch, gg) if gg is not None else g, K)
+        plan.close()
+        return float(np.sum(np.abs(v.astype(np.complex128) - u_true) ** 2)), pats
+
+    plan = _plan(torch, p, inverse=inverse)
+    v, tape = plan.solve_record(g, K, interval=interval)
+    _, gv = _loss_and_grad_v(v.cpu().numpy().astype(np.complex128), u_true)
+    gg, dl, dr = plan.backward(g, to_device(torch, gv.astype(np.complex64)), tape)
+    gg = gg.cpu().numpy().astype(np.complex128)
+    plan.close()
+    rng = np.random.default_rng(seed)
+    kinks = checks = 0
+    for _ in range(directions):
+        d = rng.standard_normal(p.m) + 1j * rng.standard_normal(p.m)
+        d /= np.linalg.norm(d)
+        h = 1e-3 * np.linalg.norm(p.g)
+        kinks += _fd_check(lambda t: E(gg=(p.g + t * d).astype(np.complex64)), 0.0, h,
+                           float(np.real(np.vdot(gg, d))), 1e-2 * np.linalg.norm(gg))
+        checks += 1
+    if check_lambda:
+        kinks += _fd_check(lambda x: E(lam=x), p.lam, 1e-3 * p.lam, dl, 0.0)
+        checks += 1
+    if inverse == "c64":
+        kinks += _fd_check(lambda x: E(rho=x), p.rho, 1e-3 * p.rho, dr, 1e-6)
+        checks += 1
+    return kinks, checks
 
 
 @pytest.mark.parametrize("name,inverse", [("consensus", "c64"), ("cra_small", "c64"), ("cra_small", "bf16")])
@@ -107,37 +162,20 @@ def test_adjoint_matches_central_differences(torch_gpu, name, inverse):
     forward computes.  The rounded inverse is a step function of rho (a step of
     1e-3 rho moves its entries by about one bf16 step), so the rho derivative,
     taken through the unrounded inverse, is checked with the FP32 inverse only."""
-    torch = torch_gpu
     p, K = _cases()[name]
-    g = to_device(torch, p.g)
-
-    def L(gg=None, lam=None, rho=None):
-        plan = _plan(torch, p, rho=rho, inverse=inverse)
-        if lam is not None:
-            plan.set_lambda(lam)
-        v = plan.solve(to_device(torch, gg) if gg is not None else g, K).cpu().numpy()
-        return float(np.sum(np.abs(v.astype(np.complex128) - p.u_true) ** 2))
-
-    plan = _plan(torch, p, inverse=inverse)
-    v, tape = plan.solve_record(g, K, interval=10)
-    _, gv = _loss_and_grad_v(v.cpu().numpy().astype(np.complex128), p.u_true)
-    gg, dl, dr = plan.backward(g, to_device(torch, gv.astype(np.complex64)), tape)
-    gg = gg.cpu().numpy().astype(np.complex128)
-    rng = np.random.default_rng(5)
-    kinks = 0
-    for _ in range(4):
-        d = rng.standard_normal(p.m) + 1j * rng.standard_normal(p.m)
-        d /= np.linalg.norm(d)
-        h = 1e-3 * np.linalg.norm(p.g)
-        f = lambda t: L(gg=(p.g + t * d).astype(np.complex64))
-        kinks += _fd_check(f, 0.0, h, float(np.real(np.vdot(gg, d))), 1e-2 * np.linalg.norm(gg))
-    kinks += _fd_check(lambda x: L(lam=x), p.lam, 1e-3 * p.lam, dl, 0.0)
-    checks = 5
-    if inverse == "c64":
-        kinks += _fd_check(lambda x: L(rho=x), p.rho, 1e-3 * p.rho, dr, 1e-6)
-        checks = 6
+    kinks, checks = _fd_all(torch_gpu, p, K, 10, inverse)
     print(f"{name} ({inverse} inverse): {kinks} of {checks} differences crossed a soft-threshold kink")
-    assert kinks <= 2
+
+
+def test_adjoint_smooth_map_central_differences(torch_gpu):
+    """lambda = 0 leaves the unrolled map without soft-threshold kinks: every
+    central difference in g and in rho must match the adjoint (TOL_FD), and
+    the zero patterns confirm that no kink was crossed.  (With lambda > 0 a
+    step of 1e-3 crosses some kink among the thousands of entries and tens of
+    iterations almost always, so there only the one-sided bracket applies.)"""
+    p, K = _cases()["lambda_zero"]
+    kinks, checks = _fd_all(torch_gpu, p, K, 10, check_lambda=False)
+    assert kinks == 0 and checks == 5
 
 
 def test_autograd_function(torch_gpu):
@@ -157,6 +195,25 @@ def test_autograd_function(torch_gpu):
     gg, dl, dr = plan2.backward(to_device(torch, p.g), 2 * (v2 - ut), tape)
     assert rel(g.grad.cpu().numpy(), gg.cpu().numpy()) <= 1e-6
     assert abs(lam.grad.item() - dl) <= 1e-6 * abs(dl) and abs(rho.grad.item() - dr) <= 1e-6 * abs(dr)
+
+
+def test_state_after_backward(torch_gpu):
+    """The reverse sweep leaves the plan at the end of the first checkpoint
+    interval: get_state reports that iteration and its image."""
+    torch = torch_gpu
+    p, K = _cases()["consensus"]
+    plan = _plan(torch, p)
+    g = to_device(torch, p.g)
+    v, tape = plan.solve_record(g, K, 7)
+    plan.backward(g, torch.zeros_like(v), tape)
+    k, vs, _, _ = plan.get_state()
+    assert k == 7
+    v7, _, _ = O.solve(p.H, p.g, p.Q, p.P, p.rho, p.lam, 7, p.row_off, p.col_off)
+    assert rel(vs.cpu().numpy(), v7) <= 1e-5
+    # a tape serves more than one backward call
+    gg1 = plan.backward(g, v, tape)[0]
+    gg2 = plan.backward(g, v, tape)[0]
+    assert torch.equal(gg1, gg2)
 
 
 def test_tape_errors(torch_gpu):

@@ -191,6 +191,41 @@ def test_warm_start_after_record_and_import(torch_gpu):
     assert torch.equal(plan.get_state()[1], v_full)
 
 
+@pytest.mark.parametrize("path", ["single_pass", "two_pass"])
+def test_graph_replay_matches_plain_launches(torch_gpu, path):
+    """Solves that replay captured graphs of 10 iterations give bitwise the
+    iterates of plain launches: several replays in a row, with the program's
+    own eager work (state reads, a plain solve on another plan) and
+    synchronisations between them, a remainder shorter than a graph, a new
+    lambda (captured again) and the tolerance stop (graphs of check_every
+    iterations)."""
+    import paper_1811_05571_amd as A
+    torch = torch_gpu
+    p, _ = _case("combined_uneven")
+    H, g = to_device(torch, p.H), to_device(torch, p.g)
+    tp = path == "two_pass"
+    pg = A.Plan(H, p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off, two_pass=tp)
+    pe = A.Plan(H, p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off, two_pass=tp)
+    pe.set_graphs(False)
+    vg, hg = pg.solve(g, 57, history=True)
+    ve, he = pe.solve(g, 57, history=True)
+    assert torch.equal(vg, ve) and torch.equal(hg, he)
+    for rep in range(4):   # warm replays with eager work between them
+        vg = pg.solve(g, 20, warm=True)
+        torch.cuda.synchronize()
+        kg = pg.get_state()
+        ve = pe.solve(g, 20, warm=True)
+        ke = pe.get_state()
+        assert torch.equal(vg, ve), rep
+        assert kg[0] == ke[0] and torch.equal(kg[2], ke[2]) and torch.equal(kg[3], ke[3])
+    for plan in (pg, pe):
+        plan.set_lambda(0.5 * p.lam)
+    assert torch.equal(pg.solve(g, 30), pe.solve(g, 30))
+    vg = pg.solve(g, 500, tol=1e-3, check_every=7)
+    ve = pe.solve(g, 500, tol=1e-3, check_every=7)
+    assert pg.iters_done == pe.iters_done and torch.equal(vg, ve)
+
+
 def test_zero_iterations_gives_zero_image(torch_gpu):
     p, _ = _case("unsplit")
     _, _, v = gpu_solve(torch_gpu, p, 0)
