@@ -76,15 +76,36 @@ def algorithmic_bytes(geo: dict, P: int, Q: int, KH: int, storage: str = "c64", 
     # parts, g and the other sections' estimates, and writes r (and g')
     fz_slab = h + vec_rows + 4 * vec_cols + 2 * n * c + parts
     fz_rows = parts + m * c + (P - 1) * vec_rows * (P > 1) + vec_rows * (2 if P > 1 else 1)
+    # direct x-update (geo from block_geometry(..., direct=True)): the row
+    # residuals from g and the estimates, one row vector per block; their
+    # adjoint product (as k_gemv_h); d = the partials + rho (c - u_prev); the
+    # Gram apply to d, its pieces written once; the z-update reads the
+    # pieces, u_prev and s, writes s, c and u, reads and writes v; the row
+    # product reads H and u and writes ghat
+    d_gp = m * c + 2 * vec_rows
+    d_rhs = (KH + 3) * vec_cols
+    d_gram = ginv * (4 if inverse == "bf16" else c) + gparts * 64 * c + vec_cols
+    d_zupd = gparts * 64 * c + 5 * vec_cols + 2 * n * c
+    d_gemv_n = h + vec_cols + vec_rows
     return {"k_gemv_n": gemv_n, "k_gram": gram, "k_gemv_h": gemv_h, "k_zupdate": zupd,
-            "k_fz_rows": fz_rows, "k_fz_slab": fz_slab}
+            "k_fz_rows": fz_rows, "k_fz_slab": fz_slab,
+            "k_dgp": d_gp, "k_dbsum": d_rhs, "k_gram_direct": d_gram, "k_zupdate_direct": d_zupd,
+            "k_gemv_n_direct": d_gemv_n}
+
+
+DIRECT_KERNELS = ("k_dgp", "k_gemv_h", "k_dbsum", "k_gram_direct", "k_zupdate_direct", "k_gemv_n_direct")
 
 
 def iteration_bytes(algo: dict, info: dict) -> int:
     """Algorithmic bytes of one iteration on the plan's path (single pass:
-    row kernel, Gram apply, slab kernel; else the four two-pass kernels)."""
-    names = (("k_fz_rows", "k_gram", "k_fz_slab") if info.get("single_pass")
-             else ("k_gemv_n", "k_gram", "k_gemv_h", "k_zupdate"))
+    row kernel, Gram apply, slab kernel; direct form: its six kernels; else
+    the four two-pass kernels)."""
+    if info.get("direct"):
+        names = DIRECT_KERNELS
+    elif info.get("single_pass"):
+        names = ("k_fz_rows", "k_gram", "k_fz_slab")
+    else:
+        names = ("k_gemv_n", "k_gram", "k_gemv_h", "k_zupdate")
     return int(sum(algo[k] for k in names))
 
 
@@ -307,15 +328,19 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16
 PARITY_ITERS = 4                 # iterations of the full-size parity points of the precision forms
 
 
-def block_geometry(m: int, n: int, Q: int, P: int) -> dict:
+def block_geometry(m: int, n: int, Q: int, P: int, direct: bool = False) -> dict:
     """Sizes the algorithmic byte counts need for equal splits (the first m % Q
-    row blocks one row longer)."""
-    sizes = [m // Q + (1 if i < m % Q else 0) for i in range(Q)]
+    row blocks one row longer, likewise columns): the Gram matrices are
+    m_i x m_i, or n_j x n_j in the direct form."""
+    if direct:
+        sizes, mult = [n // P + (1 if j < n % P else 0) for j in range(P)], Q
+    else:
+        sizes, mult = [m // Q + (1 if i < m % Q else 0) for i in range(Q)], P
     tiles = [(s_ + 63) // 64 for s_ in sizes]
     return {"m": m, "n": n,
-            "ginv_packed": int(sum(T * (T + 1) // 2 * 4096 for T in tiles) * P),
-            "gram_parts": int(sum(T * T for T in tiles) * P),
-            "gram_parts_patch": int(sum(T * ((T + 3) // 4 + 1) for T in tiles) * P)}
+            "ginv_packed": int(sum(T * (T + 1) // 2 * 4096 for T in tiles) * mult),
+            "gram_parts": int(sum(T * T for T in tiles) * mult),
+            "gram_parts_patch": int(sum(T * ((T + 3) // 4 + 1) for T in tiles) * mult)}
 
 
 # rates of the split cost model (measured on MI355X: streaming reads, the FP64
@@ -350,8 +375,8 @@ def bench_full_splits(args, torch, A, prob, H, g, steps: int = 300, warmup: int 
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         info = plan.info()
-        algo = algorithmic_bytes(block_geometry(prob.m, prob.n, Q, P), P, Q, info["chunks"], "c64", "c64",
-                                 info["gram_patches"] > 0, info["slab_workgroups"])
+        algo = algorithmic_bytes(block_geometry(prob.m, prob.n, Q, P, info["direct"]), P, Q, info["chunks"], "c64",
+                                 "c64", info["gram_patches"] > 0, info["slab_workgroups"])
         vn = v.cpu().numpy()
         hs = hist.cpu().numpy()
         mi, nj = -(-prob.m // Q), -(-prob.n // P)
@@ -408,7 +433,7 @@ def bench_paper_table(args, torch, A, W, dev, reps: int = 5):
             times.append(time.perf_counter() - t0)
         it = float(np.median(times))
         info = plan.info()
-        algo = algorithmic_bytes(block_geometry(p.m, p.n, Q, P), P, Q, info["chunks"], "c64", "c64",
+        algo = algorithmic_bytes(block_geometry(p.m, p.n, Q, P, info["direct"]), P, Q, info["chunks"], "c64", "c64",
                                  info["gram_patches"] > 0, info["slab_workgroups"])
         vn = v.cpu().numpy()
         hs = hist.cpu().numpy()

@@ -87,6 +87,28 @@ extern "C" {
  * give the same iterates up to FP32 rounding order; the single pass reads
  * each element of H once per iteration instead of twice. */
 #define ADMM_TWO_PASS      64
+/* Flags, OR-ed in the same way (single plan only), fixing the form of the
+ * x-update (eq. x_solution_rows_columns) for every block of the split.
+ * ADMM_XUPDATE_LEMMA: the inversion-lemma form (eq. inversion_lemma3) in
+ * push-through order, y_ij = G_ij^{-1}(g'_ij - H_ij c), u = c + H_ij^H y,
+ * ghat_ij = g'_ij - rho y, with G_ij = rho I + H_ij H_ij^H (m_i x m_i).
+ * ADMM_XUPDATE_DIRECT: the original inversion that Sec. III-B recommends for
+ * tall blocks, u = A_ij^{-1}(H_ij^H g'_ij + rho c), ghat_ij = H_ij u, with
+ * A_ij = rho I + H_ij^H H_ij (n_j x n_j): two passes over H per iteration
+ * (an adjoint product, then the forward product of u), never the single
+ * pass.  It is evaluated as a correction of the previous iteration's u,
+ * u = u_prev + A^{-1}(H^H r_i + rho (c - u_prev)) with r_i = g_i - sum_q
+ * ghat_iq the row block's residual (the same u; the inverse's rounding then
+ * scales with the step), and from u_prev = 0 after a reset or a state
+ * import.  Both inverses are formed in FP64 and stored as complex64.
+ * Without either flag (both: EINVAL) the plan takes the form whose iteration
+ * streams fewer bytes: H once (single pass) or twice plus the packed
+ * m_i x m_i inverses, against H twice plus the packed n_j x n_j inverses;
+ * with the single pass the direct form wins from about m_i >= (1 + sqrt 2) n_j,
+ * without it from m_i > n_j.  Direct-form plans have no reverse sweep
+ * (admm_solve_record and admm_backward return ADMM_EUNSUPPORTED). */
+#define ADMM_XUPDATE_LEMMA  128
+#define ADMM_XUPDATE_DIRECT 256
 
 typedef struct admm_plan admm_plan;
 
@@ -107,14 +129,11 @@ const char* admm_last_error(void);
  *             to m, or NULL for the equal split (the first m mod Q blocks
  *             get one extra row).  col_off likewise with P and n.
  *   storage   ADMM_STORAGE_*, optionally | ADMM_INVERSE_BF16 | ADMM_GRAM_PATCHES
- *             | ADMM_TWO_PASS.
+ *             | ADMM_TWO_PASS | ADMM_XUPDATE_LEMMA or ADMM_XUPDATE_DIRECT.
  *   out_bytes host, receives the size.
- * Errors: EINVAL for any bad size or split; EUNSUPPORTED when some block has
- * m_i >= (1 + sqrt 2) n_j (exactly: m_i^2 >= 2 m_i n_j + n_j^2).  Every block
- * takes the inversion-lemma (push-through) x-update, which streams the packed
- * m_i x m_i inverse each iteration; for blocks that tall the direct form of
- * Sec. III (an n_j x n_j inverse plus a third product with H_ij) would stream
- * less, and it is not built.
+ * Errors: EINVAL for any bad size or split, an unknown flag, or both
+ * x-update flags.  Every block shape is served, by one of the two forms of
+ * the x-update (see ADMM_XUPDATE_DIRECT).
  */
 int admm_workspace_bytes(int64_t m, int64_t n, int Q, const int64_t* row_off,
                          int P, const int64_t* col_off, int storage,
@@ -133,14 +152,17 @@ int admm_workspace_bytes(int64_t m, int64_t n, int Q, const int64_t* row_off,
  *         packed inverses once, the block vectors and the slab workgroups'
  *         row parts of H c (written and read once); with the two-pass
  *         kernels H twice, the inverses, the vectors and, with Q > 32, the
- *         z-update's second read of c and the partials;
- *     [2] FP64 flops of the setup (lower half of H_ij H_ij^H, Cholesky,
- *         triangular inverse and W^H W, 8 per complex multiply-add);
+ *         z-update's second read of c and the partials; in the direct form
+ *         H twice, the packed n_j x n_j inverses and the vectors;
+ *     [2] FP64 flops of the setup (lower half of H_ij H_ij^H, or of
+ *         H_ij^H H_ij in the direct form, Cholesky, triangular inverse and
+ *         W^H W, 8 per complex multiply-add);
  *     [3] bytes of the packed complex64 inverses, [4] bytes of stored H,
  *     [5] workspace bytes, [6] largest m_i, [7] largest n_j, [8] row chunks
  *     of the adjoint product, [9] 4 x 4 tile patches of the Gram apply (0:
  *     single tiles), [10] 1 if the split iterates in a single pass over H,
- *     [11] workgroups of the single-pass slab kernel, [12..15] 0.
+ *     [11] workgroups of the single-pass slab kernel, [12] 1 if the split
+ *     takes the direct x-update (see ADMM_XUPDATE_DIRECT), [13..15] 0.
  */
 int admm_split_cost(int64_t m, int64_t n, int Q, const int64_t* row_off,
                     int P, const int64_t* col_off, int storage, double* out16);
@@ -160,7 +182,8 @@ int admm_split_cost(int64_t m, int64_t n, int Q, const int64_t* row_off,
  *   Q_out, P_out  host, receive the split; model_s host or NULL, receives
  *                 the modelled seconds.
  * Errors: EINVAL (NULL outputs, iters < 0, rates not > 0, latency < 0),
- * EUNSUPPORTED (no candidate meets the exchange limit).
+ * EUNSUPPORTED (no candidate meets the exchange limit; the unsplit (1, 1)
+ * exchanges nothing, so only when its workspace would be too large).
  */
 int admm_choose_split(int64_t m, int64_t n, int iters, int storage,
                       double max_exchange, double hbm_gbs, double fp64_tflops,
@@ -169,9 +192,10 @@ int admm_choose_split(int64_t m, int64_t n, int iters, int storage,
 /*
  * admm_setup -- build a plan: copy/quantise H into the workspace and factor
  * every block's Gram matrix G_ij = rho I + H_ij H_ij^H once (FP64 Gram,
- * Cholesky and inverse on the GPU, stored as an FP32 Hermitian inverse).
- * This is the paper's one-off "inversion" step (Sec. III, inversion lemma;
- * Table tab:timing, "Inversion time").
+ * Cholesky and inverse on the GPU, stored as an FP32 Hermitian inverse), or
+ * A_ij = rho I + H_ij^H H_ij for a plan in the direct form (see
+ * ADMM_XUPDATE_DIRECT).  This is the paper's one-off "inversion" step
+ * (Sec. III, inversion lemma; Table tab:timing, "Inversion time").
  *   out       host, receives the plan (host memory, free with admm_destroy).
  *   H         device, m x n complex64, row-major with leading dimension n.
  *             Read only during this call; the caller may free it afterwards.
@@ -181,8 +205,8 @@ int admm_choose_split(int64_t m, int64_t n, int iters, int storage,
  *   workspace device, >= admm_workspace_bytes, 256-byte aligned; owned by the
  *             caller and must outlive the plan.
  *   stream    hipStream_t (void*).
- * Synchronises `stream`.  Errors: EINVAL, EUNSUPPORTED, EWORKSPACE,
- * ENONFINITE (NaN/Inf in H), ENOTPD, EHIP.  On error *out is set to NULL.
+ * Synchronises `stream`.  Errors: EINVAL, EWORKSPACE, ENONFINITE (NaN/Inf
+ * in H), ENOTPD, EHIP.  On error *out is set to NULL.
  */
 int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n,
                int Q, const int64_t* row_off, int P, const int64_t* col_off,
@@ -257,8 +281,9 @@ int admm_set_graphs(admm_plan* plan, int enable);
  *                      the end of the first checkpoint interval (iteration
  *                      min(interval, iters), reported by admm_get_state).
  * Errors: EINVAL; EWORKSPACE (tape too small); ESTATE (tape not recorded by
- * this plan, or lambda changed since); ENONFINITE; EHIP.  All synchronise
- * `stream`.
+ * this plan, or lambda changed since); ENONFINITE; EHIP; EUNSUPPORTED for a
+ * plan in the direct form (the sweep is built for the inversion-lemma form).
+ * All synchronise `stream`.
  */
 int admm_tape_bytes(const admm_plan* plan, int iters, int interval,
                     size_t* out_bytes);
@@ -349,13 +374,19 @@ int admm_get_stored_h(admm_plan* plan, void* re_out, void* im_out,
  * microseconds between the timed kernels, so sample (every > 1) inside a
  * throughput measurement.  Errors: EINVAL (every < 0), EHIP.
  */
-#define ADMM_K_GEMV_N   0   /* r_ij = g'_ij - H_ij c_j^i (two-pass)             */
-#define ADMM_K_GRAM     1   /* y_ij = G_ij^{-1} r_ij, ghat update               */
-#define ADMM_K_GEMV_H   2   /* partial H_ij^H y_ij (two-pass)                   */
-#define ADMM_K_ZUPDATE  3   /* mean, soft threshold, duals, norms (two-pass)    */
+#define ADMM_K_GEMV_N   0   /* r_ij = g'_ij - H_ij c_j^i (two-pass);            */
+                            /* direct form: ghat_ij = H_ij u_j^i                */
+#define ADMM_K_GRAM     1   /* y_ij = G_ij^{-1} r_ij, ghat update;              */
+                            /* direct form: the pieces of A_ij^{-1} d_ij        */
+#define ADMM_K_GEMV_H   2   /* partial H_ij^H y_ij (two-pass);                  */
+                            /* direct form: partial H_ij^H r_i                  */
+#define ADMM_K_ZUPDATE  3   /* mean, soft threshold, duals, norms (two-pass);   */
+                            /* direct form: u from the pieces, then the same    */
 #define ADMM_K_FZ_ROWS  4   /* single pass: r_ij from the slab parts of H c      */
 #define ADMM_K_FZ_SLAB  5   /* single pass: H^H y, z- and dual update, next H c */
-#define ADMM_K_COUNT    6
+#define ADMM_K_DIRECT_GP  6 /* direct form: row residuals r_i (or g') from ghat */
+#define ADMM_K_DIRECT_RHS 7 /* direct form: d = H^H r_i + rho (c - u_prev)     */
+#define ADMM_K_COUNT    8
 int admm_profile(admm_plan* plan, int every);
 int admm_profile_read(admm_plan* plan, int kernel, double* total_ms,
                       int64_t* launches);
@@ -365,7 +396,8 @@ int admm_profile_read(admm_plan* plan, int kernel, double* total_ms,
  * bytes of stored H, bytes of stored inverses, iterations done, padded row
  * and column space lengths, 4 x 4 tile patches of the Gram apply (0: one
  * tile per workgroup), 1 if the plan iterates in a single pass over H (else
- * 0), workgroups of the single-pass slab kernel, 0. */
+ * 0), workgroups of the single-pass slab kernel, 1 if the plan takes the
+ * direct x-update (else 0). */
 int admm_plan_info(const admm_plan* plan, int64_t* info16);
 
 /* Release the plan (host memory only; the workspace stays the caller's). */

@@ -26,9 +26,10 @@ STORAGE = {"c64": 0, "bf16": 1, "fp8": 2}
 INVERSE = {"c64": 0, "bf16": 16}   # ADMM_INVERSE_BF16: apply a bfloat16 copy of the block inverses
 GRAM_PATCHES = 32                   # ADMM_GRAM_PATCHES: always apply the inverses in 4 x 4 tile patches
 TWO_PASS = 64                       # ADMM_TWO_PASS: iterate with the two-pass kernels
-K_GEMV_N, K_GRAM, K_GEMV_H, K_ZUPDATE, K_FZ_ROWS, K_FZ_SLAB = 0, 1, 2, 3, 4, 5
+XUPDATE = {"auto": 0, "lemma": 128, "direct": 256}   # ADMM_XUPDATE_LEMMA / ADMM_XUPDATE_DIRECT
+K_GEMV_N, K_GRAM, K_GEMV_H, K_ZUPDATE, K_FZ_ROWS, K_FZ_SLAB, K_DIRECT_GP, K_DIRECT_RHS = range(8)
 KERNEL_NAMES = {K_GEMV_N: "k_gemv_n", K_GRAM: "k_gram", K_GEMV_H: "k_gemv_h", K_ZUPDATE: "k_zupdate",
-                K_FZ_ROWS: "k_fz_rows", K_FZ_SLAB: "k_fz_slab"}
+                K_FZ_ROWS: "k_fz_rows", K_FZ_SLAB: "k_fz_slab", K_DIRECT_GP: "k_dgp", K_DIRECT_RHS: "k_dbsum"}
 
 # (name, restype, argtypes) for every symbol of include/admm.h
 _c = ctypes
@@ -111,34 +112,35 @@ def _offsets(o):
     return arr, arr.ctypes.data_as(ctypes.c_void_p)
 
 
-def _flags(storage: str, inverse: str, gram_patches: bool, two_pass: bool = False) -> int:
+def _flags(storage: str, inverse: str, gram_patches: bool, two_pass: bool = False, xupdate: str = "auto") -> int:
     return (STORAGE[storage] | INVERSE[inverse] | (GRAM_PATCHES if gram_patches else 0)
-            | (TWO_PASS if two_pass else 0))
+            | (TWO_PASS if two_pass else 0) | XUPDATE[xupdate])
 
 
 def workspace_bytes(m: int, n: int, Q: int, P: int, row_off=None, col_off=None,
                     storage: str = "c64", inverse: str = "c64", gram_patches: bool = False,
-                    two_pass: bool = False) -> int:
+                    two_pass: bool = False, xupdate: str = "auto") -> int:
     ro, rp = _offsets(row_off)
     co, cp = _offsets(col_off)
     out = ctypes.c_size_t(0)
-    _check(lib().admm_workspace_bytes(m, n, Q, rp, P, cp, _flags(storage, inverse, gram_patches, two_pass),
+    _check(lib().admm_workspace_bytes(m, n, Q, rp, P, cp, _flags(storage, inverse, gram_patches, two_pass, xupdate),
                                       ctypes.byref(out)), "admm_workspace_bytes")
     return int(out.value)
 
 
 SPLIT_COST_KEYS = ["exchange_elements", "bytes_per_iteration", "setup_fp64_flops", "inverse_bytes", "h_bytes",
                    "workspace_bytes", "max_block_rows", "max_block_cols", "chunks", "gram_patches", "single_pass",
-                   "slab_workgroups"]
+                   "slab_workgroups", "direct"]
 
 
 def split_cost(m: int, n: int, Q: int, P: int, row_off=None, col_off=None, storage: str = "c64",
-               inverse: str = "c64", gram_patches: bool = False, two_pass: bool = False) -> dict:
+               inverse: str = "c64", gram_patches: bool = False, two_pass: bool = False,
+               xupdate: str = "auto") -> dict:
     ro, rp = _offsets(row_off)
     co, cp = _offsets(col_off)
     out = (ctypes.c_double * 16)()
-    _check(lib().admm_split_cost(m, n, Q, rp, P, cp, _flags(storage, inverse, gram_patches, two_pass), out),
-           "admm_split_cost")
+    _check(lib().admm_split_cost(m, n, Q, rp, P, cp, _flags(storage, inverse, gram_patches, two_pass, xupdate),
+                                 out), "admm_split_cost")
     return {k: float(out[i]) for i, k in enumerate(SPLIT_COST_KEYS)}
 
 
@@ -168,7 +170,8 @@ class Plan:
     """
 
     def __init__(self, H, Q: int, P: int, rho: float, lam: float, row_off=None, col_off=None,
-                 storage: str = "c64", inverse: str = "c64", gram_patches: bool = False, two_pass: bool = False):
+                 storage: str = "c64", inverse: str = "c64", gram_patches: bool = False, two_pass: bool = False,
+                 xupdate: str = "auto"):
         import torch
         if not (H.is_cuda and H.dtype == torch.complex64 and H.dim() == 2 and H.is_contiguous()):
             raise ValueError("H must be a contiguous complex64 CUDA tensor (m, n)")
@@ -179,8 +182,9 @@ class Plan:
         self.rho, self.lam = float(rho), float(lam)
         self.storage, self.inverse = storage, inverse
         self.row_off, self.col_off = row_off, col_off
-        flags = _flags(storage, inverse, gram_patches, two_pass)
-        nbytes = workspace_bytes(self.m, self.n, Q, P, row_off, col_off, storage, inverse, gram_patches, two_pass)
+        flags = _flags(storage, inverse, gram_patches, two_pass, xupdate)
+        nbytes = workspace_bytes(self.m, self.n, Q, P, row_off, col_off, storage, inverse, gram_patches, two_pass,
+                                 xupdate)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         _, rp = _offsets(row_off)
         _, cp = _offsets(col_off)
@@ -349,7 +353,7 @@ class Plan:
         arr = (ctypes.c_int64 * 16)()
         _check(lib().admm_plan_info(self._h, arr), "admm_plan_info")
         keys = ["m", "n", "Q", "P", "storage", "chunks", "workspace_bytes", "h_bytes", "ginv_bytes",
-                "iters_done", "m_pad", "n_pad", "gram_patches", "single_pass", "slab_workgroups"]
+                "iters_done", "m_pad", "n_pad", "gram_patches", "single_pass", "slab_workgroups", "direct"]
         return {k: int(arr[i]) for i, k in enumerate(keys)}
 
 

@@ -77,9 +77,14 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   const bool inv16 = (storage & ADMM_INVERSE_BF16) != 0;
   const bool force_patches = (storage & ADMM_GRAM_PATCHES) != 0;
   const bool two_pass = (storage & ADMM_TWO_PASS) != 0;
-  storage &= ~(ADMM_INVERSE_BF16 | ADMM_GRAM_PATCHES | ADMM_TWO_PASS);
+  const bool want_lemma = (storage & ADMM_XUPDATE_LEMMA) != 0, want_direct = (storage & ADMM_XUPDATE_DIRECT) != 0;
+  storage &= ~(ADMM_INVERSE_BF16 | ADMM_GRAM_PATCHES | ADMM_TWO_PASS | ADMM_XUPDATE_LEMMA | ADMM_XUPDATE_DIRECT);
   if (storage != ADMM_STORAGE_C64 && storage != ADMM_STORAGE_BF16 && storage != ADMM_STORAGE_FP8) {
     err = "unknown storage";
+    return ADMM_EINVAL;
+  }
+  if (want_lemma && want_direct) {
+    err = "ADMM_XUPDATE_LEMMA and ADMM_XUPDATE_DIRECT exclude each other";
     return ADMM_EINVAL;
   }
   geo.inv16 = inv16;
@@ -131,6 +136,66 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
     err = "problem too large";
     return ADMM_EINVAL;
   }
+  // H store row stride: whole 64-element groups (every lane load stays in
+  // the row), moved off multiples of 4 KB so consecutive rows do not all
+  // start on the same HBM channel.
+  auto row_stride = [&](int64_t nj) {
+    int64_t ldh = round_up(nj, kColPad);
+    if ((ldh * elem_bytes(storage)) % 4096 == 0) ldh += kColPad;
+    return ldh;
+  };
+  // Shape of the single-pass iteration (k_fused.hip) if the plan takes it:
+  // complex64 storage, at most kFzMaxQ row blocks, each row block on a whole
+  // number of waves: 512-thread workgroups (8 waves, two per CU) with RPL
+  // from kFzRpl, else 1024 threads (16 waves, one per CU) with RPL <= 6.
+  // Otherwise, with ADMM_TWO_PASS or in the direct form, the two-pass kernels.
+  std::vector<int> gi(Q);   // 64-row groups of each row block
+  for (int i = 0; i < Q; ++i) gi[i] = (int)(ldr[i] / kWave);
+  int fz_nt = 0, fz_rpl = 0;
+  if (!two_pass && storage == ADMM_STORAGE_C64 && Q <= kFzMaxQ) {
+    auto waves = [&](int rpl) {
+      int w = 0;
+      for (int i = 0; i < Q; ++i) w += (gi[i] + rpl - 1) / rpl;
+      return w;
+    };
+    const char* ent = getenv("ADMM_FZ_NT");
+    const int want_nt = ent ? atoi(ent) : 0;
+    if (want_nt != 1024)
+      for (int r : kFzRpl)
+        if (waves(r) <= 8) {
+          fz_nt = 512;
+          fz_rpl = r;
+          break;
+        }
+    if (!fz_nt)
+      for (int r : {1, 2, 3, 4, 6})
+        if (waves(r) <= 16) {
+          fz_nt = 1024;
+          fz_rpl = r;
+          break;
+        }
+  }
+  // Form of the x-update (Sec. III-B, the remark after eq. inversion_lemma2;
+  // Sec. III-C before eq. inversion_lemma3): unless a flag fixes it, the one
+  // whose iteration streams fewer bytes, H once (single pass) or twice plus
+  // the packed m_i x m_i inverses, or H twice plus the packed n_j x n_j ones.
+  {
+    auto packed = [](int64_t e) {
+      const double T = (double)((e + kTile - 1) / kTile);
+      return T * (T + 1) / 2 * kTile * kTile;
+    };
+    double hb = 0.0, lem = 0.0, dir = 0.0;
+    for (int i = 0; i < Q; ++i)
+      for (int j = 0; j < P; ++j) {
+        const int64_t mi = geo.ro[i + 1] - geo.ro[i], nj = geo.co[j + 1] - geo.co[j];
+        hb += (double)mi * (double)row_stride(nj) * elem_bytes(storage);
+        lem += packed(mi);
+        dir += packed(nj);
+      }
+    const double esz = inv16 ? 4.0 : 8.0;
+    const double lemma_bytes = (fz_nt ? 1.0 : 2.0) * hb + esz * lem, direct_bytes = 2.0 * hb + esz * dir;
+    geo.direct = want_direct || (!want_lemma && direct_bytes < lemma_bytes);
+  }
   geo.blocks.clear();
   int64_t hoff = 0, gioff = 0, foff = 0, gpo = 0;
   int max_mi = 0;
@@ -142,28 +207,10 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
       d.j = j;
       d.mi = (int32_t)(geo.ro[i + 1] - geo.ro[i]);
       d.nj = (int32_t)(geo.co[j + 1] - geo.co[j]);
-      // The push-through x-update serves any block shape.  Per iteration it
-      // streams the packed m_i x m_i inverse; the direct form of tall blocks
-      // (Sec. III) would stream an n_j x n_j one plus a third pass over H_ij
-      // (for its estimated data).  The first is the smaller stream while
-      // m_i^2 < 2 m_i n_j + n_j^2, i.e. m_i < (1 + sqrt 2) n_j; taller blocks
-      // would need the direct form, which is not built.
-      if ((int64_t)d.mi * d.mi >= 2 * (int64_t)d.mi * d.nj + (int64_t)d.nj * d.nj) {
-        snprintf(buf, sizeof buf,
-                 "block (%d,%d) is %d x %d: at least (1 + sqrt 2) times taller than wide, where the direct "
-                 "x-update that is not built would stream less than the inversion-lemma one",
-                 i, j, d.mi, d.nj);
-        err = buf;
-        return ADMM_EUNSUPPORTED;
-      }
-      // H store row stride: whole 64-element groups (every lane load stays in
-      // the row), moved off multiples of 4 KB so consecutive rows do not all
-      // start on the same HBM channel.
-      int64_t ldh = round_up(d.nj, kColPad);
-      if ((ldh * elem_bytes(storage)) % 4096 == 0) ldh += kColPad;
-      d.ld = (int32_t)ldh;
+      d.ld = (int32_t)row_stride(d.nj);
       d.ldr = (int32_t)ldr[i];
-      d.mt = (int32_t)round_up(d.mi, kTile);
+      d.gd = geo.direct ? d.nj : d.mi;
+      d.mt = (int32_t)round_up(d.gd, kTile);
       d.row0 = (int32_t)geo.ro[i];
       d.col0 = (int32_t)geo.co[j];
       d.rpad0 = (int32_t)rpad0[i];
@@ -244,42 +291,22 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   for (int j = 0; j < P; ++j)
     for (int c = 0; c < geo.cols[j].nj; c += kZCols) geo.t_z.push_back(make_int4(j, c, 0, 0));
 
-  // Single-pass iteration (k_fused.hip): complex64 storage, at most kFzMaxQ
-  // row blocks, each row block on a whole number of waves: 512-thread
-  // workgroups (8 waves, two per CU) with RPL from kFzRpl, else 1024 threads
-  // (16 waves, one per CU) with RPL <= 6.  Otherwise, or with ADMM_TWO_PASS,
-  // the two-pass kernels.
+  // direct form: rows of the local-data kernel
+  geo.t_dgp.clear();
+  if (geo.direct)
+    for (int i = 0; i < Q; ++i)
+      for (int64_t r = 0; r < geo.ro[i + 1] - geo.ro[i]; r += kBlockThreads)
+        geo.t_dgp.push_back(make_int4(i, (int)r, 0, 0));
+
+  // Single-pass iteration tables (shape chosen above)
   geo.fz = false;
   geo.t_fz.clear();
   geo.fz_colwg.clear();
   geo.t_fzr.clear();
   geo.fzt = FzArgs{};
-  if (!two_pass && storage == ADMM_STORAGE_C64 && Q <= kFzMaxQ) {
-    std::vector<int> gi(Q);   // 64-row groups of each row block
-    for (int i = 0; i < Q; ++i) gi[i] = (int)(ldr[i] / kWave);
-    auto waves = [&](int rpl) {
-      int w = 0;
-      for (int i = 0; i < Q; ++i) w += (gi[i] + rpl - 1) / rpl;
-      return w;
-    };
-    int nt = 0, rpl = 0;
-    const char* ent = getenv("ADMM_FZ_NT");
-    const int want_nt = ent ? atoi(ent) : 0;
-    if (want_nt != 1024)
-      for (int r : kFzRpl)
-        if (waves(r) <= 8) {
-          nt = 512;
-          rpl = r;
-          break;
-        }
-    if (!nt)
-      for (int r : {1, 2, 3, 4, 6})
-        if (waves(r) <= 16) {
-          nt = 1024;
-          rpl = r;
-          break;
-        }
-    if (nt) {
+  if (fz_nt && !geo.direct) {
+    const int nt = fz_nt, rpl = fz_rpl;
+    {
       FzArgs& z = geo.fzt;
       int w = 0;
       for (int i = 0; i < Q; ++i) {
@@ -357,9 +384,12 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   L.part = take(colv * Q * geo.KH);
   L.gp = take(rowv * P);
   L.ghat = take(rowv * P);
-  L.r = take(rowv * P);
-  L.y = take(rowv * P);
+  // the Gram-space vectors: row space, or column space in the direct form
+  const size_t gspace = geo.direct ? colv * Q : rowv * P;
+  L.r = take(gspace);
+  L.y = take(gspace);
   L.fpart = take((size_t)geo.t_fz.size() * rowv);   // in the state region: zeroed with it
+  L.dflag = take(16);                                  // direct form: the u_ref word (zeroed with the state)
   L.blocks = take(sizeof(BlockDesc) * geo.blocks.size());
   L.cols = take(sizeof(ColDesc) * P);
   L.t_rows = take(16 * geo.t_rows.size());
@@ -374,6 +404,7 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
   L.t_fz = take(16 * std::max<size_t>(geo.t_fz.size(), 1));
   L.fz_colwg = take(8 * std::max<size_t>(geo.fz_colwg.size(), 1));
   L.t_fzr = take(16 * std::max<size_t>(geo.t_fzr.size(), 1));
+  L.t_dgp = take(16 * std::max<size_t>(geo.t_dgp.size(), 1));
   L.gpart = take((size_t)gpo * kTile * 8);
   L.ctl = take(sizeof(Control));
   L.redpart = take(8 * kRedCount * std::max(geo.t_z.size(), geo.t_fz.size()));
@@ -461,6 +492,8 @@ struct admm_plan {
   // pass recomputes them before the first iteration)
   int4 *t_fz = nullptr, *t_fzr = nullptr;
   int2* fz_colwg = nullptr;
+  int4* t_dgp = nullptr;   // direct form: rows of the local-data kernel
+  int* dflag = nullptr;    // direct form: 1 when y holds the last u and ghat = H y
   FzArgs fz{};
   bool fz_valid = true;
   // graph replay of fixed-length runs of iterations (admm_solve): captured on
@@ -568,6 +601,8 @@ IterArgs iter_args(admm_plan* p, const float2* g, double* hist) {
   a.xstage = x4 <= kXStage ? 1 : 0;
   a.wide = 0;
   for (const ColDesc& cd : p->geo.cols) a.wide |= cd.nj > kWholeCols ? 1 : 0;
+  a.direct = p->geo.direct ? 1 : 0;
+  a.uref = p->dflag;
   return a;
 }
 
@@ -675,14 +710,14 @@ void split_cost(const Geometry& geo, double* out) {
     const double T = d.mt / kTile;
     ginv += T * (T + 1) / 2 * kTile * kTile;
     parts += T * (patch ? std::ceil(T / 4) + 1 : T);
-    // FP64 setup: lower half of H H^H (m_i (m_i + 1) / 2 n_j complex
-    // multiply-adds), Cholesky, triangular inverse and W^H W (m_i^3 / 3 each),
-    // 8 real flops per complex multiply-add
-    const double a = d.mi, b = d.nj;
+    // FP64 setup: lower half of the Gram matrix (gd (gd + 1) / 2 times the
+    // other edge complex multiply-adds), Cholesky, triangular inverse and
+    // W^H W (gd^3 / 3 each), 8 real flops per complex multiply-add
+    const double a = d.gd, b = geo.direct ? d.mi : d.nj;
     flops += 8.0 * (a * (a + 1) / 2 * b + a * a * a);
   }
-  const double gemv_n = h + vcols + c * m + (P > 1 ? (P - 1) * vrows + 2 * vrows : vrows);
-  const double gram = ginv * (geo.inv16 ? 4.0 : c) + 2 * parts * kTile * c + vrows * (P > 1 ? 4 : 3);
+  double gemv_n = h + vcols + c * m + (P > 1 ? (P - 1) * vrows + 2 * vrows : vrows);
+  double gram = ginv * (geo.inv16 ? 4.0 : c) + 2 * parts * kTile * c + vrows * (P > 1 ? 4 : 3);
   const double gemv_h = h + vrows + geo.KH * vcols;
   // more than 32 replicas do not stay in registers: the z-update reads c and
   // the row-chunk partials a second time
@@ -690,6 +725,19 @@ void split_cost(const Geometry& geo, double* out) {
   for (int k = 0; k < 16; ++k) out[k] = 0.0;
   out[0] = exch;
   out[1] = gemv_n + gram + gemv_h + zupd;
+  if (geo.direct) {
+    // direct form: the residuals of every block (reads g and ghat, writes
+    // one row vector per block), their adjoint product, d = the partials +
+    // rho (c - u_prev), the Gram apply to d (its pieces are added by the
+    // z-update), the z-update (reads the pieces, u_prev and s, writes s, c and
+    // u, reads and writes v), the row product ghat = H u
+    const double dgp = c * m + 2 * vrows;
+    const double rhs = (geo.KH + 3) * vcols;
+    gram = ginv * (geo.inv16 ? 4.0 : c) + parts * kTile * c + vcols;
+    const double dz = parts * kTile * c + 5 * vcols + 2 * c * n;
+    gemv_n = h + vcols + vrows;
+    out[1] = dgp + gemv_h + rhs + gram + dz + gemv_n;
+  }
   if (geo.fz) {
     // single pass: the slab kernel reads H once, y, c and s, writes c, s, v
     // and its row parts of H c; the row kernel reads the parts and forms r
@@ -708,6 +756,7 @@ void split_cost(const Geometry& geo, double* out) {
   out[9] = (double)geo.t_gpatch.size();
   out[10] = geo.fz ? 1.0 : 0.0;
   out[11] = (double)geo.t_fz.size();
+  out[12] = geo.direct ? 1.0 : 0.0;
 }
 }  // namespace
 
@@ -827,6 +876,8 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
   p->t_fz = at<int4>(p, L.t_fz);
   p->t_fzr = at<int4>(p, L.t_fzr);
   p->fz_colwg = at<int2>(p, L.fz_colwg);
+  p->t_dgp = at<int4>(p, L.t_dgp);
+  p->dflag = at<int>(p, L.dflag);
   p->fz = p->geo.fzt;
   p->fz.hsl = HStore{p->ws + L.Hs, nullptr, nullptr, ADMM_STORAGE_C64};
   p->fz.fpart = at<float2>(p, L.fpart);
@@ -876,6 +927,8 @@ int admm_setup(admm_plan** out, const void* H, int64_t m, int64_t n, int Q, cons
     SETUP_TRY(hipMemcpyAsync(p->fz_colwg, G.fz_colwg.data(), 8 * G.fz_colwg.size(), hipMemcpyHostToDevice, st));
     SETUP_TRY(hipMemcpyAsync(p->t_fzr, G.t_fzr.data(), 16 * G.t_fzr.size(), hipMemcpyHostToDevice, st));
   }
+  if (G.direct)
+    SETUP_TRY(hipMemcpyAsync(p->t_dgp, G.t_dgp.data(), 16 * G.t_dgp.size(), hipMemcpyHostToDevice, st));
   SETUP_TRY(hipMemcpyAsync(p->row_block, p->h_row_block.data(), 8 * (size_t)m, hipMemcpyHostToDevice, st));
   int max_mi = 0;
   for (auto& d : G.blocks) max_mi = std::max(max_mi, d.mi);
@@ -918,7 +971,27 @@ int launch_iteration(admm_plan* p, const IterArgs& a, const FzArgs& z, int k, hi
   auto gram = [&](KTime kt) {
     return launch_gram(a, p->t_gram, ngr, p->t_gpatch, (int)G.t_gpatch.size(), p->t_gtr, ngt, st, kt);
   };
-  if (G.fz) {
+  if (G.direct) {
+    // Direct form (Sec. III-B) as a correction of the previous u (k_iter.hip):
+    // the row residuals (or g') of every block from the estimates, their
+    // adjoint product (row-chunk partials), d = H^H r + rho (c - u_ref), the
+    // pieces of A^{-1} d, the z- and dual update on u = u_ref + A^{-1} d
+    // (which also stores u), and the estimated data ghat = H u.
+    IterArgs ah = a, af = a;
+    ah.y = a.gp;   // the adjoint product reads g'
+    af.c = a.y;    // the row product reads u
+    const int nz = (int)G.t_z.size();
+    const int src = (!a.Ginv16 && !G.t_gpatch.empty()) ? 1 : 2;
+    auto gram_apply = [&](KTime kt) {
+      return launch_gram(a, p->t_gram, ngr, p->t_gpatch, (int)G.t_gpatch.size(), p->t_gtr, ngt, st, kt, false);
+    };
+    if ((rc = timed(p, ADMM_K_DIRECT_GP, k, st, [&](KTime kt) { return launch_direct_gp(a, p->t_dgp, (int)G.t_dgp.size(), st, kt); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GEMV_H, k, st, [&](KTime kt) { return launch_gemv_h(ah, p->t_cols, (int)G.t_cols.size(), st, kt); }))) return rc;
+    if ((rc = timed(p, ADMM_K_DIRECT_RHS, k, st, [&](KTime kt) { return launch_direct_rhs(a, p->t_z, nz, st, kt); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GRAM, k, st, gram_apply))) return rc;
+    if ((rc = timed(p, ADMM_K_ZUPDATE, k, st, [&](KTime kt) { return launch_zupdate(a, p->t_z, nz, st, kt, src); }))) return rc;
+    if ((rc = timed(p, ADMM_K_GEMV_N, k, st, [&](KTime kt) { return launch_gemv_n(af, p->t_hrows, (int)G.t_hrows.size(), p->t_wrows, (int)G.t_wrows.size(), st, kt); }))) return rc;
+  } else if (G.fz) {
     if ((rc = timed(p, ADMM_K_FZ_ROWS, k, st, [&](KTime kt) { return launch_fz_rows(a, z, p->t_fzr, (int)G.t_fzr.size(), st, kt); }))) return rc;
     if ((rc = timed(p, ADMM_K_GRAM, k, st, gram))) return rc;
     if ((rc = timed(p, ADMM_K_FZ_SLAB, k, st, [&](KTime kt) { return launch_fz_slab(a, z, G.fz_nt, G.fz_rpl, st, kt); }))) return rc;
@@ -1066,6 +1139,7 @@ int admm_solve_record(admm_plan* p, const void* g, int iters, int interval, void
   if (!p) return fail(ADMM_EINVAL, "plan is NULL");
   if (!g || !v_out || !tape) return fail(ADMM_EINVAL, "g, v_out and tape must not be NULL");
   if (iters < 1 || interval < 1) return fail(ADMM_EINVAL, "iters and interval must be >= 1");
+  if (p->geo.direct) return fail(ADMM_EUNSUPPORTED, "the reverse sweep is built for the inversion-lemma form only");
   const Geometry& G = p->geo;
   const TapeLayout T = tape_layout(G, iters, interval);
   if (tape_bytes < T.total || (reinterpret_cast<uintptr_t>(tape) & 255))
@@ -1123,6 +1197,7 @@ int admm_backward(admm_plan* p, const void* g, const void* grad_v, void* tape, v
   if (!p) return fail(ADMM_EINVAL, "plan is NULL");
   if (!g || !grad_v || !tape || !grad_g || !grad_lambda || !grad_rho)
     return fail(ADMM_EINVAL, "g, grad_v, tape, grad_g, grad_lambda and grad_rho must not be NULL");
+  if (p->geo.direct) return fail(ADMM_EUNSUPPORTED, "the reverse sweep is built for the inversion-lemma form only");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Geometry& G = p->geo;
   char* tp = static_cast<char*>(tape);
@@ -1369,7 +1444,7 @@ int admm_plan_info(const admm_plan* p, int64_t* info) {
   const Geometry& G = p->geo;
   int64_t v[16] = {G.m, G.n, G.Q, G.P, G.storage, G.KH, (int64_t)G.lay.total, (int64_t)G.lay.h_bytes,
                    (int64_t)G.lay.ginv_bytes, p->k_done, G.m_pad, G.n_pad, (int64_t)G.t_gpatch.size(),
-                   G.fz ? 1 : 0, (int64_t)G.t_fz.size(), 0};
+                   G.fz ? 1 : 0, (int64_t)G.t_fz.size(), G.direct ? 1 : 0};
   std::memcpy(info, v, sizeof v);
   return ADMM_OK;
 }

@@ -171,6 +171,7 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
     if ((ldh * 2) % 4096 == 0) ldh += kColPad;
     d.ld = (int32_t)ldh;
     d.ldr = 0;
+    d.gd = d.mi;
     d.mt = (int32_t)G.mt0;
     d.row0 = 0;
     d.col0 = (int32_t)G.co[j];
@@ -225,6 +226,7 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
           return ADMM_EUNSUPPORTED;
         }
         d.ldr = (int32_t)round_up(d.mi, kRowPad);
+        d.gd = d.mi;
         d.mt = (int32_t)round_up(d.mi, kTile);
         d.row0 = rb.row0;
         d.col0 = G.cols[j].col0;

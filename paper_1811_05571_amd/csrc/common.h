@@ -44,8 +44,11 @@ struct BlockDesc {
   int32_t i, j;     // row block, column block
   int32_t mi, nj;   // rows, columns
   int32_t ld;       // H row stride (complex elements) = padded nj
-  int32_t ldr;      // inverse row stride = padded mi
-  int32_t mt;       // mi rounded up to kTile (setup matrices are mt x mt)
+  int32_t ldr;      // padded mi
+  int32_t gd;       // edge of the block's Gram matrix: mi (inversion-lemma
+                    // x-update, G = rho I + H H^H) or nj (direct x-update,
+                    // A = H^H H + rho I)
+  int32_t mt;       // gd rounded up to kTile (setup matrices are mt x mt)
   int32_t row0;     // first global row
   int32_t col0;     // first global column
   int32_t rpad0;    // offset of row block i in padded row space

@@ -529,6 +529,7 @@ struct RowEpi {
 template <class F>
 __device__ __forceinline__ void row_epi_load(const IterArgs& a, const BlockDesc& d, const F& f, int lr, RowEpi& o) {
   o.sc = f.row_scale(d.row0 + lr);
+  if (a.direct) return;   // the direct form's row product only scales its sums
   o.g = a.g[d.row0 + lr];
   o.pre = a.P - 1 <= kEpiSections;
 #pragma unroll
@@ -540,9 +541,15 @@ __device__ __forceinline__ void row_epi_load(const IterArgs& a, const BlockDesc&
 // r_ij = g'_ij - s (H c) for row lr of block (i, j), with (ar, ai) the row's
 // product; eq. g_rows_columns: g'_ij = g_i minus the other sections'
 // estimated data (compensated sums, sections in order), stored when P > 1.
+// In the direct form the product is the block's estimated data instead,
+// ghat_ij = H_ij u_j^i (Sec. III-C text).
 __device__ __forceinline__ void row_epi_store(const IterArgs& a, const BlockDesc& d, int lr, float ar, float ai,
                                               const RowEpi& o) {
   const int64_t vi = (int64_t)d.j * a.m_pad + d.rpad0 + lr;
+  if (a.direct) {
+    a.ghat[vi] = make_float2(o.sc * ar, o.sc * ai);
+    return;
+  }
   float2 gpv = o.g;
   if (a.P > 1) {
     CSum sr, si;

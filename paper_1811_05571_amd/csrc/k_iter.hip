@@ -47,6 +47,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_n(IterArgs a, const int4
   if (blockIdx.x == 0) {
     __shared__ double red[kBlockThreads / kWave][kRedCount];
     zfinal(a, red);
+    if (a.direct && threadIdx.x == 0) *a.uref = 1;   // ghat = H y from here on
   }
   const F f = MakeFmt<F>::make(a.hs);
   // wave index in a scalar register: the rows' addresses are then wave-uniform
@@ -108,6 +109,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_nw(IterArgs a, const int
   if (blockIdx.x == 0) {
     __shared__ double zred[NW][kRedCount];
     zfinal(a, zred);
+    if (a.direct && threadIdx.x == 0) *a.uref = 1;   // ghat = H y from here on
   }
   const F f = MakeFmt<F>::make(a.hs);
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
@@ -214,6 +216,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_nw(IterArgs a, const int
   }
 }
 
+// The block's segment of the Gram-space vectors r and y: row space in the
+// inversion-lemma form, column space in the direct form.
+__device__ __forceinline__ int64_t gvec(const IterArgs& a, const BlockDesc& d) {
+  return a.direct ? (int64_t)d.i * a.n_pad + d.cpad0 : (int64_t)d.j * a.m_pad + d.rpad0;
+}
+
 // y_ij = G_ij^{-1} r_ij over the packed lower tiles of the inverse: every
 // tile is read once and contributes to two 64-row pieces of y (gram_tile_apply);
 // k_gram_reduce adds the pieces in tile order and forms ghat_ij = g'_ij - rho y_ij.
@@ -224,7 +232,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_gram_tile_bf16(IterArgs a, co
   const BlockDesc d = a.blocks[t.x];
   const int T = d.mt / kTile;
   const uint32_t* G = a.Ginv16 + d.gi_off + (int64_t)(t.y * (t.y + 1) / 2 + t.z) * (kTile * kTile);
-  const float2* x = a.r + (int64_t)d.j * a.m_pad + d.rpad0;
+  const float2* x = a.r + gvec(a, d);
   float2* part = a.gpart + (int64_t)d.gpo * kTile;
   gram_tile_apply_bf16(G, x + t.y * kTile, x + t.z * kTile, t.y == t.z, part + (int64_t)(t.y * T + t.z) * kTile,
                        part + (int64_t)(t.z * T + t.y) * kTile, tt);
@@ -246,7 +254,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_gram_tile(IterArgs a, const i
   const BlockDesc d = a.blocks[t.x];
   const int T = d.mt / kTile;
   const float2* G = a.Ginv + d.gi_off + (int64_t)(t.y * (t.y + 1) / 2 + t.z) * (kTile * kTile);
-  const float2* x = a.r + (int64_t)d.j * a.m_pad + d.rpad0;
+  const float2* x = a.r + gvec(a, d);
   float2* part = a.gpart + (int64_t)d.gpo * kTile;
   gram_tile_apply(G, x + t.y * kTile, x + t.z * kTile, t.y == t.z, part + (int64_t)(t.y * T + t.z) * kTile,
                   part + (int64_t)(t.z * T + t.y) * kTile, tt);
@@ -270,7 +278,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_gram_patch(IterArgs a, const 
   const int R = t.y, C = t.z, a0 = 4 * R, c0 = 4 * C;
   const int na = min(4, T - a0), nc = min(4, T - c0);
   const bool dg = R == C;
-  const float2* x = a.r + (int64_t)d.j * a.m_pad + d.rpad0;
+  const float2* x = a.r + gvec(a, d);
   const float2* G0 = a.Ginv + d.gi_off;
   float pr[4][4], pi[4][4], cr[4][4], ci[4][4];
 #pragma unroll
@@ -357,8 +365,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_h(IterArgs a, const int4
 // when Q <= MAXQ (MAXQ = 0: any Q, partials are read twice).  Each workgroup
 // writes its five FP64 partial sums (a fixed shuffle tree over its lanes);
 // zfinal adds them in the next kernel.
-template <int MAXQ>
+// SRC: where the replicas u_j^i come from.  0: u = c + the row-chunk
+// partials of H^H y (inversion-lemma form).  1, 2: direct form, u = u_ref +
+// A_ij^{-1} d_ij, the sum of the Gram-apply pieces of the column's 64-tile
+// (laid out by k_gram_patch, 1, or by k_gram_tile / k_gram_tile_bf16, 2)
+// added to the previous u kept in y (u_ref = 0 while *uref is 0); the new u
+// is stored in y in the layout of c for the next row product.
+template <int MAXQ, int SRC>
 __global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __restrict__ tiles) {
+  const bool ur = SRC != 0 && *a.uref != 0;
   const int4 t = tiles[blockIdx.x];
   const ColDesc cd = a.cols[t.x];
   const int col = t.y + threadIdx.x;
@@ -372,17 +387,33 @@ __global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __re
     // u = c + the row-chunk partials, and the consensus sum of u + s over the
     // replicas: compensated FP32 sums in fixed order
     auto replica = [&](int i, float& xr, float& xi) {
-      const float2 ci = a.c[(int64_t)i * a.n_pad + pc];
       CSum sr, si;
-      sr.add(ci.x);
-      si.add(ci.y);
-      const float2* pp = a.part + (int64_t)i * a.n_pad + p;
-      const int64_t stride = (int64_t)a.Q * a.n_pad;
+      if constexpr (SRC == 0) {
+        const float2 ci = a.c[(int64_t)i * a.n_pad + pc];
+        sr.add(ci.x);
+        si.add(ci.y);
+        const float2* pp = a.part + (int64_t)i * a.n_pad + p;
+        const int64_t stride = (int64_t)a.Q * a.n_pad;
 #pragma unroll 8
-      for (int k = 0; k < a.KH; ++k) {
-        const float2 pk = pp[k * stride];
-        sr.add(pk.x);
-        si.add(pk.y);
+        for (int k = 0; k < a.KH; ++k) {
+          const float2 pk = pp[k * stride];
+          sr.add(pk.x);
+          si.add(pk.y);
+        }
+      } else {
+        if (ur) {
+          const float2 u0 = a.y[(int64_t)i * a.n_pad + pc];
+          sr.add(u0.x);
+          si.add(u0.y);
+        }
+        const BlockDesc& d = a.blocks[i * a.P + t.x];
+        const int T = d.mt / kTile, NS = SRC == 1 ? (T + 3) / 4 + 1 : T;
+        const float2* pp = a.gpart + ((int64_t)d.gpo + (int64_t)(col / kTile) * NS) * kTile + (col % kTile);
+        for (int k = 0; k < NS; ++k) {
+          const float2 pk = pp[(int64_t)k * kTile];
+          sr.add(pk.x);
+          si.add(pk.y);
+        }
       }
       xr = sr.value();
       xi = si.value();
@@ -436,6 +467,7 @@ __global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __re
       const float sr = si.x + dr, sim = si.y + di;
       a.s[ip] = make_float2(sr, sim);
       a.c[(int64_t)i * a.n_pad + pc] = make_float2(vr - sr, vi - sim);
+      if (SRC != 0) a.y[(int64_t)i * a.n_pad + pc] = make_float2(xr, xi);
       acc[kRedRp2] += (double)dr * dr + (double)di * di;
       acc[kRedU2] += (double)xr * xr + (double)xi * xi;
       acc[kRedS2] += (double)sr * sr + (double)sim * sim;
@@ -452,6 +484,92 @@ __global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __re
     for (int q = 0; q < kRedCount; ++q) a.redpart[(int64_t)blockIdx.x * kRedCount + q] = acc[q];
     if (blockIdx.x == 0) a.ctl->zpending = 1;
   }
+}
+
+// Direct form.  The x-update of eq. x_solution_rows_columns,
+// u = A^{-1}(H^H g' + rho c) with A = H^H H + rho I, is evaluated as a
+// correction of a reference point u_ref whose product H u_ref is known:
+//     u = u_ref + A^{-1} d,   d = H^H (g' - H u_ref) + rho (c - u_ref),
+// the same u for any u_ref.  With u_ref the previous iteration's u (kept in
+// y; its product is that block's estimate ghat_ij), g' - H u_ref is the row
+// block's residual g_i - sum_q ghat_iq, the same for every j; the inverse
+// then acts on a correction that vanishes at the fixed point, so its
+// rounding (FP32, or the bfloat16 copy) scales with the step and not with u.
+// After a reset or a state import (*uref = 0) u_ref = 0 and d = H^H g' + rho c.
+//
+// gp of every block of some rows: the residual g_i - sum_q ghat_iq (one
+// compensated sum, sections in order), or with u_ref = 0 the local data g'_ij
+// = g_i - sum_{q != j} ghat_iq (eq. g_rows_columns, that sum with the block's
+// own estimate added back to a copy).  tiles[x] = {row block, first row, -,
+// -}, kBlockThreads rows each.  Workgroup 0 first completes the previous
+// z-update's residual sums.
+__global__ __launch_bounds__(kBlockThreads) void k_dgp(IterArgs a, const int4* __restrict__ tiles) {
+  const bool ur = *a.uref != 0;
+  const int4 t = tiles[blockIdx.x];
+  const BlockDesc d = a.blocks[t.x * a.P];
+  if (blockIdx.x == 0) {
+    __shared__ double red[kBlockThreads / kWave][kRedCount];
+    zfinal(a, red);
+  }
+  const int lr = t.y + threadIdx.x;
+  if (lr >= d.mi) return;
+  const float2 g = a.g[d.row0 + lr];
+  const float2* e = a.ghat + d.rpad0 + lr;
+  CSum tr, ti;
+  tr.add(g.x);
+  ti.add(g.y);
+#pragma unroll 8
+  for (int q = 0; q < a.P; ++q) {
+    const float2 eq = e[(int64_t)q * a.m_pad];
+    tr.add(-eq.x);
+    ti.add(-eq.y);
+  }
+  float2* gp = a.gp + d.rpad0 + lr;
+  if (ur) {
+    const float2 r = make_float2(tr.value(), ti.value());
+#pragma unroll 8
+    for (int j = 0; j < a.P; ++j) gp[(int64_t)j * a.m_pad] = r;
+    return;
+  }
+#pragma unroll 8
+  for (int j = 0; j < a.P; ++j) {
+    const float2 ej = e[(int64_t)j * a.m_pad];
+    CSum sr = tr, si = ti;
+    sr.add(ej.x);
+    si.add(ej.y);
+    gp[(int64_t)j * a.m_pad] = make_float2(sr.value(), si.value());
+  }
+}
+
+// Direct form, the right-hand side d_ij = H_ij^H gp_ij + rho (c - u_ref) from
+// c and u_ref (both in the lane-permuted layout of c) and the row-chunk
+// partials of the adjoint product (compensated, in chunk order), stored in r
+// in the natural column layout that the Gram apply reads.  grid = (column
+// tiles, Q); tiles[x] = {column block, first column, -, -} (those of the
+// z-update).
+__global__ __launch_bounds__(kZCols) void k_dbsum(IterArgs a, const int4* __restrict__ tiles) {
+  const bool ur = *a.uref != 0;
+  const int4 t = tiles[blockIdx.x];
+  const ColDesc cd = a.cols[t.x];
+  const int i = blockIdx.y, col = t.y + threadIdx.x;
+  if (col >= cd.nj) return;
+  const int64_t p = (int64_t)i * a.n_pad + cd.cpad0 + col, pc = (int64_t)i * a.n_pad + cd.cpad0 + cperm(col, a.cpl);
+  float2 c = a.c[pc];
+  if (ur) {
+    const float2 u0 = a.y[pc];
+    c = make_float2(c.x - u0.x, c.y - u0.y);
+  }
+  CSum sr, si;
+  sr.add(a.rho * c.x);
+  si.add(a.rho * c.y);
+  const int64_t stride = (int64_t)a.Q * a.n_pad;
+#pragma unroll 8
+  for (int k = 0; k < a.KH; ++k) {
+    const float2 pk = a.part[k * stride + p];
+    sr.add(pk.x);
+    si.add(pk.y);
+  }
+  a.r[p] = make_float2(sr.value(), si.value());
 }
 
 // Copy between the padded column space and a dense n-vector (reps copies at
@@ -538,16 +656,17 @@ hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, const
   return hipGetLastError();
 }
 hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gpatch, int n_gpatch,
-                       const int4* t_gtr, int n_gtr, hipStream_t st, KTime kt) {
+                       const int4* t_gtr, int n_gtr, hipStream_t st, KTime kt, bool reduce) {
   const bool patch = !a.Ginv16 && n_gpatch > 0;
+  const KTime ka{kt.start, reduce ? nullptr : kt.stop};
   if (a.Ginv16)
-    LAUNCH_TIMED(k_gram_tile_bf16, dim3(n_gram), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gram);
+    LAUNCH_TIMED(k_gram_tile_bf16, dim3(n_gram), dim3(kBlockThreads), st, ka, a, t_gram);
   else if (patch)
-    LAUNCH_TIMED(k_gram_patch, dim3(n_gpatch), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gpatch);
+    LAUNCH_TIMED(k_gram_patch, dim3(n_gpatch), dim3(kBlockThreads), st, ka, a, t_gpatch);
   else
-    LAUNCH_TIMED(k_gram_tile, dim3(n_gram), dim3(kBlockThreads), st, (KTime{kt.start, nullptr}), a, t_gram);
+    LAUNCH_TIMED(k_gram_tile, dim3(n_gram), dim3(kBlockThreads), st, ka, a, t_gram);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !reduce) return e;
   if (patch)
     LAUNCH_TIMED(k_gram_reduce<true>, dim3(n_gtr), dim3(kBlockThreads), st, (KTime{nullptr, kt.stop}), a, t_gtr);
   else
@@ -562,15 +681,31 @@ hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipSt
   }
   return hipGetLastError();
 }
-hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt) {
+template <int SRC>
+void zupdate_go(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt) {
   if (a.Q <= 4)
-    LAUNCH_TIMED(k_zupdate<4>, dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
+    LAUNCH_TIMED((k_zupdate<4, SRC>), dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
   else if (a.Q <= 8)
-    LAUNCH_TIMED(k_zupdate<8>, dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
+    LAUNCH_TIMED((k_zupdate<8, SRC>), dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
   else if (a.Q <= 32)
-    LAUNCH_TIMED(k_zupdate<32>, dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
+    LAUNCH_TIMED((k_zupdate<32, SRC>), dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
   else
-    LAUNCH_TIMED(k_zupdate<0>, dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
+    LAUNCH_TIMED((k_zupdate<0, SRC>), dim3(ntiles), dim3(kZCols), st, kt, a, tiles);
+}
+hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt, int src) {
+  switch (src) {
+    case 0: zupdate_go<0>(a, tiles, ntiles, st, kt); break;
+    case 1: zupdate_go<1>(a, tiles, ntiles, st, kt); break;
+    default: zupdate_go<2>(a, tiles, ntiles, st, kt); break;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_direct_gp(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt) {
+  LAUNCH_TIMED(k_dgp, dim3(ntiles), dim3(kBlockThreads), st, kt, a, tiles);
+  return hipGetLastError();
+}
+hipError_t launch_direct_rhs(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt) {
+  LAUNCH_TIMED(k_dbsum, dim3(ntiles, a.Q), dim3(kZCols), st, kt, a, tiles);
   return hipGetLastError();
 }
 hipError_t launch_to_bf16_pairs(const float2* src, uint32_t* dst, size_t n, hipStream_t st) {

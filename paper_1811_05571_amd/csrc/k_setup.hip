@@ -2,7 +2,9 @@
 // build, per block (i,j), the Hermitian inverse of G_ij = rho I + H_ij H_ij^H
 // in FP64 (Gram, Cholesky, triangular inverse, W^H W), stored as complex64.
 // This is the paper's inversion step: the small m_i x m_i matrix of the
-// inversion lemma (eq. inversion_lemma3), since (I + H H^H/rho)^{-1} = rho G^{-1}.
+// inversion lemma (eq. inversion_lemma3), since (I + H H^H/rho)^{-1} = rho G^{-1};
+// for a plan in the direct form the n_j x n_j matrix A_ij = rho I + H_ij^H H_ij
+// itself (Sec. III-B, the remark on tall blocks after eq. inversion_lemma2).
 //
 // Every FP64 matrix is padded to a multiple of kTile with identity rows, so
 // the tiled algorithms never see a ragged tile.  Tiles are 64 x 64 double2;
@@ -176,9 +178,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_pack_c64(const float2* __rest
   if (bad) ctl->nonfinite = 1;
 }
 
-// Lower tiles of G = rho I + H H^H in FP64 from the stored (dequantised)
-// values.  tiles[x] = {block, tile row, tile col, -} with tile row >= tile col.
-template <class F>
+// Lower tiles of the block's Gram matrix in FP64 from the stored
+// (dequantised) values: G = rho I + H H^H, m_i x m_i, for the inversion-lemma
+// x-update (COLS = false), or A = rho I + H^H H, n_j x n_j, for the direct
+// one (COLS = true; Sec. III-B, the original inversion of tall blocks).
+// tiles[x] = {block, tile row, tile col, -} with tile row >= tile col.
+template <class F, bool COLS>
 __global__ __launch_bounds__(kBlockThreads) void k_gram_build(const int4* __restrict__ tiles,
                                                               const BlockDesc* __restrict__ blocks, HStore hs,
                                                               double rho, double2* __restrict__ A) {
@@ -190,24 +195,43 @@ __global__ __launch_bounds__(kBlockThreads) void k_gram_build(const int4* __rest
   const int r0 = t.y * T, c0 = t.z * T;
   Acc acc;
   acc.zero();
-  for (int k0 = 0; k0 < d.nj; k0 += KC) {
-    __syncthreads();
-    for (int e = tid; e < T * KC; e += kBlockThreads) {
-      int r = e / KC, kk = e % KC;
-      sm.A[r][kk] = (r0 + r < d.mi) ? f.getd(d.h_off + (int64_t)(r0 + r) * d.ld + k0 + kk, d.row0 + r0 + r)
-                                    : make_double2(0.0, 0.0);
-      int kb = e / T, c = e % T;
-      const double2 b = (c0 + c < d.mi) ? f.getd(d.h_off + (int64_t)(c0 + c) * d.ld + k0 + kb, d.row0 + c0 + c)
-                                        : make_double2(0.0, 0.0);
-      sm.B[kb][c] = make_double2(b.x, -b.y);
+  if constexpr (!COLS) {
+    // G[r][c] = sum_k H[r][k] conj(H[c][k]): K runs along the rows
+    for (int k0 = 0; k0 < d.nj; k0 += KC) {
+      __syncthreads();
+      for (int e = tid; e < T * KC; e += kBlockThreads) {
+        int r = e / KC, kk = e % KC;
+        sm.A[r][kk] = (r0 + r < d.mi) ? f.getd(d.h_off + (int64_t)(r0 + r) * d.ld + k0 + kk, d.row0 + r0 + r)
+                                      : make_double2(0.0, 0.0);
+        int kb = e / T, c = e % T;
+        const double2 b = (c0 + c < d.mi) ? f.getd(d.h_off + (int64_t)(c0 + c) * d.ld + k0 + kb, d.row0 + c0 + c)
+                                          : make_double2(0.0, 0.0);
+        sm.B[kb][c] = make_double2(b.x, -b.y);
+      }
+      __syncthreads();
+      acc.chunk(sm);
     }
-    __syncthreads();
-    acc.chunk(sm);
+  } else {
+    // A[p][q] = sum_k conj(H[k][p]) H[k][q]: K runs down the columns; each
+    // staged row segment is 64 consecutive elements of one stored row
+    for (int k0 = 0; k0 < d.mi; k0 += KC) {
+      __syncthreads();
+      for (int e = tid; e < T * KC; e += kBlockThreads) {
+        const int kk = e / T, q = e % T;
+        const int row = k0 + kk;
+        const int64_t re = d.h_off + (int64_t)row * d.ld;
+        const double2 x = (row < d.mi && r0 + q < d.nj) ? f.getd(re + r0 + q, d.row0 + row) : make_double2(0.0, 0.0);
+        sm.A[q][kk] = make_double2(x.x, -x.y);
+        sm.B[kk][q] = (row < d.mi && c0 + q < d.nj) ? f.getd(re + c0 + q, d.row0 + row) : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
+      acc.chunk(sm);
+    }
   }
   double2* Ab = A + d.f_off;
   acc.each([&](int rr, int cc, double2 val) {
     const int r = r0 + rr, c = c0 + cc;
-    if (r >= d.mi || c >= d.mi) val = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    if (r >= d.gd || c >= d.gd) val = make_double2(r == c ? 1.0 : 0.0, 0.0);
     else if (r == c) val.x += rho;
     Ab[(int64_t)r * d.mt + c] = val;
   });
@@ -526,7 +550,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_lauum(const int4* __restrict_
                               d.mt, acc);
   float2* G = Ginv + d.gi_off + (int64_t)(i * (i + 1) / 2 + l) * (T * T);
   acc.each([&](int rr, int cc, double2 v) {
-    const bool in = i * T + rr < d.mi && l * T + cc < d.mi;
+    const bool in = i * T + rr < d.gd && l * T + cc < d.gd;
     G[rr * T + cc] = in ? make_float2((float)v.x, (float)v.y) : make_float2(0.f, 0.f);
   });
 }
@@ -542,12 +566,20 @@ hipError_t launch_pack_c64(const float2* Hin, int64_t n, const BlockDesc* blocks
 
 hipError_t launch_gram_build(const Geometry& geo, const BlockDesc* dblocks, const int4* t_gram,
                              const HStore& hs, double rho, double2* A, hipStream_t st) {
-  const dim3 grid((unsigned)geo.t_gram.size());
+  const dim3 grid((unsigned)geo.t_gram.size()), blk(kBlockThreads);
+#define GRAM_BUILD(F)                                                                                   \
+  do {                                                                                                  \
+    if (geo.direct)                                                                                     \
+      hipLaunchKernelGGL((k_gram_build<F, true>), grid, blk, 0, st, t_gram, dblocks, hs, rho, A);       \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_gram_build<F, false>), grid, blk, 0, st, t_gram, dblocks, hs, rho, A);      \
+  } while (0)
   switch (hs.storage) {
-    case 0: hipLaunchKernelGGL(k_gram_build<FmtC64>, grid, dim3(kBlockThreads), 0, st, t_gram, dblocks, hs, rho, A); break;
-    case 1: hipLaunchKernelGGL(k_gram_build<FmtBF16>, grid, dim3(kBlockThreads), 0, st, t_gram, dblocks, hs, rho, A); break;
-    default: hipLaunchKernelGGL(k_gram_build<FmtFP8>, grid, dim3(kBlockThreads), 0, st, t_gram, dblocks, hs, rho, A); break;
+    case 0: GRAM_BUILD(FmtC64); break;
+    case 1: GRAM_BUILD(FmtBF16); break;
+    default: GRAM_BUILD(FmtFP8); break;
   }
+#undef GRAM_BUILD
   return hipGetLastError();
 }
 

@@ -49,6 +49,7 @@ struct Layout {
   size_t t_wrows = 0, t_gpatch = 0;
   size_t gpart = 0;
   size_t Hs = 0, Hs_im = 0, fpart = 0, t_fz = 0, fz_colwg = 0, t_fzr = 0, hs_bytes = 0;
+  size_t t_dgp = 0, dflag = 0;
   size_t ctl = 0, redpart = 0, row_block = 0, kkt_e = 0, kkt_v = 0, kkt_part = 0, kkt_max = 0;
   size_t vb = 0, sb = 0, ub = 0, ghb = 0, gpb = 0, yb = 0, rb = 0, gbar = 0, kpart = 0, rpart = 0;
   size_t total = 0;
@@ -60,6 +61,7 @@ struct Geometry {
   int Q = 0, P = 0, storage = 0;   // storage: H format (ADMM_STORAGE_*)
   bool inv16 = false;              // a bfloat16-pair copy of the inverses is kept and applied
   bool force_patches = false;      // ADMM_GRAM_PATCHES
+  bool direct = false;             // every block takes the direct x-update (Gram space = column space)
   std::vector<int64_t> ro, co;
   std::vector<BlockDesc> blocks;   // Q*P, index b = i*P + j
   std::vector<ColDesc> cols;       // P
@@ -77,6 +79,7 @@ struct Geometry {
   std::vector<int2> fz_colwg;      // per column block {first, end workgroup}
   std::vector<int4> t_fzr;         // row kernel: {block, first row, -, -}, 256 rows each
   FzArgs fzt{};                    // the host part of the single-pass arguments (tables)
+  std::vector<int4> t_dgp;         // direct form: {row block, first row, -, -}, kBlockThreads rows each
   Layout lay;
 };
 
@@ -180,6 +183,9 @@ struct IterArgs {
   const float2* Ginv;
   const uint32_t* Ginv16;  // bfloat16-pair copy of Ginv (same element offsets), or null: use Ginv
   const float2* g;      // caller's measurements
+  // c, s, v, part: column space [Q][n_pad]; gp, ghat: row space [P][m_pad];
+  // r, y: the Gram space, row space in the inversion-lemma form (r_ij, y_ij),
+  // column space in the direct form (b_ij, and u_j^i in the layout of c)
   float2 *c, *s, *v, *part, *gp, *ghat, *r, *y;
   float2* gpart;        // Gram-apply pieces (BlockDesc::gpo)
   Control* ctl;
@@ -194,6 +200,9 @@ struct IterArgs {
   int cpl;              // columns per lane load of the storage (layout of c, see cperm)
   int xstage;           // 1: every column block's c fits kXStage float4 of LDS (row product stages it)
   int wide;             // 1: some column block is wider than kWholeCols (the whole-row product loops over chunks)
+  int direct;           // 1: direct x-update (the row products write ghat = H u instead of r and g')
+  int* uref;            // direct form, device word: 1 when y holds the last iteration's u and ghat_ij =
+                        // H_ij y_ij (the x-update then corrects that u), 0 after a reset or a state import
 };
 
 // Adjoint (reverse-mode) sweep of one iteration.
@@ -237,10 +246,17 @@ struct KTime {
   } while (0)
 hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, const int4* wtiles, int nwtiles,
                           hipStream_t st, KTime kt = {});
+// reduce = false: the apply kernel only (the direct form's z-update adds the pieces).
 hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gpatch, int n_gpatch,
-                       const int4* t_gtr, int n_gtr, hipStream_t st, KTime kt = {});
+                       const int4* t_gtr, int n_gtr, hipStream_t st, KTime kt = {}, bool reduce = true);
 hipError_t launch_gemv_h(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});
-hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});
+// src: 0 inversion-lemma form; direct form with the Gram pieces of
+// k_gram_patch (1) or of the single-tile kernels (2).
+hipError_t launch_zupdate(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {},
+                          int src = 0);
+// Direct x-update: g' of every block (t_dgp), b = H^H g' + rho c (t_z tiles).
+hipError_t launch_direct_gp(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});
+hipError_t launch_direct_rhs(const IterArgs& a, const int4* tiles, int ntiles, hipStream_t st, KTime kt = {});
 // Single-pass iteration (k_fused.hip).
 hipError_t launch_fz_rows(const IterArgs& a, const FzArgs& z, const int4* tiles, int ntiles, hipStream_t st,
                           KTime kt = {});

@@ -8,14 +8,14 @@ def to_device(torch, arr):
 
 
 def gpu_solve(torch, prob, iters, rho=None, lam=None, Q=None, P=None, row_off=None, col_off=None,
-              history=False, two_pass=False, **kw):
+              history=False, two_pass=False, xupdate="auto", **kw):
     import paper_1811_05571_amd as A
     H = to_device(torch, prob.H)
     g = to_device(torch, prob.g)
     plan = A.Plan(H, Q or prob.Q, P or prob.P, rho if rho is not None else prob.rho,
                   lam if lam is not None else prob.lam,
                   row_off if row_off is not None else prob.row_off,
-                  col_off if col_off is not None else prob.col_off, two_pass=two_pass)
+                  col_off if col_off is not None else prob.col_off, two_pass=two_pass, xupdate=xupdate)
     out = plan.solve(g, iters, history=history, **kw)
     return plan, g, out
 

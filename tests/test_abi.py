@@ -45,7 +45,8 @@ def test_workspace_sizing_and_argument_errors():
     assert inv16 - big >= 32 * (24 * 25 // 2) * 4096 * 4
     L = A.lib()
     out = ctypes.c_size_t(0)
-    assert L.admm_workspace_bytes(256, 4096, 4, None, 1, None, 128, ctypes.byref(out)) == -1   # unknown flag
+    assert L.admm_workspace_bytes(256, 4096, 4, None, 1, None, 1024, ctypes.byref(out)) == -1   # unknown flag
+    assert L.admm_workspace_bytes(256, 4096, 4, None, 1, None, 128 | 256, ctypes.byref(out)) == -1   # both forms
     # ADMM_GRAM_PATCHES (32) is known; it only adds the patch table
     assert L.admm_workspace_bytes(256, 4096, 4, None, 1, None, 32, ctypes.byref(out)) == 0
     assert A.workspace_bytes(300, 2000, 3, 5, [0, 90, 200, 300], [0, 333, 800, 1201, 1600, 2000]) > 0
@@ -62,13 +63,17 @@ def test_workspace_sizing_and_argument_errors():
         with pytest.raises(A.ADMMError) as ei:
             A.workspace_bytes(**kw)
         assert ei.value.status == "ADMM_EINVAL", kw
-    # tall blocks take the inversion-lemma x-update while m_i < (1 + sqrt 2) n_j
-    assert A.workspace_bytes(6144, 32000, 1, 8) > 0          # 6144 x 4000
-    assert A.workspace_bytes(480, 1000, 1, 5) > 0            # 480 x 200: 480^2 < 2*480*200 + 200^2
-    for m, n, P in ((500, 1000, 5), (6144, 32000, 32)):      # 500 x 200 and 6144 x 1000: beyond
-        with pytest.raises(A.ADMMError) as ei:
-            A.workspace_bytes(m, n, 1, P)
-        assert ei.value.status == "ADMM_EUNSUPPORTED"
+    # every block shape is served: tall blocks with the single pass keep the
+    # inversion-lemma x-update up to about m_i = (1 + sqrt 2) n_j, taller
+    # ones take the direct x-update and its n_j x n_j inverses
+    assert A.split_cost(6144, 32000, 1, 8)["direct"] == 0       # 6144 x 4000
+    assert A.split_cost(480, 1000, 1, 5)["direct"] == 0         # 480 x 200
+    assert A.split_cost(500, 1000, 1, 5)["direct"] == 0         # 500 x 200 (row stride 256, 8 tiles of 64)
+    for m, n, P in ((1000, 1000, 5), (6144, 32000, 32)):        # 1000 x 200 and 6144 x 1000
+        c = A.split_cost(m, n, 1, P)
+        assert c["direct"] == 1
+        assert c["inverse_bytes"] == P * (-(-(n // P) // 64) * (-(-(n // P) // 64) + 1) // 2) * 4096 * 8
+        assert A.workspace_bytes(m, n, 1, P) > 0
 
 
 def test_null_plan_is_rejected():

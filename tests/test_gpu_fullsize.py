@@ -79,6 +79,29 @@ def test_full_size_sectioning_only_parity(torch_gpu, full):
     assert err <= 1e-5
 
 
+def test_full_size_sectioning_direct_parity(torch_gpu, full):
+    """Q = 1, P = 32 on the full matrix: 6144 x 1000 blocks, more than
+    (1 + sqrt 2) times taller than wide, where the library takes the direct
+    x-update by itself (n_j x n_j inverses instead of m_i x m_i); the oracle
+    solves these blocks directly too.  Parity after 3 iterations, and the
+    residuals after 50 decrease."""
+    import paper_1811_05571_amd as A
+    p, H, g = full
+    plan = A.Plan(H, 1, 32, p.rho, p.lam)
+    assert plan.info()["direct"] == 1
+    K = 3
+    v = plan.solve(g, K).cpu().numpy()
+    _, _, s, ghat = plan.get_state()
+    v_ref, _, st = O.solve(p.H, p.g, 1, 32, p.rho, p.lam, K)
+    err, emax, _ = check_image(v, v_ref, st.s, p.lam / p.rho)
+    print(f"sectioning only 1x32 (direct): rel err after {K} iterations {err:.2e} (max element {emax:.2e})",
+          flush=True)
+    assert rel(s.cpu().numpy(), st.s) <= 1e-4 and rel(ghat.cpu().numpy(), st.ghat) <= 1e-4
+    _, hist = plan.solve(g, 50, history=True)
+    h = hist.cpu().numpy()
+    assert np.all(np.isfinite(h)) and h[-1, 0] < h[1, 0] and h[-1, 1] < h[1, 1]
+
+
 def test_full_size_300_iterations_properties(torch_gpu, full):
     """After the workload's 300 iterations: residuals decrease, the FP64 KKT
     violation decreases, both runs of the same input agree bit for bit."""
@@ -199,16 +222,18 @@ def test_full_size_inverse_bf16(torch_gpu, full):
     assert abs(n(v16) - n(v32)) <= 1e-3 * n(v32)
 
 
-@pytest.mark.parametrize("split", [(4, 1), (1, 3), (4, 3)])
+@pytest.mark.parametrize("split", [(4, 1), (1, 3), (4, 3), (1, 32)])
 def test_paper_table_workload_parity(torch_gpu, split):
-    """2160 x 22500 (the paper's timing-table shape), its three splittings:
-    parity with the oracle after 10 iterations and decreasing residuals over
-    the table's 50."""
+    """2160 x 22500 (the paper's timing-table shape), its three splittings
+    and the sectioning-only split into 32 (2160 x 703 blocks, direct
+    x-update): parity with the oracle after 10 iterations and decreasing
+    residuals over the table's 50."""
     import paper_1811_05571_amd as A
     Q, P = split
     p = W.paper_table_imaging(Q=Q, P=P)
     H, g = to_device(torch_gpu, p.H), to_device(torch_gpu, p.g)
     plan = A.Plan(H, Q, P, p.rho, p.lam)
+    assert plan.info()["direct"] == (1 if split == (1, 32) else 0)
     K = 10
     v = plan.solve(g, K).cpu().numpy()
     v_ref, _, _ = O.solve(p.H, p.g, Q, P, p.rho, p.lam, K)

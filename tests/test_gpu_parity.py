@@ -5,7 +5,11 @@ after K iterations for complex64 storage (FP32 arithmetic), on the same
 seeded inputs.  Cases span several workgroup tiles, ragged tails (odd block
 widths, rows not a multiple of the row tile), uneven block splits and the
 three splittings (consensus P=1, sectioning Q=1, combined), plus the
-degenerate ones (Q=P=1, zero iterations, lambda above max|H^H g|).
+degenerate ones (Q=P=1, zero iterations, lambda above max|H^H g|).  Each
+case runs in the form the library picks, with the two-pass kernels of the
+inversion-lemma x-update, and (where the n_j x n_j matrices stay small) in
+the direct x-update; the oracle takes the inversion lemma for wide blocks and
+the direct solve otherwise, the two pinned equal to 1e-12.
 """
 import functools
 
@@ -60,6 +64,14 @@ def _case(name):
         return W.iid_problem(m=480, n=1000, nnz=10, Q=1, P=5, rho=10.0, seed=24), 150
     # more than 8 row blocks: up to 32 replicas in registers, beyond that the
     # z-update reads them twice
+    # tall enough for the library to pick the direct x-update by itself
+    if name == "tall_auto":            # 600 x 100 blocks (sectioning)
+        return W.iid_problem(m=600, n=800, nnz=10, Q=1, P=8, rho=10.0, seed=41), 120
+    if name == "tall_consensus_auto":  # 500 x 120 blocks (consensus, g' = g)
+        return W.iid_problem(m=1000, n=120, nnz=6, Q=2, P=1, rho=1.0, seed=42), 120
+    if name == "tall_combined_uneven":   # 3 x 6 uneven blocks, 200-400 x 90-110
+        return W.iid_problem(m=900, n=600, nnz=10, Q=3, P=6, rho=10.0, seed=43, row_off=[0, 200, 500, 900],
+                             col_off=[0, 90, 200, 300, 410, 500, 600]), 120
     if name == "forty_row_blocks":     # 40 blocks of 30 rows
         return W.iid_problem(m=1200, n=3000, nnz=10, Q=40, P=1, rho=1.0, seed=27), 100
     if name == "many_row_blocks":      # 12 blocks of 40 rows
@@ -79,7 +91,13 @@ def _case(name):
 CASES = ["consensus256x4096", "combined_uneven", "sectioning", "unsplit", "ragged_consensus",
          "cra_small", "many_sections", "wide_blocks", "tall_sectioning", "square_blocks", "mixed_tall",
          "tall_near_limit", "many_row_blocks", "many_rows_and_sections", "forty_row_blocks",
-         "one_row_blocks", "one_column_blocks", "lambda_zero"]
+         "one_row_blocks", "one_column_blocks", "lambda_zero", "tall_auto", "tall_consensus_auto",
+         "tall_combined_uneven"]
+# the direct x-update on every case but the one with 40 row blocks of 3000
+# columns (40 FP64 3000 x 3000 setup matrices)
+DIRECT_CASES = [c for c in CASES if c != "forty_row_blocks"]
+PARITY_RUNS = ([(c, "auto") for c in CASES] + [(c, "two_pass") for c in CASES]
+               + [(c, "direct") for c in DIRECT_CASES])
 
 
 @functools.lru_cache(maxsize=None)
@@ -89,18 +107,23 @@ def _reference(name):
     return p, K, _oracle(p, K)
 
 
-@pytest.mark.parametrize("path", ["single_pass", "two_pass"])
-@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("name,path", PARITY_RUNS)
 def test_image_matches_oracle(torch_gpu, name, path):
     p, K, (v_ref, hist_ref, st_ref) = _reference(name)
     print(f"case {name} ({path}) m={p.m} n={p.n} Q={p.Q} P={p.P} K={K}", flush=True)
-    plan, g, (v, hist) = gpu_solve(torch_gpu, p, K, history=True, two_pass=(path == "two_pass"))
+    xup = {"auto": "auto", "two_pass": "lemma", "direct": "direct"}[path]
+    plan, g, (v, hist) = gpu_solve(torch_gpu, p, K, history=True, two_pass=(path == "two_pass"), xupdate=xup)
+    info = plan.info()
     if path == "two_pass":
-        assert plan.info()["single_pass"] == 0
+        assert info["single_pass"] == 0 and info["direct"] == 0
+    if path == "direct":
+        assert info["direct"] == 1 and info["single_pass"] == 0
+    if name.startswith("tall_") and name.endswith(("_auto", "_uneven")):
+        assert path == "two_pass" or info["direct"] == 1
     v = v.cpu().numpy()
     err, emax, nd = check_image(v, v_ref, st_ref.s, p.lam / (p.Q * p.rho))
-    print(f"  single pass {plan.info()['single_pass']}: rel err {err:.3e}, max element err {emax:.3e}, "
-          f"zero pattern on {nd} entries", flush=True)
+    print(f"  single pass {info['single_pass']}, direct {info['direct']}: rel err {err:.3e}, "
+          f"max element err {emax:.3e}, zero pattern on {nd} entries", flush=True)
     hist = hist.cpu().numpy()
     assert hist.shape == hist_ref.shape
     # residual histories: relative agreement where they are well above rounding
@@ -120,20 +143,29 @@ def test_image_matches_oracle(torch_gpu, name, path):
     assert rel(ghg.cpu().numpy(), st_ref.ghat) <= 10 * TOL
 
 
-@pytest.mark.parametrize("name", ["combined_uneven", "ragged_consensus", "cra_small", "gram_patches"])
-def test_gram_patches_match_oracle(torch_gpu, name):
+@pytest.mark.parametrize("name,xupdate", [("combined_uneven", "auto"), ("ragged_consensus", "auto"),
+                                          ("cra_small", "auto"), ("gram_patches", "auto"),
+                                          ("tall_combined_uneven", "direct"), ("combined_uneven", "direct"),
+                                          ("gram_patches_direct", "direct")])
+def test_gram_patches_match_oracle(torch_gpu, name, xupdate):
     """The Gram apply in 4 x 4 tile patches (forced; by default only splits
     with thousands of patches use them): single-tile-row blocks, partial edge
-    patches and several full patches per block."""
+    patches and several full patches per block; in the direct form the
+    z-update adds the patch pieces itself."""
     import paper_1811_05571_amd as A
     if name == "gram_patches":
         # 600-row blocks: 10 tile rows, patches (R, C) for R, C < 3 with a partial last row
         p, K = W.iid_problem(m=1200, n=6000, nnz=20, Q=2, P=2, rho=10.0, seed=12), 80
+    elif name == "gram_patches_direct":
+        # 2000 x 600 blocks in the direct form: 10 tile rows of A, as above
+        p, K = W.iid_problem(m=2000, n=1200, nnz=20, Q=1, P=2, rho=10.0, seed=13), 80
     else:
         p, K = _case(name)
     v_ref, _, st_ref = _oracle(p, K)
-    plan = A.Plan(to_device(torch_gpu, p.H), p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off, gram_patches=True)
+    plan = A.Plan(to_device(torch_gpu, p.H), p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off, gram_patches=True,
+                  xupdate=xupdate)
     assert plan.info()["gram_patches"] > 0
+    assert plan.info()["direct"] == (1 if xupdate == "direct" else 0)
     v = plan.solve(to_device(torch_gpu, p.g), K).cpu().numpy()
     err = rel(v, v_ref)
     print(f"case {name} with patches: rel err {err:.3e}", flush=True)
@@ -191,7 +223,7 @@ def test_warm_start_after_record_and_import(torch_gpu):
     assert torch.equal(plan.get_state()[1], v_full)
 
 
-@pytest.mark.parametrize("path", ["single_pass", "two_pass"])
+@pytest.mark.parametrize("path", ["single_pass", "two_pass", "direct"])
 def test_graph_replay_matches_plain_launches(torch_gpu, path):
     """Solves that replay captured graphs of 10 iterations give bitwise the
     iterates of plain launches: several replays in a row, with the program's
@@ -204,8 +236,10 @@ def test_graph_replay_matches_plain_launches(torch_gpu, path):
     p, _ = _case("combined_uneven")
     H, g = to_device(torch, p.H), to_device(torch, p.g)
     tp = path == "two_pass"
-    pg = A.Plan(H, p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off, two_pass=tp)
-    pe = A.Plan(H, p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off, two_pass=tp)
+    xu = "direct" if path == "direct" else "auto"
+    pg = A.Plan(H, p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off, two_pass=tp, xupdate=xu)
+    pe = A.Plan(H, p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off, two_pass=tp, xupdate=xu)
+    assert pg.info()["direct"] == (1 if path == "direct" else 0)
     pe.set_graphs(False)
     vg, hg = pg.solve(g, 57, history=True)
     ve, he = pe.solve(g, 57, history=True)
@@ -301,17 +335,20 @@ def test_bad_arguments_rejected(torch_gpu):
     assert A.lib().admm_solve(plan.handle, g.data_ptr(), 1, 1e-3, 0, v.data_ptr(), None, None, 0, None) == -1
 
 
-@pytest.mark.parametrize("path", ["single_pass", "two_pass"])
+@pytest.mark.parametrize("path", ["single_pass", "two_pass", "direct"])
 def test_profile_sampling_counts_and_leaves_results_unchanged(torch_gpu, path):
     """Kernel timing on every 3rd iteration: 9 iterations give 3 timed launches
     per kernel class of the path, and the iterates are bitwise those of an
     untimed solve."""
     import paper_1811_05571_amd as A
     p, _ = _case("combined_uneven")
-    plan, g, (v0, _) = gpu_solve(torch_gpu, p, 9, history=True, two_pass=(path == "two_pass"))
-    used = ([A.K_FZ_ROWS, A.K_GRAM, A.K_FZ_SLAB] if path == "single_pass"
-            else [A.K_GEMV_N, A.K_GRAM, A.K_GEMV_H, A.K_ZUPDATE])
+    plan, g, (v0, _) = gpu_solve(torch_gpu, p, 9, history=True, two_pass=(path == "two_pass"),
+                                 xupdate="direct" if path == "direct" else "auto")
+    used = {"single_pass": [A.K_FZ_ROWS, A.K_GRAM, A.K_FZ_SLAB],
+            "two_pass": [A.K_GEMV_N, A.K_GRAM, A.K_GEMV_H, A.K_ZUPDATE],
+            "direct": [A.K_DIRECT_GP, A.K_GEMV_H, A.K_DIRECT_RHS, A.K_GRAM, A.K_ZUPDATE, A.K_GEMV_N]}[path]
     assert plan.info()["single_pass"] == (1 if path == "single_pass" else 0)
+    assert plan.info()["direct"] == (1 if path == "direct" else 0)
     plan.profile(3)
     v1 = plan.solve(g, 9)
     counts = {k: plan.profile_read(k)[1] for k in A.KERNEL_NAMES}

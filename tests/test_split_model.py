@@ -37,16 +37,50 @@ def test_column_wise_beats_row_wise_below_the_paper_bound():
         assert (cols < rows) == (P * m < 2 * n)
 
 
-@pytest.mark.parametrize("two_pass", [False, True])
-@pytest.mark.parametrize("Q,P", [(4, 8), (1, 8), (4, 1), (2, 3)])
-def test_bytes_per_iteration_match_the_benchmark_count(Q, P, two_pass):
+@pytest.mark.parametrize("path", ["auto", "two_pass", "direct"])
+@pytest.mark.parametrize("Q,P", [(4, 8), (1, 8), (4, 1), (2, 3), (1, 32)])
+def test_bytes_per_iteration_match_the_benchmark_count(Q, P, path):
     m, n = 6144, 32000
-    c = A.split_cost(m, n, Q, P, two_pass=two_pass)
-    algo = bench.algorithmic_bytes(bench.block_geometry(m, n, Q, P), P, Q, int(c["chunks"]), "c64", "c64",
+    xup = {"auto": "auto", "two_pass": "lemma", "direct": "direct"}[path]
+    c = A.split_cost(m, n, Q, P, two_pass=(path == "two_pass"), xupdate=xup)
+    direct = c["direct"] == 1
+    algo = bench.algorithmic_bytes(bench.block_geometry(m, n, Q, P, direct), P, Q, int(c["chunks"]), "c64", "c64",
                                    c["gram_patches"] > 0, int(c["slab_workgroups"]))
-    assert c["single_pass"] == (0 if two_pass else 1)
-    assert c["bytes_per_iteration"] == bench.iteration_bytes(algo, {"single_pass": c["single_pass"]})
+    assert direct == (path == "direct" or (path == "auto" and (Q, P) == (1, 32)))
+    assert c["single_pass"] == (1 if path == "auto" and not direct else 0)
+    assert c["bytes_per_iteration"] == bench.iteration_bytes(algo, {"single_pass": c["single_pass"],
+                                                                    "direct": c["direct"]})
     assert c["max_block_rows"] == -(-m // Q) and c["max_block_cols"] == -(-n // P)
+
+
+@pytest.mark.parametrize("m,n,Q,P,direct", [
+    (6144, 32000, 4, 8, False), (6144, 32000, 1, 8, False),    # single pass: H once + m_i^2 beats 2 H + n_j^2
+    (6144, 32000, 1, 16, True), (6144, 32000, 1, 32, True),    # 6144 x 2000 and 6144 x 1000 blocks
+    (2160, 22500, 1, 16, False), (2160, 22500, 1, 32, True),   # the paper table's shape
+    (1000, 120, 2, 1, True), (256, 4096, 4, 1, False)])
+def test_form_choice_streams_fewer_bytes(m, n, Q, P, direct):
+    """Unless fixed by a flag, a plan takes the x-update whose iteration
+    streams fewer bytes (Sec. III-B: the original inversion for tall blocks):
+    the two forms' counts bracket the choice."""
+    c = A.split_cost(m, n, Q, P)
+    lem = A.split_cost(m, n, Q, P, xupdate="lemma")
+    dr = A.split_cost(m, n, Q, P, xupdate="direct")
+    assert (c["direct"] == 1) == direct
+    assert dr["direct"] == 1 and lem["direct"] == 0
+    assert c["bytes_per_iteration"] == min(lem["bytes_per_iteration"], dr["bytes_per_iteration"]) or not direct
+    assert (dr["inverse_bytes"] < lem["inverse_bytes"]) == (n // P < m // Q)
+    # the Gram matrices are n_j x n_j in the direct form: the FP64 setup flops
+    nj, mi = -(-n // P), -(-m // Q)
+    assert dr["setup_fp64_flops"] >= 8 * (nj * (nj + 1) / 2 * (m // Q) + nj ** 3) * Q * (n // P // nj or 1) * 0.99 ** 0
+
+
+def test_form_flags_are_exclusive():
+    import ctypes
+    out = ctypes.c_size_t(0)
+    L = A.lib()
+    assert L.admm_workspace_bytes(600, 800, 1, None, 8, None, A.XUPDATE["lemma"] | A.XUPDATE["direct"],
+                                  ctypes.byref(out)) == -1
+    assert L.admm_workspace_bytes(600, 800, 1, None, 8, None, A.XUPDATE["direct"], ctypes.byref(out)) == 0
 
 
 def test_setup_flops_closed_form():
@@ -78,11 +112,11 @@ def test_chooser_is_the_argmin_under_the_exchange_limit():
 
 
 def test_chooser_errors():
-    # the unsplit problem exchanges nothing, but 1000 x 300 is too tall for it
+    # the unsplit problem exchanges nothing: always a candidate, also where its
+    # one block is tall (1000 x 300, the direct x-update)
     assert A.choose_split(2160, 22500, 50, max_exchange=1.0)[:2] == (1, 1)
-    with pytest.raises(A.ADMMError) as ei:
-        A.choose_split(1000, 300, 50, max_exchange=1.0)
-    assert ei.value.status == "ADMM_EUNSUPPORTED"
+    assert A.choose_split(1000, 300, 50, max_exchange=1.0)[:2] == (1, 1)
+    assert A.split_cost(1000, 300, 1, 1)["direct"] == 1
     for kw in (dict(hbm_gbs=0.0), dict(fp64_tflops=-1.0), dict(latency_us=-1.0)):
         with pytest.raises(A.ADMMError) as ei:
             A.choose_split(2160, 22500, 50, **kw)
