@@ -360,9 +360,10 @@ def split_model(A, m: int, n: int, Q: int, P: int) -> dict:
 def bench_full_splits(args, torch, A, prob, H, g, steps: int = 300, warmup: int = 300):
     """The other two methods on the full matrix: consensus only (Q = 4, P = 1,
     1536 x 32000 blocks) and sectioning only (Q = 1, P = 8, 6144 x 4000
-    blocks, taller than wide), complex64, same rho and lambda."""
+    blocks, taller than wide; Q = 1, P = 32, 6144 x 1000 blocks, which take
+    the direct x-update), complex64, same rho and lambda."""
     rows = []
-    for Q, P in ((4, 1), (1, 8)):
+    for Q, P in ((4, 1), (1, 8), (1, 32)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plan = A.Plan(H, Q, P, prob.rho, prob.lam)
@@ -383,7 +384,8 @@ def bench_full_splits(args, torch, A, prob, H, g, steps: int = 300, warmup: int 
         rows.append({
             "split": f"{Q}x{P}", "block": f"{mi}x{nj}", "value": round(steps / el, 1), "unit": "iters/s",
             "setup_ms": round(setup * 1e3, 1), "iteration_gbs": round(iteration_bytes(algo, info) * steps / el / 1e9, 1),
-            "algo_bytes_per_iteration": iteration_bytes(algo, info), "single_pass": info["single_pass"], "inverse_gb": round(info["ginv_bytes"] / 1e9, 3),
+            "algo_bytes_per_iteration": iteration_bytes(algo, info), "single_pass": info["single_pass"],
+            "direct": info["direct"], "inverse_gb": round(info["ginv_bytes"] / 1e9, 3),
             "nmse_vs_truth": float(np.linalg.norm(vn - prob.u_true) ** 2 / np.linalg.norm(prob.u_true) ** 2),
             "residuals_last": [float(x) for x in hs[-1]],
             "iter_us": round(el / steps * 1e6, 1), **split_model(A, prob.m, prob.n, Q, P),
@@ -412,7 +414,7 @@ def bench_paper_table(args, torch, A, W, dev, reps: int = 5):
     K = W.PAPER_TABLE_ITERS
     rows = []
     chosen = [A.choose_split(p.m, p.n, K, max_exchange=lim, **MODEL_RATES)[:2] for lim in (0.0, 10000.0)]
-    splits = list(W.PAPER_TABLE_SPLITS)
+    splits = list(W.PAPER_TABLE_SPLITS) + [(1, 32)]   # and the direct x-update's 2160 x 703 blocks
     for s in chosen:
         if s not in splits:
             splits.append(s)
@@ -439,7 +441,8 @@ def bench_paper_table(args, torch, A, W, dev, reps: int = 5):
         hs = hist.cpu().numpy()
         mi, nj = -(-p.m // Q), -(-p.n // P)
         rows.append({
-            "split": f"{Q}x{P}", "block": f"{mi}x{nj}", "inverse": f"{mi}x{mi}",
+            "split": f"{Q}x{P}", "block": f"{mi}x{nj}",
+            "inverse": f"{nj}x{nj}" if info["direct"] else f"{mi}x{mi}", "direct": info["direct"],
             "setup_ms": round(setup * 1e3, 2), "iters_ms": round(it * 1e3, 3),
             "total_ms": round((setup + it) * 1e3, 2), "iters_per_s": round(K / it, 1),
             "iteration_gbs": round(iteration_bytes(algo, info) * K / it / 1e9, 1),
@@ -451,7 +454,7 @@ def bench_paper_table(args, torch, A, W, dev, reps: int = 5):
         if (Q, P) in PAPER_TABLE_TIMES:
             ps, pi, pt = PAPER_TABLE_TIMES[(Q, P)]
             rows[-1]["paper_titan_v"] = {"inversion_ms": ps, "iters_ms": pi, "total_s": pt}
-        else:
+        if (Q, P) in chosen:
             rows[-1]["chosen_by_model"] = {"max_exchange": 0 if (Q, P) == chosen[0] else 10000}
         plan.close()
         print(f"[bench] paper table {Q}x{P}: setup {setup * 1e3:.1f} ms, {K} iterations {it * 1e3:.2f} ms",

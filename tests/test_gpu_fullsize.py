@@ -83,8 +83,11 @@ def test_full_size_sectioning_direct_parity(torch_gpu, full):
     """Q = 1, P = 32 on the full matrix: 6144 x 1000 blocks, more than
     (1 + sqrt 2) times taller than wide, where the library takes the direct
     x-update by itself (n_j x n_j inverses instead of m_i x m_i); the oracle
-    solves these blocks directly too.  Parity after 3 iterations, and the
-    residuals after 50 decrease."""
+    solves these blocks directly too.  Parity after 3 iterations (literal
+    oracle) and over 50 (push-through oracle, the same direct solve for these
+    blocks): at rho = 6 the 32 Jacobi sections do not settle on this
+    workload -- both residuals turn upwards after about ten iterations, in
+    the oracle as on the GPU -- and the histories agree entry by entry."""
     import paper_1811_05571_amd as A
     p, H, g = full
     plan = A.Plan(H, 1, 32, p.rho, p.lam)
@@ -97,9 +100,15 @@ def test_full_size_sectioning_direct_parity(torch_gpu, full):
     print(f"sectioning only 1x32 (direct): rel err after {K} iterations {err:.2e} (max element {emax:.2e})",
           flush=True)
     assert rel(s.cpu().numpy(), st.s) <= 1e-4 and rel(ghat.cpu().numpy(), st.ghat) <= 1e-4
-    _, hist = plan.solve(g, 50, history=True)
+    v50, hist = plan.solve(g, 50, history=True)
+    v50_ref, hist_ref, st50 = O.solve(p.H, p.g, 1, 32, p.rho, p.lam, 50, form="push_through")
     h = hist.cpu().numpy()
-    assert np.all(np.isfinite(h)) and h[-1, 0] < h[1, 0] and h[-1, 1] < h[1, 1]
+    e50 = rel(v50.cpu().numpy(), v50_ref)
+    eh = float(np.max(np.abs(h - hist_ref) / hist_ref))
+    print(f"  after 50: image {e50:.2e}, residual histories {eh:.2e} (largest relative entry difference)",
+          flush=True)
+    assert np.all(np.isfinite(h)) and eh <= 1e-3
+    assert e50 <= 1e-4
 
 
 def test_full_size_300_iterations_properties(torch_gpu, full):
