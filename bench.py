@@ -229,15 +229,21 @@ def copy_probe(torch, dev, mib: int, reps: int = 3):
 
 
 def attainable_bandwidth(torch, dev, gib: int = 2, reps: int = 5) -> dict:
-    """Reference rates of plain streaming on this GPU: a read-only sum over
-    `gib` GiB (torch's reduction, read once) and a copy of the same size
-    (read and written), best of `reps` timed runs each (HIP events)."""
+    """Reference rates of plain streaming on this GPU, best of `reps` timed
+    runs each (HIP events on torch's stream): read-only reductions over `gib`
+    GiB -- the row sums of a (rows x 4096) float32 view, the same matrix's
+    transposed product with a vector, and the flat sum -- and a copy of the
+    same size (read and written).  "read_gbs" is the fastest read."""
     n = gib * (1 << 30) // 4
     x = torch.ones(n, dtype=torch.float32, device=dev)
     y = torch.empty_like(x)
+    X = x.view(-1, 4096)
+    w = torch.ones(X.shape[0], dtype=torch.float32, device=dev)
     out = {}
-    for name, fn, nbytes in (("read", lambda: torch.sum(x), x.numel() * 4),
-                             ("copy", lambda: y.copy_(x), 2 * x.numel() * 4)):
+    reads = (("read_rowsum", lambda: X.sum(1)), ("read_gemv_t", lambda: torch.mv(X.t(), w)),
+             ("read_flat_sum", lambda: torch.sum(x)))
+    for name, fn, nbytes in [(r, f, x.numel() * 4) for r, f in reads] + [("copy", lambda: y.copy_(x),
+                                                                          2 * x.numel() * 4)]:
         fn()
         best = float("inf")
         for _ in range(reps):
@@ -248,7 +254,8 @@ def attainable_bandwidth(torch, dev, gib: int = 2, reps: int = 5) -> dict:
             torch.cuda.synchronize()
             best = min(best, e0.elapsed_time(e1) * 1e-3)
         out[f"{name}_gbs"] = round(nbytes / best / 1e9, 1)
-    del x, y
+    out["read_gbs"] = max(out[f"{r}_gbs"] for r, _ in reads)
+    del x, y, X, w
     torch.cuda.empty_cache()
     out["bytes"] = gib * (1 << 30)
     return out

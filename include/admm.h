@@ -428,8 +428,8 @@ void admm_destroy(admm_plan* plan);
  *   g        device complex64, packed like phases.
  *   v_out    device complex64 S x n (scene s at s*n).
  *   use_graph  1: replay one captured hipGraph of the iteration per step.
- * Errors: EINVAL, EUNSUPPORTED (a block with m_i >= (1 + sqrt 2) n_j, as for
- * admm_workspace_bytes), EWORKSPACE, ENONFINITE,
+ * Errors: EINVAL, EUNSUPPORTED (a block with m_i >= (1 + sqrt 2) n_j: the
+ * batch applies the inversion-lemma x-update only), EWORKSPACE, ENONFINITE,
  * ENOTPD, EHIP.  setup and solve synchronise `stream`.
  * ====================================================================== */
 typedef struct admm_batch admm_batch;

@@ -218,7 +218,8 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
         d.j = j;
         d.mi = rb.mi;
         d.nj = G.cols[j].nj;
-        // as for a single plan: the inversion-lemma x-update up to m_i < (1 + sqrt 2) n_j
+        // the batch applies the inversion-lemma x-update only; blocks this tall,
+        // where it would stream more than the direct form, are rejected
         if ((int64_t)d.mi * d.mi >= 2 * (int64_t)d.mi * d.nj + (int64_t)d.nj * d.nj) {
           snprintf(buf, sizeof buf, "scene %d block (%d,%d) is %d x %d: at least (1 + sqrt 2) times taller than wide",
                    s, i, j, d.mi, d.nj);
