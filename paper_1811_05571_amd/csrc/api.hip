@@ -325,20 +325,41 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
         z.row0[i] = (int)geo.ro[i];
       }
       z.bw[Q] = w;
-      // slabs of CPL columns per column block, spread over about
-      // ADMM_FZ_WGS workgroups in proportion to the block widths; workgroup
-      // w of a block with N workgroups takes slabs w, w + N, w + 2N, ..., so
-      // the workgroups read neighbouring slabs at the same time
+      // slabs of CPL columns per column block, spread over at most
+      // ADMM_FZ_WGS workgroups (those resident at once: two of 512 threads or
+      // one of 1024 per CU) in proportion to the block widths, by largest
+      // remainders, at least one per block; one workgroup more than fit
+      // would run alone after the others and double the kernel's time.
+      // Workgroup w of a block with N workgroups takes slabs w, w + N, w + 2N,
+      // ..., so the workgroups read neighbouring slabs at the same time.
       const int cplz = cols_per_load(storage);
       std::vector<int64_t> ns(P);
       int64_t tot = 0;
       for (int j = 0; j < P; ++j) tot += (ns[j] = (geo.cols[j].nj + cplz - 1) / cplz);
       int target = nt == 512 ? ADMM_FZ_WGS : ADMM_FZ_WGS / 2;
       if (const char* e = getenv("ADMM_FZ_WGS")) target = std::max(1, atoi(e));
+      std::vector<int64_t> nw(P);
+      std::vector<std::pair<double, int>> rem(P);
+      int64_t given = 0;
+      for (int j = 0; j < P; ++j) {
+        const double share = (double)target * (double)ns[j] / (double)tot;
+        nw[j] = std::max<int64_t>(1, std::min<int64_t>(ns[j], (int64_t)share));
+        rem[j] = {share - std::floor(share), j};
+        given += nw[j];
+      }
+      std::stable_sort(rem.begin(), rem.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+        return a.first > b.first;
+      });
+      for (int k = 0; k < P && given < target; ++k) {
+        const int j = rem[k].second;
+        if (nw[j] < ns[j]) {
+          ++nw[j];
+          ++given;
+        }
+      }
       int64_t sgb = 0;
       for (int j = 0; j < P; ++j) {
-        const int nwj = (int)std::max<int64_t>(
-            1, std::min<int64_t>(ns[j], std::llround((double)target * (double)ns[j] / (double)tot)));
+        const int nwj = (int)nw[j];
         const int w0 = (int)geo.t_fz.size();
         for (int q = 0; q < nwj; ++q) geo.t_fz.push_back(make_int4(j, q, (int)ns[j], (int)sgb));
         geo.fz_colwg.push_back(make_int2(w0, (int)geo.t_fz.size()));
