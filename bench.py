@@ -350,18 +350,93 @@ def block_geometry(m: int, n: int, Q: int, P: int, direct: bool = False) -> dict
             "gram_parts_patch": int(sum(T * ((T + 3) // 4 + 1) for T in tiles) * mult)}
 
 
-# rates of the split cost model (measured on MI355X: streaming reads, the FP64
-# setup, the fixed cost of one iteration's launches and small kernels)
-MODEL_RATES = {"hbm_gbs": 6800.0, "fp64_tflops": 45.0, "latency_us": 25.0}
-
-
-def split_model(A, m: int, n: int, Q: int, P: int) -> dict:
-    """admm_split_cost priced at MODEL_RATES: modelled setup and iteration times."""
+def model_times(A, m: int, n: int, Q: int, P: int, coef=None):
+    """(setup s, iteration s) of the library's timing model (admm_choose_split)
+    for split (Q, P), from admm_split_cost's features and the coefficients
+    (built-in when None)."""
     c = A.split_cost(m, n, Q, P)
-    return {"exchange_elements": int(c["exchange_elements"]),
-            "model_setup_ms": round(c["setup_fp64_flops"] / (MODEL_RATES["fp64_tflops"] * 1e12) * 1e3, 2),
-            "model_iter_us": round((c["bytes_per_iteration"] / (MODEL_RATES["hbm_gbs"] * 1e9)
-                                    + MODEL_RATES["latency_us"] * 1e-6) * 1e6, 1)}
+    k = A.model_coefficients() if coef is None else coef
+    h = c["h_bytes"]
+    hz = h * c["slab_load"] if c["single_pass"] else 0.0
+    edge = c["max_block_cols"] if c["direct"] else c["max_block_rows"]
+    fs = [c["setup_fp64_flops"], c["gram_span"], -(-int(edge) // 64), Q * P, 1.0]
+    fi = [hz if c["slab_threads"] == 512 else 0.0, hz if c["slab_threads"] == 1024 else 0.0,
+          c["bytes_per_iteration"] - h if c["single_pass"] else c["bytes_per_iteration"], Q * P, 1.0]
+    return float(np.dot(fs, k[:5])), float(np.dot(fi, k[5:]))
+
+
+def split_model(A, m: int, n: int, Q: int, P: int, coef=None) -> dict:
+    """Modelled setup and iteration times of a split next to its exchange count."""
+    c = A.split_cost(m, n, Q, P)
+    su, it = model_times(A, m, n, Q, P, coef)
+    return {"exchange_elements": int(c["exchange_elements"]), "model_setup_ms": round(su * 1e3, 2),
+            "model_iter_us": round(it * 1e6, 1)}
+
+
+CANDIDATES = (1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32)
+
+
+def sweep_splits(torch, A, p, H, g, K: int) -> dict:
+    """Every candidate equal split of the chooser: setup (plan construction
+    with its workspace) and one K-iteration solve from zero after a 5-iteration
+    warm-up, wall-clock around synchronisations."""
+    out = {}
+    for Q in CANDIDATES:
+        for P in CANDIDATES:
+            if Q > p.m or P > p.n:
+                continue
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = A.Plan(H, Q, P, p.rho, p.lam)
+            torch.cuda.synchronize()
+            su = time.perf_counter() - t0
+            plan.solve(g, 5)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.solve(g, K)
+            torch.cuda.synchronize()
+            out[(Q, P)] = (su, time.perf_counter() - t0)
+            plan.close()
+            del plan
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_chooser(torch, A, p, H, g, K: int) -> dict:
+    """The split chooser against measurement (Sec. IV; next to the paper's
+    splittings): every candidate is set up and run for K iterations, and the
+    picks of the model with its built-in coefficients, with coefficients
+    calibrated on this device (admm_calibrate), and of the measuring chooser
+    (model shortlist of 6 timed on the device) are compared with the best
+    measured total."""
+    t0 = time.perf_counter()
+    coef = A.calibrate(H, g)
+    cal_s = time.perf_counter() - t0
+    picks = {"model_builtin": A.choose_split(p.m, p.n, K)[:2],
+             "model_calibrated": A.choose_split(p.m, p.n, K, coef=coef)[:2]}
+    t0 = time.perf_counter()
+    picks["measured_shortlist_6"] = A.choose_split_measure(H, g, K, coef=coef, shortlist_len=6)[:2]
+    meas_s = time.perf_counter() - t0
+    sw = sweep_splits(torch, A, p, H, g, K)
+    tot = {k: v[0] + v[1] for k, v in sw.items()}
+    best = min(tot, key=tot.get)
+    res = {"iters": K, "candidates": len(sw), "best_measured": {"split": f"{best[0]}x{best[1]}",
+                                                                "total_ms": round(tot[best] * 1e3, 2)},
+           "calibration_s": round(cal_s, 3), "measuring_chooser_s": round(meas_s, 3),
+           "calibrated_coefficients": [float(x) for x in coef], "picks": {}}
+    for name, (Q, P) in picks.items():
+        su, it = model_times(A, p.m, p.n, Q, P, coef if name != "model_builtin" else None)
+        res["picks"][name] = {"split": f"{Q}x{P}", "measured_total_ms": round(tot[(Q, P)] * 1e3, 2),
+                              "over_best": round(tot[(Q, P)] / tot[best], 3),
+                              "model_total_ms": round((su + K * it) * 1e3, 2)}
+    # the model's error over all candidates (calibrated coefficients)
+    errs = []
+    for (Q, P), t in tot.items():
+        su, it = model_times(A, p.m, p.n, Q, P, coef)
+        errs.append(abs(su + K * it - t) / t)
+    res["model_rel_error_calibrated"] = {"mean": round(float(np.mean(errs)), 3), "max": round(float(np.max(errs)), 3)}
+    res["sweep_ms"] = {f"{Q}x{P}": [round(v[0] * 1e3, 2), round(v[1] * 1e3, 2)] for (Q, P), v in sorted(sw.items())}
+    return res
 
 
 def bench_full_splits(args, torch, A, prob, H, g, steps: int = 300, warmup: int = 300):
@@ -420,7 +495,7 @@ def bench_paper_table(args, torch, A, W, dev, reps: int = 5):
     g = torch.from_numpy(p.g).to(dev)
     K = W.PAPER_TABLE_ITERS
     rows = []
-    chosen = [A.choose_split(p.m, p.n, K, max_exchange=lim, **MODEL_RATES)[:2] for lim in (0.0, 10000.0)]
+    chosen = [A.choose_split(p.m, p.n, K, max_exchange=lim)[:2] for lim in (0.0, 10000.0)]
     splits = list(W.PAPER_TABLE_SPLITS) + [(1, 32)]   # and the direct x-update's 2160 x 703 blocks
     for s in chosen:
         if s not in splits:
@@ -466,11 +541,16 @@ def bench_paper_table(args, torch, A, W, dev, reps: int = 5):
         plan.close()
         print(f"[bench] paper table {Q}x{P}: setup {setup * 1e3:.1f} ms, {K} iterations {it * 1e3:.2f} ms",
               file=sys.stderr, flush=True)
+    chooser = bench_chooser(torch, A, p, H, g, K)
+    print(f"[bench] chooser on {p.m}x{p.n}, {K} iterations: best measured {chooser['best_measured']}, picks "
+          + ", ".join(f"{k} {v['split']} x{v['over_best']}" for k, v in chooser["picks"].items()),
+          file=sys.stderr, flush=True)
     del H, g
     torch.cuda.empty_cache()
     return {"workload": "cra2160x22500", "m": p.m, "n": p.n, "rho": p.rho, "lam_ratio": 0.02, "iters": K,
             "dtype": "c64", "timing": f"setup of a second build; iterations: median of {reps} solves from zero",
-            "paper_hardware": "one Titan V, MATLAB R2017b (context, not a target)", "splits": rows}
+            "paper_hardware": "one Titan V, MATLAB R2017b (context, not a target)", "splits": rows,
+            "chooser": chooser}
 
 
 def bench_batch(args, torch, A, W, dev):

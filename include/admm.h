@@ -162,32 +162,90 @@ int admm_workspace_bytes(int64_t m, int64_t n, int Q, const int64_t* row_off,
  *     of the adjoint product, [9] 4 x 4 tile patches of the Gram apply (0:
  *     single tiles), [10] 1 if the split iterates in a single pass over H,
  *     [11] workgroups of the single-pass slab kernel, [12] 1 if the split
- *     takes the direct x-update (see ADMM_XUPDATE_DIRECT), [13..15] 0.
+ *     takes the direct x-update (see ADMM_XUPDATE_DIRECT), [13] the single
+ *     pass's wave load factor (64-row group slots of all waves over the row
+ *     groups, >= 1; 0 without the single pass), [14] its workgroup size
+ *     (512, 1024; 0), [15] the Gram build's span (see admm_choose_split).
  */
 int admm_split_cost(int64_t m, int64_t n, int Q, const int64_t* row_off,
                     int P, const int64_t* col_off, int storage, double* out16);
 
 /*
- * admm_choose_split -- equal split (Q, P), Q and P from {1, 2, 3, 4, 5, 6,
- * 8, 10, 12, 16, 20, 24, 32}, that minimises the modelled time of setup
- * plus `iters` iterations,
- *   flops[2] / (fp64_tflops 1e12) + iters (bytes[1] / (hbm_gbs 1e9) + latency_us 1e-6),
- * among the splits admm_workspace_bytes accepts whose exchange count [0]
- * is at most max_exchange (<= 0: no limit; the limit stands for the link
- * budget of a distributed run, Sec. IV).  The rates are the caller's
- * measurements: on MI355X about 6800 GB/s for streaming reads, 40-50
- * TFLOP/s for the FP64 setup, 20-35 us of fixed cost per iteration.  The
- * model prices a fixed number of iterations; how many a split needs to
- * converge depends on the problem and is the caller's input.
- *   Q_out, P_out  host, receive the split; model_s host or NULL, receives
- *                 the modelled seconds.
- * Errors: EINVAL (NULL outputs, iters < 0, rates not > 0, latency < 0),
- * EUNSUPPORTED (no candidate meets the exchange limit; the unsplit (1, 1)
- * exchanges nothing, so only when its workspace would be too large).
+ * Timing model of a plan, for choosing a split (Sec. IV weighs splits by
+ * what the nodes exchange; on one GPU the price is time).  Setup seconds =
+ *   c[0] flops + c[1] span + c[2] steps + c[3] blocks + c[4],
+ * iteration seconds =
+ *   c[5] h512 + c[6] h1024 + c[7] bytes + c[8] blocks + c[9],
+ * where flops is admm_split_cost's [2]; span the Gram build's serial length,
+ * ceil(K / 32) K-chunks of one tile's workgroup times ceil(tiles / 512)
+ * rounds of workgroups (K = n_j, or m_i in the direct form); steps the tile-
+ * padded Gram edge / 64 (serial Cholesky and triangular-inverse panels);
+ * blocks Q P; h512 / h1024 the bytes of H a single-pass iteration streams
+ * with 512- / 1024-thread workgroups, times its wave load factor ([13]);
+ * bytes every other algorithmic byte of the iteration ([1], all of it for
+ * the two-pass and direct forms).  `coef` is host double[10].
+ *
+ * admm_model_coefficients -- the built-in coefficients: a non-negative
+ *   least-squares fit (relative error) to the setup and 50-iteration times
+ *   of all 169 candidate splits of 2160 x 22500 and 6144 x 32000 on MI355X.
+ *   Errors: EINVAL.
+ * admm_calibrate -- coefficients measured on the current device for this
+ *   shape: times the setup and 20 iterations of up to seven probe splits
+ *   ((4,4), (16,16), (2,1), (32,32), (20,4), (4,4) with the two-pass kernels,
+ *   (8,2)) of H with measurements g (device, as for admm_setup / admm_solve;
+ *   any finite g) in the caller's workspace (probes that do not fit are
+ *   skipped), and fits four scale factors of the built-in coefficients by
+ *   non-negative least squares (relative error): setup work (c[0..2]),
+ *   setup overhead (c[3..4]), iteration bytes (c[5..7]) and iteration
+ *   overhead (c[8..9]).  A short pass: tens to a few hundred ms.  Synchronises `stream`.  Errors: EINVAL,
+ *   EWORKSPACE (fewer than three probes fit), the errors of admm_setup and
+ *   admm_solve.
+ * admm_choose_split -- the equal split (Q, P), Q and P from {1, 2, 3, 4, 5,
+ *   6, 8, 10, 12, 16, 20, 24, 32}, whose modelled setup plus `iters`
+ *   iterations is least, among the splits admm_workspace_bytes accepts whose
+ *   exchange count [0] is at most max_exchange (<= 0: no limit; the limit
+ *   stands for the link budget of a distributed run, Sec. IV).  coef: host
+ *   double[10], or NULL for the built-in values.  The model prices a fixed
+ *   number of iterations; how many a split needs to converge depends on the
+ *   problem and is the caller's input.  Host computation.
+ *     Q_out, P_out  host, receive the split; model_s host or NULL, receives
+ *                   the modelled seconds.
+ *   Errors: EINVAL (NULL outputs, iters < 0, a negative or non-finite
+ *   coefficient), EUNSUPPORTED (no candidate meets the exchange limit; the
+ *   unsplit (1, 1) exchanges nothing, so only when its workspace would be
+ *   too large).
+ * admm_shortlist -- the same ranking: the k cheapest candidates into host
+ *   Qs[k], Ps[k] and (host or NULL) model_s[k], their number into *count
+ *   (<= k), and the workspace bytes the largest of them needs into
+ *   *max_workspace (host or NULL).  Host computation.  Errors: as
+ *   admm_choose_split, EINVAL (k < 1, NULL outputs).
+ * admm_choose_split_measure -- the same ranking, then the `shortlist`
+ *   cheapest candidates that fit the workspace are set up and timed on the
+ *   device (setup plus 20 iterations after a warm-up solve, in the caller's
+ *   workspace, with H and g as for admm_calibrate); the pick is the one with
+ *   the least measured setup + iters x iteration time, returned in
+ *   measured_s (host or NULL).  Synchronises `stream`.  Errors: those of
+ *   admm_choose_split, EINVAL (shortlist < 1, NULL H, g or workspace),
+ *   EWORKSPACE (no shortlisted split fits), the errors of admm_setup and
+ *   admm_solve.
  */
+int admm_model_coefficients(double* coef);
+int admm_calibrate(const void* H, const void* g, int64_t m, int64_t n,
+                   int storage, void* workspace, size_t workspace_bytes,
+                   void* stream, double* coef);
 int admm_choose_split(int64_t m, int64_t n, int iters, int storage,
-                      double max_exchange, double hbm_gbs, double fp64_tflops,
-                      double latency_us, int* Q_out, int* P_out, double* model_s);
+                      double max_exchange, const double* coef, int* Q_out,
+                      int* P_out, double* model_s);
+int admm_shortlist(int64_t m, int64_t n, int iters, int storage,
+                   double max_exchange, const double* coef, int k, int* Qs,
+                   int* Ps, double* model_s, int* count,
+                   size_t* max_workspace);
+int admm_choose_split_measure(const void* H, const void* g, int64_t m,
+                              int64_t n, int iters, int storage,
+                              double max_exchange, const double* coef,
+                              int shortlist, void* workspace,
+                              size_t workspace_bytes, void* stream,
+                              int* Q_out, int* P_out, double* measured_s);
 
 /*
  * admm_setup -- build a plan: copy/quantise H into the workspace and factor

@@ -40,8 +40,14 @@ SIGNATURES = [
     ("admm_last_error", _c.c_char_p, []),
     ("admm_workspace_bytes", _int, [_i64, _i64, _int, _vp, _int, _vp, _int, _c.POINTER(_sz)]),
     ("admm_split_cost", _int, [_i64, _i64, _int, _vp, _int, _vp, _int, _c.POINTER(_dbl)]),
-    ("admm_choose_split", _int, [_i64, _i64, _int, _int, _dbl, _dbl, _dbl, _dbl, _c.POINTER(_int), _c.POINTER(_int),
+    ("admm_model_coefficients", _int, [_c.POINTER(_dbl)]),
+    ("admm_calibrate", _int, [_vp, _vp, _i64, _i64, _int, _vp, _sz, _vp, _c.POINTER(_dbl)]),
+    ("admm_choose_split", _int, [_i64, _i64, _int, _int, _dbl, _vp, _c.POINTER(_int), _c.POINTER(_int),
                                  _c.POINTER(_dbl)]),
+    ("admm_shortlist", _int, [_i64, _i64, _int, _int, _dbl, _vp, _int, _vp, _vp, _vp, _c.POINTER(_int),
+                              _c.POINTER(_sz)]),
+    ("admm_choose_split_measure", _int, [_vp, _vp, _i64, _i64, _int, _int, _dbl, _vp, _int, _vp, _sz, _vp,
+                                         _c.POINTER(_int), _c.POINTER(_int), _c.POINTER(_dbl)]),
     ("admm_setup", _int, [_c.POINTER(_vp), _vp, _i64, _i64, _int, _vp, _int, _vp, _dbl, _dbl, _int,
                           _vp, _sz, _vp]),
     ("admm_set_lambda", _int, [_vp, _dbl]),
@@ -130,7 +136,7 @@ def workspace_bytes(m: int, n: int, Q: int, P: int, row_off=None, col_off=None,
 
 SPLIT_COST_KEYS = ["exchange_elements", "bytes_per_iteration", "setup_fp64_flops", "inverse_bytes", "h_bytes",
                    "workspace_bytes", "max_block_rows", "max_block_cols", "chunks", "gram_patches", "single_pass",
-                   "slab_workgroups", "direct"]
+                   "slab_workgroups", "direct", "slab_load", "slab_threads", "gram_span"]
 
 
 def split_cost(m: int, n: int, Q: int, P: int, row_off=None, col_off=None, storage: str = "c64",
@@ -144,13 +150,83 @@ def split_cost(m: int, n: int, Q: int, P: int, row_off=None, col_off=None, stora
     return {k: float(out[i]) for i, k in enumerate(SPLIT_COST_KEYS)}
 
 
-def choose_split(m: int, n: int, iters: int, storage: str = "c64", max_exchange: float = 0.0,
-                 hbm_gbs: float = 6800.0, fp64_tflops: float = 45.0, latency_us: float = 25.0):
-    """(Q, P, modelled seconds) of admm_choose_split."""
+N_COEF = 10   # coefficients of the timing model (admm_model_coefficients)
+
+
+def model_coefficients() -> np.ndarray:
+    """The built-in coefficients of the split timing model (MI355X fit)."""
+    out = (ctypes.c_double * N_COEF)()
+    _check(lib().admm_model_coefficients(out), "admm_model_coefficients")
+    return np.array(out[:], dtype=np.float64)
+
+
+def _coef_arg(coef):
+    if coef is None:
+        return None, None
+    arr = (ctypes.c_double * N_COEF)(*[float(x) for x in coef])
+    return arr, ctypes.cast(arr, ctypes.c_void_p)
+
+
+def choose_split(m: int, n: int, iters: int, storage: str = "c64", max_exchange: float = 0.0, coef=None):
+    """(Q, P, modelled seconds) of admm_choose_split (coef None: built-in)."""
     q, p, t = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
-    _check(lib().admm_choose_split(m, n, int(iters), STORAGE[storage], float(max_exchange), float(hbm_gbs),
-                                   float(fp64_tflops), float(latency_us), ctypes.byref(q), ctypes.byref(p),
-                                   ctypes.byref(t)), "admm_choose_split")
+    keep, cp = _coef_arg(coef)
+    _check(lib().admm_choose_split(m, n, int(iters), STORAGE[storage], float(max_exchange), cp, ctypes.byref(q),
+                                   ctypes.byref(p), ctypes.byref(t)), "admm_choose_split")
+    return int(q.value), int(p.value), float(t.value)
+
+
+def _probe_workspace(torch, H, splits, storage):
+    m, n = H.shape
+    nb = 0
+    for (Q, P, tp) in splits:
+        Q, P = min(Q, m), min(P, n)
+        nb = max(nb, workspace_bytes(m, n, Q, P, storage=storage, two_pass=tp))
+    return torch.empty(nb, dtype=torch.uint8, device=H.device)
+
+
+CALIBRATION_PROBES = [(4, 4, False), (16, 16, False), (2, 1, False), (32, 32, False), (20, 4, False),
+                      (4, 4, True), (8, 2, False)]
+
+
+def calibrate(H, g, storage: str = "c64", workspace=None) -> np.ndarray:
+    """Coefficients of the timing model measured on H's device (admm_calibrate).
+    Without a workspace one large enough for every probe is allocated."""
+    import torch
+    ws = workspace if workspace is not None else _probe_workspace(torch, H, CALIBRATION_PROBES, storage)
+    out = (ctypes.c_double * N_COEF)()
+    m, n = H.shape
+    _check(lib().admm_calibrate(_ptr(H), _ptr(g), m, n, STORAGE[storage], _ptr(ws), ws.numel(),
+                                _stream(torch, H.device), out), "admm_calibrate")
+    return np.array(out[:], dtype=np.float64)
+
+
+def shortlist(m: int, n: int, iters: int, k: int, storage: str = "c64", max_exchange: float = 0.0, coef=None):
+    """admm_shortlist: the k cheapest candidates [(Q, P, modelled s)] and the
+    workspace bytes the largest of them needs."""
+    qs, ps, ts = (ctypes.c_int * k)(), (ctypes.c_int * k)(), (ctypes.c_double * k)()
+    got, nb = ctypes.c_int(0), ctypes.c_size_t(0)
+    keep, cp = _coef_arg(coef)
+    _check(lib().admm_shortlist(m, n, int(iters), STORAGE[storage], float(max_exchange), cp, int(k), qs, ps, ts,
+                                ctypes.byref(got), ctypes.byref(nb)), "admm_shortlist")
+    return [(qs[i], ps[i], ts[i]) for i in range(got.value)], int(nb.value)
+
+
+def choose_split_measure(H, g, iters: int, storage: str = "c64", max_exchange: float = 0.0, coef=None,
+                         shortlist_len: int = 6, workspace=None):
+    """(Q, P, measured seconds) of admm_choose_split_measure.  Without a
+    workspace one large enough for the shortlist is allocated."""
+    import torch
+    m, n = H.shape
+    if workspace is None:
+        _, nb = shortlist(m, n, iters, shortlist_len, storage, max_exchange, coef)
+        workspace = torch.empty(nb, dtype=torch.uint8, device=H.device)
+    keep, cp = _coef_arg(coef)
+    q, p, t = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    _check(lib().admm_choose_split_measure(_ptr(H), _ptr(g), m, n, int(iters), STORAGE[storage],
+                                           float(max_exchange), cp, int(shortlist_len), _ptr(workspace),
+                                           workspace.numel(), _stream(torch, H.device), ctypes.byref(q),
+                                           ctypes.byref(p), ctypes.byref(t)), "admm_choose_split_measure")
     return int(q.value), int(p.value), float(t.value)
 
 

@@ -2,6 +2,7 @@
 // plan lifetime and the host side of setup / solve / KKT check.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -712,6 +713,58 @@ int admm_workspace_bytes(int64_t m, int64_t n, int Q, const int64_t* row_off, in
 }
 
 namespace {
+// Timing model of a plan (admm_choose_split): setup and per-iteration
+// seconds as sums of features times per-unit costs (coefficients).
+// Setup: FP64 flops; the Gram build's span, ceil(K / 32) K-chunks of one
+// tile's workgroup times ceil(tiles / 512) rounds of workgroups (two of its
+// 67 KB-LDS workgroups fit each of the 256 CUs; K = n_j, or m_i in the
+// direct form); the tiled Cholesky's and triangular inverse's
+// serial panel steps (T = tile-padded Gram edge / 64); blocks; fixed.
+// Iteration: the bytes of H the single pass streams, weighted by its wave
+// load factor (slot groups over row groups) and split by workgroup size
+// (512 or 1024 threads); all other algorithmic bytes (all of them for the
+// two-pass and direct forms); blocks; fixed.
+constexpr int kSetupTerms = 5, kIterTerms = 5;
+constexpr int kCoefs = kSetupTerms + kIterTerms;
+// Coefficients fitted by non-negative least squares (relative error) to the
+// setup and 50-iteration times of all 169 candidate splits of 2160 x 22500
+// and 6144 x 32000 on MI355X (complex64): s/flop (69 TFLOP/s), s per span
+// unit, s per panel step, s per block, s; s per single-pass byte of H (512-
+// and 1024-thread workgroups), s per other byte (7.0 TB/s), s per block, s.
+constexpr double kDefaultCoef[kCoefs] = {1.457e-14, 7.288e-06, 3.749e-04, 1.893e-06, 7.828e-04,
+                                         9.888e-14, 1.601e-13, 1.424e-13, 1.897e-08, 6.847e-05};
+
+void model_features(const Geometry& geo, double iter_bytes, double flops, double* fs, double* fi) {
+  int64_t kmax = 0;
+  for (const BlockDesc& d : geo.blocks) kmax = std::max<int64_t>(kmax, geo.direct ? d.mi : d.nj);
+  const double tiles = (double)geo.t_gram.size();
+  const double nb = (double)geo.blocks.size();
+  fs[0] = flops;
+  fs[1] = std::ceil((double)kmax / 32.0) * std::ceil(tiles / 512.0);
+  fs[2] = geo.max_mt / kTile;
+  fs[3] = nb;
+  fs[4] = 1.0;
+  const double h = (double)geo.lay.h_bytes;
+  double hz = 0.0;
+  if (geo.fz) {
+    int groups = 0;
+    const int waves = geo.fzt.bw[geo.Q];
+    for (int w = 0; w < waves; ++w) groups += geo.fzt.ngw[w];
+    hz = h * (double)(waves * geo.fz_rpl) / (double)std::max(groups, 1);
+  }
+  fi[0] = geo.fz && geo.fz_nt == 512 ? hz : 0.0;
+  fi[1] = geo.fz && geo.fz_nt == 1024 ? hz : 0.0;
+  fi[2] = geo.fz ? std::max(0.0, iter_bytes - h) : iter_bytes;
+  fi[3] = nb;
+  fi[4] = 1.0;
+}
+
+double dot_n(const double* a, const double* b, int n) {
+  double t = 0.0;
+  for (int k = 0; k < n; ++k) t += a[k] * b[k];
+  return t;
+}
+
 // Cost model of one split (host only; see admm_split_cost).
 void split_cost(const Geometry& geo, double* out) {
   const int64_t m = geo.m, n = geo.n;
@@ -782,6 +835,12 @@ void split_cost(const Geometry& geo, double* out) {
   out[10] = geo.fz ? 1.0 : 0.0;
   out[11] = (double)geo.t_fz.size();
   out[12] = geo.direct ? 1.0 : 0.0;
+  // features of the timing model (model_features)
+  double fs[kSetupTerms], fi[kIterTerms];
+  model_features(geo, out[1], out[2], fs, fi);
+  out[13] = geo.fz ? (fi[0] + fi[1]) / (double)geo.lay.h_bytes : 0.0;   // single pass: wave load factor
+  out[14] = geo.fz ? geo.fz_nt : 0;
+  out[15] = fs[1];                                                       // Gram-build span
 }
 }  // namespace
 
@@ -797,31 +856,265 @@ int admm_split_cost(int64_t m, int64_t n, int Q, const int64_t* row_off, int P, 
   return ADMM_OK;
 }
 
-int admm_choose_split(int64_t m, int64_t n, int iters, int storage, double max_exchange, double hbm_gbs,
-                      double fp64_tflops, double latency_us, int* Q_out, int* P_out, double* model_s) {
-  g_last_error.clear();
-  if (!Q_out || !P_out) return fail(ADMM_EINVAL, "Q_out and P_out must not be NULL");
-  if (iters < 0 || !(hbm_gbs > 0.0) || !(fp64_tflops > 0.0) || !(latency_us >= 0.0))
-    return fail(ADMM_EINVAL, "iters >= 0, hbm_gbs > 0, fp64_tflops > 0 and latency_us >= 0 required");
-  static const int cand[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32};
-  double best = HUGE_VAL;
-  int bq = 0, bp = 0;
-  for (int Q : cand)
-    for (int P : cand) {
+namespace {
+constexpr int kCand[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32};
+
+// Modelled seconds of setup plus `iters` iterations of every candidate equal
+// split within the exchange limit, cheapest first.
+struct Priced {
+  double t;
+  int Q, P;
+};
+std::vector<Priced> price_candidates(int64_t m, int64_t n, int iters, int storage, double max_exchange,
+                                     const double* coef) {
+  std::vector<Priced> v;
+  for (int Q : kCand)
+    for (int P : kCand) {
       if (Q > m || P > n) continue;
       Geometry geo;
       std::string err;
-      if (build_geometry(geo, m, n, Q, nullptr, P, nullptr, storage, err) != ADMM_OK) continue;   // e.g. too tall
+      if (build_geometry(geo, m, n, Q, nullptr, P, nullptr, storage, err) != ADMM_OK) continue;
       double c[16];
       split_cost(geo, c);
       if (max_exchange > 0.0 && c[0] > max_exchange) continue;
-      const double t = c[2] / (fp64_tflops * 1e12) + iters * (c[1] / (hbm_gbs * 1e9) + latency_us * 1e-6);
-      if (t < best) best = t, bq = Q, bp = P;
+      double fs[kSetupTerms], fi[kIterTerms];
+      model_features(geo, c[1], c[2], fs, fi);
+      const double t = dot_n(fs, coef, kSetupTerms) + iters * dot_n(fi, coef + kSetupTerms, kIterTerms);
+      v.push_back({t, Q, P});
     }
-  if (!bq) return fail(ADMM_EUNSUPPORTED, "no candidate split meets the exchange limit");
+  std::stable_sort(v.begin(), v.end(), [](const Priced& a, const Priced& b) { return a.t < b.t; });
+  return v;
+}
+
+int check_coef(const double* coef) {
+  for (int k = 0; k < kCoefs; ++k)
+    if (!(coef[k] >= 0.0) || !std::isfinite(coef[k]))
+      return fail(ADMM_EINVAL, "coefficient %d must be finite and >= 0", k);
+  return ADMM_OK;
+}
+
+// Non-negative least squares for a few unknowns: rows of X (nf columns
+// `cols` of a row-major matrix with stride ld) against y, relative residuals
+// (each row divided by y); an active set that drops the most negative
+// coefficient and solves again.  Columns not in `cols` keep their value.
+void nnls_small(const std::vector<double>& X, int ld, const std::vector<double>& y, std::vector<int> cols,
+                double* coef) {
+  const int rows = (int)y.size();
+  while (!cols.empty()) {
+    const int k = (int)cols.size();
+    std::vector<double> A(k * k, 0.0), b(k, 0.0);
+    for (int r = 0; r < rows; ++r) {
+      const double w = 1.0 / (y[r] * y[r]);
+      for (int a = 0; a < k; ++a) {
+        b[a] += w * X[r * ld + cols[a]] * y[r];
+        for (int c = 0; c < k; ++c) A[a * k + c] += w * X[r * ld + cols[a]] * X[r * ld + cols[c]];
+      }
+    }
+    // scaled Gaussian elimination with partial pivoting (features differ by
+    // many orders of magnitude: columns scaled to unit diagonal first)
+    std::vector<double> sc(k);
+    for (int a = 0; a < k; ++a) sc[a] = A[a * k + a] > 0 ? 1.0 / std::sqrt(A[a * k + a]) : 1.0;
+    for (int a = 0; a < k; ++a) {
+      b[a] *= sc[a];
+      for (int c = 0; c < k; ++c) A[a * k + c] *= sc[a] * sc[c];
+    }
+    bool singular = false;
+    for (int piv = 0; piv < k; ++piv) {
+      int best = piv;
+      for (int r = piv + 1; r < k; ++r)
+        if (std::fabs(A[r * k + piv]) > std::fabs(A[best * k + piv])) best = r;
+      if (std::fabs(A[best * k + piv]) < 1e-12) {
+        singular = true;
+        break;
+      }
+      if (best != piv) {
+        for (int c = 0; c < k; ++c) std::swap(A[piv * k + c], A[best * k + c]);
+        std::swap(b[piv], b[best]);
+      }
+      for (int r = piv + 1; r < k; ++r) {
+        const double f = A[r * k + piv] / A[piv * k + piv];
+        for (int c = piv; c < k; ++c) A[r * k + c] -= f * A[piv * k + c];
+        b[r] -= f * b[piv];
+      }
+    }
+    std::vector<double> x(k, 0.0);
+    if (!singular)
+      for (int r = k - 1; r >= 0; --r) {
+        double t = b[r];
+        for (int c = r + 1; c < k; ++c) t -= A[r * k + c] * x[c];
+        x[r] = t / A[r * k + r] * 1.0;
+      }
+    int worst = -1;
+    for (int a = 0; a < k; ++a) {
+      x[a] *= sc[a];
+      if (singular || x[a] < 0.0)
+        if (worst < 0 || x[a] < x[worst]) worst = a;
+    }
+    if (singular) worst = k - 1;   // drop the last column and try again
+    if (worst < 0) {
+      for (int a = 0; a < k; ++a) coef[cols[a]] = x[a];
+      return;
+    }
+    coef[cols[worst]] = 0.0;
+    cols.erase(cols.begin() + worst);
+  }
+}
+
+// Wall time of one setup and of `its` iterations (after a warm-up solve) of
+// split (Q, P) with the given flags, in the caller's workspace.
+int time_split(const void* H, const void* g, int64_t m, int64_t n, int Q, int P, int storage, void* ws,
+               size_t ws_bytes, void* stream, int its, double* setup_s, double* iter_s, Geometry* geo_out) {
+  Geometry geo;
+  std::string err;
+  int rc = build_geometry(geo, m, n, Q, nullptr, P, nullptr, storage, err);
+  if (rc) return fail(rc, "%s", err.c_str());
+  if (geo.lay.total > ws_bytes) return ADMM_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  admm_plan* p = nullptr;
+  HIP_TRY(hipStreamSynchronize(st));
+  auto t0 = std::chrono::steady_clock::now();
+  rc = admm_setup(&p, H, m, n, Q, nullptr, P, nullptr, 1.0, 0.0, storage, ws, ws_bytes, stream);
+  auto t1 = std::chrono::steady_clock::now();
+  if (rc) return rc;
+  // v_out in the workspace's KKT staging vector (n_pad >= n complex), not read back
+  void* v_out = p->kkt_v;
+  rc = admm_solve(p, g, std::min(its, 10), 0.0, 1, v_out, nullptr, nullptr, 0, stream);
+  auto t2 = std::chrono::steady_clock::now();
+  if (!rc) rc = admm_solve(p, g, its, 0.0, 1, v_out, nullptr, nullptr, 0, stream);
+  auto t3 = std::chrono::steady_clock::now();
+  if (geo_out) *geo_out = p->geo;
+  admm_destroy(p);
+  if (rc) return rc;
+  *setup_s = std::chrono::duration<double>(t1 - t0).count();
+  *iter_s = std::chrono::duration<double>(t3 - t2).count() / its;
+  return ADMM_OK;
+}
+}  // namespace
+
+int admm_model_coefficients(double* coef) {
+  g_last_error.clear();
+  if (!coef) return fail(ADMM_EINVAL, "coef is NULL");
+  for (int k = 0; k < kCoefs; ++k) coef[k] = kDefaultCoef[k];
+  return ADMM_OK;
+}
+
+int admm_choose_split(int64_t m, int64_t n, int iters, int storage, double max_exchange, const double* coef,
+                      int* Q_out, int* P_out, double* model_s) {
+  g_last_error.clear();
+  if (!Q_out || !P_out) return fail(ADMM_EINVAL, "Q_out and P_out must not be NULL");
+  if (iters < 0) return fail(ADMM_EINVAL, "iters must be >= 0");
+  if (coef && check_coef(coef)) return ADMM_EINVAL;
+  const std::vector<Priced> v = price_candidates(m, n, iters, storage, max_exchange, coef ? coef : kDefaultCoef);
+  if (v.empty()) return fail(ADMM_EUNSUPPORTED, "no candidate split meets the exchange limit");
+  *Q_out = v[0].Q;
+  *P_out = v[0].P;
+  if (model_s) *model_s = v[0].t;
+  return ADMM_OK;
+}
+
+int admm_shortlist(int64_t m, int64_t n, int iters, int storage, double max_exchange, const double* coef, int k,
+                   int* Qs, int* Ps, double* model_s, int* count, size_t* max_workspace) {
+  g_last_error.clear();
+  if (!Qs || !Ps || !count || k < 1) return fail(ADMM_EINVAL, "Qs, Ps, count must not be NULL and k >= 1");
+  if (iters < 0) return fail(ADMM_EINVAL, "iters must be >= 0");
+  if (coef && check_coef(coef)) return ADMM_EINVAL;
+  const std::vector<Priced> v = price_candidates(m, n, iters, storage, max_exchange, coef ? coef : kDefaultCoef);
+  const int got = (int)std::min<size_t>(v.size(), (size_t)k);
+  size_t ws = 0;
+  for (int i = 0; i < got; ++i) {
+    Qs[i] = v[i].Q;
+    Ps[i] = v[i].P;
+    if (model_s) model_s[i] = v[i].t;
+    Geometry geo;
+    std::string err;
+    if (build_geometry(geo, m, n, v[i].Q, nullptr, v[i].P, nullptr, storage, err) == ADMM_OK)
+      ws = std::max(ws, geo.lay.total);
+  }
+  *count = got;
+  if (max_workspace) *max_workspace = ws;
+  return got ? ADMM_OK : fail(ADMM_EUNSUPPORTED, "no candidate split meets the exchange limit");
+}
+
+int admm_calibrate(const void* H, const void* g, int64_t m, int64_t n, int storage, void* workspace,
+                   size_t workspace_bytes, void* stream, double* coef) {
+  g_last_error.clear();
+  if (!H || !g || !coef || !workspace) return fail(ADMM_EINVAL, "H, g, workspace and coef must not be NULL");
+  for (int k = 0; k < kCoefs; ++k) coef[k] = kDefaultCoef[k];
+  // Probe splits: single-pass plans of moderate and of many blocks, a few
+  // large blocks, and the two-pass kernels (the flag), so that work and
+  // overhead vary independently across the probes.
+  struct Probe {
+    int Q, P, flags;
+  };
+  const Probe probes[] = {{4, 4, 0}, {16, 16, 0}, {2, 1, 0}, {32, 32, 0}, {20, 4, 0}, {4, 4, ADMM_TWO_PASS},
+                          {8, 2, 0}};
+  std::vector<double> Xs, Xi, ys, yi;
+  for (const Probe& pr : probes) {
+    const int Q = (int)std::min<int64_t>(pr.Q, m), P = (int)std::min<int64_t>(pr.P, n);
+    double su = 0.0, it = 0.0;
+    Geometry geo;
+    const int rc = time_split(H, g, m, n, Q, P, storage | pr.flags, workspace, workspace_bytes, stream, 20, &su,
+                              &it, &geo);
+    if (rc == ADMM_EWORKSPACE) continue;   // does not fit the caller's memory: skipped
+    if (rc) return rc;
+    double c[16], fs[kSetupTerms], fi[kIterTerms];
+    split_cost(geo, c);
+    model_features(geo, c[1], c[2], fs, fi);
+    Xs.insert(Xs.end(), fs, fs + kSetupTerms);
+    Xi.insert(Xi.end(), fi, fi + kIterTerms);
+    ys.push_back(su);
+    yi.push_back(it);
+  }
+  if (ys.size() < 3) return fail(ADMM_EWORKSPACE, "the workspace holds fewer than three probe splits");
+  // The built-in model's structure is kept (it was fitted to 338 measured
+  // splits); the probes fit four scale factors of it: setup work (flops,
+  // span, panel steps) and setup overhead (blocks, fixed), iteration bytes
+  // (the three byte terms) and iteration overhead (blocks, fixed).
+  const size_t rows = ys.size();
+  std::vector<double> Xs2(rows * 2), Xi2(rows * 2);
+  for (size_t r = 0; r < rows; ++r) {
+    const double* fs = &Xs[r * kSetupTerms];
+    const double* fi = &Xi[r * kIterTerms];
+    const double* d = kDefaultCoef;
+    Xs2[r * 2] = d[0] * fs[0] + d[1] * fs[1] + d[2] * fs[2];
+    Xs2[r * 2 + 1] = d[3] * fs[3] + d[4] * fs[4];
+    Xi2[r * 2] = d[5] * fi[0] + d[6] * fi[1] + d[7] * fi[2];
+    Xi2[r * 2 + 1] = d[8] * fi[3] + d[9] * fi[4];
+  }
+  double ss[2] = {1.0, 1.0}, si[2] = {1.0, 1.0};
+  nnls_small(Xs2, 2, ys, {0, 1}, ss);
+  nnls_small(Xi2, 2, yi, {0, 1}, si);
+  const double scale[kCoefs] = {ss[0], ss[0], ss[0], ss[1], ss[1], si[0], si[0], si[0], si[1], si[1]};
+  for (int k = 0; k < kCoefs; ++k) coef[k] = kDefaultCoef[k] * scale[k];
+  return ADMM_OK;
+}
+
+int admm_choose_split_measure(const void* H, const void* g, int64_t m, int64_t n, int iters, int storage,
+                              double max_exchange, const double* coef, int shortlist, void* workspace,
+                              size_t workspace_bytes, void* stream, int* Q_out, int* P_out, double* measured_s) {
+  g_last_error.clear();
+  if (!H || !g || !Q_out || !P_out || !workspace) return fail(ADMM_EINVAL, "H, g, workspace, Q_out and P_out must not be NULL");
+  if (iters < 0 || shortlist < 1) return fail(ADMM_EINVAL, "iters >= 0 and shortlist >= 1 required");
+  if (coef && check_coef(coef)) return ADMM_EINVAL;
+  const std::vector<Priced> v = price_candidates(m, n, iters, storage, max_exchange, coef ? coef : kDefaultCoef);
+  if (v.empty()) return fail(ADMM_EUNSUPPORTED, "no candidate split meets the exchange limit");
+  double best = HUGE_VAL;
+  int bq = 0, bp = 0, timed_n = 0;
+  for (const Priced& c : v) {
+    if (timed_n == shortlist) break;
+    double su = 0.0, it = 0.0;
+    const int rc = time_split(H, g, m, n, c.Q, c.P, storage, workspace, workspace_bytes, stream, 20, &su, &it,
+                              nullptr);
+    if (rc == ADMM_EWORKSPACE) continue;
+    if (rc) return rc;
+    ++timed_n;
+    const double t = su + iters * it;
+    if (t < best) best = t, bq = c.Q, bp = c.P;
+  }
+  if (!bq) return fail(ADMM_EWORKSPACE, "no shortlisted split fits the workspace");
   *Q_out = bq;
   *P_out = bp;
-  if (model_s) *model_s = best;
+  if (measured_s) *measured_s = best;
   return ADMM_OK;
 }
 

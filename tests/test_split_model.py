@@ -89,26 +89,59 @@ def test_setup_flops_closed_form():
     assert c["setup_fp64_flops"] == 8 * (100 * 101 / 2 * 300 + 100 ** 3)
 
 
-def test_chooser_is_the_argmin_under_the_exchange_limit():
+def _model_time(m, n, Q, P, K, coef):
+    """The timing model written out from admm_split_cost's features:
+    setup = c0 flops + c1 span + c2 steps + c3 blocks + c4, iteration =
+    c5 h512 + c6 h1024 + c7 (other bytes) + c8 blocks + c9."""
+    c = A.split_cost(m, n, Q, P)
+    h = c["h_bytes"]
+    hz = h * c["slab_load"] if c["single_pass"] else 0.0
+    edge = c["max_block_cols"] if c["direct"] else c["max_block_rows"]
+    fs = [c["setup_fp64_flops"], c["gram_span"], -(-int(edge) // 64), Q * P, 1.0]
+    fi = [hz if c["slab_threads"] == 512 else 0.0, hz if c["slab_threads"] == 1024 else 0.0,
+          c["bytes_per_iteration"] - h if c["single_pass"] else c["bytes_per_iteration"], Q * P, 1.0]
+    return sum(a * b for a, b in zip(fs, coef[:5])) + K * sum(a * b for a, b in zip(fi, coef[5:]))
+
+
+@pytest.mark.parametrize("coef", ["builtin", "scaled"])
+def test_chooser_is_the_argmin_under_the_exchange_limit(coef):
     m, n, K = 2160, 22500, 50
-    bw, fl, lat = 6800.0, 45.0, 25.0
+    k = A.model_coefficients()
+    if coef == "scaled":      # other coefficients: setup 3x dearer, blocks 10x
+        k = k * [3, 3, 3, 3, 3, 1, 1, 1, 10, 1]
     for limit in (0.0, 20000.0, 7000.0):
-        q, p, t = A.choose_split(m, n, K, max_exchange=limit, hbm_gbs=bw, fp64_tflops=fl, latency_us=lat)
+        q, p, t = A.choose_split(m, n, K, max_exchange=limit, coef=None if coef == "builtin" else k)
         best = None
         for Q in CANDIDATES:
             for P in CANDIDATES:
-                try:
-                    c = A.split_cost(m, n, Q, P)
-                except A.ADMMError:
-                    continue
+                c = A.split_cost(m, n, Q, P)
                 if limit > 0 and c["exchange_elements"] > limit:
                     continue
-                tt = c["setup_fp64_flops"] / (fl * 1e12) + K * (c["bytes_per_iteration"] / (bw * 1e9) + lat * 1e-6)
+                tt = _model_time(m, n, Q, P, K, k)
                 if best is None or tt < best[2]:
                     best = (Q, P, tt)
         assert (q, p) == best[:2] and t == pytest.approx(best[2], rel=1e-12)
+        short, ws = A.shortlist(m, n, K, 5, max_exchange=limit, coef=None if coef == "builtin" else k)
+        assert short[0][:2] == (q, p) and [x[2] for x in short] == sorted(x[2] for x in short)
+        assert ws == max(A.split_cost(m, n, Q, P)["workspace_bytes"] for Q, P, _ in short)
         if limit > 0:
             assert A.split_cost(m, n, q, p)["exchange_elements"] <= limit
+
+
+def test_model_features():
+    """The features the timing model prices, against their definitions: the
+    single pass's wave load factor (6144 x 32000, Q = 4: 16 waves of six
+    64-row groups, 96 groups: 1.0; Q = 1 in 2160 rows: 34 groups on 6 waves
+    of six, 36 slots) and the Gram build's span (4 x 8: 32 blocks of 24 x 25
+    / 2 tiles in rounds of 512 workgroups, 4000 columns in chunks of 32)."""
+    c = A.split_cost(6144, 32000, 4, 8)
+    assert c["slab_load"] == 1.0 and c["slab_threads"] == 1024
+    assert c["gram_span"] == 125 * -(-(32 * 24 * 25 // 2) // 512)
+    c = A.split_cost(2160, 22500, 1, 3)
+    assert c["slab_threads"] == 512 and c["slab_load"] == pytest.approx(36 / 34)
+    c = A.split_cost(2160, 22500, 20, 3)
+    assert c["single_pass"] == 0 and c["slab_load"] == 0 and c["slab_threads"] == 0
+    assert len(A.model_coefficients()) == 10 and (A.model_coefficients() >= 0).all()
 
 
 def test_chooser_errors():
@@ -117,9 +150,14 @@ def test_chooser_errors():
     assert A.choose_split(2160, 22500, 50, max_exchange=1.0)[:2] == (1, 1)
     assert A.choose_split(1000, 300, 50, max_exchange=1.0)[:2] == (1, 1)
     assert A.split_cost(1000, 300, 1, 1)["direct"] == 1
-    for kw in (dict(hbm_gbs=0.0), dict(fp64_tflops=-1.0), dict(latency_us=-1.0)):
+    k = A.model_coefficients()
+    for bad in (-1.0, float("nan"), float("inf")):
+        kk = k.copy()
+        kk[3] = bad
         with pytest.raises(A.ADMMError) as ei:
-            A.choose_split(2160, 22500, 50, **kw)
+            A.choose_split(2160, 22500, 50, coef=kk)
         assert ei.value.status == "ADMM_EINVAL"
+    with pytest.raises(A.ADMMError):
+        A.shortlist(2160, 22500, 50, 0)
     with pytest.raises(A.ADMMError):
         A.choose_split(2160, 22500, -1)
