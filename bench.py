@@ -216,6 +216,62 @@ def summarise_traffic(fetch_csv: str, write_csv: str, probe_mib: int, workload: 
     return written
 
 
+MFMA_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_BF16", "SQ_VALU_MFMA_BUSY_CYCLES",
+                 "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
+SIMDS = 256 * 4   # MI355X: 256 CUs of 4 SIMDs
+XCDS = 8          # and 8 XCDs, each with its own GRBM
+
+
+def summarise_mfma(counter_csv: str, trace_csv: str, command: str, workload: str = "batch64_cra6144x32000"):
+    """profiles/mfma_<workload>.md: per batched GEMM kernel, the mean per
+    dispatch of the MFMA counters, the MFMA flops they give (MOPS x 512),
+    the kernel-trace duration, and the MFMA-busy fraction
+    SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / XCDs x SIMDs): the
+    busy cycles are summed over all SIMDs, GRBM_GUI_ACTIVE over the 8 XCDs
+    (each counts the kernel's cycles)."""
+    import csv
+    per = {}
+    with open(counter_csv) as f:
+        for row in csv.DictReader(f):
+            name = row["Kernel_Name"]
+            if "k_bgemm" not in name:
+                continue
+            if row["Counter_Name"] not in MFMA_COUNTERS:
+                continue
+            key = (_short_kernel(name), int(row["Dispatch_Id"]))
+            per.setdefault(key, {}).setdefault(row["Counter_Name"], 0.0)
+            per[key][row["Counter_Name"]] += float(row["Counter_Value"])
+    dur = {}
+    with open(trace_csv) as f:
+        for row in csv.DictReader(f):
+            if "k_bgemm" not in row["Kernel_Name"]:
+                continue
+            dur.setdefault(_short_kernel(row["Kernel_Name"]), []).append(
+                (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-9)
+    lines = [f"# MFMA counters: batched complex GEMMs, {workload}", "",
+             "One MI355X, ROCm 7.2.  The 64-scene batch (bf16 H0, FP32 vectors split into three bf16 terms:",
+             "12 real MFMAs per complex multiply-add) for a few iterations under rocprofv3 counter collection;",
+             "durations from the kernel trace of the same run (serialised by the counter collection, so",
+             "longer than in the timed bench).", "", "Command (`$REPO` = repository root):", "", "```",
+             command, "```", "",
+             "| kernel | dispatches | MFMA bf16 instructions | MOPS_BF16 x 512 = MFMA flops | MFMA busy cycles (all SIMDs) | GUI active cycles (sum of 8 XCDs) | MFMA busy fraction | avg trace us | MFMA TFLOP/s |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    kinds = sorted({k for k, _ in per})
+    for k in kinds:
+        rows = [v for (kk, _), v in per.items() if kk == k]
+        mean = {c: float(np.mean([r.get(c, 0.0) for r in rows])) for c in MFMA_COUNTERS}
+        flops = mean["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * 512
+        busy = mean["SQ_VALU_MFMA_BUSY_CYCLES"] / max(mean["GRBM_GUI_ACTIVE"] / XCDS * SIMDS, 1.0)
+        d = float(np.mean(dur.get(k, [float("nan")])))
+        lines.append(f"| `{k}` | {len(rows)} | {mean['SQ_INSTS_VALU_MFMA_BF16']:.4g} | {flops:.4g} | "
+                     f"{mean['SQ_VALU_MFMA_BUSY_CYCLES']:.4g} | {mean['GRBM_GUI_ACTIVE']:.4g} | {busy:.3f} | "
+                     f"{d * 1e6:.1f} | {flops / d / 1e12:.1f} |")
+    path = os.path.join(PROFILES, f"mfma_{workload}.md")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return path
+
+
 def copy_probe(torch, dev, mib: int, reps: int = 3):
     """A plain elementwise copy of known size (N bytes read, N written) that
     calibrates the memory counters."""
@@ -571,7 +627,7 @@ def bench_batch(args, torch, A, W, dev):
     info = bb.info()
     print(f"[bench] batch: {b.S} scenes generated in {gen_s:.1f}s, setup {setup_s:.2f}s, "
           f"{info['scene_tiles']} scene-tiles", file=sys.stderr, flush=True)
-    K = b.iters
+    K = args.batch_iters or b.iters
     bb.solve(g, 3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -586,6 +642,7 @@ def bench_batch(args, torch, A, W, dev):
     n, NST = b.H0.shape[1], info["scene_tiles"]
     cmacs = NST * b.tile_rows * n                      # complex MACs of one GEMM pass
     mfma_flop = 2 * 12 * cmacs                         # 3-term split: 12 real MFMA MACs per complex MAC
+    algo_flop = 8 * cmacs                              # the product itself: 8 real flops per complex MAC
     kern = {}
     for name, (ms, cnt) in prof.items():
         kern[name] = {"avg_us": round(ms / max(cnt, 1) * 1e3, 2), "launches": cnt}
@@ -593,6 +650,9 @@ def bench_batch(args, torch, A, W, dev):
         sec = kern[name]["avg_us"] * 1e-6
         kern[name]["mfma_tflops"] = round(mfma_flop / sec / 1e12, 1)
         kern[name]["mfma_frac"] = round(mfma_flop / sec / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)
+        kern[name]["algo_tflops"] = round(algo_flop / sec / 1e12, 1)
+        kern[name]["algo_frac"] = round(algo_flop / sec / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)
+        kern[name]["mfma_flop_per_pass"] = mfma_flop
         kern[name]["h0_gbs"] = round(b.H0.size * 4 / sec / 1e9, 1)
     gsec = kern["k_gram"]["avg_us"] * 1e-6
     kern["k_gram"]["gbs"] = round(info["ginv_bytes"] / gsec / 1e9, 1)
@@ -617,8 +677,8 @@ def bench_batch(args, torch, A, W, dev):
                                    np.linalg.norm(b.u_true[s]) ** 2), t2 - t1))
         plan.close()
         del Hs, plan
-    seq_t = float(np.mean([x[0] for x in seq]))
-    seq_it = float(np.mean([x[2] for x in seq]))
+    seq_t = float(np.mean([x[0] for x in seq])) if seq else float("nan")
+    seq_it = float(np.mean([x[2] for x in seq])) if seq else float("nan")
     res = {
         "workload": b.name, "scenes": b.S, "iters": K, "value": round(b.S / el, 2),
         "unit": "scenes/s (300 iterations each, setup apart)",
@@ -629,10 +689,11 @@ def bench_batch(args, torch, A, W, dev):
         "kernels": kern, "ginv_gb": round(info["ginv_bytes"] / 1e9, 2),
         "nmse_mean": float(np.mean(nmse_b)),
         "plain_one_at_a_time": {
-            "scenes": len(seq), "value": round(1.0 / seq_it, 2), "unit": "scenes/s (300 iterations each, setup apart)",
-            "value_with_setup": round(1.0 / seq_t, 2),
-            "nmse_mean": float(np.mean([x[1] for x in seq])),
-            "batched_nmse_mean_same_scenes": float(np.mean(nmse_b[:len(seq)])),
+            "scenes": len(seq), "value": round(1.0 / seq_it, 2) if seq else None,
+            "unit": "scenes/s (300 iterations each, setup apart)",
+            "value_with_setup": round(1.0 / seq_t, 2) if seq else None,
+            "nmse_mean": float(np.mean([x[1] for x in seq])) if seq else None,
+            "batched_nmse_mean_same_scenes": float(np.mean(nmse_b[:len(seq)])) if seq else None,
         },
     }
     bb.close()
@@ -684,6 +745,10 @@ def main(argv=None):
     ap.add_argument("--paper-table-only", action="store_true", help="measure only the paper's timing-table workload")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-seq", type=int, default=8, help="scenes solved one at a time for comparison")
+    ap.add_argument("--batch-iters", type=int, default=0,
+                    help="iterations of the batched solves (0: the workload's 300; counter runs use a few)")
+    ap.add_argument("--summarise-mfma", nargs=2, metavar=("COUNTER_CSV", "TRACE_CSV"),
+                    help="write profiles/mfma_<batch workload>.md from an MFMA counter run and its kernel trace")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-small", action="store_true", help="skip the 256 x 4096 workload")
     ap.add_argument("--no-form-oracle", action="store_true",
@@ -700,6 +765,9 @@ def main(argv=None):
     ap.add_argument("--command", default="", help="counter command recorded in the traffic summary")
     args = ap.parse_args(argv)
 
+    if args.summarise_mfma:
+        print(summarise_mfma(args.summarise_mfma[0], args.summarise_mfma[1], args.command))
+        return 0
     if args.summarise_traffic:
         import workloads as W
         for p in summarise_traffic(args.summarise_traffic[0], args.summarise_traffic[1], args.probe_mib,
