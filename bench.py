@@ -294,9 +294,10 @@ def attainable_bandwidth(torch, dev, gib: int = 2, reps: int = 5) -> dict:
     x = torch.ones(n, dtype=torch.float32, device=dev)
     y = torch.empty_like(x)
     X = x.view(-1, 4096)
-    w = torch.ones(X.shape[0], dtype=torch.float32, device=dev)
+    Xc = x.view(4096, -1)          # its transpose is a row-major (rows x 4096) operand read once by the gemv
+    w = torch.ones(4096, dtype=torch.float32, device=dev)
     out = {}
-    reads = (("read_rowsum", lambda: X.sum(1)), ("read_gemv_t", lambda: torch.mv(X.t(), w)),
+    reads = (("read_rowsum", lambda: X.sum(1)), ("read_gemv_t", lambda: torch.mv(Xc.t(), w)),
              ("read_flat_sum", lambda: torch.sum(x)))
     for name, fn, nbytes in [(r, f, x.numel() * 4) for r, f in reads] + [("copy", lambda: y.copy_(x),
                                                                           2 * x.numel() * 4)]:
@@ -311,7 +312,7 @@ def attainable_bandwidth(torch, dev, gib: int = 2, reps: int = 5) -> dict:
             best = min(best, e0.elapsed_time(e1) * 1e-3)
         out[f"{name}_gbs"] = round(nbytes / best / 1e9, 1)
     out["read_gbs"] = max(out[f"{r}_gbs"] for r, _ in reads)
-    del x, y, X, w
+    del x, y, X, Xc, w
     torch.cuda.empty_cache()
     out["bytes"] = gib * (1 << 30)
     return out
