@@ -865,9 +865,9 @@ struct Priced {
   double t;
   int Q, P;
 };
-std::vector<Priced> price_candidates(int64_t m, int64_t n, int iters, int storage, double max_exchange,
-                                     const double* coef) {
-  std::vector<Priced> v;
+void price_candidates(int64_t m, int64_t n, int iters, int storage, double max_exchange, const double* coef,
+                      std::vector<Priced>& v) {
+  v.clear();
   for (int Q : kCand)
     for (int P : kCand) {
       if (Q > m || P > n) continue;
@@ -883,7 +883,6 @@ std::vector<Priced> price_candidates(int64_t m, int64_t n, int iters, int storag
       v.push_back({t, Q, P});
     }
   std::stable_sort(v.begin(), v.end(), [](const Priced& a, const Priced& b) { return a.t < b.t; });
-  return v;
 }
 
 int check_coef(const double* coef) {
@@ -1004,7 +1003,8 @@ int admm_choose_split(int64_t m, int64_t n, int iters, int storage, double max_e
   if (!Q_out || !P_out) return fail(ADMM_EINVAL, "Q_out and P_out must not be NULL");
   if (iters < 0) return fail(ADMM_EINVAL, "iters must be >= 0");
   if (coef && check_coef(coef)) return ADMM_EINVAL;
-  const std::vector<Priced> v = price_candidates(m, n, iters, storage, max_exchange, coef ? coef : kDefaultCoef);
+  std::vector<Priced> v;
+  price_candidates(m, n, iters, storage, max_exchange, coef ? coef : kDefaultCoef, v);
   if (v.empty()) return fail(ADMM_EUNSUPPORTED, "no candidate split meets the exchange limit");
   *Q_out = v[0].Q;
   *P_out = v[0].P;
@@ -1018,7 +1018,8 @@ int admm_shortlist(int64_t m, int64_t n, int iters, int storage, double max_exch
   if (!Qs || !Ps || !count || k < 1) return fail(ADMM_EINVAL, "Qs, Ps, count must not be NULL and k >= 1");
   if (iters < 0) return fail(ADMM_EINVAL, "iters must be >= 0");
   if (coef && check_coef(coef)) return ADMM_EINVAL;
-  const std::vector<Priced> v = price_candidates(m, n, iters, storage, max_exchange, coef ? coef : kDefaultCoef);
+  std::vector<Priced> v;
+  price_candidates(m, n, iters, storage, max_exchange, coef ? coef : kDefaultCoef, v);
   const int got = (int)std::min<size_t>(v.size(), (size_t)k);
   size_t ws = 0;
   for (int i = 0; i < got; ++i) {
@@ -1096,7 +1097,8 @@ int admm_choose_split_measure(const void* H, const void* g, int64_t m, int64_t n
   if (!H || !g || !Q_out || !P_out || !workspace) return fail(ADMM_EINVAL, "H, g, workspace, Q_out and P_out must not be NULL");
   if (iters < 0 || shortlist < 1) return fail(ADMM_EINVAL, "iters >= 0 and shortlist >= 1 required");
   if (coef && check_coef(coef)) return ADMM_EINVAL;
-  const std::vector<Priced> v = price_candidates(m, n, iters, storage, max_exchange, coef ? coef : kDefaultCoef);
+  std::vector<Priced> v;
+  price_candidates(m, n, iters, storage, max_exchange, coef ? coef : kDefaultCoef, v);
   if (v.empty()) return fail(ADMM_EUNSUPPORTED, "no candidate split meets the exchange limit");
   double best = HUGE_VAL;
   int bq = 0, bp = 0, timed_n = 0;

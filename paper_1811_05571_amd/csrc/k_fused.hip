@@ -101,7 +101,6 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
   __shared__ float4 hl[NT * RPL];   // the slab's rows in flight (16 bytes per padded row)
   __shared__ float red[NW][2 * CPL];
   __shared__ float2 zc[kFzMaxQ * CPL], zs[kFzMaxQ * CPL], zv[CPL], cn[kFzMaxQ * CPL];
-  __shared__ double racc[kRedCount][kWave];   // residual partial sums of the z-update lanes
   __shared__ int bws[kFzMaxQ + 1];            // waves of each row block (read per lane)
   const int4 wk = z.work[blockIdx.x];
   const int j = wk.x, sl0 = wk.y, sl1 = wk.z, sgb = wk.w;
@@ -179,10 +178,13 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
     }
   };
   prefetch(sl0);
-  if (tid < kWave) {
-#pragma unroll
-    for (int q = 0; q < kRedCount; ++q) racc[q][tid] = 0.0;
-  }
+  // residual partial sums of the z-update lanes (wave 0), in registers: an
+  // LDS read-modify-write per slab would sit on the path to the barrier
+  double racc[kRedCount] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  // butterfly levels of the replica sum: lanes i*CPL + t, i < Q, span the
+  // lowest log2(CPL) + ceil(log2 Q) lane bits (the lanes above hold zeros)
+  int qspan = CPL;
+  while (qspan < QC) qspan <<= 1;
   if (tid <= Q) bws[tid] = z.bw[tid];
   lds_barrier();   // ys and bws complete
 
@@ -249,13 +251,12 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
           si0 = sv.y;
         }
         // consensus sum of u^i + s^i over the replicas (lanes t, t + CPL, ...):
-        // a compensated butterfly, so every lane of the column ends with the
-        // same total
+        // a compensated butterfly over the replica lanes, so every lane of the
+        // column ends with the same total
         float mr, er, mi, ei;
         two_sum(xr, sr0, mr, er);
         two_sum(xi, si0, mi, ei);
-#pragma unroll
-        for (int msk = CPL; msk < kWave; msk <<= 1) {
+        for (int msk = CPL; msk < qspan; msk <<= 1) {
           const float omr = __shfl_xor(mr, msk, kWave), oer = __shfl_xor(er, msk, kWave);
           const float omi = __shfl_xor(mi, msk, kWave), oei = __shfl_xor(ei, msk, kWave);
           float e1, e2;
@@ -283,15 +284,15 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
           a.s[(int64_t)i * np + p] = make_float2(sr, sim);
           a.c[(int64_t)i * np + cd.cpad0 + cperm(col, a.cpl)] = cnew;
           cn[lane] = cnew;
-          racc[kRedRp2][lane] += (double)dr * dr + (double)di * di;
-          racc[kRedU2][lane] += (double)xr * xr + (double)xi * xi;
-          racc[kRedS2][lane] += (double)sr * sr + (double)sim * sim;
+          racc[kRedRp2] += (double)dr * dr + (double)di * di;
+          racc[kRedU2] += (double)xr * xr + (double)xi * xi;
+          racc[kRedS2] += (double)sr * sr + (double)sim * sim;
           if (i == 0) {
             a.v[p] = make_float2(vr, vi);
             const float2 vo = zv[t];
             const double dvr = (double)vr - vo.x, dvi = (double)vi - vo.y;
-            racc[kRedDv2][lane] += dvr * dvr + dvi * dvi;
-            racc[kRedV2][lane] += (double)vr * vr + (double)vi * vi;
+            racc[kRedDv2] += dvr * dvr + dvi * dvi;
+            racc[kRedV2] += (double)vr * vr + (double)vi * vi;
           }
         } else if (act) {
           cn[lane] = make_float2(0.f, 0.f);
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
   if (full && wave == 0) {
     double acc[kRedCount];
 #pragma unroll
-    for (int q = 0; q < kRedCount; ++q) acc[q] = wave_sum_d(racc[q][lane]);
+    for (int q = 0; q < kRedCount; ++q) acc[q] = wave_sum_d(racc[q]);
     if (lane == 0) {
 #pragma unroll
       for (int q = 0; q < kRedCount; ++q) a.redpart[(int64_t)blockIdx.x * kRedCount + q] = acc[q];

@@ -373,7 +373,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_gemv_h(IterArgs a, const int4
 // is stored in y in the layout of c for the next row product.
 template <int MAXQ, int SRC>
 __global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __restrict__ tiles) {
-  const bool ur = SRC != 0 && *a.uref != 0;
+  const bool from_uref = SRC != 0 && *a.uref != 0;   // direct form: u = u_ref + the pieces
   const int4 t = tiles[blockIdx.x];
   const ColDesc cd = a.cols[t.x];
   const int col = t.y + threadIdx.x;
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kZCols) void k_zupdate(IterArgs a, const int4* __re
           si.add(pk.y);
         }
       } else {
-        if (ur) {
+        if (from_uref) {
           const float2 u0 = a.y[(int64_t)i * a.n_pad + pc];
           sr.add(u0.x);
           si.add(u0.y);
