@@ -358,6 +358,36 @@ def cpu_baseline(prob, n_iter: int, keep=(), H=None):
     }
 
 
+CONVERGENCE_CHECKPOINTS = (100, 300, 1000, 3000, 10000)
+
+
+def convergence(plan, g, prob, checkpoints) -> dict:
+    """The solve continued warm from zero through growing iteration counts:
+    at each, the FP64 KKT violation of v (over lambda; zero exactly at the
+    lasso minimiser), the reconstruction NMSE against the synthetic truth, and
+    the last iteration's |r_p|^2, |r_d|^2.  Where the KKT violation falls while
+    the NMSE levels off, the NMSE left is the lasso model's on this geometry,
+    not unfinished iterations."""
+    import torch
+    pts, done, t_run = [], 0, 0.0
+    for k in checkpoints:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v, hist = plan.solve(g, k - done, warm=done > 0, history=True)
+        torch.cuda.synchronize()
+        t_run += time.perf_counter() - t0
+        done = k
+        vn = v.cpu().numpy()
+        pts.append({"iterations": k, "kkt_violation": plan.kkt(g, v),
+                    "nmse_vs_truth": float(np.linalg.norm(vn - prob.u_true) ** 2 / np.linalg.norm(prob.u_true) ** 2),
+                    "nonzeros": int(np.count_nonzero(vn)),
+                    "final_residuals": [float(x) for x in hist[-1].cpu().numpy()]})
+        print(f"[bench] convergence: {k} iterations, KKT {pts[-1]['kkt_violation']:.3e}, "
+              f"NMSE {pts[-1]['nmse_vs_truth']:.4f}", file=sys.stderr, flush=True)
+    return {"checkpoints": pts, "solve_s": round(t_run, 3), "truth_nonzeros": int(np.count_nonzero(prob.u_true)),
+            "note": "one solve continued warm through the checkpoints (history on); KKT violation over lambda"}
+
+
 def bench_small(args, torch, A, W, dev, reps: int = 5) -> dict:
     """The 256 x 4096 consensus workload (Q = 4 row blocks of 64, P = 1, 200
     iterations): H is 8.4 MB and stays in the caches, so an iteration is
@@ -752,6 +782,8 @@ def main(argv=None):
                     help="write profiles/mfma_<batch workload>.md from an MFMA counter run and its kernel trace")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-small", action="store_true", help="skip the 256 x 4096 workload")
+    ap.add_argument("--no-convergence", action="store_true",
+                    help="skip the KKT violation and NMSE at growing iteration counts")
     ap.add_argument("--no-form-oracle", action="store_true",
                     help="skip the oracle runs on the dequantised bf16 / fp8 matrices")
     ap.add_argument("--seed", type=int, default=0)
@@ -880,6 +912,8 @@ def main(argv=None):
         "nmse_vs_truth": main["nmse"], "kkt_violation": main["kkt"],
         "final_residuals": main["final_residuals"],
     }
+    if not args.no_convergence:
+        out["convergence"] = convergence(plan, g, prob, CONVERGENCE_CHECKPOINTS)
     form_plans = {}
     if not args.no_forms:
         forms = {}

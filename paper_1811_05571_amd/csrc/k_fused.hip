@@ -385,8 +385,8 @@ hipError_t fz_go(const IterArgs& a, const FzArgs& z, hipStream_t st, KTime kt) {
 }  // namespace
 
 // Shapes built (complex64 storage): 512 threads (8 waves of rows, two
-// workgroups per CU, y in LDS) and 1024 threads (16 waves, one workgroup per
-// CU, y in registers), each with RPL 1..6 groups of 64 rows per wave.  bf16 / fp8 lane loads decode into four times the registers per row
+// workgroups per CU) and 1024 threads (16 waves, one workgroup per CU), each
+// with RPL 1..6 groups of 64 rows per wave and y in LDS.  bf16 / fp8 lane loads decode into four times the registers per row
 // and take the two-pass kernels.
 hipError_t launch_fz_slab(const IterArgs& a, const FzArgs& z, int nt, int rpl, hipStream_t st, KTime kt) {
   if (a.hs.storage != 0) return hipErrorInvalidValue;
