@@ -50,7 +50,12 @@ struct GemmItem {
 
 struct BatchArgs {
   const uint16_t *h_re, *h_im;     // H0 bf16 planes, block store [j][m0][ld_j]
-  const uint16_t *t_re, *t_im;     // H0^T bf16 planes [j][n_j][ldt]
+  // The GEMMs' operand stores, k-tiled: a matrix of rows x K is kept as
+  // tiles of 16 rows x 32 k, [row / 16][k / 32][row % 16][k % 32], so one
+  // k-step of a wave's 16-row subtile is one contiguous kilobyte and its
+  // k-steps follow each other in memory.
+  const uint16_t *hk_re, *hk_im;   // H0 per column block: rows m0, K = ld_j (offset h_off)
+  const uint16_t *t_re, *t_im;     // H0^T per column block: rows round_up(n_j, 16), K = ldt (offset gi_off)
   const BlockDesc* pseudo;         // per column block j: h_off/ld (H0 store), gi_off (H0^T store),
                                    // f_off/mt (FP64 Gram G0_j), nj, cpad0
   const SceneTile* stab;
@@ -83,6 +88,8 @@ hipError_t launch_bgemm_n(const BatchArgs& a, const GemmItem* items, int nitems,
 hipError_t launch_bgemm_h(const BatchArgs& a, const GemmItem* items, int nitems, int ms, hipStream_t st);
 hipError_t launch_bzupdate(const BatchArgs& a, const ColDesc* cols, const int4* tiles, int ntiles, hipStream_t st);
 hipError_t launch_btranspose(const BatchArgs& a, int P, int64_t m0, int max_nj, hipStream_t st);
+// The k-tiled copy hk of the block store (after it is written).
+hipError_t launch_btile_h(const BatchArgs& a, int P, int64_t m0, hipStream_t st);
 hipError_t launch_bgram_assemble(const int4* tiles, int ntiles, const BlockDesc* blocks, const int32_t* blk_tile0,
                                  const int32_t* tiles_flat, const float2* phases, const double2* G0,
                                  const BlockDesc* pseudo, int tile_rows, double rho, double2* A, hipStream_t st);

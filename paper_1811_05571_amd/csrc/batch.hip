@@ -70,7 +70,7 @@ struct BatchGeo {
   int64_t m_pad = 0, n_pad = 0, ldt = 0, mt0 = 0;
   int R = 0, NST = 0, max_nj = 0;
   // workspace
-  size_t o_hre = 0, o_him = 0, o_tre = 0, o_tim = 0, o_ginv = 0, o_ginv16 = 0, o_G0 = 0, o_A = 0, o_W = 0, group_bytes = 0;
+  size_t o_hre = 0, o_him = 0, o_hkre = 0, o_hkim = 0, o_tre = 0, o_tim = 0, o_ginv = 0, o_ginv16 = 0, o_G0 = 0, o_A = 0, o_W = 0, group_bytes = 0;
   bool inv16 = false;              // a bfloat16-pair copy of the inverses is kept and applied
   int64_t ginv_elems = 0;
   size_t o_c = 0, o_s = 0, o_v = 0, o_part = 0, o_gp = 0, o_ghat = 0, o_r = 0, o_y = 0, o_cs = 0, o_ys = 0, o_phase = 0;
@@ -180,7 +180,7 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
     d.gi_off = toff;
     d.f_off = foff;
     hoff += m0 * ldh;
-    toff += (int64_t)nj * G.ldt;
+    toff += (int64_t)((nj + 15) / 16 * 16) * G.ldt;   // k-tiled, rows padded to 16
     foff += G.mt0 * G.mt0;
     acc += ldc;
     G.max_nj = std::max(G.max_nj, nj);
@@ -377,6 +377,8 @@ int build_batch(BatchGeo& G, int64_t m0, int64_t n, int tile_rows, int S, const 
   };
   G.o_hre = take((size_t)hoff * 2);
   G.o_him = take((size_t)hoff * 2);
+  G.o_hkre = take((size_t)hoff * 2);
+  G.o_hkim = take((size_t)hoff * 2);
   G.o_tre = take((size_t)toff * 2);
   G.o_tim = take((size_t)toff * 2);
   G.o_ginv = take((size_t)gioff * 8);
@@ -457,6 +459,8 @@ BatchArgs batch_args(admm_batch* b, const float2* g) {
   BatchArgs a{};
   a.h_re = at<uint16_t>(b, G.o_hre);
   a.h_im = at<uint16_t>(b, G.o_him);
+  a.hk_re = at<uint16_t>(b, G.o_hkre);
+  a.hk_im = at<uint16_t>(b, G.o_hkim);
   a.t_re = at<uint16_t>(b, G.o_tre);
   a.t_im = at<uint16_t>(b, G.o_tim);
   a.pseudo = at<BlockDesc>(b, G.o_pseudo);
@@ -705,6 +709,7 @@ int admm_batch_setup(admm_batch** out, const void* H0, int64_t m0, int64_t n, in
   const BlockDesc* dpseudo = at<BlockDesc>(b, G.o_pseudo);
   STRY(launch_pack_quant(static_cast<const float2*>(H0), m0, n, dpseudo, P, (int)m0, hs, ctl, st));
   STRY(launch_btranspose(batch_args(b, nullptr), P, m0, G.max_nj, st));
+  STRY(launch_btile_h(batch_args(b, nullptr), P, m0, st));
   {
     Geometry g0;
     g0.t_gram = G.t0_gram;

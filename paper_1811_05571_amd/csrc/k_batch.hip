@@ -102,6 +102,7 @@ __device__ __forceinline__ bf16x8 as_bf16(const u32x4& v) { return __builtin_bit
 // step ahead.
 constexpr int kGN = 64;   // scene-tile columns per workgroup
 constexpr int kGK = 32;   // k per step
+constexpr int kAT = 16 * kGK;   // elements of one k-tile of the A stores (16 rows x 32 k)
 
 struct __attribute__((aligned(16))) BStage {
   uint16_t v[2][6][kGN][kGK];
@@ -138,9 +139,9 @@ __device__ __forceinline__ void bstage_frag(const BStage& bs, int buf, int nt, S
 }
 
 // Accumulates over k in [k0, k1) (multiples of kGK, at least one step):
-// a_re/a_im[m] point at this lane's A row of subtile m at k = 0 (+ its
-// 8-element k offset), bsrc at this thread's B piece at k = 0, plane stride
-// ps.  conj_a: use conj(A).  A streams from HBM, so its loads run two steps
+// a_re/a_im[m] point at this lane's 16 bytes of subtile m's k-tile at k = 0
+// in the k-tiled A store (step k is kAT elements on per kGK), bsrc at this
+// thread's B piece at k = 0, plane stride ps.  conj_a: use conj(A).  A streams from HBM, so its loads run two steps
 // ahead in three register sets used in rotation (the loop is unrolled by
 // three, so no loop-carried copy makes a step wait for loads it does not
 // use); B comes from the cache-resident split planes one step ahead through
@@ -156,8 +157,8 @@ __device__ __forceinline__ void gemm_tile(const uint16_t* const (&a_re)[MS], con
   auto load_a = [&](int k, u32x4 (&r)[MS], u32x4 (&i)[MS]) {
 #pragma unroll
     for (int m = 0; m < MS; ++m) {
-      r[m] = ld16(a_re[m] + k);
-      i[m] = ld16(a_im[m] + k);
+      r[m] = ld16(a_re[m] + (int64_t)(k / kGK) * kAT);
+      i[m] = ld16(a_im[m] + (int64_t)(k / kGK) * kAT);
     }
   };
   bstage_load(bsrc + k0, ps, br);
@@ -219,9 +220,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_bgemm_n(BatchArgs a, const Ge
   const uint16_t* aim[MS];
 #pragma unroll
   for (int m = 0; m < MS; ++m) {
-    const int64_t arow = (int64_t)it.f * a.tile_rows + it.pad[2] + 16 * (wave * MS + m) + (lane & 15);
-    are[m] = a.h_re + pj.h_off + arow * pj.ld + kq;
-    aim[m] = a.h_im + pj.h_off + arow * pj.ld + kq;
+    // 16-row subtile of this wave's rows; lane: row lane % 16, k offset kq
+    const int64_t r16 = ((int64_t)it.f * a.tile_rows + it.pad[2]) / 16 + wave * MS + m;
+    const int64_t o = pj.h_off + r16 * (pj.ld / kGK) * kAT + (lane & 15) * kGK + kq;
+    are[m] = a.hk_re + o;
+    aim[m] = a.hk_im + o;
   }
   // B piece of this thread: the split planes of c (columns beyond cnt read a
   // valid scene-tile; their results are not stored)
@@ -306,8 +309,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_bgemm_h(BatchArgs a, const Ge
   for (int m = 0; m < MS; ++m) {
     const int col = it.m0 + 16 * (wave * MS + m) + (lane & 15);
     const int64_t colc = min(col, pj.nj - 1);
-    are[m] = a.t_re + pj.gi_off + colc * a.ldt + (int64_t)it.f * a.tile_rows + kq;
-    aim[m] = a.t_im + pj.gi_off + colc * a.ldt + (int64_t)it.f * a.tile_rows + kq;
+    const int64_t o = pj.gi_off + (colc / 16) * (a.ldt / kGK) * kAT + (colc % 16) * kGK +
+                      ((int64_t)it.f * a.tile_rows / kGK) * kAT + kq;
+    are[m] = a.t_re + o;
+    aim[m] = a.t_im + o;
   }
   const int bcol = threadIdx.x >> 2;
   const SceneTile stb = a.stab[it.st0 + min(bcol, it.cnt - 1)];
@@ -427,7 +432,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_bsplit_y(BatchArgs a) {
   }
 }
 
-// H0^T store: [j][n_j][ldt] from the block store [j][m0][ld_j]; 64 x 64 tiles.
+// H0^T store, k-tiled (rows: the block's columns, padded to 16 with zeros;
+// K = ldt), from the block store [j][m0][ld_j]; 64 x 64 tiles.
 __global__ __launch_bounds__(kBlockThreads) void k_btranspose(BatchArgs a, int64_t m0) {
   __shared__ uint16_t tr[64][65], ti[64][65];
   const BlockDesc pj = a.pseudo[blockIdx.z];
@@ -447,13 +453,38 @@ __global__ __launch_bounds__(kBlockThreads) void k_btranspose(BatchArgs a, int64
   __syncthreads();
   uint16_t* ore = const_cast<uint16_t*>(a.t_re);
   uint16_t* oim = const_cast<uint16_t*>(a.t_im);
+  const int nj16 = (pj.nj + 15) / 16 * 16;
   for (int e = threadIdx.x; e < 64 * 64; e += kBlockThreads) {
     const int c = e / 64, r = e % 64;
-    if (c0 + c < pj.nj && r0 + r < a.ldt) {
-      const int64_t o = pj.gi_off + (int64_t)(c0 + c) * a.ldt + r0 + r;
+    const int cc = c0 + c, rr = r0 + r;
+    if (cc < nj16 && rr < a.ldt) {
+      const int64_t o = pj.gi_off + ((int64_t)(cc / 16) * (a.ldt / kGK) + rr / kGK) * kAT + (cc % 16) * kGK + rr % kGK;
       ore[o] = tr[r][c];
       oim[o] = ti[r][c];
     }
+  }
+}
+
+// The forward GEMM's k-tiled copy of block j = blockIdx.y of the block store
+// (same offset and size: m0 x ld_j, both multiples of 16 and 32), one
+// 16-byte unit of eight k per thread; unit u is element 8u of the tiled
+// layout.
+__global__ __launch_bounds__(kBlockThreads) void k_btile_h(BatchArgs a, int64_t m0) {
+  const BlockDesc pj = a.pseudo[blockIdx.y];
+  const int KB = pj.ld / kGK;
+  const int64_t units = m0 * pj.ld / 8;
+  uint16_t* dre = const_cast<uint16_t*>(a.hk_re) + pj.h_off;
+  uint16_t* dim = const_cast<uint16_t*>(a.hk_im) + pj.h_off;
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < units; u += (int64_t)gridDim.x * blockDim.x) {
+    const int c8 = (int)(u & 3);
+    const int64_t t = u >> 2;
+    const int rr = (int)(t & 15);
+    const int64_t t2 = t >> 4;
+    const int kb = (int)(t2 % KB);
+    const int64_t row = (t2 / KB) * 16 + rr, col = (int64_t)kb * kGK + 8 * c8;
+    const int64_t src = pj.h_off + row * pj.ld + col;
+    *reinterpret_cast<uint4*>(dre + 8 * u) = *reinterpret_cast<const uint4*>(a.h_re + src);
+    *reinterpret_cast<uint4*>(dim + 8 * u) = *reinterpret_cast<const uint4*>(a.h_im + src);
   }
 }
 
@@ -536,6 +567,11 @@ hipError_t launch_bzupdate(const BatchArgs& a, const ColDesc* cols, const int4* 
 hipError_t launch_btranspose(const BatchArgs& a, int P, int64_t m0, int max_nj, hipStream_t st) {
   hipLaunchKernelGGL(k_btranspose, dim3((unsigned)((m0 + 63) / 64), (unsigned)((max_nj + 63) / 64), P),
                      dim3(kBlockThreads), 0, st, a, m0);
+  return hipGetLastError();
+}
+
+hipError_t launch_btile_h(const BatchArgs& a, int P, int64_t m0, hipStream_t st) {
+  hipLaunchKernelGGL(k_btile_h, dim3(1024, (unsigned)P), dim3(kBlockThreads), 0, st, a, m0);
   return hipGetLastError();
 }
 
