@@ -27,24 +27,13 @@ namespace admm {
 // Workgroup barrier for data exchanged through LDS: the wave's own LDS
 // accesses complete (lgkmcnt 0), then s_barrier; the empty asm statements
 // keep the compiler from moving memory accesses across it.  Unlike
-// __syncthreads it leaves global loads in flight, including the loads into
-// LDS of the next slab (a workgroup fence would wait for those).
+// __syncthreads it leaves global loads in flight, including the next slab's
+// rows (a workgroup fence would wait for those).
 __device__ __forceinline__ void lds_barrier() {
   asm volatile("" ::: "memory");
   __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt, expcnt not waited for
   __builtin_amdgcn_s_barrier();
   asm volatile("" ::: "memory");
-}
-
-// Rows rb + 64 k (k < ngw) of a slab (16 bytes each, slab base sp) into the
-// same rows of the LDS array hl, one 16-byte load into LDS per lane and row:
-// lane l of the wave writes hl[64 g + l] for the wave-uniform row 64 g.
-template <int RPL>
-__device__ __forceinline__ void stage_rows(const char* sp, float4* hl, int rb, int lane, int ngw) {
-#pragma unroll
-  for (int k = 0; k < RPL; ++k)
-    if (k < ngw)
-      __builtin_amdgcn_global_load_lds(sp + (size_t)(rb + kWave * k) * 16, hl + (rb - lane + kWave * k), 16, 0, 0);
 }
 
 // a + b = s + e exactly (Knuth's two-sum; the same s and e for (b, a)).
@@ -88,8 +77,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_fz_rows(IterArgs a, FzArgs z,
 //             mean over the replicas by a compensated butterfly, the
 //             threshold, the duals and c, residual partial sums in FP64;
 //   forward : every lane adds H[row, slab] c^{i(row)}[slab] to its row sums.
-// The lane loads alternate between two register sets: the next slab's are
-// issued as a slab's processing starts.
+// The lane loads go to a second register set: the next slab's are issued as
+// a slab's processing starts and stay in flight through its adjoint step,
+// z-update and forward step.
 // mode 1 skips the first two steps (forward products of the state's c).
 // YL: y of the column block in LDS instead of RPL registers per lane.
 template <class F, int NT, int RPL, bool YL>
@@ -98,7 +88,6 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
   static_assert(NW <= kFzMaxWaves && RPL <= 32, "slab kernel shape");
   static_assert(kFzMaxQ * CPL <= kWave, "the z-update takes one lane of wave 0 per replica and column");
   __shared__ float2 ys[YL ? NT * RPL : 1];
-  __shared__ float4 hl[NT * RPL];   // the slab's rows in flight (16 bytes per padded row)
   __shared__ float red[NW][2 * CPL];
   __shared__ float2 zc[kFzMaxQ * CPL], zs[kFzMaxQ * CPL], zv[CPL], cn[kFzMaxQ * CPL];
   __shared__ int bws[kFzMaxQ + 1];            // waves of each row block (read per lane)
@@ -116,26 +105,24 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
   const int64_t mp = a.m_pad, np = a.n_pad;
   const bool full = z.mode == 0;
 
-  // The slab's lane loads go from HBM straight into LDS (one 16-byte load
-  // per lane and row into the wave's own rows of hl); a wave copies its rows
-  // to registers when a slab's processing starts and at once issues the next
-  // slab's loads into the same rows, which then stay in flight through the
-  // slab's adjoint step, z-update and forward step.
+  // h: the rows of the slab being processed; hn: the next slab's, loaded
+  // straight into registers while this one is processed (staging them in
+  // LDS instead measured 6 % slower: the loads into LDS and the loop's own
+  // LDS traffic share the LDS).
   typename F::Raw h[RPL];
   float2 yv[YL ? 1 : RPL];
   float fr[RPL], fi[RPL];
-  auto stage = [&](int sl) {   // the next slab's rows of this wave -> hl
-    stage_rows<RPL>(reinterpret_cast<const char*>(z.hsl.base) + ((int64_t)(sgb + sl) * mp * CPL) * 8, hl, rb, lane,
-                    ngw);
-  };
-  // hl -> registers (the wave's own rows).  The compiler does not see the
-  // lane-wise LDS writes of the loads into LDS: the empty asm tells it that
-  // hl may have changed.
-  auto unstage = [&]() {
-    asm volatile("" ::"v"(hl) : "memory");
+  typename F::Raw hn[RPL];
+  auto stage = [&](int sl) {   // slab sl's rows of this wave -> hn
+    const float4* sp = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(z.hsl.base) +
+                                                       ((int64_t)(sgb + sl) * mp * CPL) * 8);
 #pragma unroll
     for (int k = 0; k < RPL; ++k)
-      if (k < ngw) h[k] = typename F::Raw{hl[rb + kWave * k]};
+      if (k < ngw) hn[k] = typename F::Raw{ldnt4(sp + rb + kWave * k)};
+  };
+  auto unstage = [&]() {   // after the wait for hn at a slab's start
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) h[k] = hn[k];
   };
   {
     const float2* yj = a.y + (int64_t)j * mp;
@@ -144,6 +131,7 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
       fr[k] = fi[k] = 0.f;
       if (!YL) yv[k] = make_float2(0.f, 0.f);
       h[k] = typename F::Raw{};
+      hn[k] = typename F::Raw{};
       if (k < ngw) {
         const int rp = rb + kWave * k;
         float2 yy = yj[rp];
@@ -190,7 +178,7 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
 
   for (int sl = sl0; sl < sl1; sl += step) {
     const bool more = sl + step < sl1;
-    // this slab's rows in hl (loaded a slab ago), the prefetched c, s, v and
+    // this slab's rows in hn (loaded a slab ago), the prefetched c, s, v and
     // the previous slab's stores: all complete
     __builtin_amdgcn_s_waitcnt(0);
     unstage();
@@ -200,8 +188,6 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
       if (tid < CPL) zv[tid] = pv;
     }
     if (more) {
-      // the copies must have left the wave's rows of hl before they are refilled
-      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
       stage(sl + step);
     }
     if (full) {
