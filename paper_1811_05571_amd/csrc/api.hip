@@ -331,8 +331,9 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
       // one of 1024 per CU) in proportion to the block widths, by largest
       // remainders, at least one per block; one workgroup more than fit
       // would run alone after the others and double the kernel's time.
-      // Workgroup w of a block with N workgroups takes slabs w, w + N, w + 2N,
-      // ..., so the workgroups read neighbouring slabs at the same time.
+      // Workgroup q of a block of ns slabs with N workgroups takes the run of
+      // slabs [q ns / N, (q + 1) ns / N): its new s, c and v then fill whole
+      // cache lines (eight slabs at a time) instead of 16-byte pieces.
       const int cplz = cols_per_load(storage);
       std::vector<int64_t> ns(P);
       int64_t tot = 0;
@@ -362,7 +363,8 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
       for (int j = 0; j < P; ++j) {
         const int nwj = (int)nw[j];
         const int w0 = (int)geo.t_fz.size();
-        for (int q = 0; q < nwj; ++q) geo.t_fz.push_back(make_int4(j, q, (int)ns[j], (int)sgb));
+        for (int q = 0; q < nwj; ++q)
+          geo.t_fz.push_back(make_int4(j, (int)(ns[j] * q / nwj), (int)(ns[j] * (q + 1) / nwj), (int)sgb));
         geo.fz_colwg.push_back(make_int2(w0, (int)geo.t_fz.size()));
         sgb += ns[j];
       }

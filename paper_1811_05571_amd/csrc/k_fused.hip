@@ -65,8 +65,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_fz_rows(IterArgs a, FzArgs z,
   row_epi_store(a, d, lr, hc.x, hc.y, epi);
 }
 
-// The slab pass.  Workgroup w takes slabs sl0, sl0 + N, ... < sl1 of column
-// block j (work[w], N the block's workgroups); wave v holds the ngw[v] 64-row groups g0[v] .. of one row block
+// The slab pass.  Workgroup w takes the run of slabs [sl0, sl1) of column
+// block j (work[w]); wave v holds the ngw[v] 64-row groups g0[v] .. of one row block
 // wblk[v] (a row block spans whole waves), lane l row 64 g + l of group g, one
 // 16-byte lane load per row: RPL lane loads of the current slab stay in
 // registers.  Per slab:
@@ -91,10 +91,14 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
   __shared__ float red[NW][2 * CPL];
   __shared__ float2 zc[kFzMaxQ * CPL], zs[kFzMaxQ * CPL], zv[CPL], cn[kFzMaxQ * CPL];
   __shared__ int bws[kFzMaxQ + 1];            // waves of each row block (read per lane)
+  // The z-update's new s, c (replica i, column t of slab g0 + k at [k][i CPL
+  // + t]) and v of a group of kGS slabs: written out as whole 128-byte lines
+  // per replica once the group is done (16-byte pieces per slab, scattered
+  // through the stream of H, cost 7 % of the kernel's time).
+  constexpr int kGS = 8;
+  __shared__ float2 ws_s[kGS][kFzMaxQ * CPL], ws_c[kGS][kFzMaxQ * CPL], ws_v[kGS][CPL];
   const int4 wk = z.work[blockIdx.x];
   const int j = wk.x, sl0 = wk.y, sl1 = wk.z, sgb = wk.w;
-  const int2 cw = z.colwg[j];
-  const int step = cw.y - cw.x;   // the column block's workgroups take every step-th slab
   const ColDesc cd = a.cols[j];
   const F f = MakeFmt<F>::make(z.hsl);
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
@@ -166,9 +170,12 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
     }
   };
   prefetch(sl0);
-  // residual partial sums of the z-update lanes (wave 0), in registers: an
-  // LDS read-modify-write per slab would sit on the path to the barrier
-  double racc[kRedCount] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  // residual partial sums of the z-update lanes (wave 0), in LDS: the
+  // registers go to the next slab's rows
+  __shared__ double racc[kRedCount][kWave];
+  if (wave == 0)
+#pragma unroll
+    for (int q = 0; q < kRedCount; ++q) racc[q][lane] = 0.0;
   // butterfly levels of the replica sum: lanes i*CPL + t, i < Q, span the
   // lowest log2(CPL) + ceil(log2 Q) lane bits (the lanes above hold zeros)
   int qspan = CPL;
@@ -176,19 +183,39 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
   if (tid <= Q) bws[tid] = z.bw[tid];
   lds_barrier();   // ys and bws complete
 
-  for (int sl = sl0; sl < sl1; sl += step) {
-    const bool more = sl + step < sl1;
+  // slabs [g0, g1) of the group buffers -> s, c, v (wave 0; issued after a
+  // slab's wait, so the next slab's wait gives the writes a slab's time)
+  auto flush = [&](int g0, int g1) {
+    if (wave == 0) {
+      const int ncol = (g1 - g0) * CPL;
+      for (int e = lane; e < Q * kGS * CPL; e += kWave) {
+        const int i = e / (kGS * CPL), k = e - i * (kGS * CPL), col = g0 * CPL + k;
+        if (k < ncol && col < cd.nj) {
+          const int slot = k / CPL, t = k - slot * CPL;
+          // 32-bit element offsets from the (uniform) array bases
+          const uint32_t p = (uint32_t)(cd.cpad0 + col), r = (uint32_t)i * (uint32_t)np;
+          a.s[r + p] = ws_s[slot][i * CPL + t];
+          a.c[r + (uint32_t)(cd.cpad0 + cperm(col, a.cpl))] = ws_c[slot][i * CPL + t];
+          if (i == 0) a.v[p] = ws_v[slot][t];
+        }
+      }
+    }
+  };
+  for (int sl = sl0; sl < sl1; ++sl) {
+    const bool more = sl + 1 < sl1;
+    const int g0 = max(sl0, sl - sl % kGS);   // this slab's group
     // this slab's rows in hn (loaded a slab ago), the prefetched c, s, v and
     // the previous slab's stores: all complete
     __builtin_amdgcn_s_waitcnt(0);
     unstage();
+    if (full && sl > sl0 && sl % kGS == 0) flush(max(sl0, sl - kGS), sl);   // the previous group
     if (tid < QC) {   // read after this slab's first barrier
       zc[tid] = pc;
       zs[tid] = ps;
       if (tid < CPL) zv[tid] = pv;
     }
     if (more) {
-      stage(sl + step);
+      stage(sl + 1);
     }
     if (full) {
       float ar[CPL][2];
@@ -263,22 +290,21 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
             vr = mar * sc;
             vi = mai * sc;
           }
-          const int64_t p = cd.cpad0 + col;
           const float dr = xr - vr, di = xi - vi;
           const float sr = sr0 + dr, sim = si0 + di;
           const float2 cnew = make_float2(vr - sr, vi - sim);
-          a.s[(int64_t)i * np + p] = make_float2(sr, sim);
-          a.c[(int64_t)i * np + cd.cpad0 + cperm(col, a.cpl)] = cnew;
+          ws_s[sl - g0][lane] = make_float2(sr, sim);
+          ws_c[sl - g0][lane] = cnew;
           cn[lane] = cnew;
-          racc[kRedRp2] += (double)dr * dr + (double)di * di;
-          racc[kRedU2] += (double)xr * xr + (double)xi * xi;
-          racc[kRedS2] += (double)sr * sr + (double)sim * sim;
+          racc[kRedRp2][lane] += (double)dr * dr + (double)di * di;
+          racc[kRedU2][lane] += (double)xr * xr + (double)xi * xi;
+          racc[kRedS2][lane] += (double)sr * sr + (double)sim * sim;
           if (i == 0) {
-            a.v[p] = make_float2(vr, vi);
+            ws_v[sl - g0][t] = make_float2(vr, vi);
             const float2 vo = zv[t];
             const double dvr = (double)vr - vo.x, dvi = (double)vi - vo.y;
-            racc[kRedDv2] += dvr * dvr + dvi * dvi;
-            racc[kRedV2] += (double)vr * vr + (double)vi * vi;
+            racc[kRedDv2][lane] += dvr * dvr + dvi * dvi;
+            racc[kRedV2][lane] += (double)vr * vr + (double)vi * vi;
           }
         } else if (act) {
           cn[lane] = make_float2(0.f, 0.f);
@@ -290,7 +316,7 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
       if (tid < QC) cn[tid] = zc[tid];
       lds_barrier();
     }
-    if (more) prefetch(sl + step);   // into LDS at the next slab's start
+    if (more) prefetch(sl + 1);   // into LDS at the next slab's start
     float2 cb[CPL];
 #pragma unroll
     for (int q = 0; q < CPL; ++q) cb[q] = cn[blk * CPL + q];
@@ -304,6 +330,7 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
       }
     }
   }
+  if (full && sl1 > sl0) flush(max(sl0, (sl1 - 1) - (sl1 - 1) % kGS), sl1);   // the last group
   float2* fp = z.fpart + (int64_t)blockIdx.x * mp;
 #pragma unroll
   for (int k = 0; k < RPL; ++k)
@@ -311,7 +338,7 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
   if (full && wave == 0) {
     double acc[kRedCount];
 #pragma unroll
-    for (int q = 0; q < kRedCount; ++q) acc[q] = wave_sum_d(racc[q]);
+    for (int q = 0; q < kRedCount; ++q) acc[q] = wave_sum_d(racc[q][lane]);
     if (lane == 0) {
 #pragma unroll
       for (int q = 0; q < kRedCount; ++q) a.redpart[(int64_t)blockIdx.x * kRedCount + q] = acc[q];

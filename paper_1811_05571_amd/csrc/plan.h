@@ -28,7 +28,7 @@ constexpr int kFzMaxQ = 16;         // row blocks (each needs at least one wave)
 struct FzArgs {
   HStore hsl;                       // slab store (same formats as the H store; row scales by global row)
   float2* fpart;                    // [workgroup][m_pad]: that workgroup's part of H c for every row
-  const int4* work;                 // per workgroup {column block, first slab, slabs of the block, slab base of the block}
+  const int4* work;                 // per workgroup {column block, first slab, end slab, slab base of the block}
   const int2* colwg;                // per column block {first workgroup, end workgroup}
   int nwg, mode;                    // mode 0: full iteration step, 1: forward products only (c of the state)
   int ngw[kFzMaxWaves];             // 64-row groups of each wave
@@ -75,7 +75,7 @@ struct Geometry {
   bool fz = false;
   int fz_nt = 0, fz_rpl = 0;       // threads per workgroup, 64-row groups per wave
   int64_t fz_slabs = 0;            // slabs in the slab store
-  std::vector<int4> t_fz;          // per workgroup {j, first slab, slabs of block j, slab base of block j}
+  std::vector<int4> t_fz;          // per workgroup {j, first slab, end slab, slab base of block j}
   std::vector<int2> fz_colwg;      // per column block {first, end workgroup}
   std::vector<int4> t_fzr;         // row kernel: {block, first row, -, -}, 256 rows each
   FzArgs fzt{};                    // the host part of the single-pass arguments (tables)
