@@ -733,8 +733,8 @@ constexpr int kCoefs = kSetupTerms + kIterTerms;
 // and 6144 x 32000 on MI355X (complex64): s/flop (69 TFLOP/s), s per span
 // unit, s per panel step, s per block, s; s per single-pass byte of H (512-
 // and 1024-thread workgroups), s per other byte (7.0 TB/s), s per block, s.
-constexpr double kDefaultCoef[kCoefs] = {1.457e-14, 7.288e-06, 3.749e-04, 1.893e-06, 7.828e-04,
-                                         9.888e-14, 1.601e-13, 1.424e-13, 1.897e-08, 6.847e-05};
+constexpr double kDefaultCoef[kCoefs] = {1.462e-14, 7.313e-06, 3.683e-04, 2.004e-06, 7.954e-04,
+                                         7.962e-14, 1.344e-13, 1.436e-13, 1.701e-08, 6.400e-05};
 
 void model_features(const Geometry& geo, double iter_bytes, double flops, double* fs, double* fi) {
   int64_t kmax = 0;
