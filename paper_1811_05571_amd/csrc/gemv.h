@@ -465,13 +465,15 @@ __device__ __forceinline__ void gram_tile_apply(const float2* __restrict__ G, co
 __device__ __forceinline__ float2 ordered_sum(const float2* __restrict__ p, int T, int64_t stride) {
   float ar = 0.f, ai = 0.f;
   int k = 0;
-  for (; k + 4 <= T; k += 4) {
-    const float2 q0 = p[(int64_t)k * stride], q1 = p[(int64_t)(k + 1) * stride];
-    const float2 q2 = p[(int64_t)(k + 2) * stride], q3 = p[(int64_t)(k + 3) * stride];
-    ar += q0.x; ai += q0.y;
-    ar += q1.x; ai += q1.y;
-    ar += q2.x; ai += q2.y;
-    ar += q3.x; ai += q3.y;
+  for (; k + 8 <= T; k += 8) {   // eight loads in flight, added in order
+    float2 q[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) q[e] = p[(int64_t)(k + e) * stride];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      ar += q[e].x;
+      ai += q[e].y;
+    }
   }
   for (; k < T; ++k) {
     const float2 q = p[(int64_t)k * stride];
