@@ -205,7 +205,7 @@ __global__ __launch_bounds__(NT, 4) void k_fz_slab(IterArgs a, FzArgs z) {   // 
     const bool more = sl + 1 < sl1;
     const int g0 = max(sl0, sl - sl % kGS);   // this slab's group
     // this slab's rows in hn (loaded a slab ago), the prefetched c, s, v and
-    // the previous slab's stores: all complete
+    // the group stores of the previous slab's start: all complete
     __builtin_amdgcn_s_waitcnt(0);
     unstage();
     if (full && sl > sl0 && sl % kGS == 0) flush(max(sl0, sl - kGS), sl);   // the previous group
