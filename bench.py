@@ -361,31 +361,42 @@ def cpu_baseline(prob, n_iter: int, keep=(), H=None):
 CONVERGENCE_CHECKPOINTS = (100, 300, 1000, 3000, 10000)
 
 
-def convergence(plan, g, prob, checkpoints) -> dict:
-    """The solve continued warm from zero through growing iteration counts:
-    at each, the FP64 KKT violation of v (over lambda; zero exactly at the
-    lasso minimiser), the reconstruction NMSE against the synthetic truth, and
-    the last iteration's |r_p|^2, |r_d|^2.  Where the KKT violation falls while
-    the NMSE levels off, the NMSE left is the lasso model's on this geometry,
-    not unfinished iterations."""
+def convergence_run(plan, g, checkpoints):
+    """The solve continued warm from zero through growing iteration counts,
+    run back to back (the GPU kept busy): device copies of v and of the last
+    residuals at each checkpoint, for convergence_eval."""
     import torch
-    pts, done, t_run = [], 0, 0.0
+    pts, done = [], 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     for k in checkpoints:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         v, hist = plan.solve(g, k - done, warm=done > 0, history=True)
-        torch.cuda.synchronize()
-        t_run += time.perf_counter() - t0
+        pts.append((k, v, hist[-1].clone()))
         done = k
+    torch.cuda.synchronize()
+    return pts, time.perf_counter() - t0
+
+
+def convergence_eval(plan, g, prob, run) -> dict:
+    """At each checkpoint of convergence_run: the FP64 KKT violation of v (over
+    lambda; zero exactly at the lasso minimiser), the reconstruction NMSE
+    against the synthetic truth, the nonzeros and the last iteration's
+    |r_p|^2, |r_d|^2.  Where the KKT violation falls while the NMSE levels
+    off, the NMSE left is the lasso model's on this geometry, not unfinished
+    iterations."""
+    pts_dev, t_run = run
+    pts = []
+    for k, v, last in pts_dev:
         vn = v.cpu().numpy()
         pts.append({"iterations": k, "kkt_violation": plan.kkt(g, v),
                     "nmse_vs_truth": float(np.linalg.norm(vn - prob.u_true) ** 2 / np.linalg.norm(prob.u_true) ** 2),
                     "nonzeros": int(np.count_nonzero(vn)),
-                    "final_residuals": [float(x) for x in hist[-1].cpu().numpy()]})
+                    "final_residuals": [float(x) for x in last.cpu().numpy()]})
         print(f"[bench] convergence: {k} iterations, KKT {pts[-1]['kkt_violation']:.3e}, "
               f"NMSE {pts[-1]['nmse_vs_truth']:.4f}", file=sys.stderr, flush=True)
     return {"checkpoints": pts, "solve_s": round(t_run, 3), "truth_nonzeros": int(np.count_nonzero(prob.u_true)),
-            "note": "one solve continued warm through the checkpoints (history on); KKT violation over lambda"}
+            "note": "one solve continued warm through the checkpoints (history on), run back to back before the "
+                    "headline's warm-up; KKT violation over lambda"}
 
 
 def bench_small(args, torch, A, W, dev, reps: int = 5) -> dict:
@@ -839,12 +850,15 @@ def main(argv=None):
     geo = block_geometry(prob.m, prob.n, prob.Q, prob.P)
     workload = prob.name
 
-    def measure(storage: str, steps: int, warmup: int, inverse: str = "c64"):
+    def measure(storage: str, steps: int, warmup: int, inverse: str = "c64", before=None):
         t = time.perf_counter()
         plan = A.Plan(H, prob.Q, prob.P, prob.rho, prob.lam, storage=storage, inverse=inverse)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t
         info = plan.info()
+        # another measurement on the same plan first (untimed here; its solves
+        # start from zero like the timed one)
+        before_res = before(plan) if before is not None else None
         if warmup > 0:   # with the residual history, as timed (its first use costs a one-off allocation)
             plan.solve(g, warmup, history=True)
         # kernel events (on the dispatch packets) on every 10th iteration of the timed region
@@ -873,6 +887,7 @@ def main(argv=None):
         v_np = v.cpu().numpy()
         res = {
             "plan": plan, "v": v, "elapsed": elapsed, "setup_s": setup_s, "info": info, "kern": kern,
+            "before": before_res,
             "dominant": dominant,
             "roofline": {"bound": "hbm", "kernel": dominant, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(dk["gbs"] / HBM_PEAK_GBS, 4),
@@ -886,7 +901,13 @@ def main(argv=None):
               f"{elapsed * 1e3:.1f} ms", file=sys.stderr, flush=True)
         return res
 
-    main = measure("c64", args.steps, args.warmup)
+    # The convergence leg's solves (about 3 s of the same iteration, back to
+    # back) run on the headline plan before its warm-up and timed region,
+    # which then start with the GPU at the clocks it holds under this load,
+    # as in a long solve; their KKT and NMSE are evaluated afterwards.
+    main = measure("c64", args.steps, args.warmup,
+                   before=None if args.no_convergence else
+                   (lambda pl: convergence_run(pl, g, CONVERGENCE_CHECKPOINTS)))
     plan = main["plan"]
     # the same solve replaying captured graphs of 10 iterations (no kernel events)
     plan.solve(g, max(args.steps, 10), history=True)
@@ -912,8 +933,8 @@ def main(argv=None):
         "nmse_vs_truth": main["nmse"], "kkt_violation": main["kkt"],
         "final_residuals": main["final_residuals"],
     }
-    if not args.no_convergence:
-        out["convergence"] = convergence(plan, g, prob, CONVERGENCE_CHECKPOINTS)
+    if main["before"] is not None:
+        out["convergence"] = convergence_eval(plan, g, prob, main["before"])
     form_plans = {}
     if not args.no_forms:
         forms = {}
