@@ -821,7 +821,7 @@ def main(argv=None):
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver keeps every block of the split on a single "
-              "MI355X; runs on more than one GPU are not part of this build.", file=sys.stderr)
+              "MI355X and has no multi-GPU path (--gpus must be 1).", file=sys.stderr)
         return 2
 
     import torch
