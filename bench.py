@@ -910,6 +910,7 @@ def main(argv=None):
                    (lambda pl: convergence_run(pl, g, CONVERGENCE_CHECKPOINTS)))
     plan = main["plan"]
     # the same solve replaying captured graphs of 10 iterations (no kernel events)
+    plan.set_graphs(True)
     plan.solve(g, max(args.steps, 10), history=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

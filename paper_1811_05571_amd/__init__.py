@@ -297,7 +297,7 @@ class Plan:
         self.lam = float(lam)
 
     def set_graphs(self, enable: bool):
-        """Graph replay of runs of iterations in solve (on by default)."""
+        """Graph replay of runs of iterations in solve (off by default)."""
         _check(lib().admm_set_graphs(self._h, int(bool(enable))), "admm_set_graphs")
 
     def solve(self, g, iters: int, tol: float = 0.0, check_every: int = 10, warm: bool = False,

@@ -369,8 +369,18 @@ int build_geometry(Geometry& geo, int64_t m, int64_t n, int Q, const int64_t* ro
         sgb += ns[j];
       }
       geo.fz_slabs = sgb;
+      // row kernel: S threads per row share a column block's parts, S the
+      // smallest power of two that leaves each at most ADMM_FZR_LOADS of them
+      // (a row's parts are dependent loads: a long run is a chain of latencies)
+      int64_t tmax = 1;
+      for (int j = 0; j < P; ++j) tmax = std::max(tmax, nw[j]);
+      int loads = ADMM_FZR_LOADS;
+      if (const char* e = getenv("ADMM_FZR_LOADS")) loads = std::max(1, atoi(e));
+      int S = 1;
+      while (S < kWave && tmax > (int64_t)S * loads) S *= 2;
+      const int R = kBlockThreads / S;
       for (size_t b = 0; b < geo.blocks.size(); ++b)
-        for (int r = 0; r < geo.blocks[b].mi; r += kBlockThreads) geo.t_fzr.push_back(make_int4((int)b, r, 0, 0));
+        for (int r = 0; r < geo.blocks[b].mi; r += R) geo.t_fzr.push_back(make_int4((int)b, r, S, 0));
       z.nwg = (int)geo.t_fz.size();
       geo.fz = true;
       geo.fz_nt = nt;
@@ -526,7 +536,7 @@ struct admm_plan {
   bool fz_valid = true;
   // graph replay of fixed-length runs of iterations (admm_solve): captured on
   // an internal stream, keyed by what the captured launches depend on
-  bool graphs = true;
+  bool graphs = false;   // plain launches: faster than graph replay on MI355X (admm_set_graphs)
   hipStream_t gs = nullptr;
   hipEvent_t gin = nullptr, gout = nullptr;
   hipGraphExec_t gexec = nullptr;

@@ -460,7 +460,7 @@ __device__ __forceinline__ void gram_tile_apply(const float2* __restrict__ G, co
   gram_tile_compute(o, diag, out_ab, out_ba, red);
 }
 
-// Sum of T strided complex partials in index order (loads issued four at a
+// Sum of T strided complex partials in index order (loads issued eight at a
 // time; the additions keep the sequential order).
 __device__ __forceinline__ float2 ordered_sum(const float2* __restrict__ p, int T, int64_t stride) {
   float ar = 0.f, ai = 0.f;

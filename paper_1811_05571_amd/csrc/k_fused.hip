@@ -43,9 +43,12 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
-// r_ij = g'_ij - s_row (H_ij c) for 256 rows of one block, H_ij c the ordered
-// sum of the column block's workgroup parts (s_row: fp8 row scale).
-// tiles[x] = {block, first row, -, -}.  Workgroup 0 first completes the
+// r_ij = g'_ij - s_row (H_ij c) for the rows of one tile, H_ij c the sum of
+// the column block's workgroup parts (s_row: fp8 row scale).
+// tiles[x] = {block, first row, S, -}: kBlockThreads / S rows, S threads per
+// row (S a power of two); thread s of a row adds the s-th of S consecutive
+// runs of the parts in order, then the row's first thread adds the S run sums
+// in run order (S = 1: one ordered sum).  Workgroup 0 first completes the
 // previous iteration's residual sums.
 template <class F>
 __global__ __launch_bounds__(kBlockThreads) void k_fz_rows(IterArgs a, FzArgs z, const int4* __restrict__ tiles) {
@@ -57,12 +60,29 @@ __global__ __launch_bounds__(kBlockThreads) void k_fz_rows(IterArgs a, FzArgs z,
     zfinal(a, red);
   }
   const F f = MakeFmt<F>::make(a.hs);
-  const int lr = t.y + threadIdx.x;
-  if (lr >= d.mi) return;
+  const int S = t.z, R = kBlockThreads / S;
+  const int r = threadIdx.x & (R - 1), s = threadIdx.x / R;
+  const int lr = t.y + r;
+  const bool live = lr < d.mi;
+  const int T = wr.y - wr.x, w0 = T * s / S, w1 = T * (s + 1) / S;
   RowEpi epi;
-  row_epi_load(a, d, f, lr, epi);
-  const float2 hc = ordered_sum(z.fpart + (int64_t)wr.x * a.m_pad + d.rpad0 + lr, wr.y - wr.x, a.m_pad);
-  row_epi_store(a, d, lr, hc.x, hc.y, epi);
+  if (live && s == 0) row_epi_load(a, d, f, lr, epi);
+  float2 hc = make_float2(0.f, 0.f);
+  if (live) hc = ordered_sum(z.fpart + (int64_t)(wr.x + w0) * a.m_pad + d.rpad0 + lr, w1 - w0, a.m_pad);
+  if (S > 1) {
+    __shared__ float2 runs[kBlockThreads];
+    runs[threadIdx.x] = hc;
+    __syncthreads();
+    if (s == 0) {
+      float ar = 0.f, ai = 0.f;
+      for (int q = 0; q < S; ++q) {
+        ar += runs[q * R + r].x;
+        ai += runs[q * R + r].y;
+      }
+      hc = make_float2(ar, ai);
+    }
+  }
+  if (live && s == 0) row_epi_store(a, d, lr, hc.x, hc.y, epi);
 }
 
 // The slab pass.  Workgroup w takes the run of slabs [sl0, sl1) of column

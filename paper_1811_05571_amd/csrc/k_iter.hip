@@ -222,10 +222,26 @@ __device__ __forceinline__ int64_t gvec(const IterArgs& a, const BlockDesc& d) {
   return a.direct ? (int64_t)d.i * a.n_pad + d.cpad0 : (int64_t)d.j * a.m_pad + d.rpad0;
 }
 
+// y_ij and ghat_ij = g'_ij - rho y_ij of a block of one tile from its single
+// piece, read back by the workgroup that stored it (the sum k_gram_reduce
+// forms, 0 + piece, bit for bit).
+__device__ __forceinline__ void gram_single_finish(const IterArgs& a, const BlockDesc& d, const float2* part) {
+  __syncthreads();   // the piece's stores, by other threads of the workgroup
+  const int l = threadIdx.x;
+  if (l >= d.mi) return;   // d.mi <= kTile
+  const float2 v = part[l];
+  const float ar = 0.f + v.x, ai = 0.f + v.y;
+  const int64_t vi = (int64_t)d.j * a.m_pad + d.rpad0 + l;
+  a.y[vi] = make_float2(ar, ai);
+  const float2 gpv = (a.P > 1) ? a.gp[vi] : a.g[d.row0 + l];
+  a.ghat[vi] = make_float2(fmaf(-a.rho, ar, gpv.x), fmaf(-a.rho, ai, gpv.y));
+}
+
 // y_ij = G_ij^{-1} r_ij over the packed lower tiles of the inverse: every
 // tile is read once and contributes to two 64-row pieces of y (gram_tile_apply);
 // k_gram_reduce adds the pieces in tile order and forms ghat_ij = g'_ij - rho y_ij.
 // The same from the bfloat16-pair copy of the inverse.
+template <bool FIN>
 __global__ __launch_bounds__(kBlockThreads) void k_gram_tile_bf16(IterArgs a, const int4* __restrict__ tiles) {
   __shared__ float2 tt[4][64];
   const int4 t = tiles[blockIdx.x];
@@ -236,6 +252,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_gram_tile_bf16(IterArgs a, co
   float2* part = a.gpart + (int64_t)d.gpo * kTile;
   gram_tile_apply_bf16(G, x + t.y * kTile, x + t.z * kTile, t.y == t.z, part + (int64_t)(t.y * T + t.z) * kTile,
                        part + (int64_t)(t.z * T + t.y) * kTile, tt);
+  if (FIN) gram_single_finish(a, d, part);
 }
 
 // Round to nearest even of each component to bfloat16, packed as (Re | Im << 16).
@@ -248,6 +265,9 @@ __global__ void k_to_bf16_pairs(const float2* __restrict__ src, uint32_t* __rest
 }
 
 // tiles[x] = {block, tile row, tile col, -} (lower pairs), one per workgroup.
+// FIN (every block one tile): the tile's piece is y_ij itself, and the
+// workgroup also does k_gram_reduce's part (y, ghat).
+template <bool FIN>
 __global__ __launch_bounds__(kBlockThreads) void k_gram_tile(IterArgs a, const int4* __restrict__ tiles) {
   __shared__ float2 tt[4][64];
   const int4 t = tiles[blockIdx.x];
@@ -258,6 +278,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_gram_tile(IterArgs a, const i
   float2* part = a.gpart + (int64_t)d.gpo * kTile;
   gram_tile_apply(G, x + t.y * kTile, x + t.z * kTile, t.y == t.z, part + (int64_t)(t.y * T + t.z) * kTile,
                   part + (int64_t)(t.z * T + t.y) * kTile, tt);
+  if (FIN) gram_single_finish(a, d, part);
 }
 
 // y_ij = G^{-1} r over patches of up to 4 x 4 lower tiles (complex64
@@ -658,15 +679,24 @@ hipError_t launch_gemv_n(const IterArgs& a, const int4* tiles, int ntiles, const
 hipError_t launch_gram(const IterArgs& a, const int4* t_gram, int n_gram, const int4* t_gpatch, int n_gpatch,
                        const int4* t_gtr, int n_gtr, hipStream_t st, KTime kt, bool reduce) {
   const bool patch = !a.Ginv16 && n_gpatch > 0;
-  const KTime ka{kt.start, reduce ? nullptr : kt.stop};
-  if (a.Ginv16)
-    LAUNCH_TIMED(k_gram_tile_bf16, dim3(n_gram), dim3(kBlockThreads), st, ka, a, t_gram);
-  else if (patch)
+  // one lower tile per row tile: every block is a single tile
+  const bool fin = reduce && !patch && n_gram == n_gtr;
+  const KTime ka{kt.start, (reduce && !fin) ? nullptr : kt.stop};
+  if (a.Ginv16) {
+    if (fin)
+      LAUNCH_TIMED(k_gram_tile_bf16<true>, dim3(n_gram), dim3(kBlockThreads), st, ka, a, t_gram);
+    else
+      LAUNCH_TIMED(k_gram_tile_bf16<false>, dim3(n_gram), dim3(kBlockThreads), st, ka, a, t_gram);
+  } else if (patch) {
     LAUNCH_TIMED(k_gram_patch, dim3(n_gpatch), dim3(kBlockThreads), st, ka, a, t_gpatch);
-  else
-    LAUNCH_TIMED(k_gram_tile, dim3(n_gram), dim3(kBlockThreads), st, ka, a, t_gram);
+  } else {
+    if (fin)
+      LAUNCH_TIMED(k_gram_tile<true>, dim3(n_gram), dim3(kBlockThreads), st, ka, a, t_gram);
+    else
+      LAUNCH_TIMED(k_gram_tile<false>, dim3(n_gram), dim3(kBlockThreads), st, ka, a, t_gram);
+  }
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !reduce) return e;
+  if (e != hipSuccess || !reduce || fin) return e;
   if (patch)
     LAUNCH_TIMED(k_gram_reduce<true>, dim3(n_gtr), dim3(kBlockThreads), st, (KTime{nullptr, kt.stop}), a, t_gtr);
   else

@@ -37,6 +37,9 @@ struct FzArgs {
   int bw[kFzMaxQ + 1];              // waves of row block i: [bw[i], bw[i+1])
   int rpad0[kFzMaxQ], mi[kFzMaxQ], row0[kFzMaxQ];   // row blocks (row scales of fp8)
 };
+#ifndef ADMM_FZR_LOADS
+#define ADMM_FZR_LOADS 16               // most workgroup parts of H c one thread of the row kernel adds
+#endif
 constexpr int kFzRpl[] = {1, 2, 3, 4, 6};   // row groups per wave built (512 and 1024 threads)
 #ifndef ADMM_FZ_WGS
 #define ADMM_FZ_WGS 512                 // about this many slab-pass workgroups (two per CU)
@@ -77,7 +80,7 @@ struct Geometry {
   int64_t fz_slabs = 0;            // slabs in the slab store
   std::vector<int4> t_fz;          // per workgroup {j, first slab, end slab, slab base of block j}
   std::vector<int2> fz_colwg;      // per column block {first, end workgroup}
-  std::vector<int4> t_fzr;         // row kernel: {block, first row, -, -}, 256 rows each
+  std::vector<int4> t_fzr;         // row kernel: {block, first row, S, -}, 256 / S rows each
   FzArgs fzt{};                    // the host part of the single-pass arguments (tables)
   std::vector<int4> t_dgp;         // direct form: {row block, first row, -, -}, kBlockThreads rows each
   Layout lay;

@@ -240,6 +240,7 @@ def test_graph_replay_matches_plain_launches(torch_gpu, path):
     pg = A.Plan(H, p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off, two_pass=tp, xupdate=xu)
     pe = A.Plan(H, p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off, two_pass=tp, xupdate=xu)
     assert pg.info()["direct"] == (1 if path == "direct" else 0)
+    pg.set_graphs(True)
     pe.set_graphs(False)
     vg, hg = pg.solve(g, 57, history=True)
     ve, he = pe.solve(g, 57, history=True)
