@@ -133,8 +133,8 @@ TRACE_NAMES = {
     "bf16": {"k_gemv_n<FmtBF16>": "k_gemv_n", "k_gemv_nw<FmtBF16>": "k_gemv_n", "k_gemv_h<FmtBF16>": "k_gemv_h"},
     "fp8": {"k_gemv_n<FmtFP8>": "k_gemv_n", "k_gemv_nw<FmtFP8>": "k_gemv_n", "k_gemv_h<FmtFP8>": "k_gemv_h"},
 }
-SHARED_NAMES = {"k_gram_tile": "k_gram", "k_gram_patch": "k_gram", "k_gram_reduce<false>": "k_gram",
-                "k_gram_reduce<true>": "k_gram", "k_zupdate<4>": "k_zupdate"}
+SHARED_NAMES = {"k_gram_tile<false>": "k_gram", "k_gram_tile<true>": "k_gram", "k_gram_patch": "k_gram",
+                "k_gram_reduce<false>": "k_gram", "k_gram_reduce<true>": "k_gram", "k_zupdate<4>": "k_zupdate"}
 
 
 def _short_kernel(name: str) -> str:
@@ -793,6 +793,7 @@ def main(argv=None):
                     help="write profiles/mfma_<batch workload>.md from an MFMA counter run and its kernel trace")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-small", action="store_true", help="skip the 256 x 4096 workload")
+    ap.add_argument("--small-only", action="store_true", help="measure only the 256 x 4096 workload")
     ap.add_argument("--no-convergence", action="store_true",
                     help="skip the KKT violation and NMSE at growing iteration counts")
     ap.add_argument("--no-form-oracle", action="store_true",
@@ -837,6 +838,9 @@ def main(argv=None):
         return 0
     if args.paper_table_only:
         print(json.dumps({"paper_table": bench_paper_table(args, torch, A, W, dev)}), flush=True)
+        return 0
+    if args.small_only:
+        print(json.dumps({"small_256x4096": bench_small(args, torch, A, W, dev)}), flush=True)
         return 0
     t = time.perf_counter()
     prob = W.full_imaging(seed=args.seed)
