@@ -181,6 +181,27 @@ def test_deterministic(torch_gpu):
     assert torch_gpu.equal(v1, v2), "two runs from the zero state must be bitwise equal"
 
 
+@pytest.mark.parametrize("name", ["consensus256x4096", "combined_uneven"])
+def test_row_sum_split_matches_one_thread_per_row(torch_gpu, monkeypatch, name):
+    """The single pass's row kernel adds a column block's workgroup parts of
+    H c with S threads per row (S from ADMM_FZR_LOADS, read at setup): a very
+    large limit gives S = 1 (one ordered sum per row); the default split
+    (S = 32 for the 512 parts of the 256 x 4096 case) reorders only those FP32
+    sums, so both iterate to the same image within the parity bar, 1e-5."""
+    import paper_1811_05571_amd as A
+    p, K = _case(name)
+    H, g = to_device(torch_gpu, p.H), to_device(torch_gpu, p.g)
+    monkeypatch.setenv("ADMM_FZR_LOADS", "1000000")
+    one = A.Plan(H, p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off)
+    monkeypatch.delenv("ADMM_FZR_LOADS")
+    split = A.Plan(H, p.Q, p.P, p.rho, p.lam, p.row_off, p.col_off)
+    assert one.info()["single_pass"] == 1 and split.info()["single_pass"] == 1
+    v1, v2 = one.solve(g, K).cpu().numpy(), split.solve(g, K).cpu().numpy()
+    err = rel(v1, v2)
+    print(f"{name}: S = 1 against the default split: {err:.2e}")
+    assert err <= 1e-5
+
+
 def test_warm_start_continues(torch_gpu):
     p, K = _case("sectioning")
     plan, g, v_full = gpu_solve(torch_gpu, p, 80)
