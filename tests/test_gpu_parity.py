@@ -83,6 +83,10 @@ def _case(name):
         return W.iid_problem(m=8, n=300, nnz=4, Q=8, P=2, rho=10.0, seed=31), 150
     if name == "one_column_blocks":    # n_j = 1: blocks of 2 x 1 (a single column each)
         return W.iid_problem(m=6, n=12, nnz=3, Q=3, P=12, rho=40.0, seed=32), 150
+    if name == "lopsided_sections":    # a 64-column section beside a 4096-column one: the row
+        # kernel splits each row's sum for 504 slab workgroups (S = 32), so the
+        # 8 parts of the narrow section leave most of its threads' runs empty
+        return W.iid_problem(m=256, n=4160, nnz=10, Q=4, P=2, rho=10.0, seed=34, col_off=[0, 64, 4160]), 150
     if name == "lambda_zero":          # lambda = 0: kappa = 0, the least-squares iteration
         return W.iid_problem(m=200, n=1200, nnz=10, Q=2, P=2, rho=10.0, lam_ratio=0.0, seed=33), 150
     raise KeyError(name)
@@ -92,10 +96,11 @@ CASES = ["consensus256x4096", "combined_uneven", "sectioning", "unsplit", "ragge
          "cra_small", "many_sections", "wide_blocks", "tall_sectioning", "square_blocks", "mixed_tall",
          "tall_near_limit", "many_row_blocks", "many_rows_and_sections", "forty_row_blocks",
          "one_row_blocks", "one_column_blocks", "lambda_zero", "tall_auto", "tall_consensus_auto",
-         "tall_combined_uneven"]
+         "tall_combined_uneven", "lopsided_sections"]
 # the direct x-update on every case but the one with 40 row blocks of 3000
-# columns (40 FP64 3000 x 3000 setup matrices)
-DIRECT_CASES = [c for c in CASES if c != "forty_row_blocks"]
+# columns (40 FP64 3000 x 3000 setup matrices) and the one with 4096-column
+# sections (four FP64 4096 x 4096 inverses in the oracle)
+DIRECT_CASES = [c for c in CASES if c not in ("forty_row_blocks", "lopsided_sections")]
 PARITY_RUNS = ([(c, "auto") for c in CASES] + [(c, "two_pass") for c in CASES]
                + [(c, "direct") for c in DIRECT_CASES])
 
