@@ -134,6 +134,14 @@ const char* admm_last_error(void);
  * Errors: EINVAL for any bad size or split, an unknown flag, or both
  * x-update flags.  Every block shape is served, by one of the two forms of
  * the x-update (see ADMM_XUPDATE_DIRECT).
+ * Launch-shape overrides, read from the environment when the split is
+ * planned (sizing, setup, cost model), for tuning sweeps; results stay
+ * within rounding of the defaults:
+ *   ADMM_FZ_NT=1024     1024-thread slab workgroups even where 512 would do;
+ *   ADMM_FZ_WGS=N       about N slab workgroups instead of 512 (256 of 1024
+ *                       threads);
+ *   ADMM_FZR_LOADS=N    at most N workgroup parts of H c added by one thread
+ *                       of the row kernel (default 16).
  */
 int admm_workspace_bytes(int64_t m, int64_t n, int Q, const int64_t* row_off,
                          int P, const int64_t* col_off, int storage,
