@@ -138,8 +138,8 @@ const char* admm_last_error(void);
  * planned (sizing, setup, cost model), for tuning sweeps; results stay
  * within rounding of the defaults:
  *   ADMM_FZ_NT=1024     1024-thread slab workgroups even where 512 would do;
- *   ADMM_FZ_WGS=N       about N slab workgroups instead of 512 (256 of 1024
- *                       threads);
+ *   ADMM_FZ_WGS=N       about N slab workgroups (default 512 of 512 threads,
+ *                       256 of 1024);
  *   ADMM_FZR_LOADS=N    at most N workgroup parts of H c added by one thread
  *                       of the row kernel (default 16).
  */
